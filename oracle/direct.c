@@ -1,0 +1,126 @@
+/*
+ * Oracle A -- FP64 brute-force superposition.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Every ray sums the contribution of every particle (Sec. 3.2: the lensing
+ * quantities obey superposition; Sec. 5.1: theta_force = 0 is this direct
+ * sum).  Nothing here is blocked, reordered or approximated.
+ */
+#include <math.h>
+#include <string.h>
+
+#include "oracle.h"
+
+/* Normalisation of the truncated Gaussian surface density (Sec. 3.1): the
+ * kernel is divided by 1 - exp(-q^2/2) so that its total mass is m. */
+double ora_kernel_norm(double q) { return -expm1(-0.5 * q * q); }
+
+/*
+ * One particle, per unit mass, at offset d = ray - particle.
+ *
+ * Deflection (Sec. 3.2, smoothed particle; Sec. 3.5, star):
+ *   alpha = G(r) d / r^2, G = (1 - exp(-u)) / C inside the support, 1 outside,
+ *   u = r^2 / (2 s^2), C = 1 - exp(-q^2/2).  The printed exponent lacks the
+ *   square on the smoothing length; the square is what makes alpha the
+ *   enclosed mass of the Gaussian of Sec. 3.1 (checked by the kappa = div/2
+ *   tests).
+ * Convergence kappa = (1/2) div alpha (Sec. 3.2) = exp(-u) / (2 s^2 C) inside,
+ *   0 outside.
+ * Shear gamma1 = (d1 a1 - d2 a2)/2, gamma2 = d1 a2 (Sec. 3.2).  For
+ *   alpha = f(r) d one finds gamma = (kappa - G/r^2) (d1^2 - d2^2, 2 d1 d2)/r^2.
+ * Smoothing derivative d alpha / d s = -d exp(-u) / (s^3 C) inside, 0 outside.
+ */
+void ora_unit_terms(double d1, double d2, double s, double q, int inside, double out[7])
+{
+    memset(out, 0, 7 * sizeof(double));
+    const double r2 = d1 * d1 + d2 * d2;
+    const double C = ora_kernel_norm(q);
+    if (r2 == 0.0) {
+        /* a ray exactly on a particle: alpha and gamma vanish by symmetry */
+        if (inside) out[2] = 1.0 / (2.0 * s * s * C);
+        return;
+    }
+    double G = 1.0, K = 0.0, dG = 0.0;
+    if (inside) {
+        const double u = r2 / (2.0 * s * s);
+        const double e = exp(-u);
+        G = -expm1(-u) / C;
+        K = e / (2.0 * s * s * C);
+        dG = -e / (s * s * s * C); /* (d alpha / d s) = dG * d */
+    }
+    const double h = G / r2;
+    out[0] = h * d1;
+    out[1] = h * d2;
+    out[2] = K;
+    const double Gam = h - K;
+    out[3] = -Gam * (d1 * d1 - d2 * d2) / r2;
+    out[4] = -Gam * 2.0 * d1 * d2 / r2;
+    out[5] = dG * d1;
+    out[6] = dG * d2;
+}
+
+/* inside iff s > 0 and r^2 < (q s)^2 (strict, Sec. 3.1). */
+int ora_inside(double d1, double d2, double s, double q)
+{
+    if (!(s > 0.0)) return 0;
+    const double qs = q * s;
+    return d1 * d1 + d2 * d2 < qs * qs;
+}
+
+int ora_direct(const double* x, const double* y, const double* m, const double* s, int64_t n,
+               double q, const double* rx, const double* ry, int64_t nr,
+               double* a1, double* a2, double* kap, double* g1, double* g2, int nthreads)
+{
+    if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t r = 0; r < nr; ++r) {
+        double acc[5] = {0, 0, 0, 0, 0};
+        for (int64_t i = 0; i < n; ++i) {
+            const double d1 = rx[r] - x[i], d2 = ry[r] - y[i];
+            const double si = s ? s[i] : 0.0;
+            double t[7];
+            ora_unit_terms(d1, d2, si, q, ora_inside(d1, d2, si, q), t);
+            for (int k = 0; k < 5; ++k) acc[k] += m[i] * t[k];
+        }
+        a1[r] = acc[0];
+        a2[r] = acc[1];
+        kap[r] = acc[2];
+        g1[r] = acc[3];
+        g2[r] = acc[4];
+    }
+    return 0;
+}
+
+/*
+ * Gradient of L = sum_r (ga1_r alpha1_r + ga2_r alpha2_r).
+ *   dL/dm_i = sum_r ga_r . alpha_ri / m_i   (alpha is linear in m_i)
+ *   dL/dx_i = -sum_r (J_ri ga_r)_1, dL/dy_i = -sum_r (J_ri ga_r)_2, with the
+ *     symmetric magnification-matrix part J = [[k+g1, g2], [g2, k-g1]] of the
+ *     single particle (alpha depends on ray - particle only).
+ *   dL/ds_i = sum_r ga_r . d alpha_ri / d s_i.
+ */
+int ora_direct_grad(const double* x, const double* y, const double* m, const double* s, int64_t n,
+                    double q, const double* rx, const double* ry, int64_t nr,
+                    const double* ga1, const double* ga2,
+                    double* dm, double* dx, double* dy, double* ds, int nthreads)
+{
+    if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t i = 0; i < n; ++i) {
+        double gm = 0, gx = 0, gy = 0, gs = 0;
+        const double si = s ? s[i] : 0.0;
+        for (int64_t r = 0; r < nr; ++r) {
+            const double d1 = rx[r] - x[i], d2 = ry[r] - y[i];
+            double t[7];
+            ora_unit_terms(d1, d2, si, q, ora_inside(d1, d2, si, q), t);
+            gm += ga1[r] * t[0] + ga2[r] * t[1];
+            gx -= ga1[r] * (t[2] + t[3]) + ga2[r] * t[4];
+            gy -= ga1[r] * t[4] + ga2[r] * (t[2] - t[3]);
+            gs += ga1[r] * t[5] + ga2[r] * t[6];
+        }
+        dm[i] = gm;
+        dx[i] = m[i] * gx;
+        dy[i] = m[i] * gy;
+        if (ds) ds[i] = m[i] * gs;
+    }
+    return 0;
+}

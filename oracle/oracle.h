@@ -1,0 +1,91 @@
+/*
+ * CPU oracle for the lensing hot path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, FP64 reference implementations used by the tests, the smoke
+ * check and the benchmark's CPU-baseline leg.  Nothing in the product path
+ * links, loads or calls this code, and it shares no source with the GPU
+ * library.
+ *
+ *   oracle A  (direct.c) : brute-force superposition of every particle
+ *                          (Sec. 3.2, "superposition"; Sec. 5.1, theta = 0).
+ *   oracle B  (tree.c)   : the modified quad-tree solver of Sec. 3.2 written
+ *                          out as a pointer-free recursive tree in FP64.
+ *
+ * Code units: masses are m / (pi Sigma_crit), so a point mass deflects
+ * alpha = m d / |d|^2 and its Einstein radius is sqrt(m) (Sec. 3.5).
+ */
+#ifndef GLAMER_ORACLE_H
+#define GLAMER_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Contribution of one particle at offset d = ray - particle.
+ * Per unit mass; `inside` selects the truncated Gaussian kernel, otherwise the
+ * point-mass form.  out: a1 a2 kappa g1 g2 da1/ds da2/ds. */
+void ora_unit_terms(double d1, double d2, double s, double q, int inside, double out[7]);
+
+/* inside the truncated support: s > 0 and r^2 < (q s)^2 (Sec. 3.1) */
+int ora_inside(double d1, double d2, double s, double q);
+
+/* 1 - exp(-q^2/2), the kernel normalisation of the truncated Gaussian. */
+double ora_kernel_norm(double q);
+
+/* Oracle A: FP64 brute force.  Outputs are overwritten. */
+int ora_direct(const double* x, const double* y, const double* m, const double* s, int64_t n,
+               double q, const double* rx, const double* ry, int64_t nr,
+               double* a1, double* a2, double* kap, double* g1, double* g2, int nthreads);
+
+/* Oracle A adjoint: gradient of L = sum_r ga_r . alpha_r with respect to the
+ * particle masses, positions and smoothing lengths (FP64 brute force). */
+int ora_direct_grad(const double* x, const double* y, const double* m, const double* s, int64_t n,
+                    double q, const double* rx, const double* ry, int64_t nr,
+                    const double* ga1, const double* ga2,
+                    double* dm, double* dx, double* dy, double* ds, int nthreads);
+
+/* Oracle B: reference tree. */
+typedef struct ora_tree ora_tree;
+
+ora_tree* ora_tree_build(const double* x, const double* y, const double* m, const double* s,
+                         int64_t n, double q, double theta, int leaf_size, int order);
+void ora_tree_free(ora_tree* t);
+int64_t ora_tree_ncells(const ora_tree* t);
+/* root square: x0, y0, side */
+void ora_tree_root(const ora_tree* t, double out[3]);
+/* Per cell, in depth-first preorder with children in Morton order. */
+void ora_tree_export(const ora_tree* t, int32_t* level, uint32_t* ix, uint32_t* iy,
+                     int32_t* np, int32_t* leaf, int32_t* nl, int64_t* next,
+                     double* M, double* cx, double* cy, double* rcut2, double* Q /* 2(p+1) */);
+/* Member / list particle indices of one cell, ascending. Returns count. */
+int64_t ora_tree_members(const ora_tree* t, int64_t cell, int32_t* out);
+int64_t ora_tree_list(const ora_tree* t, int64_t cell, int32_t* out);
+
+/* Forward walk.  counts (nullable) receives per ray:
+ *   [0] cells visited (MAC tests)  [1] cells accepted  [2] leaf particles summed
+ *   [3] list entries examined      [4] list particles the ray falls inside */
+int ora_tree_shoot(const ora_tree* t, const double* rx, const double* ry, int64_t nr,
+                   double* a1, double* a2, double* kap, double* g1, double* g2,
+                   int64_t* counts, int nthreads);
+
+/* Decision tape: record every branch of the walk for these rays, then replay
+ * it after ora_tree_set_particles has changed masses/positions/smoothing
+ * (membership, lists and accept/open/inside decisions stay frozen). */
+int ora_tree_record(ora_tree* t, const double* rx, const double* ry, int64_t nr);
+int ora_tree_set_particles(ora_tree* t, const double* x, const double* y, const double* m,
+                           const double* s);
+int ora_tree_shoot_frozen(const ora_tree* t, const double* rx, const double* ry, int64_t nr,
+                          double* a1, double* a2, double* kap, double* g1, double* g2);
+
+/* Adjoint of the tree walk for L = sum_r ga_r . alpha_r (decisions of the
+ * unperturbed walk), FP64. */
+int ora_tree_grad(const ora_tree* t, const double* rx, const double* ry, int64_t nr,
+                  const double* ga1, const double* ga2,
+                  double* dm, double* dx, double* dy, double* ds);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module only draws inputs: particle positions, masses, smoothing lengths and
+ray positions.  It contains none of the lensing arithmetic (no deflection, no
+tree), so the GPU path and the CPU oracle can both consume its arrays without
+sharing any computation.
+
+The workloads follow the paper's synthetic lenses: random point masses in a
+region (Sec. 5.1), smoothed simulation particles whose smoothing length is the
+distance to the N_sph-th neighbour (Sec. 3.1), and stars with a mass function
+implanted near an image (Sec. 3.5).  All draws use numpy's PCG64 generator.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BASE_SEED = 11281312
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# --------------------------------------------------------------------------
+# ray sets
+# --------------------------------------------------------------------------
+def ray_grid(n: int, lo: float = -0.5, hi: float = 0.5):
+    """n x n cell-centred grid over [lo, hi]^2, row-major with x fastest."""
+    h = (hi - lo) / n
+    c = lo + (np.arange(n, dtype=np.float64) + 0.5) * h
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    return X.ravel().copy(), Y.ravel().copy()
+
+
+def uniform_points(n: int, seed: int, lo: float = -0.5, hi: float = 0.5):
+    g = rng(seed)
+    return g.uniform(lo, hi, n), g.uniform(lo, hi, n)
+
+
+# --------------------------------------------------------------------------
+# particle sets
+# --------------------------------------------------------------------------
+def nfw_projected(n: int, seed: int, c: float = 5.0, r200: float = 1.0):
+    """Projected positions of n particles drawn from a 3D NFW profile.
+
+    Radii follow the enclosed-mass fraction mu(x) = ln(1+x) - x/(1+x) on
+    x = r/r_s in [0, c] (truncated at r200 = c r_s), inverted through the
+    principal branch of the Lambert W function; directions are isotropic.
+    """
+    from scipy.special import lambertw
+
+    g = rng(seed)
+    rs = r200 / c
+    mu_c = math.log1p(c) - c / (1.0 + c)
+    t = g.uniform(0.0, 1.0, n) * mu_c
+    w = lambertw(-np.exp(-1.0 - t), 0).real
+    x = -1.0 / w - 1.0
+    r = np.clip(x, 0.0, c) * rs
+    cost = g.uniform(-1.0, 1.0, n)
+    phi = g.uniform(0.0, 2.0 * math.pi, n)
+    sint = np.sqrt(np.maximum(0.0, 1.0 - cost * cost))
+    return r * sint * np.cos(phi), r * sint * np.sin(phi)
+
+
+def knn_smoothing(x, y, k: int = 32):
+    """2D distance from each particle to its k-th nearest neighbour (self excluded)."""
+    from scipy.spatial import cKDTree
+
+    pts = np.column_stack([x, y])
+    tree = cKDTree(pts)
+    d, _ = tree.query(pts, k=k + 1, workers=-1)
+    return np.ascontiguousarray(d[:, k])
+
+
+def salpeter_masses(n: int, seed: int, lo: float = 0.1, hi: float = 1.0, slope: float = 2.35):
+    """Masses with dN/dm proportional to m^-slope on [lo, hi] (inverse CDF)."""
+    g = rng(seed)
+    a = 1.0 - slope
+    u = g.uniform(0.0, 1.0, n)
+    return (lo ** a + u * (hi ** a - lo ** a)) ** (1.0 / a)
+
+
+@dataclass
+class Lens:
+    """Particles of one lens plane (code units: a point mass deflects m d/|d|^2)."""
+
+    x: np.ndarray
+    y: np.ndarray
+    m: np.ndarray
+    s: np.ndarray  # smoothing length; 0 marks a point mass
+    q: float = 3.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+def point_masses(n: int, seed: int, m: float = 1e-3, half: float = 0.5) -> Lens:
+    """n equal point masses uniform in the square [-half, half]^2."""
+    g = rng(seed)
+    x = g.uniform(-half, half, n)
+    y = g.uniform(-half, half, n)
+    return Lens(x, y, np.full(n, m), np.zeros(n), meta={"kind": "point_masses"})
+
+
+def point_masses_disk(n: int, seed: int, m: float = 1.0, radius: float = 1.0) -> Lens:
+    """n equal point masses uniform in a disk (the paper's tree convergence test)."""
+    g = rng(seed)
+    r = radius * np.sqrt(g.uniform(0.0, 1.0, n))
+    ph = g.uniform(0.0, 2.0 * math.pi, n)
+    return Lens(r * np.cos(ph), r * np.sin(ph), np.full(n, m), np.zeros(n),
+                meta={"kind": "point_masses_disk"})
+
+
+def nfw_halo(n: int, seed: int, k: int = 32, q: float = 3.0, total_mass: float = 1.0) -> Lens:
+    """Smoothed NFW halo: equal masses summing to total_mass, kNN smoothing."""
+    x, y = nfw_projected(n, seed)
+    s = knn_smoothing(x, y, k) if n > k else np.full(n, 0.05)
+    return Lens(x, y, np.full(n, total_mass / n), s, q=q, meta={"kind": "nfw", "k": k})
+
+
+def star_patch(n: int, seed: int, center=(0.25, 0.0), side: float = 0.01,
+               kappa_star: float = 0.3) -> Lens:
+    """n point-mass stars uniform in a square patch, Salpeter masses scaled so
+    that the mean stellar convergence over the patch equals kappa_star."""
+    g = rng(seed)
+    x = center[0] + g.uniform(-side / 2, side / 2, n)
+    y = center[1] + g.uniform(-side / 2, side / 2, n)
+    m = salpeter_masses(n, seed + 1)
+    # kappa = (sum m) * pi / area in code units (m already divided by pi Sigma_crit)
+    m *= kappa_star * side * side / math.pi / m.sum()
+    return Lens(x, y, m, np.zeros(n), meta={"kind": "stars"})
+
+
+def gaussian_blobs(n: int, seed: int, s_lo: float = 0.01, s_hi: float = 0.1,
+                   half: float = 0.5, q: float = 3.0) -> Lens:
+    """Smoothed particles with random positions, masses and smoothing lengths."""
+    g = rng(seed)
+    x = g.uniform(-half, half, n)
+    y = g.uniform(-half, half, n)
+    m = g.uniform(0.1, 1.0, n) / n
+    s = np.exp(g.uniform(math.log(s_lo), math.log(s_hi), n))
+    return Lens(x, y, m, s, q=q, meta={"kind": "blobs"})
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+def workload_point_masses_1k():
+    """1,000 point masses of m=1e-3 in [-0.5,0.5]^2; 64x64 ray grid."""
+    lens = point_masses(1000, BASE_SEED + 1)
+    rx, ry = ray_grid(64)
+    return lens, rx, ry
+
+
+def workload_nfw(n: int = 1_000_000, grid: int = 2048, seed: int = BASE_SEED + 2):
+    """Smoothed NFW halo (c=5, r200=1) of n particles, kNN32 smoothing, q=3;
+    grid x grid ray grid over [-0.5,0.5]^2."""
+    lens = nfw_halo(n, seed)
+    rx, ry = ray_grid(grid)
+    return lens, rx, ry
+
+
+def sample_rays(rx, ry, k: int, seed: int):
+    """Seeded subset of k ray indices (sorted)."""
+    g = rng(seed)
+    k = min(k, rx.shape[0])
+    return np.sort(g.choice(rx.shape[0], size=k, replace=False))
