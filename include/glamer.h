@@ -1,0 +1,192 @@
+/*
+ * glamer.h -- C ABI of the MI355X (gfx950) tree ray-shooting library.
+ *
+ * For a batch of image-plane points ("rays") on one lens plane the library
+ * computes the deflection alpha, the convergence kappa and the shear
+ * (gamma1, gamma2) (Sec. 3.2, definitions of the lensing quantities), summed
+ * over point masses (Sec. 3.5) and smoothed particles with the truncated
+ * Gaussian profile of Sec. 3.1, by the modified quad-tree of Sec. 3.2:
+ * equal-area boxes, multipole moments about each box's centre of mass, the
+ * opening test |x - x_cm| > r_cut = r_cm / theta (Eq. r_cut), per-box lists of
+ * "big" particles, and direct sums in the leaves.
+ *
+ * Units: masses are m / (pi Sigma_crit) (units of length^2), so a point mass
+ * deflects alpha = m d / |d|^2 and has Einstein radius sqrt(m) (Sec. 3.5).
+ *
+ * Conventions for every entry point
+ *  - Array arguments are DEVICE pointers (HIP global memory) unless stated;
+ *    they stay owned by the caller and are never freed or retained past the
+ *    call except where a tree handle says so.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Work
+ *    is enqueued on it; calls return without waiting unless stated.
+ *  - Arguments are validated on the host before anything is launched; a
+ *    rejected call launches nothing and returns GLM_EINVAL.  glm_last_error()
+ *    returns a message for the last failing call on the calling thread.
+ *  - A failing HIP runtime call returns GLM_EHIP; asynchronous kernel faults
+ *    surface at the next synchronising call.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef GLAMER_H
+#define GLAMER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define GLM_API __attribute__((visibility("default")))
+#else
+#define GLM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GLM_OK = 0,
+    GLM_EINVAL = -1, /* bad argument (null pointer, size, parameter range) */
+    GLM_ENOMEM = -2, /* device or host allocation failed / workspace too small */
+    GLM_EHIP = -3,   /* HIP runtime error */
+    GLM_ESTATE = -4, /* handle not built, or built with other parameters */
+    GLM_EDATA = -5   /* input values rejected (NaN/Inf, negative mass or smoothing) */
+} glm_status;
+
+/* flags */
+#define GLM_ALPHA_ONLY 1u   /* skip kappa and gamma (Sec. 3.2: the solver's option) */
+#define GLM_NO_KAHAN 2u     /* plain FP32 accumulation of alpha (debug) */
+#define GLM_RAYS_ORDERED 4u /* rays already in a spatially coherent order: skip the ray sort */
+
+/* Solver parameters (Sec. 3.2 and 3.1). */
+typedef struct {
+    double theta;      /* opening parameter theta_force, 0 <= theta < 1 (0 = direct sum) */
+    double q;          /* Gaussian cutoff in smoothing lengths, q > 0 (Sec. 3.1) */
+    int32_t leaf_size; /* a box is a leaf when it holds <= leaf_size particles, 1..64 */
+    int32_t order;     /* multipole order p: moments Q_0..Q_p, 0..12 ("monopole and quadrupole" = 2) */
+    uint32_t flags;    /* GLM_* flags */
+} glm_params;
+
+/* Opaque tree handle: host struct plus library-owned device storage for the
+ * sorted particles, boxes, moments and lists.  Rebuilding reuses the storage
+ * when it is large enough. */
+typedef struct glm_tree glm_tree;
+
+typedef struct {
+    int64_t n;           /* particles */
+    int64_t ncells;      /* boxes (depth-first preorder) */
+    int64_t nleaves;
+    int64_t nlisted;     /* particles held in some box's big-particle list */
+    int32_t max_level;   /* deepest box level (root = 0, cap 32) */
+    int32_t order;
+    int32_t check_flags; /* 0 when the build's internal consistency checks passed */
+    int32_t reserved;
+    double root_x0, root_y0, root_side; /* root square */
+    size_t device_bytes; /* device memory held by the handle */
+} glm_tree_info;
+
+/* Create an empty handle.  *out receives it.  Host allocation only. */
+GLM_API glm_status glm_tree_create(glm_tree** out);
+
+/* Release the handle and its device storage.  Synchronises the device. NULL is ignored. */
+GLM_API void glm_tree_destroy(glm_tree* t);
+
+/*
+ * Build the tree of n particles (Sec. 3.2): the root square covers the
+ * particles' bounding box (side = max extent * (1 + 2^-40)); particles are
+ * ordered by 64-bit Morton keys of 32-bit quantised coordinates; boxes are the
+ * Morton-prefix ranges, a box with <= leaf_size particles (or at depth 32) is a
+ * leaf; the moments Q_k = sum m (z - z_cm)^k, k <= order, are built in FP64;
+ * r_cut^2 = (farthest-corner distance from the centre of mass / theta)^2; a
+ * smoothed particle is listed in the highest box where q s > side / 2, if that
+ * box is not below its leaf.
+ *
+ *   x, y, m : device FP64 arrays of length n (positions, masses >= 0)
+ *   s       : device FP64 smoothing lengths >= 0 (0 = point mass), or NULL for
+ *             all point masses
+ *   n       : 1 .. 2^31 - 1
+ *
+ * Synchronises `stream` once (to size the box arrays); the inputs may be
+ * reused or freed after return.  GLM_EDATA if any value is NaN/Inf or a mass
+ * or smoothing length is negative.
+ */
+GLM_API glm_status glm_build_tree(glm_tree* t, const double* x, const double* y, const double* m,
+                          const double* s, int64_t n, const glm_params* params, void* stream);
+
+/* Host copy of the tree summary. */
+GLM_API glm_status glm_tree_get_info(const glm_tree* t, glm_tree_info* out);
+
+/*
+ * Copy the tree out to HOST arrays (each may be NULL to skip), for checking:
+ *   per box, preorder (ncells): level, ix, iy (box index at its level), beg,
+ *     end (range in Morton order), next (preorder index past the subtree),
+ *     leaf (0/1), lbeg, lend (range in the list arrays);
+ *     M, cx, cy, rcut2 (FP64); Q: 2*(order+1) doubles per box, (Re, Im) of
+ *     Q_0..Q_order about the centre of mass (Q_1 as computed, ~0);
+ *   per particle (n, Morton order): perm (original index of the k-th
+ *     particle), key (its 64-bit Morton key, x bits even, y bits odd);
+ *   per list entry (nlisted): list_idx (original particle index).
+ * Synchronises the device.
+ */
+GLM_API glm_status glm_tree_export(const glm_tree* t, int32_t* level, uint32_t* ix, uint32_t* iy,
+                           int32_t* beg, int32_t* end, int32_t* next, int32_t* leaf,
+                           int32_t* lbeg, int32_t* lend, double* M, double* cx, double* cy,
+                           double* rcut2, double* Q, int32_t* perm, uint64_t* key,
+                           int32_t* list_idx);
+
+/* Bytes of device workspace glm_shoot / glm_shoot_adjoint need for nrays rays. */
+GLM_API glm_status glm_shoot_workspace_bytes(int64_t nrays, size_t* bytes);
+
+/*
+ * Forward tree walk (Sec. 3.2) for nrays rays at (rx[i], ry[i]) (device FP64).
+ * Outputs (device FP32, length nrays, input order): a1, a2, kappa, g1, g2.
+ * kappa, g1, g2 may be NULL when the tree was built with GLM_ALPHA_ONLY or
+ * `flags` carries it.  counts (device int32, 4 per ray, nullable) receives per
+ * ray: boxes visited (opening tests), boxes accepted, leaf particles summed,
+ * list particles the ray falls inside.  The walk is FP32 with compensated
+ * summation of alpha; ray-particle and ray-box offsets and every accept/inside
+ * decision are taken in FP64.
+ *   workspace: device buffer of at least glm_shoot_workspace_bytes(nrays).
+ *   flags: GLM_ALPHA_ONLY, GLM_NO_KAHAN, GLM_RAYS_ORDERED (or-ed with the
+ *   tree's).
+ * nrays may be 0 (nothing is launched).
+ */
+GLM_API glm_status glm_shoot(const glm_tree* t, const double* rx, const double* ry, int64_t nrays,
+                     float* a1, float* a2, float* kappa, float* g1, float* g2, int32_t* counts,
+                     uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Plain direct sum over all n particles (theta = 0 equivalent; Sec. 5.1), for
+ * rays (device FP64).  fp64 != 0: outputs are device double arrays; else
+ * float arrays with FP32 evaluation and compensated accumulation.
+ * out5: device pointers a1, a2, kappa, g1, g2 (kappa/g1/g2 nullable).
+ * s may be NULL (point masses).
+ */
+GLM_API glm_status glm_shoot_direct(const double* x, const double* y, const double* m, const double* s,
+                            int64_t n, double q, const double* rx, const double* ry,
+                            int64_t nrays, int fp64, void* const out5[5], void* stream);
+
+/*
+ * Adjoint of glm_shoot for L with cotangents ga1 = dL/dalpha1, ga2 = dL/dalpha2
+ * (device FP32, length nrays, input order).  Replays the forward walk's
+ * decisions on the same tree and rays, and ACCUMULATES (+=) into the device
+ * FP64 arrays (original particle order, length n): dm, dx, dy, ds (each
+ * nullable; ds is zero for point masses).  Moment contributions are pushed
+ * down from boxes to particles through dQ_k/dm_i, dQ_k/dz_i and dz_cm.
+ * Uses FP64 atomics: results are reproducible to rounding, not bitwise.
+ *   workspace: at least glm_shoot_workspace_bytes(nrays) plus the tree's
+ *   box-adjoint scratch, which the handle owns.
+ */
+GLM_API glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* ry,
+                             int64_t nrays, const float* ga1, const float* ga2, double* dm,
+                             double* dx, double* dy, double* ds, uint32_t flags, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+GLM_API const char* glm_last_error(void);
+
+/* Library version string. */
+GLM_API const char* glm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLAMER_H */

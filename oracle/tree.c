@@ -130,8 +130,8 @@ static void cell_moments(ora_tree* t, int64_t c)
     ocell* cl = &t->cells[c];
     double complex* Q = t->Q + c * (t->p + 1);
     const double side = ldexp(t->S, -cl->level);
-    const double bx0 = t->x0 + (double)cl->ix * side, bx1 = t->x0 + (double)(cl->ix + 1u) * side;
-    const double by0 = t->y0 + (double)cl->iy * side, by1 = t->y0 + (double)(cl->iy + 1u) * side;
+    const double bx0 = t->x0 + (double)cl->ix * side, bx1 = t->x0 + ((double)cl->ix + 1.0) * side;
+    const double by0 = t->y0 + (double)cl->iy * side, by1 = t->y0 + ((double)cl->iy + 1.0) * side;
     double M = 0, sx = 0, sy = 0;
     for (int64_t k = cl->beg; k < cl->end; ++k) {
         const int64_t i = t->perm[k];

@@ -1,0 +1,191 @@
+"""MI355X (gfx950) tree ray-shooting for one lens plane (GLAMER, Sec. 3).
+
+Thin Python binding over libglamer.so (include/glamer.h).  PyTorch supplies
+device memory and streams; every step of the computation runs in the HIP
+kernels of the library.  Inputs are CUDA (HIP) float64 tensors.
+
+    tree = Tree().build(x, y, m, s, theta=0.3, q=3.0, leaf_size=8, order=8)
+    out = shoot(tree, rx, ry)           # dict of float32 tensors a1 a2 kappa g1 g2
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _capi
+from ._capi import (GLM_ALPHA_ONLY, GLM_NO_KAHAN, GLM_RAYS_ORDERED, GlamerError, GlmParams,  # noqa: F401
+                    GlmTreeInfo)
+
+__all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
+           "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes"]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _f64(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    return t.contiguous()
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def workspace_bytes(nrays: int) -> int:
+    lib = _capi.load()
+    b = ctypes.c_size_t(0)
+    _capi.check(lib.glm_shoot_workspace_bytes(int(nrays), ctypes.byref(b)))
+    return int(b.value)
+
+
+class Tree:
+    """Handle of a tree built on the GPU (glm_tree)."""
+
+    def __init__(self):
+        self._lib = _capi.load()
+        h = ctypes.c_void_p()
+        _capi.check(self._lib.glm_tree_create(ctypes.byref(h)))
+        self._h = h
+        self.params = None
+        self.n = 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.glm_tree_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def build(self, x, y, m, s=None, theta=0.3, q=3.0, leaf_size=8, order=8, flags=0):
+        x, y, m = _f64(x, "x"), _f64(y, "y"), _f64(m, "m")
+        s = _f64(s, "s") if s is not None else None
+        n = x.shape[0]
+        if y.shape[0] != n or m.shape[0] != n or (s is not None and s.shape[0] != n):
+            raise ValueError("x, y, m, s must have the same length")
+        p = GlmParams(float(theta), float(q), int(leaf_size), int(order), int(flags))
+        _capi.check(self._lib.glm_build_tree(self._h, _ptr(x), _ptr(y), _ptr(m), _ptr(s), n,
+                                             ctypes.byref(p), _stream()))
+        self.params = p
+        self.n = n
+        return self
+
+    def info(self) -> dict:
+        inf = GlmTreeInfo()
+        _capi.check(self._lib.glm_tree_get_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in GlmTreeInfo._fields_}
+
+    def export(self) -> dict:
+        """Host copy of the boxes (preorder), the Morton order and the lists."""
+        import numpy as np
+
+        inf = self.info()
+        nc, n, nl, P = inf["ncells"], inf["n"], inf["nlisted"], inf["order"] + 1
+        out = dict(level=np.zeros(nc, np.int32), ix=np.zeros(nc, np.uint32), iy=np.zeros(nc, np.uint32),
+                   beg=np.zeros(nc, np.int32), end=np.zeros(nc, np.int32), next=np.zeros(nc, np.int32),
+                   leaf=np.zeros(nc, np.int32), lbeg=np.zeros(nc, np.int32), lend=np.zeros(nc, np.int32),
+                   M=np.zeros(nc), cx=np.zeros(nc), cy=np.zeros(nc), rcut2=np.zeros(nc),
+                   Q=np.zeros((nc, P, 2)), perm=np.zeros(n, np.int32), key=np.zeros(n, np.uint64),
+                   list_idx=np.zeros(max(nl, 1), np.int32))
+        order = ["level", "ix", "iy", "beg", "end", "next", "leaf", "lbeg", "lend", "M", "cx", "cy", "rcut2", "Q",
+                 "perm", "key", "list_idx"]
+        _capi.check(self._lib.glm_tree_export(self._h, *[ctypes.c_void_p(out[k].ctypes.data) for k in order]))
+        out["Q"] = out["Q"][..., 0] + 1j * out["Q"][..., 1]
+        out["list_idx"] = out["list_idx"][:nl]
+        out.update(inf)
+        return out
+
+
+def shoot(tree: Tree, rx, ry, counts: bool = False, alpha_only: bool = False, kahan: bool = True,
+          ordered: bool = False, out=None, workspace=None):
+    """Forward walk: returns a dict of float32 tensors a1, a2 (and kappa, g1, g2
+    unless alpha_only), plus counts [R, 4] int32 if requested."""
+    rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
+    R = rx.shape[0]
+    dev = rx.device
+    flags = (GLM_ALPHA_ONLY if alpha_only else 0) | (0 if kahan else GLM_NO_KAHAN) | \
+            (GLM_RAYS_ORDERED if ordered else 0)
+    if out is None:
+        names = ["a1", "a2"] if alpha_only else ["a1", "a2", "kappa", "g1", "g2"]
+        out = {k: torch.empty(R, dtype=torch.float32, device=dev) for k in names}
+    cnt = torch.empty((R, 4), dtype=torch.int32, device=dev) if counts else None
+    if workspace is None and not ordered:
+        workspace = torch.empty(max(workspace_bytes(R), 1), dtype=torch.uint8, device=dev)
+    ws_bytes = workspace.numel() if workspace is not None else 0
+    lib = _capi.load()
+    _capi.check(lib.glm_shoot(tree.handle, _ptr(rx), _ptr(ry), R, _ptr(out["a1"]), _ptr(out["a2"]),
+                              _ptr(out.get("kappa")), _ptr(out.get("g1")), _ptr(out.get("g2")), _ptr(cnt), flags,
+                              _ptr(workspace), ws_bytes, _stream()))
+    if counts:
+        out["counts"] = cnt
+    return out
+
+
+def shoot_direct(x, y, m, s, q, rx, ry, fp64: bool = False, alpha_only: bool = False):
+    """Plain direct sum over all particles on the GPU."""
+    x, y, m = _f64(x, "x"), _f64(y, "y"), _f64(m, "m")
+    s = _f64(s, "s") if s is not None else None
+    rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
+    R = rx.shape[0]
+    dt = torch.float64 if fp64 else torch.float32
+    names = ["a1", "a2"] if alpha_only else ["a1", "a2", "kappa", "g1", "g2"]
+    out = {k: torch.empty(R, dtype=dt, device=rx.device) for k in names}
+    arr = (ctypes.c_void_p * 5)(*[out[k].data_ptr() if k in out else None
+                                  for k in ["a1", "a2", "kappa", "g1", "g2"]])
+    lib = _capi.load()
+    _capi.check(lib.glm_shoot_direct(_ptr(x), _ptr(y), _ptr(m), _ptr(s), x.shape[0], float(q), _ptr(rx), _ptr(ry),
+                                     R, 1 if fp64 else 0, arr, _stream()))
+    return out
+
+
+def shoot_adjoint(tree: Tree, rx, ry, ga1, ga2, dm=None, dx=None, dy=None, ds=None, ordered: bool = False,
+                  workspace=None):
+    """Adjoint walk: accumulates dL/d(m, x, y, s) (float64, original particle
+    order) for cotangents ga = dL/dalpha (float32).  Returns (dm, dx, dy, ds)."""
+    rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
+    R = rx.shape[0]
+    dev = rx.device
+    ga1 = ga1.to(torch.float32).contiguous()
+    ga2 = ga2.to(torch.float32).contiguous()
+    n = tree.n
+    dm = torch.zeros(n, dtype=torch.float64, device=dev) if dm is None else dm
+    dx = torch.zeros(n, dtype=torch.float64, device=dev) if dx is None else dx
+    dy = torch.zeros(n, dtype=torch.float64, device=dev) if dy is None else dy
+    ds = torch.zeros(n, dtype=torch.float64, device=dev) if ds is None else ds
+    if workspace is None and not ordered:
+        workspace = torch.empty(max(workspace_bytes(R), 1), dtype=torch.uint8, device=dev)
+    ws_bytes = workspace.numel() if workspace is not None else 0
+    flags = GLM_RAYS_ORDERED if ordered else 0
+    lib = _capi.load()
+    _capi.check(lib.glm_shoot_adjoint(tree.handle, _ptr(rx), _ptr(ry), R, _ptr(ga1), _ptr(ga2), _ptr(dm), _ptr(dx),
+                                      _ptr(dy), _ptr(ds), flags, _ptr(workspace), ws_bytes, _stream()))
+    return dm, dx, dy, ds
+
+
+class ShootFn(torch.autograd.Function):
+    """alpha(rays; m, x, y, s) through the tree, differentiable in the particle
+    masses, positions and smoothing lengths (the tree topology and every walk
+    decision are those of the forward call)."""
+
+    @staticmethod
+    def forward(ctx, rx, ry, m, x, y, s, params: dict):
+        tree = Tree().build(x.detach(), y.detach(), m.detach(), s.detach() if s is not None else None, **params)
+        out = shoot(tree, rx, ry, alpha_only=True)
+        ctx.tree = tree
+        ctx.save_for_backward(rx, ry)
+        ctx.has_s = s is not None
+        return out["a1"], out["a2"]
+
+    @staticmethod
+    def backward(ctx, g1, g2):
+        rx, ry = ctx.saved_tensors
+        dm, dx, dy, ds = shoot_adjoint(ctx.tree, rx, ry, g1, g2)
+        return None, None, dm, dx, dy, (ds if ctx.has_s else None), None

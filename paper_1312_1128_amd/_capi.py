@@ -1,0 +1,92 @@
+"""ctypes declarations of the C ABI in include/glamer.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libglamer.so")
+
+GLM_OK = 0
+GLM_EINVAL = -1
+GLM_ENOMEM = -2
+GLM_EHIP = -3
+GLM_ESTATE = -4
+GLM_EDATA = -5
+
+GLM_ALPHA_ONLY = 1
+GLM_NO_KAHAN = 2
+GLM_RAYS_ORDERED = 4
+
+# every symbol include/glamer.h declares
+EXPORTED = [
+    "glm_tree_create", "glm_tree_destroy", "glm_build_tree", "glm_tree_get_info", "glm_tree_export",
+    "glm_shoot_workspace_bytes", "glm_shoot", "glm_shoot_direct", "glm_shoot_adjoint",
+    "glm_last_error", "glm_version",
+]
+
+
+class GlmParams(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("q", ctypes.c_double), ("leaf_size", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class GlmTreeInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ncells", ctypes.c_int64), ("nleaves", ctypes.c_int64),
+                ("nlisted", ctypes.c_int64), ("max_level", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("check_flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("root_x0", ctypes.c_double), ("root_y0", ctypes.c_double), ("root_side", ctypes.c_double),
+                ("device_bytes", ctypes.c_size_t)]
+
+
+class GlamerError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"glamer status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libglamer.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1312_1128_amd.build_ext.build()")
+    import torch  # noqa: F401  -- the HIP runtime torch loaded is the one this library binds to
+
+    lib = ctypes.CDLL(path)
+    vp, i64, u32, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int
+    st = ctypes.c_int
+    P = ctypes.POINTER
+    lib.glm_tree_create.argtypes = [P(vp)]
+    lib.glm_tree_create.restype = st
+    lib.glm_tree_destroy.argtypes = [vp]
+    lib.glm_tree_destroy.restype = None
+    lib.glm_build_tree.argtypes = [vp, vp, vp, vp, vp, i64, P(GlmParams), vp]
+    lib.glm_build_tree.restype = st
+    lib.glm_tree_get_info.argtypes = [vp, P(GlmTreeInfo)]
+    lib.glm_tree_get_info.restype = st
+    lib.glm_tree_export.argtypes = [vp] + [vp] * 17
+    lib.glm_tree_export.restype = st
+    lib.glm_shoot_workspace_bytes.argtypes = [i64, P(ctypes.c_size_t)]
+    lib.glm_shoot_workspace_bytes.restype = st
+    lib.glm_shoot.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp]
+    lib.glm_shoot.restype = st
+    lib.glm_shoot_direct.argtypes = [vp, vp, vp, vp, i64, ctypes.c_double, vp, vp, i64, i32, P(vp), vp]
+    lib.glm_shoot_direct.restype = st
+    lib.glm_shoot_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp]
+    lib.glm_shoot_adjoint.restype = st
+    lib.glm_last_error.argtypes = []
+    lib.glm_last_error.restype = ctypes.c_char_p
+    lib.glm_version.argtypes = []
+    lib.glm_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(rc: int):
+    if rc != GLM_OK:
+        raise GlamerError(rc, load().glm_last_error().decode())

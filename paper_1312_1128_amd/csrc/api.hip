@@ -1,0 +1,226 @@
+// C ABI of the gfx950 tree ray-shooting library (include/glamer.h): argument
+// validation, handle and buffer ownership, error messages.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "walk.hpp"
+
+namespace glm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+glm_status fail(glm_status st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+
+glm_status DevBuf::ensure(size_t want)
+{
+    if (want <= bytes && p) return GLM_OK;
+    release();
+    hipError_t e = hipMalloc(&p, want > 0 ? want : 256);
+    if (e != hipSuccess) {
+        p = nullptr;
+        bytes = 0;
+        return fail(GLM_ENOMEM, std::string("device allocation of ") + std::to_string(want) +
+                                    " bytes failed: " + hipGetErrorString(e));
+    }
+    bytes = want;
+    return GLM_OK;
+}
+
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+static glm_status check_params(const glm_params* p)
+{
+    if (!p) return fail(GLM_EINVAL, "params is NULL");
+    if (!(p->theta >= 0.0 && p->theta < 1.0)) return fail(GLM_EINVAL, "theta must be in [0, 1)");
+    if (!(p->q > 0.0) || !isfinite(p->q)) return fail(GLM_EINVAL, "q must be finite and > 0");
+    if (p->leaf_size < 1 || p->leaf_size > 64) return fail(GLM_EINVAL, "leaf_size must be in 1..64");
+    if (p->order < 0 || p->order > kMaxOrder) return fail(GLM_EINVAL, "order must be in 0..12");
+    if (p->flags & ~(GLM_ALPHA_ONLY | GLM_NO_KAHAN | GLM_RAYS_ORDERED)) return fail(GLM_EINVAL, "unknown flag bits");
+    return GLM_OK;
+}
+
+} // namespace glm
+
+struct glm_tree {
+    glm::TreeStorage ts;
+};
+
+using namespace glm;
+
+extern "C" {
+
+const char* glm_last_error(void) { return g_err.c_str(); }
+
+const char* glm_version(void) { return "glamer-gfx950 0.1"; }
+
+glm_status glm_tree_create(glm_tree** out)
+{
+    if (!out) return fail(GLM_EINVAL, "out is NULL");
+    *out = new (std::nothrow) glm_tree();
+    if (!*out) return fail(GLM_ENOMEM, "host allocation failed");
+    return GLM_OK;
+}
+
+void glm_tree_destroy(glm_tree* t)
+{
+    if (!t) return;
+    (void)hipDeviceSynchronize();
+    t->ts.pbuf.release();
+    t->ts.cbuf.release();
+    t->ts.abuf.release();
+    delete t;
+}
+
+glm_status glm_build_tree(glm_tree* t, const double* x, const double* y, const double* m, const double* s, int64_t n,
+                          const glm_params* params, void* stream)
+{
+    if (!t) return fail(GLM_EINVAL, "tree handle is NULL");
+    glm_status rc = check_params(params);
+    if (rc != GLM_OK) return rc;
+    if (!x || !y || !m) return fail(GLM_EINVAL, "x, y and m must be device pointers");
+    if (n < 1 || n > 0x7ffffff0) return fail(GLM_EINVAL, "n must be in 1 .. 2^31 - 16");
+    t->ts.built = false;
+    return build_tree_device(t->ts, x, y, m, s, n, *params, static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_tree_get_info(const glm_tree* t, glm_tree_info* out)
+{
+    if (!t || !out) return fail(GLM_EINVAL, "NULL argument");
+    if (!t->ts.built) return fail(GLM_ESTATE, "tree not built");
+    BuildSync hs;
+    GLM_HIP(hipDeviceSynchronize());
+    GLM_HIP(hipMemcpy(&hs, t->ts.sync, sizeof(hs), hipMemcpyDeviceToHost));
+    out->n = t->ts.n;
+    out->ncells = t->ts.ncells;
+    out->nleaves = hs.nleaves;
+    out->nlisted = hs.nlisted;
+    out->max_level = hs.max_level;
+    out->order = t->ts.params.order;
+    out->check_flags = hs.internal;
+    out->reserved = 0;
+    out->root_x0 = t->ts.x0;
+    out->root_y0 = t->ts.y0;
+    out->root_side = t->ts.side;
+    out->device_bytes = t->ts.pbuf.bytes + t->ts.cbuf.bytes + t->ts.abuf.bytes;
+    return GLM_OK;
+}
+
+glm_status glm_tree_export(const glm_tree* t, int32_t* level, uint32_t* ix, uint32_t* iy, int32_t* beg, int32_t* end,
+                           int32_t* next, int32_t* leaf, int32_t* lbeg, int32_t* lend, double* M, double* cx,
+                           double* cy, double* rcut2, double* Q, int32_t* perm, uint64_t* key, int32_t* list_idx)
+{
+    if (!t) return fail(GLM_EINVAL, "tree handle is NULL");
+    if (!t->ts.built) return fail(GLM_ESTATE, "tree not built");
+    const TreeStorage& ts = t->ts;
+    const size_t nc = (size_t)ts.ncells, n = (size_t)ts.n;
+    GLM_HIP(hipDeviceSynchronize());
+    auto cp = [](void* dst, const void* src, size_t bytes) -> hipError_t {
+        return dst ? hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) : hipSuccess;
+    };
+    GLM_HIP(cp(level, ts.b.level, 4 * nc));
+    GLM_HIP(cp(ix, ts.b.ix, 4 * nc));
+    GLM_HIP(cp(iy, ts.b.iy, 4 * nc));
+    GLM_HIP(cp(beg, ts.b.beg, 4 * nc));
+    GLM_HIP(cp(end, ts.b.end, 4 * nc));
+    GLM_HIP(cp(next, ts.b.next, 4 * nc));
+    GLM_HIP(cp(leaf, ts.b.leaf, 4 * nc));
+    GLM_HIP(cp(lbeg, ts.b.lbeg, 4 * nc));
+    GLM_HIP(cp(lend, ts.b.lend, 4 * nc));
+    GLM_HIP(cp(M, ts.dev.cM, 8 * nc));
+    GLM_HIP(cp(cx, ts.ccx, 8 * nc));
+    GLM_HIP(cp(cy, ts.ccy, 8 * nc));
+    GLM_HIP(cp(Q, ts.dev.cq, 16 * nc * (size_t)(ts.params.order + 1)));
+    GLM_HIP(cp(perm, ts.perm, 4 * n));
+    GLM_HIP(cp(key, ts.key, 8 * n));
+    if (rcut2) {
+        std::vector<CellHdr> h(nc);
+        GLM_HIP(hipMemcpy(h.data(), ts.dev.hdr, sizeof(CellHdr) * nc, hipMemcpyDeviceToHost));
+        for (size_t c = 0; c < nc; ++c) rcut2[c] = h[c].rcut2;
+    }
+    if (list_idx) {
+        BuildSync hs;
+        GLM_HIP(hipMemcpy(&hs, ts.sync, sizeof(hs), hipMemcpyDeviceToHost));
+        std::vector<PRec> l((size_t)hs.nlisted);
+        if (hs.nlisted > 0)
+            GLM_HIP(hipMemcpy(l.data(), ts.dev.lst, sizeof(PRec) * l.size(), hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < l.size(); ++k) list_idx[k] = (int32_t)(l[k].meta & 0x7fffffffu);
+    }
+    return GLM_OK;
+}
+
+glm_status glm_shoot_workspace_bytes(int64_t nrays, size_t* bytes)
+{
+    if (!bytes || nrays < 0) return fail(GLM_EINVAL, "bad argument");
+    *bytes = ray_layout(nrays).bytes;
+    return GLM_OK;
+}
+
+glm_status glm_shoot(const glm_tree* t, const double* rx, const double* ry, int64_t nrays, float* a1, float* a2,
+                     float* kappa, float* g1, float* g2, int32_t* counts, uint32_t flags, void* workspace,
+                     size_t workspace_bytes, void* stream)
+{
+    if (!t) return fail(GLM_EINVAL, "tree handle is NULL");
+    if (!t->ts.built) return fail(GLM_ESTATE, "tree not built");
+    if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays must be in 0 .. 2^31 - 256");
+    if (nrays == 0) return GLM_OK;
+    if (!rx || !ry || !a1 || !a2) return fail(GLM_EINVAL, "rx, ry, a1, a2 must be device pointers");
+    if (flags & ~(GLM_ALPHA_ONLY | GLM_NO_KAHAN | GLM_RAYS_ORDERED)) return fail(GLM_EINVAL, "unknown flag bits");
+    flags |= t->ts.params.flags;
+    if (!(flags & GLM_ALPHA_ONLY) && (!kappa || !g1 || !g2))
+        return fail(GLM_EINVAL, "kappa, g1, g2 are required unless GLM_ALPHA_ONLY");
+    if (!(flags & GLM_RAYS_ORDERED)) {
+        const size_t need = ray_layout(nrays).bytes;
+        if (!workspace || workspace_bytes < need)
+            return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_workspace_bytes(nrays) = " + std::to_string(need));
+    }
+    return shoot_device(t->ts, rx, ry, nrays, a1, a2, kappa, g1, g2, counts, flags, workspace,
+                        static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_shoot_direct(const double* x, const double* y, const double* m, const double* s, int64_t n, double q,
+                            const double* rx, const double* ry, int64_t nrays, int fp64, void* const out5[5],
+                            void* stream)
+{
+    if (!x || !y || !m || !rx || !ry || !out5 || !out5[0] || !out5[1])
+        return fail(GLM_EINVAL, "NULL device pointer");
+    if (n < 1 || n > 0x7ffffff0) return fail(GLM_EINVAL, "n must be in 1 .. 2^31 - 16");
+    if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays out of range");
+    if (!(q > 0.0) || !isfinite(q)) return fail(GLM_EINVAL, "q must be finite and > 0");
+    return direct_device(x, y, m, s, n, q, rx, ry, nrays, fp64, out5, static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* ry, int64_t nrays, const float* ga1,
+                             const float* ga2, double* dm, double* dx, double* dy, double* ds, uint32_t flags,
+                             void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!t) return fail(GLM_EINVAL, "tree handle is NULL");
+    if (!t->ts.built) return fail(GLM_ESTATE, "tree not built");
+    if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays out of range");
+    if (nrays == 0) return GLM_OK;
+    if (!rx || !ry || !ga1 || !ga2) return fail(GLM_EINVAL, "rx, ry, ga1, ga2 must be device pointers");
+    if (flags & ~(GLM_NO_KAHAN | GLM_RAYS_ORDERED | GLM_ALPHA_ONLY)) return fail(GLM_EINVAL, "unknown flag bits");
+    if (!(flags & GLM_RAYS_ORDERED)) {
+        const size_t need = ray_layout(nrays).bytes;
+        if (!workspace || workspace_bytes < need)
+            return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_workspace_bytes(nrays) = " + std::to_string(need));
+    }
+    return adjoint_device(const_cast<glm_tree*>(t)->ts, rx, ry, nrays, ga1, ga2, dm, dx, dy, ds, flags, workspace,
+                          static_cast<hipStream_t>(stream));
+}
+
+} // extern "C"

@@ -1,0 +1,688 @@
+// Tree construction on gfx950 (Sec. 3.2): root square, Morton order, the
+// equal-area quad-tree as Morton-prefix ranges in depth-first preorder,
+// big-particle lists, and FP64 multipole moments built bottom-up.
+//
+// Layout: a box is identified by (first particle in Morton order, level).
+// Sorting boxes by that pair is exactly depth-first preorder with children in
+// Morton order, so a box's preorder index is (number of boxes starting before
+// its first particle) + (its level - the shallowest level that starts there),
+// and the box after its subtree starts at its end position.  Every step is a
+// flat per-particle or per-box kernel; the only host round trip reads the box
+// count to size the box arrays.
+#include <math.h>
+
+#include "build.hpp"
+
+namespace glm {
+
+namespace {
+
+constexpr uint32_t kUnlisted32 = 0xFFFFFFFFu;
+
+__device__ inline uint64_t spread_bits(uint32_t v)
+{
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+__device__ inline uint32_t compact_bits(uint64_t x)
+{
+    x &= 0x5555555555555555ull;
+    x = (x | (x >> 1)) & 0x3333333333333333ull;
+    x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+    return (uint32_t)x;
+}
+
+__device__ inline uint64_t prefix_at(uint64_t k, int level) { return level == 0 ? 0ull : (k >> (64 - 2 * level)); }
+
+// shallowest level at which a box starts at Morton position i (33: none)
+__device__ inline int level_start(const uint64_t* K, int i)
+{
+    if (i == 0) return 0;
+    const uint64_t d = K[i] ^ K[i - 1];
+    if (d == 0) return 33;
+    const int b = 63 - __clzll((long long)d);
+    return (65 - b) >> 1;
+}
+
+// first j in [lo, hi) whose level-`level` prefix exceeds P
+__device__ inline int upper_prefix(const uint64_t* K, int lo, int hi, uint64_t P, int level)
+{
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (prefix_at(K[mid], level) > P) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// first j in [lo, hi) whose prefix is >= P
+__device__ inline int lower_prefix(const uint64_t* K, int lo, int hi, uint64_t P, int level)
+{
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (prefix_at(K[mid], level) >= P) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// ----------------------------------------------------------------- inputs
+
+__global__ __launch_bounds__(kBlock) void k_bbox_partial(const double* __restrict__ x, const double* __restrict__ y,
+                                                        const double* __restrict__ m, const double* __restrict__ s,
+                                                        int64_t n, double* __restrict__ part)
+{
+    __shared__ double red[4][kBlock];
+    __shared__ uint32_t bad_s;
+    if (threadIdx.x == 0) bad_s = 0;
+    __syncthreads();
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    uint32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double xi = x[i], yi = y[i], mi = m[i], si = s ? s[i] : 0.0;
+        if (!isfinite(xi) || !isfinite(yi) || !isfinite(mi) || !isfinite(si) || mi < 0.0 || si < 0.0) bad = 1;
+        x0 = fmin(x0, xi);
+        x1 = fmax(x1, xi);
+        y0 = fmin(y0, yi);
+        y1 = fmax(y1, yi);
+    }
+    if (bad) atomicOr(&bad_s, 1u);
+    red[0][threadIdx.x] = x0;
+    red[1][threadIdx.x] = x1;
+    red[2][threadIdx.x] = y0;
+    red[3][threadIdx.x] = y1;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+            red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][threadIdx.x + o]);
+            red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x * 5 + 0] = red[0][0];
+        part[blockIdx.x * 5 + 1] = red[1][0];
+        part[blockIdx.x * 5 + 2] = red[2][0];
+        part[blockIdx.x * 5 + 3] = red[3][0];
+        part[blockIdx.x * 5 + 4] = bad_s ? 1.0 : 0.0;
+    }
+}
+
+// Root square: centre of the bounding box, side = max extent * (1 + 2^-40)
+// (1 if the extent is 0), 32-bit quantisation scale 2^32 / side.
+__global__ void k_root(const double* __restrict__ part, int nb, BuildSync* __restrict__ sync)
+{
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    int bad = 0;
+    for (int b = 0; b < nb; ++b) {
+        x0 = fmin(x0, part[b * 5 + 0]);
+        x1 = fmax(x1, part[b * 5 + 1]);
+        y0 = fmin(y0, part[b * 5 + 2]);
+        y1 = fmax(y1, part[b * 5 + 3]);
+        bad |= part[b * 5 + 4] != 0.0;
+    }
+    const double ex = x1 - x0, ey = y1 - y0;
+    const double ext = ex > ey ? ex : ey;
+    double S = ext * (1.0 + 0x1p-40);
+    if (!(S > 0.0)) S = 1.0;
+    sync->x0 = 0.5 * (x0 + x1) - 0.5 * S;
+    sync->y0 = 0.5 * (y0 + y1) - 0.5 * S;
+    sync->side = S;
+    sync->scale = 4294967296.0 / S;
+    sync->bad = bad;
+}
+
+__device__ inline uint32_t quantise(double v, double v0, double scale)
+{
+#pragma clang fp contract(off)
+    const double t = (v - v0) * scale;
+    if (!(t >= 0.0)) return 0u;
+    if (t >= 4294967295.0) return 4294967295u;
+    return (uint32_t)floor(t);
+}
+
+__global__ __launch_bounds__(kBlock) void k_morton(const double* __restrict__ x, const double* __restrict__ y,
+                                                  int64_t n, const BuildSync* __restrict__ sync,
+                                                  uint64_t* __restrict__ key, uint32_t* __restrict__ val)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t qx = quantise(x[i], sync->x0, sync->scale);
+    const uint32_t qy = quantise(y[i], sync->y0, sync->scale);
+    key[i] = spread_bits(qx) | (spread_bits(qy) << 1);
+    val[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(const uint32_t* __restrict__ perm, const double* __restrict__ x,
+                                                  const double* __restrict__ y, const double* __restrict__ m,
+                                                  const double* __restrict__ s, int64_t n, double* __restrict__ xs,
+                                                  double* __restrict__ ys, double* __restrict__ ms,
+                                                  double* __restrict__ ss)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t i = perm[k];
+    xs[k] = x[i];
+    ys[k] = y[i];
+    ms[k] = m[i];
+    ss[k] = s ? s[i] : 0.0;
+}
+
+// --------------------------------------------------------------- topology
+
+// Per Morton position i: number of boxes whose range starts at i.  A box at
+// level l >= 1 exists iff its parent holds more than L particles (every
+// ancestor then does too); the boxes starting at i form a chain from the
+// shallowest new level down to the first leaf.
+__global__ __launch_bounds__(kBlock) void k_topo_count(const uint64_t* __restrict__ K, int n, int L,
+                                                      int32_t* __restrict__ cnt, int8_t* __restrict__ lstart)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int ls = level_start(K, i);
+    lstart[i] = (int8_t)ls;
+    int c = 0;
+    if (ls <= kMaxLevel) {
+        int hi = n;
+        bool exists = true;
+        if (ls > 0) {
+            const uint64_t P = prefix_at(K[i], ls - 1);
+            const int lo = lower_prefix(K, 0, i, P, ls - 1);
+            hi = upper_prefix(K, i, n, P, ls - 1);
+            exists = (hi - lo) > L;
+        }
+        if (exists) {
+            for (int l = ls;; ++l) {
+                const int end = l == 0 ? n : upper_prefix(K, i, hi, prefix_at(K[i], l), l);
+                ++c;
+                if (end - i <= L || l == kMaxLevel) break;
+                hi = end;
+            }
+        }
+    }
+    cnt[i] = c;
+}
+
+__global__ void k_sync_counts(const int32_t* __restrict__ cs, int n, BuildSync* __restrict__ sync)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) sync->ncells = cs[n];
+}
+
+__global__ __launch_bounds__(kBlock) void k_topo_emit(const uint64_t* __restrict__ K, int n, int L,
+                                                     const int32_t* __restrict__ cs, const int8_t* __restrict__ lstart,
+                                                     BoxArrays b, BuildSync* __restrict__ sync)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int c0 = cs[i], c = cs[i + 1] - c0;
+    if (c == 0) return;
+    const int ls = lstart[i];
+    int hi = n;
+    if (ls > 0) hi = upper_prefix(K, i, n, prefix_at(K[i], ls - 1), ls - 1);
+    const uint32_t qx = compact_bits(K[i]), qy = compact_bits(K[i] >> 1);
+    int leaves = 0, maxl = 0;
+    for (int k = 0; k < c; ++k) {
+        const int l = ls + k;
+        const int end = l == 0 ? n : upper_prefix(K, i, hi, prefix_at(K[i], l), l);
+        const int idx = c0 + k;
+        const bool leaf = (k == c - 1);
+        b.beg[idx] = i;
+        b.end[idx] = end;
+        b.level[idx] = l;
+        b.next[idx] = cs[end];
+        b.leaf[idx] = leaf ? 1 : 0;
+        b.ix[idx] = l == 0 ? 0u : (uint32_t)((uint64_t)qx >> (32 - l));
+        b.iy[idx] = l == 0 ? 0u : (uint32_t)((uint64_t)qy >> (32 - l));
+        b.lbeg[idx] = 0;
+        b.lend[idx] = 0;
+        hi = end;
+        if (leaf) {
+            leaves++;
+            maxl = l;
+        }
+    }
+    atomicAdd(&sync->nleaves, leaves);
+    atomicMax(&sync->max_level, maxl);
+}
+
+__global__ __launch_bounds__(kBlock) void k_leaf_of(BoxArrays b, int ncells, int32_t* __restrict__ leaf_of)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncells || !b.leaf[c]) return;
+    for (int j = b.beg[c]; j < b.end[c]; ++j) leaf_of[j] = c;
+}
+
+// Big-particle lists (Sec. 3.2): a smoothed particle of support radius q s is
+// listed in the highest box where q s > side / 2, provided that box is not
+// below the particle's leaf.  Key = box index (kUnlisted otherwise).
+__global__ __launch_bounds__(kBlock) void k_list_assign(const uint64_t* __restrict__ K, int n, const double* __restrict__ ss,
+                                                       double q, BuildSync* __restrict__ sync, int ncells,
+                                                       const int32_t* __restrict__ leaf_of, BoxArrays b,
+                                                       const int32_t* __restrict__ cs, const int8_t* __restrict__ lstart,
+                                                       uint32_t unlisted, uint32_t* __restrict__ lkey,
+                                                       uint32_t* __restrict__ lval)
+{
+#pragma clang fp contract(off)
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    uint32_t key = unlisted;
+    const double sj = ss[j];
+    if (sj > 0.0) {
+        const double qs = q * sj;
+        int l = 0;
+        while (l <= kMaxLevel && !(qs > ldexp(sync->side, -(l + 1)))) ++l;
+        const int lf = leaf_of[j];
+        if (lf < 0 || lf >= ncells) {
+            atomicOr(&sync->internal, 1);
+        } else if (l <= kMaxLevel && l <= b.level[lf]) {
+            const int bb = l == 0 ? 0 : lower_prefix(K, 0, j, prefix_at(K[j], l), l);
+            const int cell = cs[bb] + (l - lstart[bb]);
+            if (cell >= 0 && cell < ncells) key = (uint32_t)cell;
+            else atomicOr(&sync->internal, 2);
+        }
+    }
+    lkey[j] = key;
+    lval[j] = (uint32_t)j;
+}
+
+__device__ inline void fill_rec(PRec& r, double x, double y, double m, double s, double q, double invC, bool listed,
+                                uint32_t orig)
+{
+#pragma clang fp contract(off)
+    const double qs = q * s;
+    r.x = x;
+    r.y = y;
+    r.qs2 = s > 0.0 ? qs * qs : 0.0;
+    r.m = (float)m;
+    r.mC = (float)(m * invC);
+    r.h = s > 0.0 ? (float)(1.0 / (2.0 * s * s)) : 0.0f;
+    r.meta = orig | (listed ? 0x80000000u : 0u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_particle_records(int n, const double* __restrict__ xs,
+                                                            const double* __restrict__ ys, const double* __restrict__ ms,
+                                                            const double* __restrict__ ss, const uint32_t* __restrict__ perm,
+                                                            const uint32_t* __restrict__ lkey, uint32_t unlisted,
+                                                            double q, double invC, PRec* __restrict__ prt)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    PRec r;
+    fill_rec(r, xs[j], ys[j], ms[j], ss[j], q, invC, lkey[j] != unlisted, perm[j]);
+    prt[j] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_ranges(int n, const uint32_t* __restrict__ lkey,
+                                                       const uint32_t* __restrict__ lval, uint32_t unlisted,
+                                                       const double* __restrict__ xs, const double* __restrict__ ys,
+                                                       const double* __restrict__ ms, const double* __restrict__ ss,
+                                                       const uint32_t* __restrict__ perm, double q, double invC,
+                                                       BoxArrays b, PRec* __restrict__ lst,
+                                                       BuildSync* __restrict__ sync)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t key = lkey[k];
+    if (key == unlisted) return;
+    if (k == 0 || lkey[k - 1] != key) b.lbeg[key] = k;
+    const bool last = (k == n - 1) || lkey[k + 1] != key;
+    if (last) b.lend[key] = k + 1;
+    if (k == n - 1 || lkey[k + 1] == unlisted) sync->nlisted = k + 1;
+    const uint32_t j = lval[k];
+    PRec r;
+    fill_rec(r, xs[j], ys[j], ms[j], ss[j], q, invC, true, perm[j]);
+    lst[k] = r;
+}
+
+// ---------------------------------------------------------------- moments
+
+__constant__ double c_binom[kMaxOrder + 1][kMaxOrder + 1] = {
+    {1},
+    {1, 1},
+    {1, 2, 1},
+    {1, 3, 3, 1},
+    {1, 4, 6, 4, 1},
+    {1, 5, 10, 10, 5, 1},
+    {1, 6, 15, 20, 15, 6, 1},
+    {1, 7, 21, 35, 35, 21, 7, 1},
+    {1, 8, 28, 56, 70, 56, 28, 8, 1},
+    {1, 9, 36, 84, 126, 126, 84, 36, 9, 1},
+    {1, 10, 45, 120, 210, 252, 210, 120, 45, 10, 1},
+    {1, 11, 55, 165, 330, 462, 462, 330, 165, 55, 11, 1},
+    {1, 12, 66, 220, 495, 792, 924, 792, 495, 220, 66, 12, 1},
+};
+
+__device__ inline void box_bounds(const BoxArrays& b, int c, const BuildSync* sync, double* bx0, double* bx1,
+                                  double* by0, double* by1)
+{
+#pragma clang fp contract(off)
+    const double side = ldexp(sync->side, -b.level[c]);
+    *bx0 = sync->x0 + (double)b.ix[c] * side;
+    *bx1 = sync->x0 + ((double)b.ix[c] + 1.0) * side;
+    *by0 = sync->y0 + (double)b.iy[c] * side;
+    *by1 = sync->y0 + ((double)b.iy[c] + 1.0) * side;
+}
+
+// One level of the bottom-up pass.  Leaves: moments from their particles.
+// Internal boxes: centre of mass of the children, then the children's moments
+// translated, Q_k = sum_children sum_j C(k, j) Q_j(child) t^(k-j) with
+// t = z_child - z_cm (exact re-expansion of sum m (z - z_cm)^k).
+__global__ __launch_bounds__(kBlock) void k_moments_level(int level, int ncells, int p, BoxArrays b,
+                                                         const double* __restrict__ xs, const double* __restrict__ ys,
+                                                         const double* __restrict__ ms,
+                                                         const BuildSync* __restrict__ sync, double* __restrict__ cM,
+                                                         double* __restrict__ ccx, double* __restrict__ ccy,
+                                                         double* __restrict__ cQ)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncells || b.level[c] != level) return;
+    const int P = p + 1;
+    double Qr[kMaxOrder + 1], Qi[kMaxOrder + 1];
+    for (int k = 0; k < P; ++k) Qr[k] = Qi[k] = 0.0;
+    double M = 0.0, cx, cy;
+    if (b.leaf[c]) {
+        double sx = 0.0, sy = 0.0;
+        for (int j = b.beg[c]; j < b.end[c]; ++j) {
+            M += ms[j];
+            sx += ms[j] * xs[j];
+            sy += ms[j] * ys[j];
+        }
+        if (M > 0.0) {
+            cx = sx / M;
+            cy = sy / M;
+        } else {
+            double bx0, bx1, by0, by1;
+            box_bounds(b, c, sync, &bx0, &bx1, &by0, &by1);
+            cx = 0.5 * (bx0 + bx1);
+            cy = 0.5 * (by0 + by1);
+        }
+        for (int j = b.beg[c]; j < b.end[c]; ++j) {
+            const double dr = xs[j] - cx, di = ys[j] - cy;
+            double pr = ms[j], pi = 0.0;
+            for (int k = 0; k < P; ++k) {
+                Qr[k] += pr;
+                Qi[k] += pi;
+                const double t = pr * dr - pi * di;
+                pi = pr * di + pi * dr;
+                pr = t;
+            }
+        }
+    } else {
+        double sx = 0.0, sy = 0.0;
+        for (int ch = c + 1; ch < b.next[c]; ch = b.next[ch] > ch ? b.next[ch] : ch + 1) {
+            M += cM[ch];
+            sx += cM[ch] * ccx[ch];
+            sy += cM[ch] * ccy[ch];
+        }
+        if (M > 0.0) {
+            cx = sx / M;
+            cy = sy / M;
+        } else {
+            double bx0, bx1, by0, by1;
+            box_bounds(b, c, sync, &bx0, &bx1, &by0, &by1);
+            cx = 0.5 * (bx0 + bx1);
+            cy = 0.5 * (by0 + by1);
+        }
+        for (int ch = c + 1; ch < b.next[c]; ch = b.next[ch] > ch ? b.next[ch] : ch + 1) {
+            const double tr = ccx[ch] - cx, ti = ccy[ch] - cy;
+            double tpr[kMaxOrder + 1], tpi[kMaxOrder + 1];
+            tpr[0] = 1.0;
+            tpi[0] = 0.0;
+            for (int k = 1; k < P; ++k) {
+                tpr[k] = tpr[k - 1] * tr - tpi[k - 1] * ti;
+                tpi[k] = tpr[k - 1] * ti + tpi[k - 1] * tr;
+            }
+            const double* q = cQ + (size_t)ch * P * 2;
+            for (int k = 0; k < P; ++k) {
+                double sr = 0.0, si = 0.0;
+                for (int j = 0; j <= k; ++j) {
+                    const double br = c_binom[k][j] * q[2 * j], bi = c_binom[k][j] * q[2 * j + 1];
+                    sr += br * tpr[k - j] - bi * tpi[k - j];
+                    si += br * tpi[k - j] + bi * tpr[k - j];
+                }
+                Qr[k] += sr;
+                Qi[k] += si;
+            }
+        }
+    }
+    cM[c] = M;
+    ccx[c] = cx;
+    ccy[c] = cy;
+    double* q = cQ + (size_t)c * P * 2;
+    for (int k = 0; k < P; ++k) {
+        q[2 * k] = Qr[k];
+        q[2 * k + 1] = Qi[k];
+    }
+}
+
+// Opening radius and the FP32 walk records.
+__global__ __launch_bounds__(kBlock) void k_finalize(int ncells, int p, double theta, BoxArrays b,
+                                                    const BuildSync* __restrict__ sync, const double* __restrict__ cM,
+                                                    const double* __restrict__ ccx, const double* __restrict__ ccy,
+                                                    const double* __restrict__ cQ, CellHdr* __restrict__ hdr,
+                                                    CellExt* __restrict__ ext, float* __restrict__ mom)
+{
+#pragma clang fp contract(off)
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncells) return;
+    double bx0, bx1, by0, by1;
+    box_bounds(b, c, sync, &bx0, &bx1, &by0, &by1);
+    const double cx = ccx[c], cy = ccy[c];
+    const double X[4] = {bx0, bx1, bx0, bx1}, Y[4] = {by0, by0, by1, by1};
+    double dmax2 = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        const double e1 = X[k] - cx, e2 = Y[k] - cy;
+        const double d2 = e1 * e1 + e2 * e2;
+        if (d2 > dmax2) dmax2 = d2;
+    }
+    CellHdr h;
+    h.cx = cx;
+    h.cy = cy;
+    h.rcut2 = theta > 0.0 ? dmax2 / (theta * theta) : INFINITY;
+    h.next = b.next[c];
+    h.info = (b.leaf[c] ? kInfoLeaf : 0u) | (b.lend[c] > b.lbeg[c] ? kInfoList : 0u);
+    hdr[c] = h;
+    CellExt e;
+    e.pbeg = b.beg[c];
+    e.pend = b.end[c];
+    e.lbeg = b.lbeg[c];
+    e.lend = b.lend[c];
+    ext[c] = e;
+    const int st = mom_stride(p);
+    float* mo = mom + (size_t)c * st;
+    const double M = cM[c];
+    const double rcm = sqrt(dmax2);
+    mo[0] = (float)M;
+    mo[1] = (float)rcm;
+    const double* q = cQ + (size_t)c * (p + 1) * 2;
+    double scale = (M > 0.0) ? 1.0 / M : 0.0;
+    const double irc = 1.0 / rcm;
+    scale *= irc; // k = 1
+    for (int k = 2; k <= p; ++k) {
+        scale *= irc;
+        mo[2 + 2 * (k - 2)] = (float)(q[2 * k] * scale);
+        mo[3 + 2 * (k - 2)] = (float)(q[2 * k + 1] * scale);
+    }
+    for (int k = 2 + 2 * (p > 1 ? p - 1 : 0); k < st; ++k) mo[k] = 0.0f;
+}
+
+} // namespace
+
+// ------------------------------------------------------------------- host
+
+glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, const double* m, const double* s,
+                             int64_t n64, const glm_params& prm, hipStream_t st)
+{
+    const int n = (int)n64;
+    const int p = prm.order, L = prm.leaf_size;
+    const double q = prm.q;
+    const double invC = 1.0 / (-expm1(-0.5 * q * q));
+
+    // ---- per-particle arena
+    Arena pa;
+    const int nbb = 256;
+    const size_t o_sync = pa.take(sizeof(BuildSync));
+    const size_t o_part = pa.take(sizeof(double) * 5 * nbb);
+    const size_t o_k0 = pa.take(8ull * n), o_k1 = pa.take(8ull * n);
+    const size_t o_v0 = pa.take(4ull * n), o_v1 = pa.take(4ull * n);
+    const size_t o_perm = pa.take(4ull * n);
+    const size_t o_hist = pa.take(4ull * radix_hist_words(n));
+    const size_t o_xs = pa.take(8ull * n), o_ys = pa.take(8ull * n), o_ms = pa.take(8ull * n),
+                 o_ss = pa.take(8ull * n);
+    const size_t o_cnt = pa.take(4ull * (n + 1));
+    const size_t o_scr = pa.take(4ull * scan_scratch_words(n + 1));
+    const size_t o_ls = pa.take((size_t)n);
+    const size_t o_leafof = pa.take(4ull * n);
+    const size_t o_prt = pa.take(sizeof(PRec) * (size_t)n);
+    const size_t o_lst = pa.take(sizeof(PRec) * (size_t)n);
+    glm_status rc = ts.pbuf.ensure(pa.size);
+    if (rc != GLM_OK) return rc;
+    char* P0 = ts.pbuf.as<char>();
+    BuildSync* sync = reinterpret_cast<BuildSync*>(P0 + o_sync);
+    double* part = reinterpret_cast<double*>(P0 + o_part);
+    uint64_t* k0 = reinterpret_cast<uint64_t*>(P0 + o_k0);
+    uint64_t* k1 = reinterpret_cast<uint64_t*>(P0 + o_k1);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(P0 + o_v0);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(P0 + o_v1);
+    uint32_t* perm = reinterpret_cast<uint32_t*>(P0 + o_perm);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(P0 + o_hist);
+    double* xs = reinterpret_cast<double*>(P0 + o_xs);
+    double* ys = reinterpret_cast<double*>(P0 + o_ys);
+    double* ms = reinterpret_cast<double*>(P0 + o_ms);
+    double* ss = reinterpret_cast<double*>(P0 + o_ss);
+    int32_t* cnt = reinterpret_cast<int32_t*>(P0 + o_cnt);
+    int32_t* scr = reinterpret_cast<int32_t*>(P0 + o_scr);
+    int8_t* lstart = reinterpret_cast<int8_t*>(P0 + o_ls);
+    int32_t* leaf_of = reinterpret_cast<int32_t*>(P0 + o_leafof);
+    PRec* prt = reinterpret_cast<PRec*>(P0 + o_prt);
+    PRec* lst = reinterpret_cast<PRec*>(P0 + o_lst);
+
+    GLM_HIP(hipMemsetAsync(sync, 0, sizeof(BuildSync), st));
+    const int gb = ceil_div(n, kBlock);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kBlock), 0, st, x, y, m, s, (int64_t)n, part);
+    hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, st, part, nbb, sync);
+    hipLaunchKernelGGL(k_morton, dim3(gb), dim3(kBlock), 0, st, x, y, (int64_t)n, sync, k0, v0);
+    const int where = radix_sort_u64(k0, v0, k1, v1, n, 8, hist, st);
+    uint64_t* K = where ? k1 : k0;
+    uint32_t* pv = where ? v1 : v0;
+    GLM_HIP(hipMemcpyAsync(perm, pv, 4ull * n, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_gather, dim3(gb), dim3(kBlock), 0, st, perm, x, y, m, s, (int64_t)n, xs, ys, ms, ss);
+    hipLaunchKernelGGL(k_topo_count, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart);
+    exclusive_scan_i32(cnt, cnt, n, scr, st);
+    hipLaunchKernelGGL(k_sync_counts, dim3(1), dim3(1), 0, st, cnt, n, sync);
+    GLM_HIP(hipGetLastError());
+
+    BuildSync hs;
+    GLM_HIP(hipMemcpyAsync(&hs, sync, sizeof(BuildSync), hipMemcpyDeviceToHost, st));
+    GLM_HIP(hipStreamSynchronize(st));
+    if (hs.bad) return fail(GLM_EDATA, "build_tree: NaN/Inf value or negative mass/smoothing length");
+    const int nc = hs.ncells;
+
+    // ---- per-box arena
+    Arena ca;
+    const int P = p + 1, stride = mom_stride(p);
+    const size_t o_beg = ca.take(4ull * nc), o_end = ca.take(4ull * nc), o_lev = ca.take(4ull * nc),
+                 o_next = ca.take(4ull * nc), o_leaf = ca.take(4ull * nc), o_ix = ca.take(4ull * nc),
+                 o_iy = ca.take(4ull * nc), o_lbeg = ca.take(4ull * nc), o_lend = ca.take(4ull * nc);
+    const size_t o_M = ca.take(8ull * nc), o_cx = ca.take(8ull * nc), o_cy = ca.take(8ull * nc);
+    const size_t o_Q = ca.take(16ull * P * nc);
+    const size_t o_hdr = ca.take(sizeof(CellHdr) * (size_t)nc);
+    const size_t o_ext = ca.take(sizeof(CellExt) * (size_t)nc);
+    const size_t o_mom = ca.take(4ull * stride * nc);
+    rc = ts.cbuf.ensure(ca.size);
+    if (rc != GLM_OK) return rc;
+    char* C0 = ts.cbuf.as<char>();
+    BoxArrays b;
+    b.beg = reinterpret_cast<int32_t*>(C0 + o_beg);
+    b.end = reinterpret_cast<int32_t*>(C0 + o_end);
+    b.level = reinterpret_cast<int32_t*>(C0 + o_lev);
+    b.next = reinterpret_cast<int32_t*>(C0 + o_next);
+    b.leaf = reinterpret_cast<int32_t*>(C0 + o_leaf);
+    b.ix = reinterpret_cast<uint32_t*>(C0 + o_ix);
+    b.iy = reinterpret_cast<uint32_t*>(C0 + o_iy);
+    b.lbeg = reinterpret_cast<int32_t*>(C0 + o_lbeg);
+    b.lend = reinterpret_cast<int32_t*>(C0 + o_lend);
+    double* cM = reinterpret_cast<double*>(C0 + o_M);
+    double* ccx = reinterpret_cast<double*>(C0 + o_cx);
+    double* ccy = reinterpret_cast<double*>(C0 + o_cy);
+    double* cQ = reinterpret_cast<double*>(C0 + o_Q);
+    CellHdr* hdr = reinterpret_cast<CellHdr*>(C0 + o_hdr);
+    CellExt* ext = reinterpret_cast<CellExt*>(C0 + o_ext);
+    float* mom = reinterpret_cast<float*>(C0 + o_mom);
+
+    const int gc = ceil_div(nc, kBlock);
+    hipLaunchKernelGGL(k_topo_emit, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart, b, sync);
+    GLM_HIP(hipMemsetAsync(leaf_of, 0xff, 4ull * n, st)); // -1: no leaf (an internal error if it stays)
+    hipLaunchKernelGGL(k_leaf_of, dim3(gc), dim3(kBlock), 0, st, b, nc, leaf_of);
+    // list keys: box index, or all-ones on the sorted bits for unlisted particles
+    int passes = 1;
+    while (passes < 4 && ((uint64_t)nc >= (1ull << (8 * passes)) - 1)) ++passes;
+    const uint32_t unlisted = passes >= 4 ? kUnlisted32 : (uint32_t)((1ull << (8 * passes)) - 1);
+    uint32_t* lk0 = reinterpret_cast<uint32_t*>(k1);        // reuse the spare key buffers
+    uint32_t* lk1 = reinterpret_cast<uint32_t*>(k1) + n;
+    uint32_t* lv0 = where ? v0 : v1;
+    uint32_t* lv1 = reinterpret_cast<uint32_t*>(leaf_of);   // leaf_of is dead after assignment
+    if (where) { // K lives in k1: use k0 as the spare
+        lk0 = reinterpret_cast<uint32_t*>(k0);
+        lk1 = reinterpret_cast<uint32_t*>(k0) + n;
+    }
+    hipLaunchKernelGGL(k_list_assign, dim3(gb), dim3(kBlock), 0, st, K, n, ss, q, sync, nc, leaf_of, b, cnt, lstart,
+                       unlisted, lk0, lv0);
+    hipLaunchKernelGGL(k_particle_records, dim3(gb), dim3(kBlock), 0, st, n, xs, ys, ms, ss, perm, lk0, unlisted, q,
+                       invC, prt);
+    const int lw = radix_sort_u32(lk0, lv0, lk1, lv1, n, passes, hist, st);
+    hipLaunchKernelGGL(k_list_ranges, dim3(gb), dim3(kBlock), 0, st, n, lw ? lk1 : lk0, lw ? lv1 : lv0, unlisted, xs,
+                       ys, ms, ss, perm, q, invC, b, lst, sync);
+    for (int l = kMaxLevel; l >= 0; --l)
+        hipLaunchKernelGGL(k_moments_level, dim3(gc), dim3(kBlock), 0, st, l, nc, p, b, xs, ys, ms, sync, cM, ccx, ccy,
+                           cQ);
+    hipLaunchKernelGGL(k_finalize, dim3(gc), dim3(kBlock), 0, st, nc, p, prm.theta, b, sync, cM, ccx, ccy, cQ, hdr, ext,
+                       mom);
+    GLM_HIP(hipGetLastError());
+
+    ts.n = n;
+    ts.ncells = nc;
+    ts.params = prm;
+    ts.x0 = hs.x0;
+    ts.y0 = hs.y0;
+    ts.side = hs.side;
+    ts.sync = sync;
+    ts.b = b;
+    ts.perm = reinterpret_cast<int32_t*>(perm);
+    ts.key = K;
+    ts.dev.hdr = hdr;
+    ts.dev.ext = ext;
+    ts.dev.mom = mom;
+    ts.dev.prt = prt;
+    ts.dev.lst = lst;
+    ts.dev.cq = cQ;
+    ts.dev.cM = cM;
+    ts.dev.cbeg = b.beg;
+    ts.dev.cend = b.end;
+    ts.dev.perm = reinterpret_cast<int32_t*>(perm);
+    ts.dev.ncells = nc;
+    ts.dev.n = n;
+    ts.dev.nlisted = -1; // read on demand (sync->nlisted)
+    ts.dev.order = p;
+    ts.dev.invC = (float)invC;
+    ts.dev.q = q;
+    ts.ccx = ccx;
+    ts.ccy = ccy;
+    ts.built = true;
+    return GLM_OK;
+}
+
+} // namespace glm

@@ -1,0 +1,56 @@
+// Tree storage owned by a glm_tree handle, and the build entry point.
+#pragma once
+
+#include "common.hpp"
+
+namespace glm {
+
+// Small device struct written by the build kernels; copied to the host once.
+struct BuildSync {
+    double x0, y0, side, scale; // root square and 32-bit quantisation scale
+    int32_t ncells;
+    int32_t bad;                // input validation flag
+    int32_t nleaves;
+    int32_t max_level;
+    int32_t nlisted;
+    int32_t internal;           // consistency flags of the build (0 = ok)
+};
+
+// Build-side per-box arrays (preorder).
+struct BoxArrays {
+    int32_t *beg, *end, *level, *next, *leaf;
+    uint32_t *ix, *iy;
+    int32_t *lbeg, *lend;
+};
+
+// Bump layout of one device buffer (256-byte aligned pieces).
+struct Arena {
+    size_t size = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t o = size;
+        size += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+struct TreeStorage {
+    DevBuf pbuf;  // per-particle data (sorted particles, records, lists, scratch)
+    DevBuf cbuf;  // per-box data
+    DevBuf abuf;  // adjoint scratch (box adjoints)
+    bool built = false;
+    int32_t n = 0, ncells = 0;
+    glm_params params{};
+    double x0 = 0, y0 = 0, side = 0;
+    BuildSync* sync = nullptr; // device
+    BoxArrays b{};
+    int32_t* perm = nullptr;   // Morton position -> original index
+    uint64_t* key = nullptr;   // sorted Morton keys
+    double *ccx = nullptr, *ccy = nullptr;
+    TreeDev dev{};
+};
+
+glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, const double* m, const double* s,
+                             int64_t n, const glm_params& prm, hipStream_t st);
+
+} // namespace glm

@@ -1,0 +1,117 @@
+// Internal declarations of the gfx950 tree ray-shooting library: device data
+// layout of a built tree, launch helpers and error plumbing.  Not installed;
+// the public interface is include/glamer.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "glamer.h"
+
+namespace glm {
+
+constexpr int kWave = 64;     // CDNA wavefront
+constexpr int kBlock = 256;   // 4 waves per workgroup
+constexpr int kMaxOrder = 12;
+constexpr int kMaxLevel = 32; // 32-bit quantised coordinates per axis
+
+// ---------------------------------------------------------------------------
+// Walk-side records.  Box and particle records are read with wave-uniform
+// (scalar) loads by every lane of a ray group, so they are AoS and aligned.
+// ---------------------------------------------------------------------------
+
+// 32 B: what the opening test needs.
+struct alignas(32) CellHdr {
+    double cx, cy;   // centre of mass (FP64)
+    double rcut2;    // (r_cm / theta)^2, +inf when theta = 0
+    int32_t next;    // preorder index one past the subtree
+    uint32_t info;   // bit0 leaf, bit1 non-empty big-particle list
+};
+
+// 16 B: ranges into the leaf-particle and list arrays.
+struct alignas(16) CellExt {
+    int32_t pbeg, pend; // particles (Morton order) -- leaves only
+    int32_t lbeg, lend; // big-particle list entries
+};
+
+// 40 B: one particle as the walk evaluates it.
+struct alignas(8) PRec {
+    double x, y;   // position (FP64)
+    double qs2;    // (q s)^2 in FP64, the support of the Gaussian; 0 for point masses
+    float m;       // mass
+    float mC;      // m / (1 - exp(-q^2/2))
+    float h;       // 1 / (2 s^2), 0 for point masses
+    uint32_t meta; // original particle index | (listed in a big-particle list) << 31
+};
+
+constexpr uint32_t kInfoLeaf = 1u;
+constexpr uint32_t kInfoList = 2u;
+
+// Moment stride (floats) per box for order p: M, r_cm, then (Re, Im) of the
+// normalised moments Q_k / (M r_cm^k) for k = 2..p, padded to 4 floats.
+__host__ __device__ constexpr int mom_stride(int p) { return ((2 + 2 * (p > 1 ? p - 1 : 0)) + 3) & ~3; }
+
+// Device view of a built tree (passed by value to kernels).
+struct TreeDev {
+    const CellHdr* hdr;
+    const CellExt* ext;
+    const float* mom;       // ncells * mom_stride(p)
+    const PRec* prt;        // n, Morton order
+    const PRec* lst;        // nlisted, grouped by box, Morton order inside a box
+    const double* cq;       // FP64 moments about the centre of mass: ncells * (p+1) * 2
+    const double* cM;       // FP64 box masses
+    const int32_t* cbeg;    // box particle range (Morton order)
+    const int32_t* cend;
+    const int32_t* perm;    // Morton position -> original index
+    int32_t ncells;
+    int32_t n;
+    int32_t nlisted;
+    int32_t order;
+    float invC;             // 1 / (1 - exp(-q^2/2))
+    float pad;
+    double q;
+};
+
+// ---------------------------------------------------------------------------
+// host-side error plumbing
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+glm_status fail(glm_status st, const std::string& msg);
+
+#define GLM_HIP(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::glm::fail(GLM_EHIP, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Device buffer owned by the library (grow-only).
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    glm_status ensure(size_t want);
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// radix sort and scans (sort.hip)
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (key, value) pairs on bits [0, 8*passes) with 8-bit
+// digits.  Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result
+// ends in (k0, v0), 1 if in (k1, v1).  hist needs radix_hist_words(n) words.
+size_t radix_hist_words(int64_t n);
+int radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t n, int passes,
+                   uint32_t* hist, hipStream_t s);
+int radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int passes,
+                   uint32_t* hist, hipStream_t s);
+// Exclusive scan of n int32 values into out[0..n] (out[n] = total).  in and
+// out may alias.  scratch needs scan_scratch_words(n) words.
+size_t scan_scratch_words(int64_t n);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s);
+
+} // namespace glm

@@ -1,0 +1,233 @@
+// Stable LSD radix sort (8-bit digits) and exclusive scan for gfx950.
+//
+// Sort pass = histogram per 2048-key tile -> one exclusive scan of the
+// digit-major histogram -> scatter, where each tile ranks its keys stably with
+// wave ballots (8 ballots give the lanes holding the same digit) and per-wave
+// digit counts in LDS.  Loads are coalesced; the scatter writes runs per digit.
+#include "common.hpp"
+
+namespace glm {
+
+namespace {
+
+constexpr int kItems = 8;                  // keys per thread per tile
+constexpr int kTile = kBlock * kItems;     // 2048
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems; // 4096
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive scan over the 256 threads of a block; returns the block total in *tot
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* lds_w, uint32_t* tot)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(v, lane);
+    if (lane == kWave - 1) lds_w[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / kWave; ++k) {
+        const uint32_t x = lds_w[k];
+        off += (k < w) ? x : 0u;
+        all += x;
+    }
+    __syncthreads();
+    *tot = all;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t* in, int64_t n, uint32_t* part)
+{
+    __shared__ uint32_t lw[kBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        if (i < n) s += (uint32_t)in[i];
+    }
+    uint32_t tot;
+    block_excl_scan(s, lw, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of nb partials, total into out[n]
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* part, int nb, int32_t* out, int64_t n)
+{
+    __shared__ uint32_t lw[1024 / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    const int per = (nb + 1023) / 1024;
+    const int b0 = t * per;
+    uint32_t s = 0;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nb) s += part[b0 + k];
+    const uint32_t inc = wave_incl_scan(s, lane);
+    if (lane == kWave - 1) lw[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, all = 0;
+    for (int k = 0; k < 1024 / kWave; ++k) {
+        off += (k < w) ? lw[k] : 0u;
+        all += lw[k];
+    }
+    uint32_t run = off + inc - s;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nb) {
+            const uint32_t x = part[b0 + k];
+            part[b0 + k] = run;
+            run += x;
+        }
+    if (t == 0) out[n] = (int32_t)all;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t* in, int32_t* out, int64_t n,
+                                                      const uint32_t* part)
+{
+    __shared__ uint32_t lw[kBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j;
+        v[j] = i < n ? (uint32_t)in[i] : 0u;
+        s += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(s, lw, &tot) + part[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j;
+        if (i < n) out[i] = (int32_t)run;
+        run += v[j];
+    }
+}
+
+template <class K>
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const K* keys, int64_t n, int shift, uint32_t* hist,
+                                                      int nb)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+template <class K>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const K* kin, const uint32_t* vin, K* kout,
+                                                         uint32_t* vout, int64_t n, int shift,
+                                                         const int32_t* offs, int nb)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kBlock / kWave][256];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    run[t] = (uint32_t)offs[(int64_t)t * nb + blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kBlock / kWave; ++k) wcnt[k][t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const uint64_t lt = __lanemask_lt();
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t i = base + (int64_t)j * kBlock + t;
+        const bool valid = i < n;
+        const K key = valid ? kin[i] : (K)0;
+        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            same &= bit ? bb : ~bb;
+        }
+        const uint32_t lrank = (uint32_t)__popcll(same & lt);
+        if (valid && lrank == 0) wcnt[w][d] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + lrank;
+            for (int k = 0; k < w; ++k) pos += wcnt[k][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int k = 0; k < kBlock / kWave; ++k) {
+            add += wcnt[k][t];
+            wcnt[k][t] = 0;
+        }
+        run[t] += add;
+        __syncthreads();
+    }
+}
+
+template <class K>
+int radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n, int passes, uint32_t* hist,
+                    hipStream_t s)
+{
+    if (n <= 1 || passes <= 0) return 0;
+    const int nb = ceil_div(n, kTile);
+    const int64_t hn = (int64_t)256 * nb;
+    int32_t* offs = reinterpret_cast<int32_t*>(hist);
+    int32_t* scr = offs + hn + 1;
+    K* ki = k0;
+    uint32_t* vi = v0;
+    K* ko = k1;
+    uint32_t* vo = v1;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(kBlock), 0, s, ki, n, shift, hist, nb);
+        exclusive_scan_i32(offs, offs, hn, scr, s);
+        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, n, shift,
+                           offs, nb);
+        K* tk = ki; ki = ko; ko = tk;
+        uint32_t* tv = vi; vi = vo; vo = tv;
+    }
+    return (passes & 1) ? 1 : 0;
+}
+
+} // namespace
+
+size_t scan_scratch_words(int64_t n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanTile) + 1; }
+
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s)
+{
+    const int nb = ceil_div(n > 0 ? n : 1, kScanTile);
+    uint32_t* part = reinterpret_cast<uint32_t*>(scratch);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, nb, out, n);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, in, out, n, part);
+}
+
+size_t radix_hist_words(int64_t n)
+{
+    const int64_t hn = (int64_t)256 * ceil_div(n > 0 ? n : 1, kTile);
+    return (size_t)hn + 1 + scan_scratch_words(hn);
+}
+
+int radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t n, int passes,
+                   uint32_t* hist, hipStream_t s)
+{
+    return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n, passes, hist, s);
+}
+
+int radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int passes,
+                   uint32_t* hist, hipStream_t s)
+{
+    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, passes, hist, s);
+}
+
+} // namespace glm

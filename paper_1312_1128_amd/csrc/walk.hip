@@ -1,0 +1,281 @@
+// Forward tree walk on gfx950 (Sec. 3.2) with ray staging.
+//
+// One wavefront walks the tree for a group of 64 rays that are neighbours in
+// Morton order.  The group shares one depth-first traversal of the preorder
+// box array without a stack: every lane keeps the preorder index at which it
+// becomes active again (after it accepted a box, it sleeps until the end of
+// that box's subtree), the wave descends into a box if any awake lane opens
+// it and jumps over the subtree otherwise.  Every decision is per ray, as in
+// the paper's walk: per lane FP64 opening test |x - x_cm|^2 > r_cut^2, per
+// lane FP64 inside test for each particle.  Box headers, moments and particle
+// records are wave-uniform and come through scalar loads; only the
+// big-particle lists are first filtered lane-parallel against the group's
+// bounding box.  Evaluation is FP32: the multipole series is a Horner scheme
+// in t = r_cm / w on moments normalised by M r_cm^k, alpha is accumulated with
+// compensated (Kahan) summation.
+#include <math.h>
+
+#include "eval.hpp"
+#include "walk.hpp"
+
+namespace glm {
+
+namespace {
+
+template <int P, bool AONLY>
+__global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __restrict__ rxs,
+                                                const double* __restrict__ rys, const uint32_t* __restrict__ rperm,
+                                                int64_t nrays, float* __restrict__ o_a1, float* __restrict__ o_a2,
+                                                float* __restrict__ o_k, float* __restrict__ o_g1,
+                                                float* __restrict__ o_g2, int32_t* __restrict__ counts, int kahan_i)
+{
+    const bool kahan = kahan_i != 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t r = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const bool valid = r < nrays;
+    if (!__any(valid)) return;
+    const double X = valid ? rxs[r] : 0.0, Y = valid ? rys[r] : 0.0;
+    const double gx0 = wave_min(valid ? X : INFINITY), gx1 = wave_max(valid ? X : -INFINITY);
+    const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
+
+    Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+    int n_vis = 0, n_acc = 0, n_dir = 0, n_hit = 0;
+    int skip = valid ? 0 : 0x7fffffff;
+    const int nc = T.ncells;
+    int cur = 0;
+    while (cur < nc) {
+        cur = __builtin_amdgcn_readfirstlane(cur);
+        const CellHdr h = T.hdr[cur];
+        const bool act = cur >= skip;
+        n_vis += act;
+        if (h.info & kInfoList) {
+            const CellExt e = T.ext[cur];
+            for (int base = e.lbeg; base < e.lend; base += kWave) {
+                const int j = base + lane;
+                bool cand = false;
+                if (j < e.lend) {
+                    const PRec pr = T.lst[j];
+                    const double dx = fmax(fmax(gx0 - pr.x, pr.x - gx1), 0.0);
+                    const double dy = fmax(fmax(gy0 - pr.y, pr.y - gy1), 0.0);
+                    cand = dx * dx + dy * dy < pr.qs2 * (1.0 + 1e-9);
+                }
+                uint64_t cm = __ballot(cand);
+                while (cm) {
+                    const int k = __ffsll((unsigned long long)cm) - 1;
+                    cm &= cm - 1;
+                    const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
+                    if (act) eval_particle<AONLY>(pr, X, Y, 1, A, kahan, n_hit);
+                }
+            }
+        }
+        double w1, w2;
+        const double d2 = sqdist(X, Y, h.cx, h.cy, &w1, &w2);
+        const bool acc = act && d2 > h.rcut2;
+        const bool opn = act && !acc;
+        n_acc += acc;
+        if (__any(acc)) {
+            if (acc) eval_box<P, AONLY>(T.mom + (size_t)cur * mom_stride(P), w1, w2, A, kahan);
+        }
+        if (h.info & kInfoLeaf) {
+            if (__any(opn)) {
+                const CellExt e = T.ext[cur];
+                if (opn) n_dir += e.pend - e.pbeg;
+                int dummy = 0;
+                for (int j = e.pbeg; j < e.pend; ++j) {
+                    const PRec pr = T.prt[j];
+                    if (opn) eval_particle<AONLY>(pr, X, Y, 0, A, kahan, dummy);
+                }
+            }
+            cur = cur + 1;
+        } else if (__any(opn)) {
+            if (acc) skip = h.next;
+            cur = cur + 1;
+        } else {
+            cur = h.next > cur ? h.next : cur + 1; // preorder: the subtree ends after cur
+        }
+    }
+    if (!valid) return;
+    const int64_t o = rperm ? (int64_t)rperm[r] : r;
+    // fold the FP64 balance of the big-particle point terms into the result
+    o_a1[o] = (float)((double)A.a1 + A.b1);
+    o_a2[o] = (float)((double)A.a2 + A.b2);
+    if (!AONLY) {
+        if (o_k) o_k[o] = A.k;
+        if (o_g1) o_g1[o] = (float)((double)A.g1 + A.bg1);
+        if (o_g2) o_g2[o] = (float)((double)A.g2 + A.bg2);
+    }
+    if (counts) {
+        counts[4 * o + 0] = n_vis;
+        counts[4 * o + 1] = n_acc;
+        counts[4 * o + 2] = n_dir;
+        counts[4 * o + 3] = n_hit;
+    }
+}
+
+// ------------------------------------------------------------ ray staging
+
+__global__ __launch_bounds__(kBlock) void k_ray_bbox(const double* __restrict__ x, const double* __restrict__ y,
+                                                    int64_t n, double* __restrict__ part)
+{
+    __shared__ double red[4][kBlock];
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        x0 = fmin(x0, x[i]);
+        x1 = fmax(x1, x[i]);
+        y0 = fmin(y0, y[i]);
+        y1 = fmax(y1, y[i]);
+    }
+    red[0][threadIdx.x] = x0;
+    red[1][threadIdx.x] = x1;
+    red[2][threadIdx.x] = y0;
+    red[3][threadIdx.x] = y1;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+            red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][threadIdx.x + o]);
+            red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) part[blockIdx.x * 4 + k] = red[k][0];
+}
+
+__device__ inline uint32_t spread16(uint32_t v)
+{
+    uint32_t x = v & 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+// 16-bit-per-axis Morton keys of the rays in their bounding square
+__global__ __launch_bounds__(kBlock) void k_ray_keys(const double* __restrict__ x, const double* __restrict__ y,
+                                                    int64_t n, const double* __restrict__ part, int nb,
+                                                    uint32_t* __restrict__ key, uint32_t* __restrict__ val)
+{
+    __shared__ double bb[4];
+    if (threadIdx.x < 4) {
+        double v = (threadIdx.x & 1) ? -INFINITY : INFINITY;
+        for (int b = 0; b < nb; ++b) {
+            const double p = part[b * 4 + threadIdx.x];
+            v = (threadIdx.x & 1) ? fmax(v, p) : fmin(v, p);
+        }
+        bb[threadIdx.x] = v;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double ext = fmax(bb[1] - bb[0], bb[3] - bb[2]);
+    if (!(ext > 0.0)) ext = 1.0;
+    const double sc = 65535.0 / ext;
+    const uint32_t qx = (uint32_t)fmin(fmax((x[i] - bb[0]) * sc, 0.0), 65535.0);
+    const uint32_t qy = (uint32_t)fmin(fmax((y[i] - bb[2]) * sc, 0.0), 65535.0);
+    key[i] = spread16(qx) | (spread16(qy) << 1);
+    val[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ray_gather(const uint32_t* __restrict__ perm, const double* __restrict__ x,
+                                                      const double* __restrict__ y, int64_t n, double* __restrict__ xs,
+                                                      double* __restrict__ ys)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    xs[k] = x[perm[k]];
+    ys[k] = y[perm[k]];
+}
+
+template <int P, bool AONLY>
+void launch_walk(const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm, int64_t nrays,
+                 float* a1, float* a2, float* k, float* g1, float* g2, int32_t* counts, int kahan, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_walk<P, AONLY>), dim3(ceil_div(nrays, kBlock)), dim3(kBlock), 0, st, T, rxs, rys, rperm,
+                       nrays, a1, a2, k, g1, g2, counts, kahan);
+}
+
+template <bool AONLY>
+void dispatch_walk(int p, const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm,
+                   int64_t nrays, float* a1, float* a2, float* k, float* g1, float* g2, int32_t* counts, int kahan,
+                   hipStream_t st)
+{
+#define GLM_CASE(PP) \
+    case PP: launch_walk<PP, AONLY>(T, rxs, rys, rperm, nrays, a1, a2, k, g1, g2, counts, kahan, st); break;
+    switch (p) {
+        GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
+        GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
+        default: break;
+    }
+#undef GLM_CASE
+}
+
+} // namespace
+
+RayLayout ray_layout(int64_t nrays)
+{
+    RayLayout L;
+    Arena a;
+    L.k0 = a.take(4ull * nrays);
+    L.k1 = a.take(4ull * nrays);
+    L.v0 = a.take(4ull * nrays);
+    L.v1 = a.take(4ull * nrays);
+    L.xs = a.take(8ull * nrays);
+    L.ys = a.take(8ull * nrays);
+    L.hist = a.take(4ull * radix_hist_words(nrays));
+    L.part = a.take(sizeof(double) * 4 * 256);
+    L.bytes = a.size;
+    return L;
+}
+
+glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* ws, const RayLayout& L,
+                      StagedRays* out, hipStream_t st)
+{
+    char* W = static_cast<char*>(ws);
+    uint32_t* k0 = reinterpret_cast<uint32_t*>(W + L.k0);
+    uint32_t* k1 = reinterpret_cast<uint32_t*>(W + L.k1);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(W + L.v0);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(W + L.v1);
+    double* xs = reinterpret_cast<double*>(W + L.xs);
+    double* ys = reinterpret_cast<double*>(W + L.ys);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(W + L.hist);
+    double* part = reinterpret_cast<double*>(W + L.part);
+    const int nbb = 256;
+    const int g = ceil_div(nrays, kBlock);
+    hipLaunchKernelGGL(k_ray_bbox, dim3(nbb), dim3(kBlock), 0, st, rx, ry, nrays, part);
+    hipLaunchKernelGGL(k_ray_keys, dim3(g), dim3(kBlock), 0, st, rx, ry, nrays, part, nbb, k0, v0);
+    const int w = radix_sort_u32(k0, v0, k1, v1, nrays, 4, hist, st);
+    const uint32_t* perm = w ? v1 : v0;
+    hipLaunchKernelGGL(k_ray_gather, dim3(g), dim3(kBlock), 0, st, perm, rx, ry, nrays, xs, ys);
+    GLM_HIP(hipGetLastError());
+    out->xs = xs;
+    out->ys = ys;
+    out->perm = perm;
+    return GLM_OK;
+}
+
+glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, float* a1,
+                        float* a2, float* k, float* g1, float* g2, int32_t* counts, uint32_t flags, void* ws,
+                        hipStream_t st)
+{
+    if (nrays == 0) return GLM_OK;
+    StagedRays sr{rx, ry, nullptr};
+    if (!(flags & GLM_RAYS_ORDERED)) {
+        const RayLayout L = ray_layout(nrays);
+        glm_status rc = stage_rays(rx, ry, nrays, ws, L, &sr, st);
+        if (rc != GLM_OK) return rc;
+    }
+    const int kahan = (flags & GLM_NO_KAHAN) ? 0 : 1;
+    if (flags & GLM_ALPHA_ONLY)
+        dispatch_walk<true>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays, a1, a2, nullptr, nullptr, nullptr,
+                            counts, kahan, st);
+    else
+        dispatch_walk<false>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays, a1, a2, k, g1, g2, counts, kahan,
+                             st);
+    GLM_HIP(hipGetLastError());
+    return GLM_OK;
+}
+
+} // namespace glm

@@ -1,0 +1,37 @@
+// Ray staging and the forward / adjoint walks.
+#pragma once
+
+#include "build.hpp"
+
+namespace glm {
+
+// Byte offsets of the ray workspace pieces.
+struct RayLayout {
+    size_t k0, k1, v0, v1, xs, ys, hist, part, bytes;
+};
+RayLayout ray_layout(int64_t nrays);
+
+struct StagedRays {
+    const double* xs;
+    const double* ys;
+    const uint32_t* perm; // sorted -> input position, or null when unsorted
+};
+
+// Morton-sort the rays (16 bits per axis in their bounding square) so that
+// each 64-ray group is spatially compact.
+glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* ws, const RayLayout& L,
+                      StagedRays* out, hipStream_t st);
+
+glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, float* a1,
+                        float* a2, float* k, float* g1, float* g2, int32_t* counts, uint32_t flags, void* ws,
+                        hipStream_t st);
+
+glm_status direct_device(const double* x, const double* y, const double* m, const double* s, int64_t n, double q,
+                         const double* rx, const double* ry, int64_t nrays, int fp64, void* const out5[5],
+                         hipStream_t st);
+
+glm_status adjoint_device(TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, const float* ga1,
+                          const float* ga2, double* dm, double* dx, double* dy, double* ds, uint32_t flags, void* ws,
+                          hipStream_t st);
+
+} // namespace glm

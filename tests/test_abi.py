@@ -1,0 +1,97 @@
+"""The C ABI library loads and exports every symbol include/glamer.h declares;
+host-side argument validation works without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1312_1128_amd import _capi, build_ext
+
+    if not os.path.exists(_capi.LIB_PATH):
+        build_ext.build()
+    return _capi.load()
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "glamer.h")).read()
+    return sorted(set(re.findall(r"GLM_API\s+[\w\s\*]+?\b(glm_\w+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    from paper_1312_1128_amd import _capi
+
+    assert declared_symbols() == sorted(_capi.EXPORTED)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert lib.glm_version().startswith(b"glamer")
+
+
+def test_only_the_abi_is_exported():
+    from paper_1312_1128_amd import _capi
+    import subprocess
+
+    out = subprocess.run(["nm", "-D", "--defined-only", _capi.LIB_PATH], capture_output=True, text=True).stdout
+    syms = sorted(l.split()[-1] for l in out.splitlines() if " T " in l)
+    assert syms == sorted(_capi.EXPORTED)
+
+
+def test_host_validation(lib):
+    from paper_1312_1128_amd import _capi
+
+    h = ctypes.c_void_p()
+    assert lib.glm_tree_create(ctypes.byref(h)) == 0
+    buf = (ctypes.c_double * 4)()
+    for theta, q, leaf, order, flags in [(1.0, 3.0, 8, 2, 0), (-0.1, 3.0, 8, 2, 0), (0.3, 0.0, 8, 2, 0),
+                                         (0.3, float("inf"), 8, 2, 0), (0.3, 3.0, 0, 2, 0), (0.3, 3.0, 65, 2, 0),
+                                         (0.3, 3.0, 8, 13, 0), (0.3, 3.0, 8, -1, 0), (0.3, 3.0, 8, 2, 64)]:
+        p = _capi.GlmParams(theta, q, leaf, order, flags)
+        rc = lib.glm_build_tree(h, buf, buf, buf, None, 4, ctypes.byref(p), None)
+        assert rc == _capi.GLM_EINVAL, (theta, q, leaf, order, flags)
+        assert lib.glm_last_error()
+    p = _capi.GlmParams(0.3, 3.0, 8, 2, 0)
+    assert lib.glm_build_tree(h, None, buf, buf, None, 4, ctypes.byref(p), None) == _capi.GLM_EINVAL
+    assert lib.glm_build_tree(h, buf, buf, buf, None, 0, ctypes.byref(p), None) == _capi.GLM_EINVAL
+    assert lib.glm_build_tree(None, buf, buf, buf, None, 4, ctypes.byref(p), None) == _capi.GLM_EINVAL
+    # an unbuilt tree cannot be walked
+    rc = lib.glm_shoot(h, buf, buf, 4, buf, buf, buf, buf, buf, None, 0, None, 0, None)
+    assert rc == _capi.GLM_ESTATE
+    rc = lib.glm_shoot_adjoint(h, buf, buf, 4, buf, buf, None, None, None, None, 0, None, 0, None)
+    assert rc == _capi.GLM_ESTATE
+    info = _capi.GlmTreeInfo()
+    assert lib.glm_tree_get_info(h, ctypes.byref(info)) == _capi.GLM_ESTATE
+    # workspace size is a host-side function of the ray count
+    b = ctypes.c_size_t()
+    assert lib.glm_shoot_workspace_bytes(1 << 20, ctypes.byref(b)) == 0 and b.value > (1 << 20) * 32
+    assert lib.glm_shoot_workspace_bytes(-1, ctypes.byref(b)) == _capi.GLM_EINVAL
+    arr = (ctypes.c_void_p * 5)()
+    assert lib.glm_shoot_direct(buf, buf, buf, None, 4, 3.0, buf, buf, 4, 0, arr, None) == _capi.GLM_EINVAL
+    lib.glm_tree_destroy(None)
+    lib.glm_tree_destroy(h)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_1312_1128_amd import _capi
+
+    with pytest.raises(RuntimeError):
+        _capi.load.__wrapped__(str(tmp_path / "missing.so")) if hasattr(_capi.load, "__wrapped__") else \
+            _load_fresh(str(tmp_path / "missing.so"))
+
+
+def _load_fresh(path):
+    from paper_1312_1128_amd import _capi
+
+    saved = _capi._lib
+    _capi._lib = None
+    try:
+        return _capi.load(path)
+    finally:
+        _capi._lib = saved

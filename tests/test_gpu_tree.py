@@ -1,0 +1,205 @@
+"""GPU parity of the tree build and the forward walk (through the C ABI)
+against the CPU oracle: oracle B (same tree definition) must agree on the
+topology exactly and on the per-ray interaction counts exactly; oracle A (brute
+force) bounds the approximation of the whole method."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import build, dev, rel_err, say, shoot, stats
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_lens(n, seed, s_lo=0.003, s_hi=0.3, frac_points=0.2):
+    lens = synth.gaussian_blobs(n, seed, s_lo=s_lo, s_hi=s_hi)
+    g = synth.rng(seed + 1)
+    lens.s[g.random(n) < frac_points] = 0.0
+    return lens
+
+
+CASES = {
+    "point_masses_1k": (lambda: synth.point_masses(1000, synth.BASE_SEED + 1), 0.5, 8, 2),
+    "nfw_20k": (lambda: synth.nfw_halo(20000, synth.BASE_SEED + 3), 0.3, 8, 6),
+    "mixed_3k_leaf3": (lambda: mixed_lens(3000, 17), 0.5, 3, 4),
+    "mixed_5k_leaf1": (lambda: mixed_lens(5000, 19), 0.4, 1, 3),
+}
+
+
+def compare_topology(ora, lens, theta, leaf, order):
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, theta, leaf, order)
+    ex = T.export()
+    tree = build(lens, theta, leaf, order)
+    g = tree.export()
+    assert g["check_flags"] == 0
+    nc = T.ncells
+    assert g["ncells"] == nc, (g["ncells"], nc)
+    np.testing.assert_array_equal(g["level"], ex["level"])
+    np.testing.assert_array_equal(g["ix"], ex["ix"])
+    np.testing.assert_array_equal(g["iy"], ex["iy"])
+    np.testing.assert_array_equal(g["end"] - g["beg"], ex["np"])
+    np.testing.assert_array_equal(g["leaf"], ex["leaf"])
+    np.testing.assert_array_equal(g["next"], ex["next"])
+    np.testing.assert_array_equal(g["lend"] - g["lbeg"], ex["nl"])
+    x0, y0, S = T.root()
+    assert (g["root_x0"], g["root_y0"], g["root_side"]) == (x0, y0, S)
+    # every leaf holds the same particles; every list the same particles
+    perm = g["perm"]
+    for c in np.nonzero(g["leaf"])[0]:
+        np.testing.assert_array_equal(np.sort(perm[g["beg"][c]:g["end"][c]]), T.members(c))
+    for c in np.nonzero(g["lend"] > g["lbeg"])[0]:
+        np.testing.assert_array_equal(np.sort(g["list_idx"][g["lbeg"][c]:g["lend"][c]]), T.list_of(c))
+    # moments (FP64, bottom-up on the GPU vs directly from the members)
+    np.testing.assert_allclose(g["M"], ex["M"], rtol=1e-12)
+    side = S / 2.0 ** ex["level"]
+    assert np.all(np.abs(g["cx"] - ex["cx"]) <= 1e-12 * np.maximum(side, 1e-300) + 1e-15)
+    assert np.all(np.abs(g["cy"] - ex["cy"]) <= 1e-12 * np.maximum(side, 1e-300) + 1e-15)
+    np.testing.assert_allclose(g["rcut2"], ex["rcut2"], rtol=1e-10)
+    for k in range(order + 1):
+        scale = ex["M"] * (np.sqrt(2) * side) ** k
+        assert np.all(np.abs(g["Q"][:, k] - ex["Q"][:, k]) <= 1e-10 * scale + 1e-300), k
+    return T, tree
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_tree_and_walk_match_oracle_tree(ora, case):
+    make, theta, leaf, order = CASES[case]
+    lens = make()
+    say(f"[gpu] {case}: n={lens.n} theta={theta} leaf={leaf} p={order}")
+    T, tree = compare_topology(ora, lens, theta, leaf, order)
+    rx, ry = synth.ray_grid(67)  # 4489 rays: 70 groups + a ragged tail
+    ref, rcnt = T.shoot(rx, ry, counts=True)
+    got, gcnt = shoot(tree, rx, ry, counts=True)
+    # identical decisions: boxes visited, accepted, leaf particles, list hits
+    np.testing.assert_array_equal(gcnt, rcnt[:, [0, 1, 2, 4]])
+    ea, ek, eg = rel_err(got, ref)
+    stats("alpha vs oracle tree", ea)
+    stats("gamma vs oracle tree", eg)
+    assert np.quantile(ea, 0.999) < 1e-5 and ea.max() < 1e-4
+    if lens.s.max() > 0:
+        ok = np.abs(ref[:, 2]) > 0
+        stats("kappa vs oracle tree", ek[ok])
+        assert np.all(ek[ok] < 1e-4)
+    else:
+        assert np.all(got[:, 2] == 0.0)
+    gn = np.linalg.norm(ref[:, 3:], axis=1)
+    assert np.all(np.linalg.norm(got[:, 3:] - ref[:, 3:], axis=1) <= 1e-4 * gn + 1e-6 * np.median(gn))
+
+
+def test_theta_zero_walk_is_direct_sum(ora):
+    lens = mixed_lens(4000, 23)
+    say("[gpu] theta=0 walk vs oracle A")
+    tree = build(lens, 0.0, 8, 2)
+    rx, ry = synth.uniform_points(1000, 24)
+    got, cnt = shoot(tree, rx, ry, counts=True)
+    ref = ora.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx, ry)
+    assert np.all(cnt[:, 1] == 0) and np.all(cnt[:, 2] == lens.n)
+    ea, ek, eg = rel_err(got, ref)
+    stats("alpha", ea)
+    stats("gamma", eg)
+    assert ea.max() < 1e-5 and ek.max() < 1e-5
+
+
+def test_headline_nfw_1e6_vs_bruteforce(ora):
+    """1e6 smoothed NFW particles (c = 5, kNN32, q = 3), the full 2048^2 ray grid
+    shot at theta = 0.3 with p = 8; 2048 seeded rays checked against the FP64
+    brute force: max fractional error <= 1e-4 for alpha, kappa and gamma."""
+    lens, rx, ry = synth.workload_nfw()
+    say(f"[gpu] headline nfw n={lens.n} rays={rx.size}")
+    tree = build(lens, 0.3, 8, 8)
+    assert tree.info()["check_flags"] == 0
+    got, cnt = shoot(tree, rx, ry, counts=True)
+    idx = synth.sample_rays(rx, ry, 2048, synth.BASE_SEED + 7)
+    ref = ora.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx[idx], ry[idx])
+    ea, ek, eg = rel_err(got[idx], ref)
+    stats("alpha vs brute force", ea)
+    stats("kappa vs brute force", ek)
+    stats("gamma vs brute force", eg)
+    say(f"  mean counts per ray (visited, accepted, leaf, list hits): {cnt.mean(0)}")
+    assert ea.max() <= 1e-4 and ek.max() <= 1e-4 and eg.max() <= 1e-4
+    # the same sampled rays through the oracle tree: identical decisions
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.3, 8, 8)
+    refB, rc = T.shoot(rx[idx], ry[idx], counts=True)
+    np.testing.assert_array_equal(cnt[idx], rc[:, [0, 1, 2, 4]])
+
+
+def test_edge_cases(ora):
+    import paper_1312_1128_amd as g
+    import torch
+
+    say("[gpu] edge cases")
+    # one particle; fewer than a leaf; coincident particles (depth cap)
+    for n, L in [(1, 8), (5, 8), (9, 8)]:
+        lens = mixed_lens(n, 31 + n)
+        tree = build(lens, 0.5, L, 4)
+        rx, ry = synth.uniform_points(130, 32)
+        got = shoot(tree, rx, ry)
+        ref = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.5, L, 4).shoot(rx, ry)
+        np.testing.assert_allclose(got, ref, rtol=2e-5, atol=1e-6 * np.abs(ref).max())
+    lens = synth.point_masses(40, 33)
+    lens.x[:20] = 0.1
+    lens.y[:20] = -0.2
+    tree = build(lens, 0.5, 4, 3)
+    inf = tree.info()
+    assert inf["max_level"] == 32 and inf["check_flags"] == 0
+    rx, ry = synth.uniform_points(64, 34)
+    got = shoot(tree, rx, ry)
+    ref = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.5, 4, 3).shoot(rx, ry)
+    np.testing.assert_allclose(got[:, :2], ref[:, :2], rtol=2e-5, atol=1e-6 * np.abs(ref[:, :2]).max())
+    # zero rays and a single ray
+    out = g.shoot(tree, dev(np.zeros(0)), dev(np.zeros(0)))
+    assert out["a1"].numel() == 0
+    got1 = shoot(tree, rx[:1], ry[:1])
+    np.testing.assert_allclose(got1[0, :2], ref[0, :2], rtol=2e-5)
+    # rays far outside the particles: pure multipoles of the root
+    far = shoot(tree, np.array([50.0, -80.0]), np.array([3.0, 40.0]))
+    reff = ora.direct(lens.x, lens.y, lens.m, lens.s, 3.0, np.array([50.0, -80.0]), np.array([3.0, 40.0]))
+    np.testing.assert_allclose(far[:, :2], reff[:, :2], rtol=1e-5)
+    torch.cuda.synchronize()
+
+
+def test_determinism_and_flags(ora):
+    import paper_1312_1128_amd as g
+
+    say("[gpu] determinism and flags")
+    lens = synth.nfw_halo(30000, 41)
+    rx, ry = synth.ray_grid(100)
+    tree = build(lens, 0.3, 8, 6)
+    a = shoot(tree, rx, ry)
+    b = shoot(tree, rx, ry)
+    np.testing.assert_array_equal(a, b)  # no atomics in the forward: bitwise repeatable
+    tree2 = build(lens, 0.3, 8, 6)
+    np.testing.assert_array_equal(shoot(tree2, rx, ry), a)  # rebuild is deterministic too
+    ao = shoot(tree, rx, ry, alpha_only=True)
+    np.testing.assert_array_equal(ao[:, :2], a[:, :2])
+    # rays passed as they are (no ray sort): other groups, same per-ray decisions and arithmetic
+    od = shoot(tree, rx, ry, ordered=True)
+    np.testing.assert_array_equal(od, a)
+    nk = shoot(tree, rx, ry, kahan=False)  # plain FP32 summation of alpha: ~sqrt(terms) eps
+    ea = np.linalg.norm(nk[:, :2] - a[:, :2], axis=1) / np.linalg.norm(a[:, :2], axis=1)
+    assert ea.max() < 1e-5
+
+
+def test_bad_inputs_are_rejected():
+    import paper_1312_1128_amd as g
+
+    say("[gpu] error paths")
+    lens = synth.point_masses(100, 51)
+    x = lens.x.copy()
+    x[7] = np.nan
+    with pytest.raises(g.GlamerError) as e:
+        g.Tree().build(dev(x), dev(lens.y), dev(lens.m), None)
+    assert e.value.status == -5
+    m = lens.m.copy()
+    m[3] = -1.0
+    with pytest.raises(g.GlamerError):
+        g.Tree().build(dev(lens.x), dev(lens.y), dev(m), None)
+    with pytest.raises(g.GlamerError) as e:
+        g.Tree().build(dev(lens.x), dev(lens.y), dev(lens.m), None, theta=1.0)
+    assert e.value.status == -1
+    with pytest.raises(g.GlamerError):
+        g.Tree().build(dev(lens.x), dev(lens.y), dev(lens.m), None, order=13)
+    t = g.Tree()
+    with pytest.raises(g.GlamerError) as e:
+        g.shoot(t, dev(np.zeros(3)), dev(np.zeros(3)))
+    assert e.value.status == -4
