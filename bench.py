@@ -1,0 +1,224 @@
+"""Benchmark of the tree ray-shooting hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (the configuration the headline metric is quoted on): 1e6 smoothed
+NFW particles (c = 5, truncated at r200 = 1, equal masses summing to 1,
+smoothing length = distance to the 32nd neighbour, q = 3) and the 2048 x 2048
+cell-centred ray grid over [-0.5, 0.5]^2; theta = 0.3, multipole order 8, leaf
+size 8.  Synthetic, seeded inputs (no dataset exists for this workload).
+
+A step is one pass of the hot path over that batch: build the tree from the
+particles (bounding square, Morton sort, boxes, lists, FP64 moments) and shoot
+every ray (ray sort + walk), inputs already in HBM.  `value` = rays / step time.
+
+Printed as one JSON line, with:
+  roofline     -- the walk kernel alone, timed with HIP events on the stream it
+                  runs on; algorithmic FLOPs from its own per-ray interaction
+                  counts times fixed per-interaction weights;
+  cpu_baseline -- the FP64 brute-force oracle on a bounded ray sample on the
+                  host cores (also yields the sample's error vs FP64);
+  extras       -- build time, walk-only rate, plain GPU direct sum rates.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays/s (α,κ,γ) at 1e6 particles, rel err ≤1e-4 vs FP64; fwd+adjoint rays/s"
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (dense)
+THETA, ORDER, LEAF = 0.3, 8, 8
+
+# algorithmic FLOPs per interaction (FMA = 2): opening test, accepted box at
+# order p, leaf particle, big-particle correction
+def flops_per_ray(counts: np.ndarray, p: int) -> np.ndarray:
+    return 5.0 * counts[:, 0] + (20.0 + 16.0 * p) * counts[:, 1] + 22.0 * counts[:, 2] + 60.0 * counts[:, 3]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_threads() -> int:
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    return max(1, min(aff, int(env))) if env and env.isdigit() else aff
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_1312_1128_amd as g
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    lens = synth.nfw_halo(1_000_000, synth.BASE_SEED + 2)
+    rx_t, ry_t = synth.ray_grid_tiled(2048)  # grid stored in 8x8-tile order
+    R = rx_t.size
+    log(f"inputs generated in {time.time() - t0:.1f}s: n={lens.n} rays={R}")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    x, y, m, s = d(lens.x), d(lens.y), d(lens.m), d(lens.s)
+    rx, ry = d(rx_t), d(ry_t)
+    stream = torch.cuda.current_stream()
+
+    tree = g.Tree()
+    out = {k: torch.empty(R, dtype=torch.float32, device=dev) for k in ["a1", "a2", "kappa", "g1", "g2"]}
+    ws = torch.empty(g.workspace_bytes(R), dtype=torch.uint8, device=dev)
+
+    def step():
+        tree.build(x, y, m, s, theta=THETA, q=lens.q, leaf_size=LEAF, order=ORDER)
+        g.shoot(tree, rx, ry, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    ms_step = 1e3 * el / args.steps
+    value = R * args.steps / el
+    log(f"step (build + shoot): {ms_step:.3f} ms -> {value:.4e} rays/s")
+
+    # build alone
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tb = []
+    for _ in range(5):
+        t = time.perf_counter()
+        tree.build(x, y, m, s, theta=THETA, q=lens.q, leaf_size=LEAF, order=ORDER)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t)
+    build_ms = 1e3 * float(np.median(tb))
+    info = tree.info()
+
+    # walk kernel alone: rays already in tile order, so the launch is k_walk only
+    nrep = 10
+    ev0.record(stream)
+    for _ in range(nrep):
+        g.shoot(tree, rx, ry, out=out, ordered=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    walk_ms = ev0.elapsed_time(ev1) / nrep
+    # per-ray interaction counts (separate launch, outside every timed region)
+    cnt = g.shoot(tree, rx, ry, counts=True, ordered=True)["counts"].cpu().numpy().astype(np.float64)
+    flop = float(flops_per_ray(cnt, ORDER).sum())
+    achieved = flop / (walk_ms * 1e-3) / 1e12
+    log(f"walk: {walk_ms:.3f} ms, {flop:.3e} algorithmic FLOP -> {achieved:.2f} TFLOP/s "
+        f"({achieved / PEAK_FP32_TFLOPS:.3f} of FP32 peak); counts/ray {cnt.mean(0)}")
+
+    # plain GPU direct sum on a slice of the rays
+    nd = 262144
+    res = {}
+    for fp64 in (False, True):
+        g.shoot_direct(x, y, m, s, lens.q, rx[:256], ry[:256], fp64=fp64)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.shoot_direct(x, y, m, s, lens.q, rx[:nd], ry[:nd], fp64=fp64)
+        torch.cuda.synchronize()
+        res[fp64] = nd / (time.perf_counter() - t)
+    log(f"direct sum: fp32 {res[False]:.3e} rays/s, fp64 {res[True]:.3e} rays/s")
+
+    # forward + adjoint on the lens-fitting workload: 1e5 particles, 1e5 rays,
+    # L = sum |x - alpha - beta*|^2 (step = build + alpha walk + adjoint walk)
+    lens5 = synth.nfw_halo(100_000, synth.BASE_SEED + 5)
+    r5x, r5y = synth.uniform_points(100_000, synth.BASE_SEED + 6)
+    x5, y5, m5, s5, rx5, ry5 = (d(a) for a in (lens5.x, lens5.y, lens5.m, lens5.s, r5x, r5y))
+    bx5 = rx5 - 0.1 * rx5  # fixed target source positions (only the data flow matters for timing)
+    by5 = ry5 - 0.1 * ry5
+    tree5 = g.Tree()
+    ws5 = torch.empty(g.workspace_bytes(rx5.numel()), dtype=torch.uint8, device=dev)
+    out5 = {k: torch.empty(rx5.numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2"]}
+    grads5 = [torch.zeros(lens5.n, dtype=torch.float64, device=dev) for _ in range(4)]
+
+    def step5():
+        tree5.build(x5, y5, m5, s5, theta=THETA, q=lens5.q, leaf_size=LEAF, order=ORDER)
+        g.shoot(tree5, rx5, ry5, out=out5, workspace=ws5, alpha_only=True)
+        ga1 = (-2.0 * (rx5 - out5["a1"] - bx5)).float()
+        ga2 = (-2.0 * (ry5 - out5["a2"] - by5)).float()
+        for t_ in grads5:
+            t_.zero_()
+        g.shoot_adjoint(tree5, rx5, ry5, ga1, ga2, *grads5, workspace=ws5)
+
+    for _ in range(2):
+        step5()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    n5 = max(3, args.steps)
+    for _ in range(n5):
+        step5()
+    torch.cuda.synchronize()
+    fa_ms = 1e3 * (time.perf_counter() - t) / n5
+    log(f"fwd+adjoint (1e5 particles, 1e5 rays): {fa_ms:.3f} ms -> {rx5.numel() / (fa_ms * 1e-3):.4e} rays/s")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "nfw_1e6_particles_grid2048", "particles": lens.n, "rays": R, "theta": THETA,
+                   "order": ORDER, "leaf_size": LEAF, "q": lens.q, "step": "build_tree + shoot (alpha, kappa, gamma)"},
+        "roofline": {"bound": "alu", "kernel": "k_walk", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel_ms": walk_ms, "flop_per_launch": flop},
+        "extras": {"build_ms": build_ms, "walk_only_rays_per_s": R / (walk_ms * 1e-3),
+                   "ncells": info["ncells"], "nlisted": info["nlisted"],
+                   "counts_per_ray": dict(zip(["visited", "accepted", "leaf", "list_hits"], cnt.mean(0).tolist())),
+                   "direct_fp32_rays_per_s": res[False], "direct_fp64_rays_per_s": res[True],
+                   "fwd_adjoint_rays_per_s": rx5.numel() / (fa_ms * 1e-3), "fwd_adjoint_ms": fa_ms,
+                   "fwd_adjoint_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2"},
+    }
+
+    if not args.no_cpu:
+        import oracle
+
+        oracle.build(force=False)
+        nt = cpu_threads()
+        gen = synth.rng(synth.BASE_SEED + 99)
+        probe = gen.choice(R, 256, replace=False)
+        t = time.perf_counter()
+        oracle.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx_t[probe], ry_t[probe], threads=nt)
+        per_ray = (time.perf_counter() - t) / probe.size
+        k = int(min(R, max(256, 15.0 / per_ray)))
+        idx = np.sort(gen.choice(R, k, replace=False))
+        t = time.perf_counter()
+        ref = oracle.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx_t[idx], ry_t[idx], threads=nt)
+        cpu_el = time.perf_counter() - t
+        g.shoot(tree, rx, ry, out=out, workspace=ws)
+        got = np.stack([out[kk].double().cpu().numpy()[idx] for kk in ["a1", "a2", "kappa", "g1", "g2"]], axis=1)
+        ea = np.linalg.norm(got[:, :2] - ref[:, :2], axis=1) / np.linalg.norm(ref[:, :2], axis=1)
+        ek = np.abs(got[:, 2] - ref[:, 2]) / np.abs(ref[:, 2])
+        eg = np.linalg.norm(got[:, 3:] - ref[:, 3:], axis=1) / np.linalg.norm(ref[:, 3:], axis=1)
+        line["cpu_baseline"] = {"value": k / cpu_el, "unit": "rays/s", "cores": nt, "kind": "oracle",
+                                "sample": f"{k} random rays of the 2048^2 grid, FP64 brute force over all "
+                                          f"{lens.n} particles ({cpu_el:.1f} s)"}
+        line["parity_vs_fp64_sample"] = {"rays": k, "alpha_max": float(ea.max()), "kappa_max": float(ek.max()),
+                                         "gamma_max": float(eg.max())}
+        log(f"cpu oracle: {k / cpu_el:.1f} rays/s on {nt} threads; sample max rel err "
+            f"alpha {ea.max():.2e} kappa {ek.max():.2e} gamma {eg.max():.2e}")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,12 +1,364 @@
-// Adjoint tree walk (placeholder until the backward walk lands).
+// Adjoint of the forward tree walk: dL/d(m, x, y, s) of the particles for
+// cotangents ga = dL/dalpha of the rays, on the frozen topology and decisions
+// of the forward walk (the same traversal runs again and takes the same FP64
+// decisions).
+//
+// Direct terms (leaf particles, big-particle corrections) give particle
+// gradients directly:
+//   dL/dm_i = ga . alpha_i / m_i,  dL/dz_i = -J_i ga  (alpha depends on x - x_i,
+//   J_i = [[k + g1, g2], [g2, k - g1]] of the single particle),
+//   dL/ds_i = ga . d alpha_i / d s_i = -m (ga . d) e^-u / (s^3 C) inside.
+// An accepted box contributes F = alpha1 - i alpha2 = sum_k Q_k w^-(k+1), so
+// with g_hat = ga1 + i ga2 the walk accumulates per box
+//   Abar_k r_cm^k = sum_r g_hat v t^k   (v = 1/w, t = r_cm v)
+//   Bbar          = sum_r g_hat M v^2 (P(t) + t P'(t))     (= g_hat dF/dz_cm)
+// and a push-down pass gives every particle its share through
+//   dQ_k/dm_i = d^k - k Q_{k-1} d / M,  dQ_k/dz_i = k m_i d^(k-1) - k Q_{k-1} m_i / M,
+//   dz_cm/dm_i = d / M,  dz_cm/dz_i = m_i / M  (d = z_i - z_cm; all holomorphic).
+// Per-lane terms are reduced across the wavefront before one FP64 atomic per
+// quantity; the point-mass parts of big-particle pairs are reduced in FP64 so
+// that they cancel like the forward's balance.
+#include <math.h>
+
+#include "eval.hpp"
 #include "walk.hpp"
 
 namespace glm {
 
-glm_status adjoint_device(TreeStorage&, const double*, const double*, int64_t, const float*, const float*, double*,
-                          double*, double*, double*, uint32_t, void*, hipStream_t)
+namespace {
+
+__device__ inline double wave_sum_d(double v)
 {
-    return fail(GLM_ESTATE, "shoot_adjoint is not available in this build");
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ inline float wave_sum_f(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Gradient terms of one particle for this lane, per the same cases as the
+// forward's eval_particle.  Returns FP64 (m, x, y, s) contributions in G.
+// mode 0: leaf sum; mode 1: big-particle correction (Gaussian - point).
+__device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mode, bool act, float g1, float g2,
+                                     float invC, double G[4])
+{
+    G[0] = G[1] = G[2] = G[3] = 0.0;
+    if (!act) return false;
+    double d1, d2;
+    const double r2 = sqdist(X, Y, pr.x, pr.y, &d1, &d2);
+    const bool inside = r2 < pr.qs2;
+    const bool listed = (pr.meta >> 31) != 0;
+    if (mode == 1 && !inside) return false;
+    const float f1 = (float)d1, f2 = (float)d2, r2f = (float)r2;
+    const float ir2 = r2f > 0.0f ? __builtin_amdgcn_rcpf(r2f) : 0.0f;
+    const float gd = g1 * f1 + g2 * f2;
+    // point mass, per unit mass: alpha = d / r^2, gamma = -(cos 2phi, sin 2phi) / r^2, kappa = 0
+    float P[4];
+    point_terms(1.0f, f1, f2, ir2, P);
+    const float pm_m = g1 * P[0] + g2 * P[1];
+    const float pm_x = -(g1 * P[2] + g2 * P[3]) * pr.m;
+    const float pm_y = -(g1 * P[3] - g2 * P[2]) * pr.m;
+    const bool gauss = inside && !(mode == 0 && listed);
+    if (!gauss) { // point mass (a listed+inside point pairs with the list box's -point)
+        G[0] = (double)pm_m;
+        G[1] = (double)pm_x;
+        G[2] = (double)pm_y;
+        return true;
+    }
+    const float u = r2f * pr.h;
+    const float e = __expf(-u);
+    const float hu = invC * pr.h; // per unit mass m/C/(2 s^2)
+    float Au, Gu;
+    gauss_terms(u, e, ir2, invC, hu, &Au, &Gu);
+    const float Ku = hu * e;
+    const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = 2.0f * f1 * f2 * ir2;
+    const float ga1 = -Gu * c2, ga2 = -Gu * s2; // gamma per unit mass
+    const float em = Au * gd;
+    const float ex = -(g1 * (Ku + ga1) + g2 * ga2) * pr.m;
+    const float ey = -(g1 * ga2 + g2 * (Ku - ga1)) * pr.m;
+    // d alpha / d s = -m d e^-u / (s^3 C), 1/s^3 = 2h sqrt(2h)
+    const float es = -pr.m * hu * e * 2.0f * __builtin_sqrtf(2.0f * pr.h) * gd;
+    if (mode == 1) {
+        G[0] = (double)em - (double)pm_m;
+        G[1] = (double)ex - (double)pm_x;
+        G[2] = (double)ey - (double)pm_y;
+    } else {
+        G[0] = (double)em;
+        G[1] = (double)ex;
+        G[2] = (double)ey;
+    }
+    G[3] = (double)es;
+    return true;
+}
+
+__device__ inline void reduce_and_add(const double G[4], bool any_s, uint32_t meta, double* __restrict__ dm,
+                                      double* __restrict__ dx, double* __restrict__ dy, double* __restrict__ ds,
+                                      int lane)
+{
+    const double s0 = wave_sum_d(G[0]), s1 = wave_sum_d(G[1]), s2 = wave_sum_d(G[2]);
+    const double s3 = any_s ? wave_sum_d(G[3]) : 0.0;
+    if (lane == 0) {
+        const uint32_t i = meta & 0x7fffffffu;
+        if (dm) unsafeAtomicAdd(dm + i, s0);
+        if (dx) unsafeAtomicAdd(dx + i, s1);
+        if (dy) unsafeAtomicAdd(dy + i, s2);
+        if (ds && any_s) unsafeAtomicAdd(ds + i, s3);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double* __restrict__ rxs,
+                                                        const double* __restrict__ rys,
+                                                        const uint32_t* __restrict__ rperm, int64_t nrays,
+                                                        const float* __restrict__ ga1, const float* __restrict__ ga2,
+                                                        double* __restrict__ dm, double* __restrict__ dx,
+                                                        double* __restrict__ dy, double* __restrict__ ds,
+                                                        double* __restrict__ abar)
+{
+    constexpr int NA = 2 * (P + 1) + 2; // (Re, Im) of Abar_0..Abar_P, Bbar
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t r = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const bool valid = r < nrays;
+    if (!__any(valid)) return;
+    const double X = valid ? rxs[r] : 0.0, Y = valid ? rys[r] : 0.0;
+    const int64_t o = valid ? (rperm ? (int64_t)rperm[r] : r) : 0;
+    const float g1 = valid ? ga1[o] : 0.0f, g2 = valid ? ga2[o] : 0.0f;
+    const double gx0 = wave_min(valid ? X : INFINITY), gx1 = wave_max(valid ? X : -INFINITY);
+    const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
+    const float invC = T.invC;
+
+    int skip = valid ? 0 : 0x7fffffff;
+    const int nc = T.ncells;
+    int cur = 0;
+    double G[4];
+    while (cur < nc) {
+        cur = __builtin_amdgcn_readfirstlane(cur);
+        const CellHdr h = T.hdr[cur];
+        const bool act = cur >= skip;
+        if (h.info & kInfoList) {
+            const CellExt e = T.ext[cur];
+            for (int base = e.lbeg; base < e.lend; base += kWave) {
+                const int j = base + lane;
+                bool cand = false;
+                if (j < e.lend) {
+                    const PRec pr = T.lst[j];
+                    const double dxb = fmax(fmax(gx0 - pr.x, pr.x - gx1), 0.0);
+                    const double dyb = fmax(fmax(gy0 - pr.y, pr.y - gy1), 0.0);
+                    cand = dxb * dxb + dyb * dyb < pr.qs2 * (1.0 + 1e-9);
+                }
+                uint64_t cm = __ballot(cand);
+                while (cm) {
+                    const int k = __ffsll((unsigned long long)cm) - 1;
+                    cm &= cm - 1;
+                    const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
+                    const bool hit = particle_grad(pr, X, Y, 1, act, g1, g2, invC, G);
+                    if (__any(hit)) reduce_and_add(G, true, pr.meta, dm, dx, dy, ds, lane);
+                }
+            }
+        }
+        double w1, w2;
+        const double d2 = sqdist(X, Y, h.cx, h.cy, &w1, &w2);
+        const bool acc = act && d2 > h.rcut2;
+        const bool opn = act && !acc;
+        if (__any(acc)) {
+            // per-lane box adjoint terms (zero on lanes that did not accept)
+            float a[NA];
+#pragma unroll
+            for (int k = 0; k < NA; ++k) a[k] = 0.0f;
+            if (acc) {
+                const float* mo = T.mom + (size_t)cur * mom_stride(P);
+                const float M = mo[0], rcm = mo[1];
+                const float f1 = (float)w1, f2 = (float)w2;
+                const float inv = __builtin_amdgcn_rcpf(f1 * f1 + f2 * f2);
+                const float v1 = f1 * inv, v2 = -f2 * inv;
+                const float t1 = rcm * v1, t2 = rcm * v2;
+                // g_hat v t^k
+                float p1 = g1 * v1 - g2 * v2, p2 = g1 * v2 + g2 * v1;
+#pragma unroll
+                for (int k = 0; k <= P; ++k) {
+                    a[2 * k] = p1;
+                    a[2 * k + 1] = p2;
+                    const float n1 = p1 * t1 - p2 * t2, n2 = p1 * t2 + p2 * t1;
+                    p1 = n1;
+                    p2 = n2;
+                }
+                // S = P(t) + t P'(t) = sum (k+1) Qn_k t^k  (Qn_0 = 1, Qn_1 = 0)
+                float b1 = 1.0f, b2 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+                if constexpr (P >= 2) {
+                    b1 = mo[2 + 2 * (P - 2)];
+                    b2 = mo[3 + 2 * (P - 2)];
+#pragma unroll
+                    for (int k = P - 1; k >= 0; --k) {
+                        const float n1 = c1 * t1 - c2 * t2 + b1, n2 = c1 * t2 + c2 * t1 + b2;
+                        c1 = n1;
+                        c2 = n2;
+                        const float q1 = k >= 2 ? mo[2 + 2 * (k - 2)] : (k == 0 ? 1.0f : 0.0f);
+                        const float q2 = k >= 2 ? mo[3 + 2 * (k - 2)] : 0.0f;
+                        const float m1 = b1 * t1 - b2 * t2 + q1, m2 = b1 * t2 + b2 * t1 + q2;
+                        b1 = m1;
+                        b2 = m2;
+                    }
+                }
+                const float S1 = b1 + t1 * c1 - t2 * c2, S2 = b2 + t1 * c2 + t2 * c1;
+                const float w21 = v1 * v1 - v2 * v2, w22 = 2.0f * v1 * v2;
+                const float V1 = M * (w21 * S1 - w22 * S2), V2 = M * (w21 * S2 + w22 * S1);
+                a[NA - 2] = g1 * V1 - g2 * V2;
+                a[NA - 1] = g1 * V2 + g2 * V1;
+            }
+#pragma unroll
+            for (int k = 0; k < NA; ++k) a[k] = wave_sum_f(a[k]);
+            if (lane == 0) {
+                double* dst = abar + (size_t)cur * NA;
+#pragma unroll
+                for (int k = 0; k < NA; ++k) unsafeAtomicAdd(dst + k, (double)a[k]);
+            }
+        }
+        if (h.info & kInfoLeaf) {
+            if (__any(opn)) {
+                const CellExt e = T.ext[cur];
+                for (int j = e.pbeg; j < e.pend; ++j) {
+                    const PRec pr = T.prt[j];
+                    const bool hit = particle_grad(pr, X, Y, 0, opn, g1, g2, invC, G);
+                    const bool any_s = __any(hit && G[3] != 0.0);
+                    reduce_and_add(G, any_s, pr.meta, dm, dx, dy, ds, lane);
+                }
+            }
+            cur = cur + 1;
+        } else if (__any(opn)) {
+            if (acc) skip = h.next;
+            cur = cur + 1;
+        } else {
+            cur = h.next > cur ? h.next : cur + 1;
+        }
+    }
+}
+
+// Box adjoints -> particles.  One thread per particle walks its ancestors.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __restrict__ ms,
+                                                    const double* __restrict__ abar, double* __restrict__ dm,
+                                                    double* __restrict__ dx, double* __restrict__ dy)
+{
+    constexpr int NA = 2 * (P + 1) + 2;
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= T.n) return;
+    const PRec pr = T.prt[k];
+    const uint32_t i = pr.meta & 0x7fffffffu;
+    const double mi = ms[k];
+    double gm = 0.0, gzr = 0.0, gzi = 0.0;
+    int c = 0;
+    for (int guard = 0; guard <= kMaxLevel && c < T.ncells; ++guard) {
+        const double* ab = abar + (size_t)c * NA;
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) any |= ab[q] != 0.0;
+        const CellHdr h = T.hdr[c];
+        if (any) {
+            const double M = T.cM[c];
+            const double rcm = (double)T.mom[(size_t)c * mom_stride(P) + 1];
+            const double* Q = T.cq + (size_t)c * (P + 1) * 2;
+            const double dr = pr.x - h.cx, di = pr.y - h.cy;
+            // sm = sum_k Abar_k dQ_k/dm + Bbar d/M ; sz = sum_k Abar_k dQ_k/dz + Bbar m/M
+            double smr = 0.0, smi = 0.0, szr = 0.0, szi = 0.0;
+            double dkr = 1.0, dki = 0.0, dkm1r = 0.0, dkm1i = 0.0; // d^k, d^(k-1)
+            double irk = 1.0;                                      // r_cm^-k
+            const double irc = 1.0 / rcm;
+            for (int kk = 0; kk <= P; ++kk) {
+                const double Ar = ab[2 * kk] * irk, Ai = ab[2 * kk + 1] * irk;
+                double tmr = dkr, tmi = dki;                     // d^k
+                double tzr = kk * mi * dkm1r, tzi = kk * mi * dkm1i; // k m d^(k-1)
+                if (M > 0.0 && kk > 0) {
+                    const double qr = Q[2 * (kk - 1)], qi = Q[2 * (kk - 1) + 1];
+                    // k Q_{k-1} d / M and k Q_{k-1} m / M
+                    tmr -= kk * (qr * dr - qi * di) / M;
+                    tmi -= kk * (qr * di + qi * dr) / M;
+                    tzr -= kk * qr * mi / M;
+                    tzi -= kk * qi * mi / M;
+                }
+                smr += Ar * tmr - Ai * tmi;
+                smi += Ar * tmi + Ai * tmr;
+                szr += Ar * tzr - Ai * tzi;
+                szi += Ar * tzi + Ai * tzr;
+                dkm1r = dkr;
+                dkm1i = dki;
+                const double nr = dkr * dr - dki * di, ni = dkr * di + dki * dr;
+                dkr = nr;
+                dki = ni;
+                irk *= irc;
+            }
+            if (M > 0.0) {
+                const double Br = ab[NA - 2], Bi = ab[NA - 1];
+                smr += (Br * dr - Bi * di) / M;
+                smi += (Br * di + Bi * dr) / M;
+                szr += Br * mi / M;
+                szi += Bi * mi / M;
+            }
+            gm += smr;
+            gzr += szr;
+            gzi += szi;
+        }
+        if (h.info & kInfoLeaf) break;
+        // descend into the child whose Morton range holds position k
+        int ch = c + 1;
+        while (ch < h.next && !(k >= T.cbeg[ch] && k < T.cend[ch])) ch = T.hdr[ch].next > ch ? T.hdr[ch].next : ch + 1;
+        if (ch >= h.next) break;
+        c = ch;
+    }
+    if (dm) dm[i] += gm;
+    if (dx) dx[i] += gzr;
+    if (dy) dy[i] -= gzi;
+}
+
+__global__ void k_fill_zero(double* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+template <int P>
+glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, const float* ga1, const float* ga2,
+                          double* dm, double* dx, double* dy, double* ds, hipStream_t st)
+{
+    constexpr int NA = 2 * (P + 1) + 2;
+    const size_t words = (size_t)ts.ncells * NA;
+    glm_status rc = ts.abuf.ensure(words * sizeof(double));
+    if (rc != GLM_OK) return rc;
+    double* abar = ts.abuf.as<double>();
+    hipLaunchKernelGGL(k_fill_zero, dim3(ceil_div((int64_t)words, kBlock)), dim3(kBlock), 0, st, abar, (int64_t)words);
+    hipLaunchKernelGGL((k_adjoint_walk<P>), dim3(ceil_div(nrays, kBlock)), dim3(kBlock), 0, st, ts.dev, sr.xs, sr.ys,
+                       sr.perm, nrays, ga1, ga2, dm, dx, dy, ds, abar);
+    hipLaunchKernelGGL((k_pushdown<P>), dim3(ceil_div(ts.n, kBlock)), dim3(kBlock), 0, st, ts.dev, ts.ms, abar, dm, dx,
+                       dy);
+    GLM_HIP(hipGetLastError());
+    return GLM_OK;
+}
+
+} // namespace
+
+glm_status adjoint_device(TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, const float* ga1,
+                          const float* ga2, double* dm, double* dx, double* dy, double* ds, uint32_t flags, void* ws,
+                          hipStream_t st)
+{
+    if (nrays == 0) return GLM_OK;
+    StagedRays sr{rx, ry, nullptr};
+    if (!(flags & GLM_RAYS_ORDERED)) {
+        const RayLayout L = ray_layout(nrays);
+        glm_status rc = stage_rays(rx, ry, nrays, ws, L, &sr, st);
+        if (rc != GLM_OK) return rc;
+    }
+#define GLM_CASE(PP) \
+    case PP: return launch_adjoint<PP>(ts, sr, nrays, ga1, ga2, dm, dx, dy, ds, st);
+    switch (ts.params.order) {
+        GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
+        GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
+        default: return fail(GLM_ESTATE, "unsupported order");
+    }
+#undef GLM_CASE
 }
 
 } // namespace glm

@@ -121,19 +121,39 @@ __global__ __launch_bounds__(kBlock) void k_bbox_partial(const double* __restric
 
 // Root square: centre of the bounding box, side = max extent * (1 + 2^-40)
 // (1 if the extent is 0), 32-bit quantisation scale 2^32 / side.
-__global__ void k_root(const double* __restrict__ part, int nb, BuildSync* __restrict__ sync)
+__global__ __launch_bounds__(kBlock) void k_root(const double* __restrict__ part, int nb, BuildSync* __restrict__ sync)
 {
 #pragma clang fp contract(off)
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
-    int bad = 0;
-    for (int b = 0; b < nb; ++b) {
+    __shared__ double red[5][kBlock];
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY, bad = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
         x0 = fmin(x0, part[b * 5 + 0]);
         x1 = fmax(x1, part[b * 5 + 1]);
         y0 = fmin(y0, part[b * 5 + 2]);
         y1 = fmax(y1, part[b * 5 + 3]);
-        bad |= part[b * 5 + 4] != 0.0;
+        bad = fmax(bad, part[b * 5 + 4]);
     }
+    red[0][threadIdx.x] = x0;
+    red[1][threadIdx.x] = x1;
+    red[2][threadIdx.x] = y0;
+    red[3][threadIdx.x] = y1;
+    red[4][threadIdx.x] = bad;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+            red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][threadIdx.x + o]);
+            red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
+            red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    x0 = red[0][0];
+    x1 = red[1][0];
+    y0 = red[2][0];
+    y1 = red[3][0];
     const double ex = x1 - x0, ey = y1 - y0;
     const double ext = ex > ey ? ex : ey;
     double S = ext * (1.0 + 0x1p-40);
@@ -142,7 +162,7 @@ __global__ void k_root(const double* __restrict__ part, int nb, BuildSync* __res
     sync->y0 = 0.5 * (y0 + y1) - 0.5 * S;
     sync->side = S;
     sync->scale = 4294967296.0 / S;
-    sync->bad = bad;
+    sync->bad = red[4][0] != 0.0;
 }
 
 __device__ inline uint32_t quantise(double v, double v0, double scale)
@@ -188,32 +208,40 @@ __global__ __launch_bounds__(kBlock) void k_gather(const uint32_t* __restrict__ 
 // ancestor then does too); the boxes starting at i form a chain from the
 // shallowest new level down to the first leaf.
 __global__ __launch_bounds__(kBlock) void k_topo_count(const uint64_t* __restrict__ K, int n, int L,
-                                                      int32_t* __restrict__ cnt, int8_t* __restrict__ lstart)
+                                                      int32_t* __restrict__ cnt, int8_t* __restrict__ lstart,
+                                                      BuildSync* __restrict__ sync)
 {
+    __shared__ int32_t hist[kMaxLevel + 1];
+    if (threadIdx.x <= kMaxLevel) hist[threadIdx.x] = 0;
+    __syncthreads();
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int ls = level_start(K, i);
-    lstart[i] = (int8_t)ls;
-    int c = 0;
-    if (ls <= kMaxLevel) {
-        int hi = n;
-        bool exists = true;
-        if (ls > 0) {
-            const uint64_t P = prefix_at(K[i], ls - 1);
-            const int lo = lower_prefix(K, 0, i, P, ls - 1);
-            hi = upper_prefix(K, i, n, P, ls - 1);
-            exists = (hi - lo) > L;
-        }
-        if (exists) {
-            for (int l = ls;; ++l) {
-                const int end = l == 0 ? n : upper_prefix(K, i, hi, prefix_at(K[i], l), l);
-                ++c;
-                if (end - i <= L || l == kMaxLevel) break;
-                hi = end;
+    if (i < n) {
+        const int ls = level_start(K, i);
+        lstart[i] = (int8_t)ls;
+        int c = 0;
+        if (ls <= kMaxLevel) {
+            int hi = n;
+            bool exists = true;
+            if (ls > 0) {
+                const uint64_t P = prefix_at(K[i], ls - 1);
+                const int lo = lower_prefix(K, 0, i, P, ls - 1);
+                hi = upper_prefix(K, i, n, P, ls - 1);
+                exists = (hi - lo) > L;
+            }
+            if (exists) {
+                for (int l = ls;; ++l) {
+                    const int end = l == 0 ? n : upper_prefix(K, i, hi, prefix_at(K[i], l), l);
+                    ++c;
+                    atomicAdd(&hist[l], 1);
+                    if (end - i <= L || l == kMaxLevel) break;
+                    hi = end;
+                }
             }
         }
+        cnt[i] = c;
     }
-    cnt[i] = c;
+    __syncthreads();
+    if (threadIdx.x <= kMaxLevel && hist[threadIdx.x]) atomicAdd(&sync->levcnt[threadIdx.x], hist[threadIdx.x]);
 }
 
 __global__ void k_sync_counts(const int32_t* __restrict__ cs, int n, BuildSync* __restrict__ sync)
@@ -223,39 +251,64 @@ __global__ void k_sync_counts(const int32_t* __restrict__ cs, int n, BuildSync* 
 
 __global__ __launch_bounds__(kBlock) void k_topo_emit(const uint64_t* __restrict__ K, int n, int L,
                                                      const int32_t* __restrict__ cs, const int8_t* __restrict__ lstart,
-                                                     BoxArrays b, BuildSync* __restrict__ sync)
+                                                     BoxArrays b, BuildSync* __restrict__ sync, LevelTable lt,
+                                                     int32_t* __restrict__ levidx)
 {
+    __shared__ int32_t lcnt[kMaxLevel + 1], lbase[kMaxLevel + 1];
+    __shared__ int32_t s_leaves, s_maxl;
+    if (threadIdx.x <= kMaxLevel) lcnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        s_leaves = 0;
+        s_maxl = 0;
+    }
+    __syncthreads();
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int c0 = cs[i], c = cs[i + 1] - c0;
-    if (c == 0) return;
-    const int ls = lstart[i];
-    int hi = n;
-    if (ls > 0) hi = upper_prefix(K, i, n, prefix_at(K[i], ls - 1), ls - 1);
-    const uint32_t qx = compact_bits(K[i]), qy = compact_bits(K[i] >> 1);
-    int leaves = 0, maxl = 0;
-    for (int k = 0; k < c; ++k) {
-        const int l = ls + k;
-        const int end = l == 0 ? n : upper_prefix(K, i, hi, prefix_at(K[i], l), l);
-        const int idx = c0 + k;
-        const bool leaf = (k == c - 1);
-        b.beg[idx] = i;
-        b.end[idx] = end;
-        b.level[idx] = l;
-        b.next[idx] = cs[end];
-        b.leaf[idx] = leaf ? 1 : 0;
-        b.ix[idx] = l == 0 ? 0u : (uint32_t)((uint64_t)qx >> (32 - l));
-        b.iy[idx] = l == 0 ? 0u : (uint32_t)((uint64_t)qy >> (32 - l));
-        b.lbeg[idx] = 0;
-        b.lend[idx] = 0;
-        hi = end;
-        if (leaf) {
-            leaves++;
-            maxl = l;
+    int c0 = 0, c = 0, ls = 0, hi0 = n;
+    if (i < n) {
+        c0 = cs[i];
+        c = cs[i + 1] - c0;
+        ls = lstart[i];
+        if (c > 0 && ls > 0) hi0 = upper_prefix(K, i, n, prefix_at(K[i], ls - 1), ls - 1);
+    }
+    for (int k = 0; k < c; ++k) atomicAdd(&lcnt[ls + k], 1);
+    __syncthreads();
+    if (threadIdx.x <= kMaxLevel) {
+        lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&sync->levfill[threadIdx.x], lcnt[threadIdx.x]) : 0;
+        lcnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    if (c > 0) {
+        const uint32_t qx = compact_bits(K[i]), qy = compact_bits(K[i] >> 1);
+        int hi = hi0;
+        for (int k = 0; k < c; ++k) {
+            const int l = ls + k;
+            const int end = l == 0 ? n : upper_prefix(K, i, hi, prefix_at(K[i], l), l);
+            const int idx = c0 + k;
+            const bool leaf = (k == c - 1);
+            b.beg[idx] = i;
+            b.end[idx] = end;
+            b.level[idx] = l;
+            b.next[idx] = cs[end];
+            b.leaf[idx] = leaf ? 1 : 0;
+            b.ix[idx] = l == 0 ? 0u : (uint32_t)((uint64_t)qx >> (32 - l));
+            b.iy[idx] = l == 0 ? 0u : (uint32_t)((uint64_t)qy >> (32 - l));
+            b.lbeg[idx] = 0;
+            b.lend[idx] = 0;
+            const int slot = lbase[l] + atomicAdd(&lcnt[l], 1);
+            if (slot < lt.cnt[l]) levidx[lt.off[l] + slot] = idx;
+            else atomicOr(&sync->internal, 4);
+            hi = end;
+            if (leaf) {
+                atomicAdd(&s_leaves, 1);
+                atomicMax(&s_maxl, l);
+            }
         }
     }
-    atomicAdd(&sync->nleaves, leaves);
-    atomicMax(&sync->max_level, maxl);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_leaves) atomicAdd(&sync->nleaves, s_leaves);
+        atomicMax(&sync->max_level, s_maxl);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_leaf_of(BoxArrays b, int ncells, int32_t* __restrict__ leaf_of)
@@ -380,15 +433,16 @@ __device__ inline void box_bounds(const BoxArrays& b, int c, const BuildSync* sy
 // Internal boxes: centre of mass of the children, then the children's moments
 // translated, Q_k = sum_children sum_j C(k, j) Q_j(child) t^(k-j) with
 // t = z_child - z_cm (exact re-expansion of sum m (z - z_cm)^k).
-__global__ __launch_bounds__(kBlock) void k_moments_level(int level, int ncells, int p, BoxArrays b,
+__global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restrict__ levidx, int count, int p, BoxArrays b,
                                                          const double* __restrict__ xs, const double* __restrict__ ys,
                                                          const double* __restrict__ ms,
                                                          const BuildSync* __restrict__ sync, double* __restrict__ cM,
                                                          double* __restrict__ ccx, double* __restrict__ ccy,
                                                          double* __restrict__ cQ)
 {
-    const int c = blockIdx.x * kBlock + threadIdx.x;
-    if (c >= ncells || b.level[c] != level) return;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= count) return;
+    const int c = levidx[t];
     const int P = p + 1;
     double Qr[kMaxOrder + 1], Qi[kMaxOrder + 1];
     for (int k = 0; k < P; ++k) Qr[k] = Qi[k] = 0.0;
@@ -573,14 +627,14 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     GLM_HIP(hipMemsetAsync(sync, 0, sizeof(BuildSync), st));
     const int gb = ceil_div(n, kBlock);
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kBlock), 0, st, x, y, m, s, (int64_t)n, part);
-    hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, st, part, nbb, sync);
+    hipLaunchKernelGGL(k_root, dim3(1), dim3(kBlock), 0, st, part, nbb, sync);
     hipLaunchKernelGGL(k_morton, dim3(gb), dim3(kBlock), 0, st, x, y, (int64_t)n, sync, k0, v0);
     const int where = radix_sort_u64(k0, v0, k1, v1, n, 8, hist, st);
     uint64_t* K = where ? k1 : k0;
     uint32_t* pv = where ? v1 : v0;
     GLM_HIP(hipMemcpyAsync(perm, pv, 4ull * n, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_gather, dim3(gb), dim3(kBlock), 0, st, perm, x, y, m, s, (int64_t)n, xs, ys, ms, ss);
-    hipLaunchKernelGGL(k_topo_count, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart);
+    hipLaunchKernelGGL(k_topo_count, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart, sync);
     exclusive_scan_i32(cnt, cnt, n, scr, st);
     hipLaunchKernelGGL(k_sync_counts, dim3(1), dim3(1), 0, st, cnt, n, sync);
     GLM_HIP(hipGetLastError());
@@ -602,6 +656,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     const size_t o_hdr = ca.take(sizeof(CellHdr) * (size_t)nc);
     const size_t o_ext = ca.take(sizeof(CellExt) * (size_t)nc);
     const size_t o_mom = ca.take(4ull * stride * nc);
+    const size_t o_levidx = ca.take(4ull * nc);
     rc = ts.cbuf.ensure(ca.size);
     if (rc != GLM_OK) return rc;
     char* C0 = ts.cbuf.as<char>();
@@ -622,9 +677,20 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     CellHdr* hdr = reinterpret_cast<CellHdr*>(C0 + o_hdr);
     CellExt* ext = reinterpret_cast<CellExt*>(C0 + o_ext);
     float* mom = reinterpret_cast<float*>(C0 + o_mom);
+    int32_t* levidx = reinterpret_cast<int32_t*>(C0 + o_levidx);
+    LevelTable lt;
+    {
+        int off = 0;
+        for (int l = 0; l <= kMaxLevel + 1; ++l) {
+            lt.off[l] = off;
+            lt.cnt[l] = l <= kMaxLevel ? hs.levcnt[l] : 0;
+            off += lt.cnt[l];
+        }
+        if (off != nc) return fail(GLM_EHIP, "build_tree: per-level box counts disagree with the box total");
+    }
 
     const int gc = ceil_div(nc, kBlock);
-    hipLaunchKernelGGL(k_topo_emit, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart, b, sync);
+    hipLaunchKernelGGL(k_topo_emit, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart, b, sync, lt, levidx);
     GLM_HIP(hipMemsetAsync(leaf_of, 0xff, 4ull * n, st)); // -1: no leaf (an internal error if it stays)
     hipLaunchKernelGGL(k_leaf_of, dim3(gc), dim3(kBlock), 0, st, b, nc, leaf_of);
     // list keys: box index, or all-ones on the sorted bits for unlisted particles
@@ -647,8 +713,9 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     hipLaunchKernelGGL(k_list_ranges, dim3(gb), dim3(kBlock), 0, st, n, lw ? lk1 : lk0, lw ? lv1 : lv0, unlisted, xs,
                        ys, ms, ss, perm, q, invC, b, lst, sync);
     for (int l = kMaxLevel; l >= 0; --l)
-        hipLaunchKernelGGL(k_moments_level, dim3(gc), dim3(kBlock), 0, st, l, nc, p, b, xs, ys, ms, sync, cM, ccx, ccy,
-                           cQ);
+        if (lt.cnt[l] > 0)
+            hipLaunchKernelGGL(k_moments_level, dim3(ceil_div(lt.cnt[l], kBlock)), dim3(kBlock), 0, st, levidx + lt.off[l],
+                               lt.cnt[l], p, b, xs, ys, ms, sync, cM, ccx, ccy, cQ);
     hipLaunchKernelGGL(k_finalize, dim3(gc), dim3(kBlock), 0, st, nc, p, prm.theta, b, sync, cM, ccx, ccy, cQ, hdr, ext,
                        mom);
     GLM_HIP(hipGetLastError());
@@ -680,6 +747,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     ts.dev.invC = (float)invC;
     ts.dev.q = q;
     ts.ccx = ccx;
+    ts.ms = ms;
     ts.ccy = ccy;
     ts.built = true;
     return GLM_OK;

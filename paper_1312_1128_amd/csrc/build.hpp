@@ -14,6 +14,14 @@ struct BuildSync {
     int32_t max_level;
     int32_t nlisted;
     int32_t internal;           // consistency flags of the build (0 = ok)
+    int32_t levcnt[kMaxLevel + 2];  // boxes per level
+    int32_t levfill[kMaxLevel + 2]; // fill counters of the per-level box index
+};
+
+// Host copy of the per-level layout of the box index.
+struct LevelTable {
+    int32_t off[kMaxLevel + 2];
+    int32_t cnt[kMaxLevel + 2];
 };
 
 // Build-side per-box arrays (preorder).
@@ -47,6 +55,7 @@ struct TreeStorage {
     int32_t* perm = nullptr;   // Morton position -> original index
     uint64_t* key = nullptr;   // sorted Morton keys
     double *ccx = nullptr, *ccy = nullptr;
+    double* ms = nullptr;      // FP64 masses in Morton order
     TreeDev dev{};
 };
 

@@ -153,28 +153,44 @@ __device__ inline uint32_t spread16(uint32_t v)
     return x;
 }
 
+// bounding box of the rays from the per-block partials
+__global__ __launch_bounds__(kBlock) void k_ray_root(const double* __restrict__ part, int nb, double* __restrict__ bb)
+{
+    __shared__ double red[4][kBlock];
+    double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        v[0] = fmin(v[0], part[b * 4 + 0]);
+        v[1] = fmax(v[1], part[b * 4 + 1]);
+        v[2] = fmin(v[2], part[b * 4 + 2]);
+        v[3] = fmax(v[3], part[b * 4 + 3]);
+    }
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+            red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][threadIdx.x + o]);
+            red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) bb[threadIdx.x] = red[threadIdx.x][0];
+}
+
 // 16-bit-per-axis Morton keys of the rays in their bounding square
 __global__ __launch_bounds__(kBlock) void k_ray_keys(const double* __restrict__ x, const double* __restrict__ y,
-                                                    int64_t n, const double* __restrict__ part, int nb,
+                                                    int64_t n, const double* __restrict__ bb,
                                                     uint32_t* __restrict__ key, uint32_t* __restrict__ val)
 {
-    __shared__ double bb[4];
-    if (threadIdx.x < 4) {
-        double v = (threadIdx.x & 1) ? -INFINITY : INFINITY;
-        for (int b = 0; b < nb; ++b) {
-            const double p = part[b * 4 + threadIdx.x];
-            v = (threadIdx.x & 1) ? fmax(v, p) : fmin(v, p);
-        }
-        bb[threadIdx.x] = v;
-    }
-    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    double ext = fmax(bb[1] - bb[0], bb[3] - bb[2]);
+    const double bx0 = bb[0], by0 = bb[2];
+    double ext = fmax(bb[1] - bx0, bb[3] - by0);
     if (!(ext > 0.0)) ext = 1.0;
     const double sc = 65535.0 / ext;
-    const uint32_t qx = (uint32_t)fmin(fmax((x[i] - bb[0]) * sc, 0.0), 65535.0);
-    const uint32_t qy = (uint32_t)fmin(fmax((y[i] - bb[2]) * sc, 0.0), 65535.0);
+    const uint32_t qx = (uint32_t)fmin(fmax((x[i] - bx0) * sc, 0.0), 65535.0);
+    const uint32_t qy = (uint32_t)fmin(fmax((y[i] - by0) * sc, 0.0), 65535.0);
     key[i] = spread16(qx) | (spread16(qy) << 1);
     val[i] = (uint32_t)i;
 }
@@ -225,7 +241,7 @@ RayLayout ray_layout(int64_t nrays)
     L.xs = a.take(8ull * nrays);
     L.ys = a.take(8ull * nrays);
     L.hist = a.take(4ull * radix_hist_words(nrays));
-    L.part = a.take(sizeof(double) * 4 * 256);
+    L.part = a.take(sizeof(double) * 4 * 257);
     L.bytes = a.size;
     return L;
 }
@@ -245,7 +261,8 @@ glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* w
     const int nbb = 256;
     const int g = ceil_div(nrays, kBlock);
     hipLaunchKernelGGL(k_ray_bbox, dim3(nbb), dim3(kBlock), 0, st, rx, ry, nrays, part);
-    hipLaunchKernelGGL(k_ray_keys, dim3(g), dim3(kBlock), 0, st, rx, ry, nrays, part, nbb, k0, v0);
+    hipLaunchKernelGGL(k_ray_root, dim3(1), dim3(kBlock), 0, st, part, nbb, part + 4 * nbb);
+    hipLaunchKernelGGL(k_ray_keys, dim3(g), dim3(kBlock), 0, st, rx, ry, nrays, part + 4 * nbb, k0, v0);
     const int w = radix_sort_u32(k0, v0, k1, v1, nrays, 4, hist, st);
     const uint32_t* perm = w ? v1 : v0;
     hipLaunchKernelGGL(k_ray_gather, dim3(g), dim3(kBlock), 0, st, perm, rx, ry, nrays, xs, ys);

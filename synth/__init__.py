@@ -35,6 +35,25 @@ def ray_grid(n: int, lo: float = -0.5, hi: float = 0.5):
     return X.ravel().copy(), Y.ravel().copy()
 
 
+def ray_grid_tiled(n: int, lo: float = -0.5, hi: float = 0.5):
+    """The same n x n cell-centred grid, listed in Z (Morton) order of the grid
+    indices -- a storage order in which every 64 consecutive rays form an 8x8
+    tile (n a power of two)."""
+    i = np.arange(n, dtype=np.uint64)
+    def spread(v):
+        v = v & np.uint64(0xFFFF)
+        v = (v | (v << np.uint64(8))) & np.uint64(0x00FF00FF)
+        v = (v | (v << np.uint64(4))) & np.uint64(0x0F0F0F0F)
+        v = (v | (v << np.uint64(2))) & np.uint64(0x33333333)
+        v = (v | (v << np.uint64(1))) & np.uint64(0x55555555)
+        return v
+    IX, IY = np.meshgrid(i, i, indexing="xy")
+    z = spread(IX.ravel()) | (spread(IY.ravel()) << np.uint64(1))
+    order = np.argsort(z, kind="stable")
+    x, y = ray_grid(n, lo, hi)
+    return x[order].copy(), y[order].copy()
+
+
 def uniform_points(n: int, seed: int, lo: float = -0.5, hi: float = 0.5):
     g = rng(seed)
     return g.uniform(lo, hi, n), g.uniform(lo, hi, n)

@@ -1,0 +1,122 @@
+"""GPU adjoint walk (glm_shoot_adjoint through the C ABI) against the CPU
+oracle: the oracle tree's FP64 adjoint on the same tree and cotangents (itself
+pinned by frozen-walk finite differences on the CPU), the FP64 brute-force
+gradient, and exact identities of the lensing sums."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import build, dev, say, shoot
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_grad(tree, rx, ry, ga):
+    import paper_1312_1128_amd as g
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(ga, dtype=np.float32)).cuda()
+    out = g.shoot_adjoint(tree, dev(rx), dev(ry), t[:, 0].contiguous(), t[:, 1].contiguous())
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in out]
+
+
+def compare(name, got, ref, rtol, scale_frac):
+    sc = np.abs(ref).max()
+    err = np.abs(got - ref)
+    bad = err > rtol * np.abs(ref) + scale_frac * sc
+    say(f"  {name}: max |err|/max|ref| {err.max() / sc:.3e}, bad {bad.sum()}")
+    assert not bad.any(), name
+
+
+def mixed_lens(n, seed):
+    lens = synth.gaussian_blobs(n, seed, s_lo=0.003, s_hi=0.3)
+    g = synth.rng(seed + 1)
+    lens.s[g.random(n) < 0.2] = 0.0
+    return lens
+
+
+@pytest.mark.parametrize("case", ["mixed_3k", "nfw_20k", "point_masses_2k"])
+def test_adjoint_matches_oracle_tree(ora, case):
+    if case == "mixed_3k":
+        lens, theta, leaf, order = mixed_lens(3000, 301), 0.5, 4, 4
+    elif case == "nfw_20k":
+        lens, theta, leaf, order = synth.nfw_halo(20000, 303), 0.3, 8, 8
+    else:
+        lens, theta, leaf, order = synth.point_masses(2000, 305), 0.5, 8, 3
+    say(f"[gpu] adjoint {case}: n={lens.n} theta={theta} p={order}")
+    rx, ry = synth.uniform_points(3000, 307)
+    ga = synth.rng(309).normal(size=(rx.size, 2)).astype(np.float32).astype(np.float64)
+    tree = build(lens, theta, leaf, order)
+    dm, dx, dy, ds = gpu_grad(tree, rx, ry, ga)
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, theta, leaf, order)
+    rm, rxg, ryg, rs = T.grad(rx, ry, ga)
+    compare("dL/dm", dm, rm, 1e-4, 2e-6)
+    compare("dL/dx", dx, rxg, 1e-4, 2e-6)
+    compare("dL/dy", dy, ryg, 1e-4, 2e-6)
+    compare("dL/ds", ds, rs, 1e-4, 2e-6)
+
+
+def test_adjoint_fitting_workload_vs_bruteforce(ora):
+    """1e5 smoothed NFW particles, 1e5 rays uniform in [-0.5, 0.5]^2; target
+    source positions beta* = x - alpha_true + N(0, 1e-4); L = sum |x - alpha -
+    beta*|^2, so dL/dalpha = -2 (x - alpha - beta*).  Tree theta = 0.3, p = 8."""
+    lens = synth.nfw_halo(100_000, synth.BASE_SEED + 5)
+    rx, ry = synth.uniform_points(100_000, synth.BASE_SEED + 6)
+    say(f"[gpu] adjoint fitting workload n={lens.n} rays={rx.size}")
+    a_true = ora.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx, ry)[:, :2]
+    noise = synth.rng(synth.BASE_SEED + 8).normal(0.0, 1e-4, size=(rx.size, 2))
+    bx, by = rx - a_true[:, 0] + noise[:, 0], ry - a_true[:, 1] + noise[:, 1]
+    tree = build(lens, 0.3, 8, 8)
+    A = shoot(tree, rx, ry)
+    ga = np.stack([-2 * (rx - A[:, 0] - bx), -2 * (ry - A[:, 1] - by)], axis=1)
+    ga = ga.astype(np.float32).astype(np.float64)
+    dm, dx, dy, ds = gpu_grad(tree, rx, ry, ga)
+    # the same tree in FP64 (decisions identical to the GPU walk)
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.3, 8, 8)
+    rm, rxg, ryg, rs = T.grad(rx, ry, ga)
+    compare("tree dL/dm", dm, rm, 1e-4, 2e-6)
+    compare("tree dL/dx", dx, rxg, 1e-4, 2e-6)
+    compare("tree dL/dy", dy, ryg, 1e-4, 2e-6)
+    compare("tree dL/ds", ds, rs, 1e-4, 2e-6)
+    # brute force: the tree's Jacobian is an approximation at the 1e-5 level
+    bm, bxg, byg, bs = ora.direct_grad(lens.x, lens.y, lens.m, lens.s, lens.q, rx, ry, ga)
+    for nm, a, b in [("m", dm, bm), ("x", dx, bxg), ("y", dy, byg), ("s", ds, bs)]:
+        e = np.abs(a - b).max() / np.abs(b).max()
+        say(f"  brute-force dL/d{nm}: max |err| / max |grad| = {e:.3e}")
+        assert e < 1e-3
+    # Euler: alpha is homogeneous of degree 1 in the masses
+    L1 = np.sum(ga[:, 0] * A[:, 0] + ga[:, 1] * A[:, 1])
+    assert abs(np.sum(lens.m * dm) - L1) <= 1e-4 * np.sum(np.abs(lens.m * dm))
+
+
+def test_adjoint_identities_and_autograd(ora):
+    import paper_1312_1128_amd as g
+    import torch
+
+    lens = mixed_lens(4000, 311)
+    rx, ry = synth.uniform_points(2000, 313)
+    say("[gpu] adjoint identities + autograd")
+    ga = synth.rng(315).normal(size=(rx.size, 2)).astype(np.float32).astype(np.float64)
+    tree = build(lens, 0.5, 8, 5)
+    B = shoot(tree, rx, ry)
+    dm, dx, dy, ds = gpu_grad(tree, rx, ry, ga)
+    L1 = np.sum(ga[:, 0] * B[:, 0] + ga[:, 1] * B[:, 1])
+    assert abs(np.sum(lens.m * dm) - L1) <= 1e-4 * np.sum(np.abs(lens.m * dm))
+    k, g1, g2 = B[:, 2], B[:, 3], B[:, 4]
+    tx = -np.sum((k + g1) * ga[:, 0] + g2 * ga[:, 1])
+    ty = -np.sum(g2 * ga[:, 0] + (k - g1) * ga[:, 1])
+    sc = np.sum(np.abs(dx)) + np.sum(np.abs(dy))
+    assert abs(np.sum(dx) - tx) <= 1e-4 * sc and abs(np.sum(dy) - ty) <= 1e-4 * sc
+    # the autograd wrapper gives the same gradient
+    m_t = dev(lens.m).requires_grad_(True)
+    x_t = dev(lens.x).requires_grad_(True)
+    y_t = dev(lens.y).requires_grad_(True)
+    s_t = dev(lens.s).requires_grad_(True)
+    a1, a2 = g.ShootFn.apply(dev(rx), dev(ry), m_t, x_t, y_t, s_t,
+                             dict(theta=0.5, q=lens.q, leaf_size=8, order=5))
+    gt = torch.from_numpy(ga.astype(np.float32)).cuda()
+    (a1 * gt[:, 0] + a2 * gt[:, 1]).sum().backward()
+    np.testing.assert_allclose(m_t.grad.cpu().numpy(), dm, rtol=1e-6, atol=1e-9 * np.abs(dm).max())
+    np.testing.assert_allclose(x_t.grad.cpu().numpy(), dx, rtol=1e-6, atol=1e-9 * np.abs(dx).max())
+    np.testing.assert_allclose(s_t.grad.cpu().numpy(), ds, rtol=1e-6, atol=1e-9 * np.abs(ds).max())
