@@ -173,6 +173,58 @@ def main():
     fa_ms = 1e3 * (time.perf_counter() - t) / n5
     log(f"fwd+adjoint (1e5 particles, 1e5 rays): {fa_ms:.3f} ms -> {rx5.numel() / (fa_ms * 1e-3):.4e} rays/s")
 
+    # microlensing refinement: halo + 1e5 stars, 256^2 base cells over the star
+    # patch, 6 rounds refining the top 10% by 3x3, all rounds in one HIP graph
+    lens3, cx3, cy3, side3 = synth.workload_microlensing()
+    x3, y3, m3, s3 = d(lens3.x), d(lens3.y), d(lens3.m), d(lens3.s)
+    tree3 = g.Tree().build(x3, y3, m3, s3, theta=THETA, q=lens3.q, leaf_size=LEAF, order=ORDER)
+    run3 = g.RefinementRun(tree3, d(cx3), d(cy3), d(side3), g.refine_schedule(cx3.size))
+    n3 = run3.run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        run3.run()
+    torch.cuda.synchronize()
+    eager3 = (time.perf_counter() - t) / 3
+    graph3 = run3.capture()
+    graph3.replay()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        graph3.replay()
+    torch.cuda.synchronize()
+    graph3_s = (time.perf_counter() - t) / 3
+    log(f"refinement (6 rounds, {n3} rays): graph {1e3 * graph3_s:.2f} ms, eager {1e3 * eager3:.2f} ms "
+        f"-> {n3 / graph3_s:.4e} rays/s")
+
+    # 64 independent lenses in one persistent launch
+    lenses4 = synth.workload_batched_lenses(64)
+    trees4, rays4 = [], []
+    for l4, r4x, r4y in lenses4:
+        trees4.append(g.Tree().build(d(l4.x), d(l4.y), d(l4.m), d(l4.s), theta=THETA, q=l4.q, leaf_size=LEAF,
+                                     order=ORDER))
+        rays4.append((d(r4x), d(r4y)))
+    R4 = sum(r[0].numel() for r in rays4)
+    outs4 = [{k: torch.empty(r[0].numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2", "kappa", "g1", "g2"]}
+             for r in rays4]
+    ws4 = torch.empty(g.batch.batched_workspace_bytes([r[0].numel() for r in rays4]), dtype=torch.uint8, device=dev)
+    g.shoot_batched(trees4, rays4, outs=outs4, workspace=ws4)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        g.shoot_batched(trees4, rays4, outs=outs4, workspace=ws4)
+    torch.cuda.synchronize()
+    b4 = (time.perf_counter() - t) / 3
+    ws4b = torch.empty(g.workspace_bytes(max(r[0].numel() for r in rays4)), dtype=torch.uint8, device=dev)
+    t = time.perf_counter()
+    for _ in range(3):
+        for tr, (r4x, r4y), o4 in zip(trees4, rays4, outs4):
+            g.shoot(tr, r4x, r4y, out=o4, workspace=ws4b)
+    torch.cuda.synchronize()
+    l4 = (time.perf_counter() - t) / 3
+    log(f"64 lenses ({R4} rays): one persistent launch {1e3 * b4:.2f} ms ({R4 / b4:.4e} rays/s), "
+        f"per-lens launches {1e3 * l4:.2f} ms")
+
     line = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -187,7 +239,12 @@ def main():
                    "counts_per_ray": dict(zip(["visited", "accepted", "leaf", "list_hits"], cnt.mean(0).tolist())),
                    "direct_fp32_rays_per_s": res[False], "direct_fp64_rays_per_s": res[True],
                    "fwd_adjoint_rays_per_s": rx5.numel() / (fa_ms * 1e-3), "fwd_adjoint_ms": fa_ms,
-                   "fwd_adjoint_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2"},
+                   "fwd_adjoint_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2",
+                   "refinement_rays": n3, "refinement_graph_ms": 1e3 * graph3_s, "refinement_eager_ms": 1e3 * eager3,
+                   "refinement_rays_per_s": n3 / graph3_s,
+                   "refinement_workload": "nfw_1e6 + 1e5 Salpeter stars, 256^2 base, 6 rounds top-10% 3x3",
+                   "batched_lenses": len(lenses4), "batched_rays": R4, "batched_ms": 1e3 * b4,
+                   "batched_rays_per_s": R4 / b4, "per_lens_launches_ms": 1e3 * l4},
     }
 
     if not args.no_cpu:

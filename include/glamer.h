@@ -180,6 +180,55 @@ GLM_API glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const 
                              double* dx, double* dy, double* ds, uint32_t flags, void* workspace,
                              size_t workspace_bytes, void* stream);
 
+/* One lens of a batched walk. */
+typedef struct {
+    const glm_tree* tree; /* built tree; every tree of a batch has the same order */
+    const double* rx;     /* device FP64 ray positions, nrays each */
+    const double* ry;
+    int64_t nrays;        /* >= 0 */
+    float* a1;            /* device FP32 outputs, input order; kappa/g1/g2 NULL with GLM_ALPHA_ONLY */
+    float* a2;
+    float* kappa;
+    float* g1;
+    float* g2;
+} glm_lens_rays;
+
+/* Bytes of device workspace for a batch with these ray counts (host array). */
+GLM_API glm_status glm_shoot_batched_workspace_bytes(const int64_t* nrays, int nlens, size_t* bytes);
+
+/*
+ * Walk many independent lenses in ONE persistent launch (Sec. 3.3: the solver
+ * parallelises over points, and bigger batches are more efficient): the rays
+ * of every lens are Morton-sorted within their lens, cut into 64-ray groups,
+ * and the wavefronts of one launch take (lens, group) items from a device
+ * counter, lenses with the most expected work (rays x log2 particles) first.
+ * Results equal glm_shoot per lens.  `lenses` is a HOST array of nlens
+ * entries.  Copies the small lens table host->device (not graph-capturable).
+ */
+GLM_API glm_status glm_shoot_batched(const glm_lens_rays* lenses, int nlens, uint32_t flags,
+                                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Bytes of device workspace for glm_refine_round on ncells cells. */
+GLM_API glm_status glm_refine_workspace_bytes(int64_t ncells, size_t* bytes);
+
+/*
+ * One adaptive refinement round of a grid of square cells (Sec. 4: a cell is
+ * refined by adding rays around its already shot centre ray, 3 x 3).
+ *   cx, cy, side: device FP64 cell centres and sides, capacity >= ncells + 8 nrefine;
+ *   kappa, g1, g2: device FP32 shot outputs of the ncells cells;
+ * The nrefine cells with the largest side^2 (kappa^2 + g1^2 + g2^2) (ties: lower
+ * index first) are split: their side becomes side/3 and 8 cells of side/3 are
+ * appended at [ncells, ncells + 8 nrefine), 8 per refined cell in row order
+ * (dy = -1, 0, 1; dx = -1, 0, 1; centre skipped).  The appended centres are
+ * the new rays to shoot.  refined (device int32, nrefine, nullable) receives
+ * the refined cells in rank order.  No host synchronisation, no memset:
+ * capturable in a HIP graph.
+ */
+GLM_API glm_status glm_refine_round(double* cx, double* cy, double* side, const float* kappa,
+                                    const float* g1, const float* g2, int64_t ncells, int64_t nrefine,
+                                    int32_t* refined, void* workspace, size_t workspace_bytes,
+                                    void* stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 GLM_API const char* glm_last_error(void);
 

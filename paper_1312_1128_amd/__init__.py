@@ -18,7 +18,8 @@ from ._capi import (GLM_ALPHA_ONLY, GLM_NO_KAHAN, GLM_RAYS_ORDERED, GlamerError,
                     GlmTreeInfo)
 
 __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
-           "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes"]
+           "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
+           "refine_schedule", "RefinementRun", "autotune"]
 
 
 def _ptr(t):
@@ -189,3 +190,6 @@ class ShootFn(torch.autograd.Function):
         rx, ry = ctx.saved_tensors
         dm, dx, dy, ds = shoot_adjoint(ctx.tree, rx, ry, g1, g2)
         return None, None, dm, dx, dy, (ds if ctx.has_s else None), None
+
+
+from .batch import RefinementRun, autotune, refine_round, refine_schedule, shoot_batched  # noqa: E402

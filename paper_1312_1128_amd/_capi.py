@@ -22,7 +22,8 @@ GLM_RAYS_ORDERED = 4
 EXPORTED = [
     "glm_tree_create", "glm_tree_destroy", "glm_build_tree", "glm_tree_get_info", "glm_tree_export",
     "glm_shoot_workspace_bytes", "glm_shoot", "glm_shoot_direct", "glm_shoot_adjoint",
-    "glm_last_error", "glm_version",
+    "glm_last_error", "glm_version", "glm_shoot_batched_workspace_bytes", "glm_shoot_batched",
+    "glm_refine_workspace_bytes", "glm_refine_round",
 ]
 
 
@@ -37,6 +38,12 @@ class GlmTreeInfo(ctypes.Structure):
                 ("check_flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("root_x0", ctypes.c_double), ("root_y0", ctypes.c_double), ("root_side", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t)]
+
+
+class GlmLensRays(ctypes.Structure):
+    _fields_ = [("tree", ctypes.c_void_p), ("rx", ctypes.c_void_p), ("ry", ctypes.c_void_p),
+                ("nrays", ctypes.c_int64), ("a1", ctypes.c_void_p), ("a2", ctypes.c_void_p),
+                ("kappa", ctypes.c_void_p), ("g1", ctypes.c_void_p), ("g2", ctypes.c_void_p)]
 
 
 class GlamerError(RuntimeError):
@@ -79,6 +86,14 @@ def load(path: str = LIB_PATH):
     lib.glm_shoot_direct.restype = st
     lib.glm_shoot_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp]
     lib.glm_shoot_adjoint.restype = st
+    lib.glm_shoot_batched_workspace_bytes.argtypes = [P(ctypes.c_int64), i32, P(ctypes.c_size_t)]
+    lib.glm_shoot_batched_workspace_bytes.restype = st
+    lib.glm_shoot_batched.argtypes = [P(GlmLensRays), i32, u32, vp, ctypes.c_size_t, vp]
+    lib.glm_shoot_batched.restype = st
+    lib.glm_refine_workspace_bytes.argtypes = [i64, P(ctypes.c_size_t)]
+    lib.glm_refine_workspace_bytes.restype = st
+    lib.glm_refine_round.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, vp, vp, ctypes.c_size_t, vp]
+    lib.glm_refine_round.restype = st
     lib.glm_last_error.argtypes = []
     lib.glm_last_error.restype = ctypes.c_char_p
     lib.glm_version.argtypes = []

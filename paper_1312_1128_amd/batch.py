@@ -1,0 +1,187 @@
+"""Batched walks, device-side refinement rounds (graph-capturable) and the
+parameter autotuner.  Argument marshalling over the C ABI; the work runs in
+the library's kernels."""
+from __future__ import annotations
+
+import ctypes
+import math
+import time
+
+import torch
+
+from . import _capi
+from ._capi import GLM_ALPHA_ONLY, GlmLensRays
+
+
+def _ptr(t):
+    return t.data_ptr() if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def batched_workspace_bytes(nrays) -> int:
+    lib = _capi.load()
+    arr = (ctypes.c_int64 * len(nrays))(*[int(n) for n in nrays])
+    b = ctypes.c_size_t(0)
+    _capi.check(lib.glm_shoot_batched_workspace_bytes(arr, len(nrays), ctypes.byref(b)))
+    return int(b.value)
+
+
+def shoot_batched(trees, rays, alpha_only: bool = False, outs=None, workspace=None):
+    """Walk len(trees) lenses in one persistent launch.  rays: list of (rx, ry)
+    float64 CUDA tensors.  Returns a list of output dicts (float32)."""
+    n = len(trees)
+    assert len(rays) == n and n > 0
+    dev = rays[0][0].device
+    names = ["a1", "a2"] if alpha_only else ["a1", "a2", "kappa", "g1", "g2"]
+    if outs is None:
+        outs = [{k: torch.empty(r[0].numel(), dtype=torch.float32, device=dev) for k in names} for r in rays]
+    ents = (GlmLensRays * n)()
+    for i, (t, (rx, ry), o) in enumerate(zip(trees, rays, outs)):
+        assert rx.dtype == torch.float64 and rx.is_contiguous() and ry.is_contiguous()
+        ents[i] = GlmLensRays(t.handle.value, _ptr(rx), _ptr(ry), rx.numel(), _ptr(o["a1"]), _ptr(o["a2"]),
+                              _ptr(o.get("kappa")), _ptr(o.get("g1")), _ptr(o.get("g2")))
+    if workspace is None:
+        workspace = torch.empty(max(batched_workspace_bytes([r[0].numel() for r in rays]), 1), dtype=torch.uint8,
+                                device=dev)
+    lib = _capi.load()
+    _capi.check(lib.glm_shoot_batched(ents, n, GLM_ALPHA_ONLY if alpha_only else 0, ctypes.c_void_p(_ptr(workspace)),
+                                      workspace.numel(), _stream()))
+    return outs
+
+
+def refine_workspace_bytes(ncells: int) -> int:
+    lib = _capi.load()
+    b = ctypes.c_size_t(0)
+    _capi.check(lib.glm_refine_workspace_bytes(int(ncells), ctypes.byref(b)))
+    return int(b.value)
+
+
+def refine_round(cx, cy, side, kappa, g1, g2, ncells: int, nrefine: int, refined=None, workspace=None):
+    """One 3x3 refinement round of the nrefine highest-ranked cells (in place;
+    8 new cells appended at [ncells, ncells + 8 nrefine))."""
+    if workspace is None:
+        workspace = torch.empty(max(refine_workspace_bytes(ncells), 1), dtype=torch.uint8, device=cx.device)
+    lib = _capi.load()
+    _capi.check(lib.glm_refine_round(ctypes.c_void_p(_ptr(cx)), ctypes.c_void_p(_ptr(cy)), ctypes.c_void_p(_ptr(side)),
+                                     ctypes.c_void_p(_ptr(kappa)), ctypes.c_void_p(_ptr(g1)), ctypes.c_void_p(_ptr(g2)),
+                                     int(ncells), int(nrefine), ctypes.c_void_p(_ptr(refined)),
+                                     ctypes.c_void_p(_ptr(workspace)), workspace.numel(), _stream()))
+
+
+def refine_schedule(n0: int, rounds: int = 6, frac: float = 0.1, max_new_rays: int = 600_000):
+    """Cells refined per round: floor(frac * cells), with 8 new rays per refined
+    cell capped at max_new_rays."""
+    out, n = [], n0
+    for _ in range(rounds):
+        k = min(int(math.floor(frac * n)), max_new_rays // 8)
+        out.append(k)
+        n += 8 * k
+    return out
+
+
+class RefinementRun:
+    """A base grid of square cells on one tree, then refinement rounds, each
+    shooting its 8 new rays per refined cell.  Buffers have fixed capacity, so
+    run() can be captured once in a HIP graph (capture()) and replayed."""
+
+    def __init__(self, tree, cx0, cy0, side0, schedule):
+        from . import shoot, workspace_bytes
+
+        self._shoot = shoot
+        self.tree = tree
+        self.schedule = list(schedule)
+        self.n0 = cx0.numel()
+        self.cap = self.n0 + 8 * sum(self.schedule)
+        dev = cx0.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.cx = torch.zeros(self.cap, **f64)
+        self.cy = torch.zeros(self.cap, **f64)
+        self.side = torch.zeros(self.cap, **f64)
+        self.base = (cx0.clone(), cy0.clone(), side0.clone())
+        self.out = {k: torch.zeros(self.cap, **f32) for k in ["a1", "a2", "kappa", "g1", "g2"]}
+        self.refined = torch.zeros(max(self.schedule + [1]), dtype=torch.int32, device=dev)
+        new_max = max([self.n0] + [8 * k for k in self.schedule])
+        self.ws_shoot = torch.empty(workspace_bytes(new_max), dtype=torch.uint8, device=dev)
+        self.ws_refine = torch.empty(max(refine_workspace_bytes(self.cap), 1), dtype=torch.uint8, device=dev)
+        self.sizes = [self.n0] + [8 * k for k in self.schedule]
+
+    def _shoot_range(self, a, b):
+        o = {k: v[a:b] for k, v in self.out.items()}
+        self._shoot(self.tree, self.cx[a:b], self.cy[a:b], out=o, workspace=self.ws_shoot)
+
+    def run(self):
+        bx, by, bs = self.base
+        self.cx[: self.n0].copy_(bx)
+        self.cy[: self.n0].copy_(by)
+        self.side[: self.n0].copy_(bs)
+        self._shoot_range(0, self.n0)
+        n = self.n0
+        for k in self.schedule:
+            refine_round(self.cx, self.cy, self.side, self.out["kappa"], self.out["g1"], self.out["g2"], n, k,
+                         refined=self.refined, workspace=self.ws_refine)
+            self._shoot_range(n, n + 8 * k)
+            n += 8 * k
+        return n
+
+    def capture(self):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        return g
+
+
+def autotune(x, y, m, s, rx, ry, q: float = 3.0, tol: float = 1e-4, thetas=(0.2, 0.3, 0.4, 0.5),
+             orders=(4, 6, 8, 10), leaves=(4, 8, 16), sample: int = 512, reps: int = 3, seed: int = 0):
+    """Pick (theta, order, leaf size) for one lens: the fastest build + walk
+    whose max fractional error of alpha, kappa and gamma on a seeded ray sample
+    stays below `tol` against the library's FP64 direct sum on the GPU.  The
+    walk group is one wavefront (64 rays) by construction.  Returns (best, table)."""
+    from . import Tree, shoot, shoot_direct, workspace_bytes
+
+    R = rx.numel()
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    idx = torch.randperm(R, generator=gen)[: min(sample, R)].to(rx.device)
+    sx, sy = rx[idx].contiguous(), ry[idx].contiguous()
+    ref = shoot_direct(x, y, m, s, q, sx, sy, fp64=True)
+    ra = torch.stack([ref["a1"], ref["a2"]], 1)
+    rg = torch.stack([ref["g1"], ref["g2"]], 1)
+    rk = ref["kappa"]
+    ws = torch.empty(workspace_bytes(R), dtype=torch.uint8, device=rx.device)
+    out = {k: torch.empty(R, dtype=torch.float32, device=rx.device) for k in ["a1", "a2", "kappa", "g1", "g2"]}
+    table = []
+    best = None
+    for L in leaves:
+        for th in thetas:
+            for p in orders:
+                tree = Tree().build(x, y, m, s, theta=th, q=q, leaf_size=L, order=p)
+                o = shoot(tree, sx, sy)
+                ea = ((torch.stack([o["a1"], o["a2"]], 1).double() - ra).norm(dim=1) / ra.norm(dim=1)).max().item()
+                eg = ((torch.stack([o["g1"], o["g2"]], 1).double() - rg).norm(dim=1) / rg.norm(dim=1)).max().item()
+                nz = rk != 0
+                ek = ((o["kappa"].double() - rk).abs()[nz] / rk.abs()[nz]).max().item() if bool(nz.any()) else 0.0
+                ok = max(ea, eg, ek) <= tol
+                ms = float("nan")
+                if ok:
+                    torch.cuda.synchronize()
+                    ts = []
+                    for _ in range(reps):
+                        t0 = time.perf_counter()
+                        tree.build(x, y, m, s, theta=th, q=q, leaf_size=L, order=p)
+                        shoot(tree, rx, ry, out=out, workspace=ws)
+                        torch.cuda.synchronize()
+                        ts.append(time.perf_counter() - t0)
+                    ms = 1e3 * sorted(ts)[len(ts) // 2]
+                    if best is None or ms < best["ms"]:
+                        best = dict(theta=th, order=p, leaf_size=L, ms=ms, err=max(ea, eg, ek))
+                table.append(dict(theta=th, order=p, leaf_size=L, err_alpha=ea, err_kappa=ek, err_gamma=eg, ok=ok, ms=ms))
+    return best, table

@@ -3,7 +3,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -221,6 +223,85 @@ glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* 
     }
     return adjoint_device(const_cast<glm_tree*>(t)->ts, rx, ry, nrays, ga1, ga2, dm, dx, dy, ds, flags, workspace,
                           static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_shoot_batched_workspace_bytes(const int64_t* nrays, int nlens, size_t* bytes)
+{
+    if (!nrays || !bytes || nlens < 1 || nlens > 4096) return fail(GLM_EINVAL, "bad argument");
+    int64_t total = 0;
+    for (int l = 0; l < nlens; ++l) {
+        if (nrays[l] < 0) return fail(GLM_EINVAL, "negative ray count");
+        total += nrays[l];
+    }
+    if (total > 0x7fffff00) return fail(GLM_EINVAL, "too many rays in one batch");
+    *bytes = batch_workspace_bytes(nlens, total);
+    return GLM_OK;
+}
+
+glm_status glm_shoot_batched(const glm_lens_rays* lenses, int nlens, uint32_t flags, void* workspace,
+                             size_t workspace_bytes, void* stream)
+{
+    if (!lenses || nlens < 1 || nlens > 4096) return fail(GLM_EINVAL, "lenses must hold 1..4096 entries");
+    if (flags & ~(GLM_ALPHA_ONLY | GLM_NO_KAHAN)) return fail(GLM_EINVAL, "unknown flag bits");
+    std::vector<int64_t> counts(nlens);
+    std::vector<std::pair<double, int>> rank(nlens);
+    int order = -1;
+    int64_t total = 0;
+    for (int l = 0; l < nlens; ++l) {
+        const glm_lens_rays& e = lenses[l];
+        if (!e.tree || !e.tree->ts.built) return fail(GLM_ESTATE, "lens " + std::to_string(l) + ": tree not built");
+        if (e.nrays < 0) return fail(GLM_EINVAL, "lens " + std::to_string(l) + ": negative ray count");
+        if (e.nrays > 0 && (!e.rx || !e.ry || !e.a1 || !e.a2))
+            return fail(GLM_EINVAL, "lens " + std::to_string(l) + ": NULL ray or output pointer");
+        if (e.nrays > 0 && !(flags & GLM_ALPHA_ONLY) && (!e.kappa || !e.g1 || !e.g2))
+            return fail(GLM_EINVAL, "lens " + std::to_string(l) + ": kappa, g1, g2 required unless GLM_ALPHA_ONLY");
+        const int p = e.tree->ts.params.order;
+        if (order >= 0 && p != order) return fail(GLM_EINVAL, "all trees of a batch must have the same order");
+        order = p;
+        counts[l] = e.nrays;
+        total += e.nrays;
+        rank[l] = {-(double)e.nrays * log2((double)e.tree->ts.n + 1.0), l};
+    }
+    if (total > 0x7fffff00) return fail(GLM_EINVAL, "too many rays in one batch");
+    const size_t need = batch_workspace_bytes(nlens, total);
+    if (!workspace || workspace_bytes < need)
+        return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_batched_workspace_bytes = " + std::to_string(need));
+    std::stable_sort(rank.begin(), rank.end());
+    std::vector<BatchLens> tab(nlens);
+    for (int r = 0; r < nlens; ++r) {
+        const glm_lens_rays& e = lenses[rank[r].second];
+        BatchLens& b = tab[r];
+        b.tree = e.tree->ts.dev;
+        b.nrays = e.nrays;
+        b.ray_off = 0;
+        b.rx = e.rx;
+        b.ry = e.ry;
+        b.out = WalkOut{e.a1, e.a2, (flags & GLM_ALPHA_ONLY) ? nullptr : e.kappa,
+                        (flags & GLM_ALPHA_ONLY) ? nullptr : e.g1, (flags & GLM_ALPHA_ONLY) ? nullptr : e.g2, nullptr};
+    }
+    return shoot_batched_device(tab.data(), nlens, order, flags, workspace, static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_refine_workspace_bytes(int64_t ncells, size_t* bytes)
+{
+    if (!bytes || ncells < 0 || ncells > 0x7fffff00) return fail(GLM_EINVAL, "bad argument");
+    *bytes = refine_workspace_bytes(ncells);
+    return GLM_OK;
+}
+
+glm_status glm_refine_round(double* cx, double* cy, double* side, const float* kappa, const float* g1, const float* g2,
+                            int64_t ncells, int64_t nrefine, int32_t* refined, void* workspace, size_t workspace_bytes,
+                            void* stream)
+{
+    if (!cx || !cy || !side || !kappa || !g1 || !g2) return fail(GLM_EINVAL, "NULL device pointer");
+    if (ncells < 1 || ncells > 0x7fffff00) return fail(GLM_EINVAL, "ncells out of range");
+    if (nrefine < 0 || nrefine > ncells) return fail(GLM_EINVAL, "nrefine must be in 0..ncells");
+    if (ncells + 8 * nrefine > 0x7fffff00) return fail(GLM_EINVAL, "too many cells");
+    const size_t need = refine_workspace_bytes(ncells);
+    if (!workspace || workspace_bytes < need)
+        return fail(GLM_ENOMEM, "workspace smaller than glm_refine_workspace_bytes = " + std::to_string(need));
+    return refine_round_device(cx, cy, side, kappa, g1, g2, ncells, nrefine, refined, workspace,
+                               static_cast<hipStream_t>(stream));
 }
 
 } // extern "C"

@@ -15,6 +15,9 @@
 // compensated (Kahan) summation.
 #include <math.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "eval.hpp"
 #include "walk.hpp"
 
@@ -22,23 +25,14 @@ namespace glm {
 
 namespace {
 
+// The traversal of one 64-ray group (see the file comment).  Every lane of
+// the wave must call it; `valid` lanes carry a ray.
 template <int P, bool AONLY>
-__global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __restrict__ rxs,
-                                                const double* __restrict__ rys, const uint32_t* __restrict__ rperm,
-                                                int64_t nrays, float* __restrict__ o_a1, float* __restrict__ o_a2,
-                                                float* __restrict__ o_k, float* __restrict__ o_g1,
-                                                float* __restrict__ o_g2, int32_t* __restrict__ counts, int kahan_i)
+__device__ inline void walk_group(const TreeDev& T, double X, double Y, bool valid, int lane, bool kahan, Acc& A,
+                                  int cnt[4])
 {
-    const bool kahan = kahan_i != 0;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t r = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const bool valid = r < nrays;
-    if (!__any(valid)) return;
-    const double X = valid ? rxs[r] : 0.0, Y = valid ? rys[r] : 0.0;
     const double gx0 = wave_min(valid ? X : INFINITY), gx1 = wave_max(valid ? X : -INFINITY);
     const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
-
-    Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
     int n_vis = 0, n_acc = 0, n_dir = 0, n_hit = 0;
     int skip = valid ? 0 : 0x7fffffff;
     const int nc = T.ncells;
@@ -94,21 +88,79 @@ __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __rest
             cur = h.next > cur ? h.next : cur + 1; // preorder: the subtree ends after cur
         }
     }
-    if (!valid) return;
-    const int64_t o = rperm ? (int64_t)rperm[r] : r;
+    cnt[0] = n_vis;
+    cnt[1] = n_acc;
+    cnt[2] = n_dir;
+    cnt[3] = n_hit;
+}
+
+template <bool AONLY>
+__device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, const WalkOut& out)
+{
     // fold the FP64 balance of the big-particle point terms into the result
-    o_a1[o] = (float)((double)A.a1 + A.b1);
-    o_a2[o] = (float)((double)A.a2 + A.b2);
+    out.a1[o] = (float)((double)A.a1 + A.b1);
+    out.a2[o] = (float)((double)A.a2 + A.b2);
     if (!AONLY) {
-        if (o_k) o_k[o] = A.k;
-        if (o_g1) o_g1[o] = (float)((double)A.g1 + A.bg1);
-        if (o_g2) o_g2[o] = (float)((double)A.g2 + A.bg2);
+        if (out.k) out.k[o] = A.k;
+        if (out.g1) out.g1[o] = (float)((double)A.g1 + A.bg1);
+        if (out.g2) out.g2[o] = (float)((double)A.g2 + A.bg2);
     }
-    if (counts) {
-        counts[4 * o + 0] = n_vis;
-        counts[4 * o + 1] = n_acc;
-        counts[4 * o + 2] = n_dir;
-        counts[4 * o + 3] = n_hit;
+    if (out.counts) {
+        out.counts[4 * o + 0] = cnt[0];
+        out.counts[4 * o + 1] = cnt[1];
+        out.counts[4 * o + 2] = cnt[2];
+        out.counts[4 * o + 3] = cnt[3];
+    }
+}
+
+template <int P, bool AONLY>
+__global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __restrict__ rxs,
+                                                const double* __restrict__ rys, const uint32_t* __restrict__ rperm,
+                                                int64_t nrays, WalkOut out, int kahan_i)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t r = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const bool valid = r < nrays;
+    if (!__any(valid)) return;
+    const double X = valid ? rxs[r] : 0.0, Y = valid ? rys[r] : 0.0;
+    Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+    int cnt[4];
+    walk_group<P, AONLY>(T, X, Y, valid, lane, kahan_i != 0, A, cnt);
+    if (!valid) return;
+    write_out<AONLY>(A, cnt, rperm ? (int64_t)rperm[r] : r, out);
+}
+
+// Persistent walk over many lenses: every wavefront takes (lens, 64-ray group)
+// items from a device counter until the queue is empty.  Lenses are ranked by
+// estimated cost, so the largest ray groups start first.
+template <int P, bool AONLY>
+__global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __restrict__ lenses, int nlens,
+                                                        const int64_t* __restrict__ gprefix, int* __restrict__ counter,
+                                                        const double* __restrict__ xs, const double* __restrict__ ys,
+                                                        const uint32_t* __restrict__ perm, int kahan_i)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t total = gprefix[nlens];
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(counter, 1);
+        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, kWave));
+        if (it >= total) break;
+        int lo = 0, hi = nlens; // largest l with gprefix[l] <= it
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (gprefix[mid] <= it) lo = mid;
+            else hi = mid;
+        }
+        const BatchLens& L = lenses[lo];
+        const int64_t rl = (int64_t)(it - gprefix[lo]) * kWave + lane;
+        const bool valid = rl < L.nrays;
+        const int64_t gi = L.ray_off + (valid ? rl : 0);
+        const double X = valid ? xs[gi] : 0.0, Y = valid ? ys[gi] : 0.0;
+        Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+        int cnt[4];
+        walk_group<P, AONLY>(L.tree, X, Y, valid, lane, kahan_i != 0, A, cnt);
+        if (valid) write_out<AONLY>(A, cnt, (int64_t)perm[gi] - L.ray_off, L.out);
     }
 }
 
@@ -207,19 +259,18 @@ __global__ __launch_bounds__(kBlock) void k_ray_gather(const uint32_t* __restric
 
 template <int P, bool AONLY>
 void launch_walk(const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm, int64_t nrays,
-                 float* a1, float* a2, float* k, float* g1, float* g2, int32_t* counts, int kahan, hipStream_t st)
+                 const WalkOut& out, int kahan, hipStream_t st)
 {
     hipLaunchKernelGGL((k_walk<P, AONLY>), dim3(ceil_div(nrays, kBlock)), dim3(kBlock), 0, st, T, rxs, rys, rperm,
-                       nrays, a1, a2, k, g1, g2, counts, kahan);
+                       nrays, out, kahan);
 }
 
 template <bool AONLY>
 void dispatch_walk(int p, const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm,
-                   int64_t nrays, float* a1, float* a2, float* k, float* g1, float* g2, int32_t* counts, int kahan,
-                   hipStream_t st)
+                   int64_t nrays, const WalkOut& out, int kahan, hipStream_t st)
 {
 #define GLM_CASE(PP) \
-    case PP: launch_walk<PP, AONLY>(T, rxs, rys, rperm, nrays, a1, a2, k, g1, g2, counts, kahan, st); break;
+    case PP: launch_walk<PP, AONLY>(T, rxs, rys, rperm, nrays, out, kahan, st); break;
     switch (p) {
         GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
         GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
@@ -273,6 +324,182 @@ glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* w
     return GLM_OK;
 }
 
+// ------------------------------------------------------------ batched walk
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_batch_bbox(const BatchLens* __restrict__ lenses, double* __restrict__ bb)
+{
+    __shared__ double red[4][kBlock];
+    const BatchLens& L = lenses[blockIdx.x];
+    double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int64_t i = threadIdx.x; i < L.nrays; i += kBlock) {
+        const double x = L.rx[i], y = L.ry[i];
+        v[0] = fmin(v[0], x);
+        v[1] = fmax(v[1], x);
+        v[2] = fmin(v[2], y);
+        v[3] = fmax(v[3], y);
+    }
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+            red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][threadIdx.x + o]);
+            red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) bb[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__device__ inline int find_lens(const int64_t* __restrict__ roff, int nlens, int64_t gi)
+{
+    int lo = 0, hi = nlens;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (roff[mid] <= gi) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// key = lens rank << 32 | 16-bit-per-axis Morton code in the lens's ray box
+__global__ __launch_bounds__(kBlock) void k_batch_keys(const BatchLens* __restrict__ lenses, int nlens,
+                                                      const int64_t* __restrict__ roff, const double* __restrict__ bb,
+                                                      int64_t total, uint64_t* __restrict__ key,
+                                                      uint32_t* __restrict__ val)
+{
+    const int64_t gi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gi >= total) return;
+    const int l = find_lens(roff, nlens, gi);
+    const int64_t i = gi - roff[l];
+    const double bx0 = bb[4 * l], by0 = bb[4 * l + 2];
+    double ext = fmax(bb[4 * l + 1] - bx0, bb[4 * l + 3] - by0);
+    if (!(ext > 0.0)) ext = 1.0;
+    const double sc = 65535.0 / ext;
+    const uint32_t qx = (uint32_t)fmin(fmax((lenses[l].rx[i] - bx0) * sc, 0.0), 65535.0);
+    const uint32_t qy = (uint32_t)fmin(fmax((lenses[l].ry[i] - by0) * sc, 0.0), 65535.0);
+    key[gi] = ((uint64_t)l << 32) | (uint64_t)(spread16(qx) | (spread16(qy) << 1));
+    val[gi] = (uint32_t)gi;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchLens* __restrict__ lenses,
+                                                        const int64_t* __restrict__ roff,
+                                                        const uint64_t* __restrict__ key,
+                                                        const uint32_t* __restrict__ val, int64_t total,
+                                                        double* __restrict__ xs, double* __restrict__ ys)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= total) return;
+    const int l = (int)(key[k] >> 32);
+    const int64_t i = (int64_t)val[k] - roff[l];
+    xs[k] = lenses[l].rx[i];
+    ys[k] = lenses[l].ry[i];
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+struct BatchLayout {
+    size_t table, roff, gpre, bb, counter, k0, k1, v0, v1, xs, ys, hist, bytes;
+};
+
+BatchLayout batch_layout(int nlens, int64_t total)
+{
+    BatchLayout B;
+    Arena a;
+    B.table = a.take(sizeof(BatchLens) * (size_t)nlens);
+    B.roff = a.take(8ull * (nlens + 1));
+    B.gpre = a.take(8ull * (nlens + 1));
+    B.bb = a.take(32ull * nlens);
+    B.counter = a.take(64);
+    B.k0 = a.take(8ull * total);
+    B.k1 = a.take(8ull * total);
+    B.v0 = a.take(4ull * total);
+    B.v1 = a.take(4ull * total);
+    B.xs = a.take(8ull * total);
+    B.ys = a.take(8ull * total);
+    B.hist = a.take(4ull * radix_hist_words(total));
+    B.bytes = a.size;
+    return B;
+}
+
+template <int P, bool AONLY>
+void launch_batched(const BatchLens* table, int nlens, const int64_t* gpre, int* counter, const double* xs,
+                    const double* ys, const uint32_t* perm, int64_t items, int kahan, hipStream_t st)
+{
+    const int blocks = (int)std::min<int64_t>((items + 3) / 4, 256 * 8);
+    hipLaunchKernelGGL((k_walk_batched<P, AONLY>), dim3(blocks), dim3(kBlock), 0, st, table, nlens, gpre, counter, xs,
+                       ys, perm, kahan);
+}
+
+} // namespace
+
+size_t batch_workspace_bytes(int nlens, int64_t total) { return batch_layout(nlens, total).bytes; }
+
+glm_status shoot_batched_device(const BatchLens* host_table, int nlens, int order, uint32_t flags, void* ws,
+                                hipStream_t st)
+{
+    int64_t total = 0, items = 0;
+    std::vector<int64_t> roff(nlens + 1), gpre(nlens + 1);
+    for (int l = 0; l < nlens; ++l) {
+        roff[l] = total;
+        gpre[l] = items;
+        total += host_table[l].nrays;
+        items += (host_table[l].nrays + kWave - 1) / kWave;
+    }
+    roff[nlens] = total;
+    gpre[nlens] = items;
+    if (total == 0) return GLM_OK;
+    std::vector<BatchLens> tab(host_table, host_table + nlens);
+    for (int l = 0; l < nlens; ++l) tab[l].ray_off = roff[l];
+    const BatchLayout B = batch_layout(nlens, total);
+    char* W = static_cast<char*>(ws);
+    BatchLens* dtab = reinterpret_cast<BatchLens*>(W + B.table);
+    int64_t* droff = reinterpret_cast<int64_t*>(W + B.roff);
+    int64_t* dgpre = reinterpret_cast<int64_t*>(W + B.gpre);
+    double* bb = reinterpret_cast<double*>(W + B.bb);
+    int* counter = reinterpret_cast<int*>(W + B.counter);
+    uint64_t* k0 = reinterpret_cast<uint64_t*>(W + B.k0);
+    uint64_t* k1 = reinterpret_cast<uint64_t*>(W + B.k1);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(W + B.v0);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(W + B.v1);
+    double* xs = reinterpret_cast<double*>(W + B.xs);
+    double* ys = reinterpret_cast<double*>(W + B.ys);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(W + B.hist);
+    GLM_HIP(hipMemcpyAsync(dtab, tab.data(), sizeof(BatchLens) * nlens, hipMemcpyHostToDevice, st));
+    GLM_HIP(hipMemcpyAsync(droff, roff.data(), 8ull * (nlens + 1), hipMemcpyHostToDevice, st));
+    GLM_HIP(hipMemcpyAsync(dgpre, gpre.data(), 8ull * (nlens + 1), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, counter);
+    hipLaunchKernelGGL(k_batch_bbox, dim3(nlens), dim3(kBlock), 0, st, dtab, bb);
+    const int g = ceil_div(total, kBlock);
+    hipLaunchKernelGGL(k_batch_keys, dim3(g), dim3(kBlock), 0, st, dtab, nlens, droff, bb, total, k0, v0);
+    int lens_bits = 0;
+    while ((1 << lens_bits) < nlens) ++lens_bits;
+    const int passes = 4 + (lens_bits + 7) / 8;
+    const int w = radix_sort_u64(k0, v0, k1, v1, total, passes, hist, st);
+    const uint64_t* ks = w ? k1 : k0;
+    const uint32_t* perm = w ? v1 : v0;
+    hipLaunchKernelGGL(k_batch_gather, dim3(g), dim3(kBlock), 0, st, dtab, droff, ks, perm, total, xs, ys);
+    const int kahan = (flags & GLM_NO_KAHAN) ? 0 : 1;
+#define GLM_CASE(PP)                                                                                     \
+    case PP:                                                                                             \
+        if (flags & GLM_ALPHA_ONLY)                                                                      \
+            launch_batched<PP, true>(dtab, nlens, dgpre, counter, xs, ys, perm, items, kahan, st);       \
+        else                                                                                             \
+            launch_batched<PP, false>(dtab, nlens, dgpre, counter, xs, ys, perm, items, kahan, st);      \
+        break;
+    switch (order) {
+        GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
+        GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
+        default: return fail(GLM_EINVAL, "unsupported order");
+    }
+#undef GLM_CASE
+    GLM_HIP(hipGetLastError());
+    return GLM_OK;
+}
+
 glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, float* a1,
                         float* a2, float* k, float* g1, float* g2, int32_t* counts, uint32_t flags, void* ws,
                         hipStream_t st)
@@ -286,11 +513,11 @@ glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* r
     }
     const int kahan = (flags & GLM_NO_KAHAN) ? 0 : 1;
     if (flags & GLM_ALPHA_ONLY)
-        dispatch_walk<true>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays, a1, a2, nullptr, nullptr, nullptr,
-                            counts, kahan, st);
+        dispatch_walk<true>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays,
+                            WalkOut{a1, a2, nullptr, nullptr, nullptr, counts}, kahan, st);
     else
-        dispatch_walk<false>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays, a1, a2, k, g1, g2, counts, kahan,
-                             st);
+        dispatch_walk<false>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays, WalkOut{a1, a2, k, g1, g2, counts},
+                             kahan, st);
     GLM_HIP(hipGetLastError());
     return GLM_OK;
 }

@@ -5,6 +5,33 @@
 
 namespace glm {
 
+// Outputs of a walk (input order of the rays).
+struct WalkOut {
+    float *a1, *a2, *k, *g1, *g2;
+    int32_t* counts;
+};
+
+// One lens of a batched walk (device table entry).
+struct BatchLens {
+    TreeDev tree;
+    int64_t nrays;
+    int64_t ray_off;   // offset of its rays in the concatenated staged arrays
+    const double* rx;  // the caller's rays (input order)
+    const double* ry;
+    WalkOut out;
+};
+
+// Persistent walk over several lenses; host_table is in queue order (largest
+// expected work first), every tree built with the same order.
+size_t batch_workspace_bytes(int nlens, int64_t total_rays);
+glm_status shoot_batched_device(const BatchLens* host_table, int nlens, int order, uint32_t flags, void* ws,
+                                hipStream_t st);
+
+size_t refine_workspace_bytes(int64_t ncells);
+glm_status refine_round_device(double* cx, double* cy, double* side, const float* ka, const float* g1,
+                               const float* g2, int64_t ncells, int64_t nrefine, int32_t* refined, void* ws,
+                               hipStream_t st);
+
 // Byte offsets of the ray workspace pieces.
 struct RayLayout {
     size_t k0, k1, v0, v1, xs, ys, hist, part, bytes;

@@ -184,6 +184,36 @@ def workload_nfw(n: int = 1_000_000, grid: int = 2048, seed: int = BASE_SEED + 2
     return lens, rx, ry
 
 
+def workload_microlensing(n_halo: int = 1_000_000, n_stars: int = 100_000, base: int = 256,
+                          center=(0.25, 0.0), patch: float = 0.01):
+    """The smoothed NFW halo plus n_stars point-mass stars in a patch x patch
+    square around an image position (Salpeter masses, mean stellar convergence
+    0.3 over the patch), and a base x base grid of square cells over the patch
+    (centres and sides)."""
+    halo = nfw_halo(n_halo, BASE_SEED + 2)
+    stars = star_patch(n_stars, BASE_SEED + 20, center=center, side=patch)
+    lens = Lens(np.concatenate([halo.x, stars.x]), np.concatenate([halo.y, stars.y]),
+                np.concatenate([halo.m, stars.m]), np.concatenate([halo.s, stars.s]), q=halo.q,
+                meta={"kind": "halo+stars", "n_stars": n_stars})
+    cx, cy = ray_grid(base, -patch / 2, patch / 2)
+    return lens, cx + center[0], cy + center[1], np.full(base * base, patch / base)
+
+
+def workload_batched_lenses(nlens: int = 64, seed: int = BASE_SEED + 30, scale: float = 1.0):
+    """nlens independent smoothed NFW lenses: particle counts log-uniform in
+    [1e3, 1e5], ray grids n x n with n log-uniform in [256, 1024] over
+    [-0.5, 0.5]^2 (scale < 1 shrinks both for quick runs)."""
+    g = rng(seed)
+    out = []
+    for l in range(nlens):
+        n = int(round(10 ** g.uniform(3, 5) * scale))
+        side = int(round(2 ** g.uniform(8, 10) * math.sqrt(scale)))
+        lens = nfw_halo(max(n, 40), seed + 1000 + l)
+        rx, ry = ray_grid(max(side, 8))
+        out.append((lens, rx, ry))
+    return out
+
+
 def sample_rays(rx, ry, k: int, seed: int):
     """Seeded subset of k ray indices (sorted)."""
     g = rng(seed)
