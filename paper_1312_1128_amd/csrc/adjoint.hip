@@ -27,19 +27,9 @@ namespace glm {
 
 namespace {
 
-__device__ inline double wave_sum_d(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
+__device__ inline double wave_sum_d(double v) { return wave_sum<double>(v); }
 
-__device__ inline float wave_sum_f(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
+__device__ inline float wave_sum_f(float v) { return wave_sum<float>(v); }
 
 // Gradient terms of one particle for this lane, per the same cases as the
 // forward's eval_particle.  Returns FP64 (m, x, y, s) contributions in G.
@@ -178,12 +168,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 const float v1 = f1 * inv, v2 = -f2 * inv;
                 const float t1 = rcm * v1, t2 = rcm * v2;
                 // g_hat v t^k
-                float p1 = g1 * v1 - g2 * v2, p2 = g1 * v2 + g2 * v1;
+                float p1 = fmaf(g1, v1, -g2 * v2), p2 = fmaf(g1, v2, g2 * v1);
 #pragma unroll
                 for (int k = 0; k <= P; ++k) {
                     a[2 * k] = p1;
                     a[2 * k + 1] = p2;
-                    const float n1 = p1 * t1 - p2 * t2, n2 = p1 * t2 + p2 * t1;
+                    const float n1 = fmaf(p1, t1, -p2 * t2), n2 = fmaf(p1, t2, p2 * t1);
                     p1 = n1;
                     p2 = n2;
                 }
@@ -192,21 +182,25 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 if constexpr (P >= 2) {
                     b1 = mo[2 + 2 * (P - 2)];
                     b2 = mo[3 + 2 * (P - 2)];
+                    c1 = b1;
+                    c2 = b2;
 #pragma unroll
                     for (int k = P - 1; k >= 0; --k) {
-                        const float n1 = c1 * t1 - c2 * t2 + b1, n2 = c1 * t2 + c2 * t1 + b2;
-                        c1 = n1;
-                        c2 = n2;
                         const float q1 = k >= 2 ? mo[2 + 2 * (k - 2)] : (k == 0 ? 1.0f : 0.0f);
                         const float q2 = k >= 2 ? mo[3 + 2 * (k - 2)] : 0.0f;
-                        const float m1 = b1 * t1 - b2 * t2 + q1, m2 = b1 * t2 + b2 * t1 + q2;
+                        const float m1 = fmaf(b1, t1, fmaf(-b2, t2, q1)), m2 = fmaf(b1, t2, fmaf(b2, t1, q2));
                         b1 = m1;
                         b2 = m2;
+                        if (k > 0) {
+                            const float n1 = fmaf(c1, t1, fmaf(-c2, t2, b1)), n2 = fmaf(c1, t2, fmaf(c2, t1, b2));
+                            c1 = n1;
+                            c2 = n2;
+                        }
                     }
                 }
-                const float S1 = b1 + t1 * c1 - t2 * c2, S2 = b2 + t1 * c2 + t2 * c1;
-                const float w21 = v1 * v1 - v2 * v2, w22 = 2.0f * v1 * v2;
-                const float V1 = M * (w21 * S1 - w22 * S2), V2 = M * (w21 * S2 + w22 * S1);
+                const float S1 = fmaf(t1, c1, fmaf(-t2, c2, b1)), S2 = fmaf(t1, c2, fmaf(t2, c1, b2));
+                const float w21 = fmaf(v1, v1, -v2 * v2), w22 = 2.0f * v1 * v2;
+                const float V1 = M * fmaf(w21, S1, -w22 * S2), V2 = M * fmaf(w21, S2, w22 * S1);
                 a[NA - 2] = g1 * V1 - g2 * V2;
                 a[NA - 1] = g1 * V2 + g2 * V1;
             }

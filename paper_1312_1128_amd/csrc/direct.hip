@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kBlock) void k_direct32(const double* __restrict__ 
         tile[threadIdx.x] = t;
         __syncthreads();
         const int cnt = min(kBlock, n - base);
-        for (int k = 0; k < cnt; ++k) eval_particle<AONLY>(tile[k], X, Y, 0, A, true, dummy);
+        for (int k = 0; k < cnt; ++k) eval_particle<AONLY, true>(tile[k], X, Y, 0, A, dummy);
         __syncthreads();
     }
     if (!valid) return;

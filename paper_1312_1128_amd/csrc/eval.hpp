@@ -17,12 +17,18 @@ struct Acc {
     double b1, b2, bg1, bg2;
 };
 
-__device__ inline void kadd(float& s, float& c, float v, bool kahan)
+// compensated (Kahan) summation step; plain FP32 addition when KAHAN is false
+template <bool KAHAN>
+__device__ inline void kadd(float& s, float& c, float v)
 {
-    const float y = v - c;
-    const float t = s + y;
-    c = kahan ? (t - s) - y : 0.0f;
-    s = t;
+    if constexpr (KAHAN) {
+        const float y = v - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    } else {
+        s += v;
+    }
 }
 
 // FP64 offset and its squared length, rounded exactly as written (the inside
@@ -39,24 +45,33 @@ __device__ inline double sqdist(double X, double Y, double px, double py, double
 // mh = mC / (2 s^2): the deflection coefficient A (alpha = A d) and
 // Gamma = A - kappa (gamma = -Gamma (cos 2phi, sin 2phi)):
 //   A = mC (1 - e^-u) / r^2 = mh (1 - e^-u)/u,  Gamma = mh ((1 - e^-u)/u - e^-u).
-// Below u = 1/2, where 1 - e^-u cancels, both use their Taylor series.
+// Below u = 1/2, where 1 - e^-u cancels, both use their Taylor series.  Each
+// branch is evaluated only if some lane of the wavefront needs it.
 __device__ inline void gauss_terms(float u, float e, float ir2, float mC, float mh, float* A, float* G)
 {
-    const float sg = 1.0f +
-                     u * (-1.0f / 2 +
-                          u * (1.0f / 6 +
-                               u * (-1.0f / 24 +
-                                    u * (1.0f / 120 +
-                                         u * (-1.0f / 720 + u * (1.0f / 5040 + u * (-1.0f / 40320 + u * (1.0f / 362880))))))));
-    const float sd = u * (1.0f / 2 +
-                          u * (-1.0f / 3 +
-                               u * (1.0f / 8 +
-                                    u * (-1.0f / 30 +
-                                         u * (1.0f / 144 + u * (-1.0f / 840 + u * (1.0f / 5760 + u * (-1.0f / 45360 + u * (1.0f / 403200)))))))));
-    const float Al = mC * (1.0f - e) * ir2;
     const bool small = u < 0.5f;
-    *A = small ? mh * sg : Al;
-    *G = small ? mh * sd : Al - mh * e;
+    float As = 0.0f, Gs = 0.0f, Al = 0.0f, Gl = 0.0f;
+    if (__any(small)) {
+        const float sg = 1.0f +
+                         u * (-1.0f / 2 +
+                              u * (1.0f / 6 +
+                                   u * (-1.0f / 24 +
+                                        u * (1.0f / 120 +
+                                             u * (-1.0f / 720 + u * (1.0f / 5040 + u * (-1.0f / 40320 + u * (1.0f / 362880))))))));
+        const float sd = u * (1.0f / 2 +
+                              u * (-1.0f / 3 +
+                                   u * (1.0f / 8 +
+                                        u * (-1.0f / 30 +
+                                             u * (1.0f / 144 + u * (-1.0f / 840 + u * (1.0f / 5760 + u * (-1.0f / 45360 + u * (1.0f / 403200)))))))));
+        As = mh * sg;
+        Gs = mh * sd;
+    }
+    if (__any(!small)) {
+        Al = mC * (1.0f - e) * ir2;
+        Gl = Al - mh * e;
+    }
+    *A = small ? As : Al;
+    *G = small ? Gs : Gl;
 }
 
 // Point-mass terms of one particle (Sec. 3.5): alpha = m d / r^2 and
@@ -82,8 +97,8 @@ __device__ inline void point_terms(float m, float f1, float f2, float ir2, float
 //    individually and removed from the tree part).
 // The point part of every "inside" pair (mode 1, and mode 0 for a listed
 // particle) goes to the FP64 balance so the pair cancels exactly.
-template <bool AONLY>
-__device__ inline void eval_particle(const PRec& pr, double X, double Y, int mode, Acc& A, bool kahan, int& hits)
+template <bool AONLY, bool KAHAN>
+__device__ inline void eval_particle(const PRec& pr, double X, double Y, int mode, Acc& A, int& hits)
 {
     double d1, d2;
     const double r2 = sqdist(X, Y, pr.x, pr.y, &d1, &d2);
@@ -92,8 +107,8 @@ __device__ inline void eval_particle(const PRec& pr, double X, double Y, int mod
     if (mode == 1 && !inside) return;
     const float f1 = (float)d1, f2 = (float)d2, r2f = (float)r2;
     const float ir2 = r2f > 0.0f ? __builtin_amdgcn_rcpf(r2f) : 0.0f;
-    float P[4];
-    point_terms(pr.m, f1, f2, ir2, P);
+    float P[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (!inside || mode == 1 || listed) point_terms(pr.m, f1, f2, ir2, P);
     if (!inside || (mode == 0 && listed)) {
         if (inside) { // listed and inside: the list box already added Gaussian - point
             A.b1 += (double)P[0];
@@ -103,8 +118,8 @@ __device__ inline void eval_particle(const PRec& pr, double X, double Y, int mod
                 A.bg2 += (double)P[3];
             }
         } else {
-            kadd(A.a1, A.c1, P[0], kahan);
-            kadd(A.a2, A.c2, P[1], kahan);
+            kadd<KAHAN>(A.a1, A.c1, P[0]);
+            kadd<KAHAN>(A.a2, A.c2, P[1]);
             if (!AONLY) {
                 A.g1 += P[2];
                 A.g2 += P[3];
@@ -118,8 +133,8 @@ __device__ inline void eval_particle(const PRec& pr, double X, double Y, int mod
     const float mh = pr.mC * pr.h;
     float Acoef, Gam;
     gauss_terms(u, e, ir2, pr.mC, mh, &Acoef, &Gam);
-    kadd(A.a1, A.c1, Acoef * f1, kahan);
-    kadd(A.a2, A.c2, Acoef * f2, kahan);
+    kadd<KAHAN>(A.a1, A.c1, Acoef * f1);
+    kadd<KAHAN>(A.a2, A.c2, Acoef * f2);
     if (!AONLY) {
         A.k += mh * e;
         const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = 2.0f * f1 * f2 * ir2;
@@ -140,43 +155,51 @@ __device__ inline void eval_particle(const PRec& pr, double X, double Y, int mod
 // Multipole expansion of an accepted box about its centre of mass (Sec. 3.2):
 //   alpha1 - i alpha2 = M v P(t),  gamma1 - i gamma2 = -M v^2 (P(t) + t P'(t)),
 // v = 1/w, t = r_cm v, P(t) = 1 + sum_{k>=2} Qn_k t^k, Qn_k = Q_k / (M r_cm^k).
-template <int P, bool AONLY>
-__device__ inline void eval_box(const float* __restrict__ mo, double w1, double w2, Acc& A, bool kahan)
+template <int P, bool AONLY, bool KAHAN>
+__device__ inline void eval_box(const float* __restrict__ mo, double w1, double w2, Acc& A)
 {
     const float M = mo[0], rcm = mo[1];
     const float f1 = (float)w1, f2 = (float)w2;
-    const float inv = __builtin_amdgcn_rcpf(f1 * f1 + f2 * f2);
+    const float inv = __builtin_amdgcn_rcpf(fmaf(f1, f1, f2 * f2));
     const float v1 = f1 * inv, v2 = -f2 * inv;
     const float t1 = rcm * v1, t2 = rcm * v2;
+    // Horner in t for b = P(t) and c = P'(t): c <- c t + b, b <- b t + Qn_k,
+    // each complex multiply-add as two FMAs per component
     float b1 = 1.0f, b2 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     if constexpr (P >= 2) {
         b1 = mo[2 + 2 * (P - 2)];
         b2 = mo[3 + 2 * (P - 2)];
+        c1 = b1; // first step: c = 0 * t + b
+        c2 = b2;
 #pragma unroll
         for (int k = P - 1; k >= 0; --k) {
-            if constexpr (!AONLY) {
-                const float n1 = c1 * t1 - c2 * t2 + b1;
-                const float n2 = c1 * t2 + c2 * t1 + b2;
-                c1 = n1;
-                c2 = n2;
-            }
             const float q1 = k >= 2 ? mo[2 + 2 * (k - 2)] : (k == 0 ? 1.0f : 0.0f);
             const float q2 = k >= 2 ? mo[3 + 2 * (k - 2)] : 0.0f;
-            const float n1 = b1 * t1 - b2 * t2 + q1;
-            const float n2 = b1 * t2 + b2 * t1 + q2;
+            const float n1 = fmaf(b1, t1, fmaf(-b2, t2, q1));
+            const float n2 = fmaf(b1, t2, fmaf(b2, t1, q2));
             b1 = n1;
             b2 = n2;
+            if constexpr (!AONLY) {
+                if (k > 0) {
+                    const float m1 = fmaf(c1, t1, fmaf(-c2, t2, b1));
+                    const float m2 = fmaf(c1, t2, fmaf(c2, t1, b2));
+                    c1 = m1;
+                    c2 = m2;
+                }
+            }
         }
     }
-    const float F1 = M * (v1 * b1 - v2 * b2), F2 = M * (v1 * b2 + v2 * b1);
-    kadd(A.a1, A.c1, F1, kahan);
-    kadd(A.a2, A.c2, -F2, kahan);
+    // alpha1 - i alpha2 = M v b
+    const float F1 = M * fmaf(v1, b1, -v2 * b2), F2 = M * fmaf(v1, b2, v2 * b1);
+    kadd<KAHAN>(A.a1, A.c1, F1);
+    kadd<KAHAN>(A.a2, A.c2, -F2);
     if constexpr (!AONLY) {
-        const float S1 = b1 + t1 * c1 - t2 * c2, S2 = b2 + t1 * c2 + t2 * c1;
-        const float w21 = v1 * v1 - v2 * v2, w22 = 2.0f * v1 * v2;
-        const float G1 = -M * (w21 * S1 - w22 * S2), G2 = -M * (w21 * S2 + w22 * S1);
-        A.g1 += G1;
-        A.g2 -= G2;
+        // gamma1 - i gamma2 = -M v^2 (b + t c)
+        const float S1 = fmaf(t1, c1, fmaf(-t2, c2, b1)), S2 = fmaf(t1, c2, fmaf(t2, c1, b2));
+        const float w21 = fmaf(v1, v1, -v2 * v2), w22 = 2.0f * v1 * v2;
+        const float G1 = M * fmaf(w21, S1, -w22 * S2), G2 = M * fmaf(w21, S2, w22 * S1);
+        A.g1 -= G1;
+        A.g2 += G2;
     }
 }
 
@@ -201,6 +224,52 @@ __device__ inline double wave_max(double v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
     return v;
+}
+
+// Full-wavefront sums with DPP lane moves (each step one VALU op, no LDS
+// crossbar): pairs and quads (quad_perm), 8 and 16 lanes (half-row and row
+// mirrors), then rows via row_bcast15 / row_bcast31.  Lane 63 ends with the
+// total, returned to every lane through readlane.  Fixed order, so the result
+// is deterministic.  Must be called with every lane of the wavefront active.
+template <int CTRL, int ROWS>
+__device__ inline int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ inline float dpp_step(float v)
+{
+    return v + __builtin_bit_cast(float, dpp_i<CTRL, ROWS>(__builtin_bit_cast(int, v)));
+}
+
+template <int CTRL, int ROWS>
+__device__ inline double dpp_step(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp_i<CTRL, ROWS>((int)(b & 0xffffffffll));
+    const int hi = dpp_i<CTRL, ROWS>((int)(b >> 32));
+    const long long m = ((long long)(unsigned)lo) | ((long long)hi << 32);
+    return v + __builtin_bit_cast(double, m);
+}
+
+template <class T>
+__device__ inline T wave_sum(T v)
+{
+    v = dpp_step<0xB1, 0xF>(v);  // quad_perm [1,0,3,2]
+    v = dpp_step<0x4E, 0xF>(v);  // quad_perm [2,3,0,1]
+    v = dpp_step<0x141, 0xF>(v); // row_half_mirror
+    v = dpp_step<0x140, 0xF>(v); // row_mirror
+    v = dpp_step<0x142, 0xA>(v); // row_bcast15 into rows 1, 3
+    v = dpp_step<0x143, 0xC>(v); // row_bcast31 into rows 2, 3
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+    } else {
+        const long long b = __builtin_bit_cast(long long, v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+        return __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
+    }
 }
 
 } // namespace glm

@@ -27,10 +27,19 @@ namespace {
 
 // The traversal of one 64-ray group (see the file comment).  Every lane of
 // the wave must call it; `valid` lanes carry a ray.
-template <int P, bool AONLY>
-__device__ inline void walk_group(const TreeDev& T, double X, double Y, bool valid, int lane, bool kahan, Acc& A,
-                                  int cnt[4])
+// MODE: 0 = Kahan-compensated alpha (the product walk), 1 = the same plus
+// per-ray interaction counts, 2 = plain FP32 accumulation.
+template <int MODE>
+struct WalkMode {
+    static constexpr bool kahan = MODE != 2;
+    static constexpr bool stats = MODE == 1;
+};
+
+template <int P, bool AONLY, int MODE>
+__device__ inline void walk_group(const TreeDev& T, double X, double Y, bool valid, int lane, Acc& A, int cnt[4])
 {
+    constexpr bool KAHAN = WalkMode<MODE>::kahan;
+    constexpr bool STATS = WalkMode<MODE>::stats;
     const double gx0 = wave_min(valid ? X : INFINITY), gx1 = wave_max(valid ? X : -INFINITY);
     const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
     int n_vis = 0, n_acc = 0, n_dir = 0, n_hit = 0;
@@ -41,7 +50,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
         cur = __builtin_amdgcn_readfirstlane(cur);
         const CellHdr h = T.hdr[cur];
         const bool act = cur >= skip;
-        n_vis += act;
+        if constexpr (STATS) n_vis += act;
         if (h.info & kInfoList) {
             const CellExt e = T.ext[cur];
             for (int base = e.lbeg; base < e.lend; base += kWave) {
@@ -58,7 +67,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                     const int k = __ffsll((unsigned long long)cm) - 1;
                     cm &= cm - 1;
                     const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
-                    if (act) eval_particle<AONLY>(pr, X, Y, 1, A, kahan, n_hit);
+                    if (act) eval_particle<AONLY, KAHAN>(pr, X, Y, 1, A, n_hit);
                 }
             }
         }
@@ -66,18 +75,20 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
         const double d2 = sqdist(X, Y, h.cx, h.cy, &w1, &w2);
         const bool acc = act && d2 > h.rcut2;
         const bool opn = act && !acc;
-        n_acc += acc;
+        if constexpr (STATS) n_acc += acc;
         if (__any(acc)) {
-            if (acc) eval_box<P, AONLY>(T.mom + (size_t)cur * mom_stride(P), w1, w2, A, kahan);
+            if (acc) eval_box<P, AONLY, KAHAN>(T.mom + (size_t)cur * mom_stride(P), w1, w2, A);
         }
         if (h.info & kInfoLeaf) {
             if (__any(opn)) {
                 const CellExt e = T.ext[cur];
-                if (opn) n_dir += e.pend - e.pbeg;
+                if constexpr (STATS) {
+                    if (opn) n_dir += e.pend - e.pbeg;
+                }
                 int dummy = 0;
                 for (int j = e.pbeg; j < e.pend; ++j) {
                     const PRec pr = T.prt[j];
-                    if (opn) eval_particle<AONLY>(pr, X, Y, 0, A, kahan, dummy);
+                    if (opn) eval_particle<AONLY, KAHAN>(pr, X, Y, 0, A, dummy);
                 }
             }
             cur = cur + 1;
@@ -94,7 +105,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
     cnt[3] = n_hit;
 }
 
-template <bool AONLY>
+template <bool AONLY, bool STATS>
 __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, const WalkOut& out)
 {
     // fold the FP64 balance of the big-particle point terms into the result
@@ -105,7 +116,7 @@ __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, cons
         if (out.g1) out.g1[o] = (float)((double)A.g1 + A.bg1);
         if (out.g2) out.g2[o] = (float)((double)A.g2 + A.bg2);
     }
-    if (out.counts) {
+    if (STATS && out.counts) {
         out.counts[4 * o + 0] = cnt[0];
         out.counts[4 * o + 1] = cnt[1];
         out.counts[4 * o + 2] = cnt[2];
@@ -113,10 +124,10 @@ __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, cons
     }
 }
 
-template <int P, bool AONLY>
+template <int P, bool AONLY, int MODE>
 __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __restrict__ rxs,
                                                 const double* __restrict__ rys, const uint32_t* __restrict__ rperm,
-                                                int64_t nrays, WalkOut out, int kahan_i)
+                                                int64_t nrays, WalkOut out)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t r = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
@@ -125,19 +136,19 @@ __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __rest
     const double X = valid ? rxs[r] : 0.0, Y = valid ? rys[r] : 0.0;
     Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
     int cnt[4];
-    walk_group<P, AONLY>(T, X, Y, valid, lane, kahan_i != 0, A, cnt);
+    walk_group<P, AONLY, MODE>(T, X, Y, valid, lane, A, cnt);
     if (!valid) return;
-    write_out<AONLY>(A, cnt, rperm ? (int64_t)rperm[r] : r, out);
+    write_out<AONLY, WalkMode<MODE>::stats>(A, cnt, rperm ? (int64_t)rperm[r] : r, out);
 }
 
 // Persistent walk over many lenses: every wavefront takes (lens, 64-ray group)
 // items from a device counter until the queue is empty.  Lenses are ranked by
 // estimated cost, so the largest ray groups start first.
-template <int P, bool AONLY>
+template <int P, bool AONLY, int MODE>
 __global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __restrict__ lenses, int nlens,
                                                         const int64_t* __restrict__ gprefix, int* __restrict__ counter,
                                                         const double* __restrict__ xs, const double* __restrict__ ys,
-                                                        const uint32_t* __restrict__ perm, int kahan_i)
+                                                        const uint32_t* __restrict__ perm)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t total = gprefix[nlens];
@@ -159,8 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __rest
         const double X = valid ? xs[gi] : 0.0, Y = valid ? ys[gi] : 0.0;
         Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
         int cnt[4];
-        walk_group<P, AONLY>(L.tree, X, Y, valid, lane, kahan_i != 0, A, cnt);
-        if (valid) write_out<AONLY>(A, cnt, (int64_t)perm[gi] - L.ray_off, L.out);
+        walk_group<P, AONLY, MODE>(L.tree, X, Y, valid, lane, A, cnt);
+        if (valid) write_out<AONLY, false>(A, cnt, (int64_t)perm[gi] - L.ray_off, L.out);
     }
 }
 
@@ -259,18 +270,23 @@ __global__ __launch_bounds__(kBlock) void k_ray_gather(const uint32_t* __restric
 
 template <int P, bool AONLY>
 void launch_walk(const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm, int64_t nrays,
-                 const WalkOut& out, int kahan, hipStream_t st)
+                 const WalkOut& out, int mode, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_walk<P, AONLY>), dim3(ceil_div(nrays, kBlock)), dim3(kBlock), 0, st, T, rxs, rys, rperm,
-                       nrays, out, kahan);
+    const dim3 g(ceil_div(nrays, kBlock)), b(kBlock);
+    if (mode == 1)
+        hipLaunchKernelGGL((k_walk<P, AONLY, 1>), g, b, 0, st, T, rxs, rys, rperm, nrays, out);
+    else if (mode == 2)
+        hipLaunchKernelGGL((k_walk<P, AONLY, 2>), g, b, 0, st, T, rxs, rys, rperm, nrays, out);
+    else
+        hipLaunchKernelGGL((k_walk<P, AONLY, 0>), g, b, 0, st, T, rxs, rys, rperm, nrays, out);
 }
 
 template <bool AONLY>
 void dispatch_walk(int p, const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm,
-                   int64_t nrays, const WalkOut& out, int kahan, hipStream_t st)
+                   int64_t nrays, const WalkOut& out, int mode, hipStream_t st)
 {
 #define GLM_CASE(PP) \
-    case PP: launch_walk<PP, AONLY>(T, rxs, rys, rperm, nrays, out, kahan, st); break;
+    case PP: launch_walk<PP, AONLY>(T, rxs, rys, rperm, nrays, out, mode, st); break;
     switch (p) {
         GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
         GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
@@ -328,12 +344,14 @@ glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* w
 
 namespace {
 
-__global__ __launch_bounds__(kBlock) void k_batch_bbox(const BatchLens* __restrict__ lenses, double* __restrict__ bb)
+constexpr int kBboxSplit = 32; // blocks per lens for the ray bounding boxes
+
+__global__ __launch_bounds__(kBlock) void k_batch_bbox(const BatchLens* __restrict__ lenses, double* __restrict__ part)
 {
     __shared__ double red[4][kBlock];
     const BatchLens& L = lenses[blockIdx.x];
     double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
-    for (int64_t i = threadIdx.x; i < L.nrays; i += kBlock) {
+    for (int64_t i = (int64_t)blockIdx.y * kBlock + threadIdx.x; i < L.nrays; i += (int64_t)kBlock * kBboxSplit) {
         const double x = L.rx[i], y = L.ry[i];
         v[0] = fmin(v[0], x);
         v[1] = fmax(v[1], x);
@@ -351,7 +369,20 @@ __global__ __launch_bounds__(kBlock) void k_batch_bbox(const BatchLens* __restri
         }
         __syncthreads();
     }
-    if (threadIdx.x < 4) bb[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 4) part[((size_t)blockIdx.x * kBboxSplit + blockIdx.y) * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_batch_bbox_final(const double* __restrict__ part, int nlens, double* __restrict__ bb)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * nlens) return;
+    const int l = t / 4, k = t % 4;
+    double v = (k & 1) ? -INFINITY : INFINITY;
+    for (int b = 0; b < kBboxSplit; ++b) {
+        const double p = part[((size_t)l * kBboxSplit + b) * 4 + k];
+        v = (k & 1) ? fmax(v, p) : fmin(v, p);
+    }
+    bb[t] = v;
 }
 
 __device__ inline int find_lens(const int64_t* __restrict__ roff, int nlens, int64_t gi)
@@ -402,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchLens* __rest
 __global__ void k_zero_int(int* p) { *p = 0; }
 
 struct BatchLayout {
-    size_t table, roff, gpre, bb, counter, k0, k1, v0, v1, xs, ys, hist, bytes;
+    size_t table, roff, gpre, bb, bbpart, counter, k0, k1, v0, v1, xs, ys, hist, bytes;
 };
 
 BatchLayout batch_layout(int nlens, int64_t total)
@@ -413,6 +444,7 @@ BatchLayout batch_layout(int nlens, int64_t total)
     B.roff = a.take(8ull * (nlens + 1));
     B.gpre = a.take(8ull * (nlens + 1));
     B.bb = a.take(32ull * nlens);
+    B.bbpart = a.take(32ull * nlens * kBboxSplit);
     B.counter = a.take(64);
     B.k0 = a.take(8ull * total);
     B.k1 = a.take(8ull * total);
@@ -430,8 +462,12 @@ void launch_batched(const BatchLens* table, int nlens, const int64_t* gpre, int*
                     const double* ys, const uint32_t* perm, int64_t items, int kahan, hipStream_t st)
 {
     const int blocks = (int)std::min<int64_t>((items + 3) / 4, 256 * 8);
-    hipLaunchKernelGGL((k_walk_batched<P, AONLY>), dim3(blocks), dim3(kBlock), 0, st, table, nlens, gpre, counter, xs,
-                       ys, perm, kahan);
+    if (kahan)
+        hipLaunchKernelGGL((k_walk_batched<P, AONLY, 0>), dim3(blocks), dim3(kBlock), 0, st, table, nlens, gpre,
+                           counter, xs, ys, perm);
+    else
+        hipLaunchKernelGGL((k_walk_batched<P, AONLY, 2>), dim3(blocks), dim3(kBlock), 0, st, table, nlens, gpre,
+                           counter, xs, ys, perm);
 }
 
 } // namespace
@@ -472,7 +508,9 @@ glm_status shoot_batched_device(const BatchLens* host_table, int nlens, int orde
     GLM_HIP(hipMemcpyAsync(droff, roff.data(), 8ull * (nlens + 1), hipMemcpyHostToDevice, st));
     GLM_HIP(hipMemcpyAsync(dgpre, gpre.data(), 8ull * (nlens + 1), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, counter);
-    hipLaunchKernelGGL(k_batch_bbox, dim3(nlens), dim3(kBlock), 0, st, dtab, bb);
+    double* bbpart = reinterpret_cast<double*>(W + B.bbpart);
+    hipLaunchKernelGGL(k_batch_bbox, dim3(nlens, kBboxSplit), dim3(kBlock), 0, st, dtab, bbpart);
+    hipLaunchKernelGGL(k_batch_bbox_final, dim3(ceil_div(4 * nlens, 64)), dim3(64), 0, st, bbpart, nlens, bb);
     const int g = ceil_div(total, kBlock);
     hipLaunchKernelGGL(k_batch_keys, dim3(g), dim3(kBlock), 0, st, dtab, nlens, droff, bb, total, k0, v0);
     int lens_bits = 0;
@@ -511,13 +549,14 @@ glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* r
         glm_status rc = stage_rays(rx, ry, nrays, ws, L, &sr, st);
         if (rc != GLM_OK) return rc;
     }
-    const int kahan = (flags & GLM_NO_KAHAN) ? 0 : 1;
+    // counts requested: Kahan walk with counters; else plain or Kahan walk
+    const int mode = counts ? 1 : ((flags & GLM_NO_KAHAN) ? 2 : 0);
     if (flags & GLM_ALPHA_ONLY)
         dispatch_walk<true>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays,
-                            WalkOut{a1, a2, nullptr, nullptr, nullptr, counts}, kahan, st);
+                            WalkOut{a1, a2, nullptr, nullptr, nullptr, counts}, mode, st);
     else
         dispatch_walk<false>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays, WalkOut{a1, a2, k, g1, g2, counts},
-                             kahan, st);
+                             mode, st);
     GLM_HIP(hipGetLastError());
     return GLM_OK;
 }
