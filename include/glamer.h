@@ -144,7 +144,9 @@ GLM_API glm_status glm_shoot_workspace_bytes(int64_t nrays, size_t* bytes);
  * list particles the ray falls inside.  The walk is FP32 with compensated
  * summation of alpha; ray-particle and ray-box offsets and every accept/inside
  * decision are taken in FP64.
- *   workspace: device buffer of at least glm_shoot_workspace_bytes(nrays).
+ *   workspace: device buffer of at least glm_shoot_workspace_bytes(nrays)
+ *   (ray sort, and for small ray counts the partial sums of several
+ *   wavefronts per ray group, each walking one range of the box array).
  *   flags: GLM_ALPHA_ONLY, GLM_NO_KAHAN, GLM_RAYS_ORDERED (or-ed with the
  *   tree's).
  * nrays may be 0 (nothing is launched).

@@ -118,7 +118,7 @@ def shoot(tree: Tree, rx, ry, counts: bool = False, alpha_only: bool = False, ka
         names = ["a1", "a2"] if alpha_only else ["a1", "a2", "kappa", "g1", "g2"]
         out = {k: torch.empty(R, dtype=torch.float32, device=dev) for k in names}
     cnt = torch.empty((R, 4), dtype=torch.int32, device=dev) if counts else None
-    if workspace is None and not ordered:
+    if workspace is None:
         workspace = torch.empty(max(workspace_bytes(R), 1), dtype=torch.uint8, device=dev)
     ws_bytes = workspace.numel() if workspace is not None else 0
     lib = _capi.load()
@@ -161,9 +161,9 @@ def shoot_adjoint(tree: Tree, rx, ry, ga1, ga2, dm=None, dx=None, dy=None, ds=No
     dx = torch.zeros(n, dtype=torch.float64, device=dev) if dx is None else dx
     dy = torch.zeros(n, dtype=torch.float64, device=dev) if dy is None else dy
     ds = torch.zeros(n, dtype=torch.float64, device=dev) if ds is None else ds
-    if workspace is None and not ordered:
+    if workspace is None:
         workspace = torch.empty(max(workspace_bytes(R), 1), dtype=torch.uint8, device=dev)
-    ws_bytes = workspace.numel() if workspace is not None else 0
+    ws_bytes = workspace.numel()
     flags = GLM_RAYS_ORDERED if ordered else 0
     lib = _capi.load()
     _capi.check(lib.glm_shoot_adjoint(tree.handle, _ptr(rx), _ptr(ry), R, _ptr(ga1), _ptr(ga2), _ptr(dm), _ptr(dx),

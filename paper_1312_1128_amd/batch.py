@@ -104,8 +104,8 @@ class RefinementRun:
         self.base = (cx0.clone(), cy0.clone(), side0.clone())
         self.out = {k: torch.zeros(self.cap, **f32) for k in ["a1", "a2", "kappa", "g1", "g2"]}
         self.refined = torch.zeros(max(self.schedule + [1]), dtype=torch.int32, device=dev)
-        new_max = max([self.n0] + [8 * k for k in self.schedule])
-        self.ws_shoot = torch.empty(workspace_bytes(new_max), dtype=torch.uint8, device=dev)
+        ws = max(workspace_bytes(n) for n in [self.n0] + [8 * k for k in self.schedule])
+        self.ws_shoot = torch.empty(ws, dtype=torch.uint8, device=dev)
         self.ws_refine = torch.empty(max(refine_workspace_bytes(self.cap), 1), dtype=torch.uint8, device=dev)
         self.sizes = [self.n0] + [8 * k for k in self.schedule]
 

@@ -108,13 +108,19 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                                                         const float* __restrict__ ga1, const float* __restrict__ ga2,
                                                         double* __restrict__ dm, double* __restrict__ dx,
                                                         double* __restrict__ dy, double* __restrict__ ds,
-                                                        double* __restrict__ abar)
+                                                        double* __restrict__ abar, int K,
+                                                        const int* __restrict__ split_box)
 {
     constexpr int NA = 2 * (P + 1) + 2; // (Re, Im) of Abar_0..Abar_P, Bbar
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t r = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t groups = (nrays + kWave - 1) / kWave;
+    // wave-uniform work item (kept in SGPRs): box range kr, ray group grp
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    int kr;
+    int64_t grp;
+    if (!walk_task(blockIdx.x, w, groups, K, &kr, &grp)) return;
+    const int64_t r = grp * kWave + lane;
     const bool valid = r < nrays;
-    if (!__any(valid)) return;
     const double X = valid ? rxs[r] : 0.0, Y = valid ? rys[r] : 0.0;
     const int64_t o = valid ? (rperm ? (int64_t)rperm[r] : r) : 0;
     const float g1 = valid ? ga1[o] : 0.0f, g2 = valid ? ga2[o] : 0.0f;
@@ -122,11 +128,22 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
     const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
     const float invC = T.invC;
 
-    int skip = valid ? 0 : 0x7fffffff;
+    // this wavefront's range of the preorder box array (see ancestor_skip)
     const int nc = T.ncells;
-    int cur = 0;
+    int c0 = 0, c1 = nc;
+    if (K > 1) {
+        const int B = __builtin_amdgcn_readfirstlane(*split_box);
+        if (B >= 0) {
+            split_range(kr, K, B, T.hdr[B].next, nc, &c0, &c1);
+        } else { // no split: the first range takes every box
+            c1 = kr == 0 ? nc : 0;
+        }
+    }
+    int skip = valid ? 0 : 0x7fffffff;
+    if (c0 > 0) skip = ancestor_skip(T, X, Y, c0, skip);
+    int cur = c0;
     double G[4];
-    while (cur < nc) {
+    while (cur < c1) {
         cur = __builtin_amdgcn_readfirstlane(cur);
         const CellHdr h = T.hdr[cur];
         const bool act = cur >= skip;
@@ -316,7 +333,7 @@ __global__ void k_fill_zero(double* p, int64_t n)
 
 template <int P>
 glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, const float* ga1, const float* ga2,
-                          double* dm, double* dx, double* dy, double* ds, hipStream_t st)
+                          double* dm, double* dx, double* dy, double* ds, int K, const int* split_box, hipStream_t st)
 {
     constexpr int NA = 2 * (P + 1) + 2;
     const size_t words = (size_t)ts.ncells * NA;
@@ -324,8 +341,9 @@ glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, 
     if (rc != GLM_OK) return rc;
     double* abar = ts.abuf.as<double>();
     hipLaunchKernelGGL(k_fill_zero, dim3(ceil_div((int64_t)words, kBlock)), dim3(kBlock), 0, st, abar, (int64_t)words);
-    hipLaunchKernelGGL((k_adjoint_walk<P>), dim3(ceil_div(nrays, kBlock)), dim3(kBlock), 0, st, ts.dev, sr.xs, sr.ys,
-                       sr.perm, nrays, ga1, ga2, dm, dx, dy, ds, abar);
+    const int64_t blocks = walk_grid_blocks((nrays + kWave - 1) / kWave, K);
+    hipLaunchKernelGGL((k_adjoint_walk<P>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ts.dev, sr.xs,
+                       sr.ys, sr.perm, nrays, ga1, ga2, dm, dx, dy, ds, abar, K, split_box);
     hipLaunchKernelGGL((k_pushdown<P>), dim3(ceil_div(ts.n, kBlock)), dim3(kBlock), 0, st, ts.dev, ts.ms, abar, dm, dx,
                        dy);
     GLM_HIP(hipGetLastError());
@@ -340,13 +358,21 @@ glm_status adjoint_device(TreeStorage& ts, const double* rx, const double* ry, i
 {
     if (nrays == 0) return GLM_OK;
     StagedRays sr{rx, ry, nullptr};
+    const RayLayout L = ray_layout(nrays);
     if (!(flags & GLM_RAYS_ORDERED)) {
-        const RayLayout L = ray_layout(nrays);
         glm_status rc = stage_rays(rx, ry, nrays, ws, L, &sr, st);
         if (rc != GLM_OK) return rc;
     }
+    int K = L.split;
+    while (K > 1 && (int64_t)K * 64 > ts.ncells) --K;
+    if (K < 4) K = 1;
+    int* split_box = nullptr;
+    if (K > 1) {
+        glm_status rc = split_box_device(ts, rx, ry, nrays, ws, L, !(flags & GLM_RAYS_ORDERED), &split_box, st);
+        if (rc != GLM_OK) return rc;
+    }
 #define GLM_CASE(PP) \
-    case PP: return launch_adjoint<PP>(ts, sr, nrays, ga1, ga2, dm, dx, dy, ds, st);
+    case PP: return launch_adjoint<PP>(ts, sr, nrays, ga1, ga2, dm, dx, dy, ds, K, split_box, st);
     switch (ts.params.order) {
         GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
         GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)

@@ -185,7 +185,7 @@ glm_status glm_shoot(const glm_tree* t, const double* rx, const double* ry, int6
     flags |= t->ts.params.flags;
     if (!(flags & GLM_ALPHA_ONLY) && (!kappa || !g1 || !g2))
         return fail(GLM_EINVAL, "kappa, g1, g2 are required unless GLM_ALPHA_ONLY");
-    if (!(flags & GLM_RAYS_ORDERED)) {
+    {
         const size_t need = ray_layout(nrays).bytes;
         if (!workspace || workspace_bytes < need)
             return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_workspace_bytes(nrays) = " + std::to_string(need));
@@ -216,7 +216,7 @@ glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* 
     if (nrays == 0) return GLM_OK;
     if (!rx || !ry || !ga1 || !ga2) return fail(GLM_EINVAL, "rx, ry, ga1, ga2 must be device pointers");
     if (flags & ~(GLM_NO_KAHAN | GLM_RAYS_ORDERED | GLM_ALPHA_ONLY)) return fail(GLM_EINVAL, "unknown flag bits");
-    if (!(flags & GLM_RAYS_ORDERED)) {
+    {
         const size_t need = ray_layout(nrays).bytes;
         if (!workspace || workspace_bytes < need)
             return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_workspace_bytes(nrays) = " + std::to_string(need));

@@ -203,14 +203,77 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
     }
 }
 
-__device__ inline int xcd_remap(int b, int nb)
+// The walk of a preorder range [c0, c1) of boxes: every ancestor of a box in
+// the range is either in the range or an ancestor of c0.  A lane that accepts
+// an ancestor of c0 skips that ancestor's whole subtree; returns the preorder
+// index at which the lane becomes active (its current skip if none).
+__device__ inline int ancestor_skip(const TreeDev& T, double X, double Y, int c0, int skip)
 {
-    // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of ray groups so that its L2 sees neighbouring rays
-    constexpr int nx = 8;
-    const int per = nb / nx, rem = nb % nx;
-    const int x = b % nx, k = b / nx;
-    return x * per + (x < rem ? x : rem) + k;
+    int a = 0;
+    while (a < c0) {
+        a = __builtin_amdgcn_readfirstlane(a);
+        const CellHdr ha = T.hdr[a];
+        double w1, w2;
+        const double d2 = sqdist(X, Y, ha.cx, ha.cy, &w1, &w2);
+        if (skip == 0 && d2 > ha.rcut2) skip = ha.next;
+        int ch = a + 1; // the child of a whose subtree holds c0
+        for (int guard = 0; guard < 4; ++guard) {
+            const int nx = T.hdr[ch].next;
+            if (c0 < nx) break;
+            ch = nx;
+        }
+        a = ch > a ? ch : a + 1;
+    }
+    return skip;
+}
+
+// Box range [c0, c1) of split k of K: everything before box B, K-2 equal
+// slices of B's subtree [B, NB), everything after it (B = the deepest box
+// holding all rays of the launch, so that the slices share the work).
+__device__ inline void split_range(int k, int K, int B, int NB, int nc, int* c0, int* c1)
+{
+    if (K == 1) {
+        *c0 = 0;
+        *c1 = nc;
+        return;
+    }
+    if (k == 0) {
+        *c0 = 0;
+        *c1 = B;
+        return;
+    }
+    if (k == K - 1) {
+        *c0 = NB;
+        *c1 = nc;
+        return;
+    }
+    const int64_t w = NB - B;
+    *c0 = B + (int)((int64_t)(k - 1) * w / (K - 2));
+    *c1 = B + (int)((int64_t)k * w / (K - 2));
+}
+
+// Work of one wavefront in a walk launch over `groups` ray groups, each walked
+// by K wavefronts (one per box range).  Workgroups are dispatched round-robin
+// over the 8 XCDs: each XCD takes a contiguous chunk of ray groups (its L2 then
+// holds the boxes of neighbouring rays), and inside an XCD the waves run
+// range-major, so that the first range of every group is dispatched first.
+constexpr int kXcds = 8;
+
+__host__ __device__ inline int64_t walk_grid_blocks(int64_t groups, int K)
+{
+    const int64_t gx = (groups + kXcds - 1) / kXcds;
+    return kXcds * ((K * gx + kBlock / kWave - 1) / (kBlock / kWave));
+}
+
+// b: workgroup index, w: wave in the workgroup (both wave-uniform).  Returns
+// false for the waves of the padded grid that have no work.
+__device__ inline bool walk_task(int b, int w, int64_t groups, int K, int* k, int64_t* group)
+{
+    const int64_t gx = (groups + kXcds - 1) / kXcds;
+    const int64_t wj = (int64_t)(b / kXcds) * (kBlock / kWave) + w;
+    *k = (int)(wj / gx);
+    *group = (int64_t)(b % kXcds) * gx + wj % gx;
+    return *k < K && *group < groups;
 }
 
 __device__ inline double wave_min(double v)

@@ -36,7 +36,8 @@ struct WalkMode {
 };
 
 template <int P, bool AONLY, int MODE>
-__device__ inline void walk_group(const TreeDev& T, double X, double Y, bool valid, int lane, Acc& A, int cnt[4])
+__device__ inline void walk_group(const TreeDev& T, double X, double Y, bool valid, int lane, Acc& A, int cnt[4],
+                                  int c0, int c1)
 {
     constexpr bool KAHAN = WalkMode<MODE>::kahan;
     constexpr bool STATS = WalkMode<MODE>::stats;
@@ -44,9 +45,9 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
     const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
     int n_vis = 0, n_acc = 0, n_dir = 0, n_hit = 0;
     int skip = valid ? 0 : 0x7fffffff;
-    const int nc = T.ncells;
-    int cur = 0;
-    while (cur < nc) {
+    if (c0 > 0) skip = ancestor_skip(T, X, Y, c0, skip);
+    int cur = c0;
+    while (cur < c1) {
         cur = __builtin_amdgcn_readfirstlane(cur);
         const CellHdr h = T.hdr[cur];
         const bool act = cur >= skip;
@@ -109,8 +110,8 @@ template <bool AONLY, bool STATS>
 __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, const WalkOut& out)
 {
     // fold the FP64 balance of the big-particle point terms into the result
-    out.a1[o] = (float)((double)A.a1 + A.b1);
-    out.a2[o] = (float)((double)A.a2 + A.b2);
+    out.a1[o] = (float)(((double)A.a1 - (double)A.c1) + A.b1);
+    out.a2[o] = (float)(((double)A.a2 - (double)A.c2) + A.b2);
     if (!AONLY) {
         if (out.k) out.k[o] = A.k;
         if (out.g1) out.g1[o] = (float)((double)A.g1 + A.bg1);
@@ -127,18 +128,87 @@ __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, cons
 template <int P, bool AONLY, int MODE>
 __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __restrict__ rxs,
                                                 const double* __restrict__ rys, const uint32_t* __restrict__ rperm,
-                                                int64_t nrays, WalkOut out)
+                                                int64_t nrays, WalkOut out, int K, Partial* __restrict__ parts,
+                                                const int* __restrict__ split_box)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t r = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t groups = (nrays + kWave - 1) / kWave;
+    // wave-uniform work item (kept in SGPRs): box range k, ray group grp
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    int k;
+    int64_t grp;
+    if (!walk_task(blockIdx.x, w, groups, K, &k, &grp)) return;
+    const int64_t r = grp * kWave + lane;
     const bool valid = r < nrays;
-    if (!__any(valid)) return;
     const double X = valid ? rxs[r] : 0.0, Y = valid ? rys[r] : 0.0;
+    const int nc = T.ncells;
+    int c0, c1;
+    if (K > 1) {
+        const int B = __builtin_amdgcn_readfirstlane(*split_box);
+        if (B >= 0) {
+            split_range(k, K, B, T.hdr[B].next, nc, &c0, &c1);
+        } else { // no split: the first range takes every box
+            c0 = 0;
+            c1 = k == 0 ? nc : 0;
+        }
+    } else {
+        c0 = 0;
+        c1 = nc;
+    }
     Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
     int cnt[4];
-    walk_group<P, AONLY, MODE>(T, X, Y, valid, lane, A, cnt);
+    walk_group<P, AONLY, MODE>(T, X, Y, valid, lane, A, cnt, c0, c1);
     if (!valid) return;
-    write_out<AONLY, WalkMode<MODE>::stats>(A, cnt, rperm ? (int64_t)rperm[r] : r, out);
+    if (K == 1) {
+        write_out<AONLY, WalkMode<MODE>::stats>(A, cnt, rperm ? (int64_t)rperm[r] : r, out);
+        return;
+    }
+    Partial q;
+    q.a1 = A.a1;
+    q.c1 = A.c1;
+    q.a2 = A.a2;
+    q.c2 = A.c2;
+    q.k = A.k;
+    q.g1 = A.g1;
+    q.g2 = A.g2;
+    q.pad = 0.0f;
+    q.b1 = A.b1;
+    q.b2 = A.b2;
+    q.bg1 = A.bg1;
+    q.bg2 = A.bg2;
+    for (int i = 0; i < 4; ++i) q.cnt[i] = WalkMode<MODE>::stats ? cnt[i] : 0;
+    parts[(int64_t)k * nrays + r] = q;
+}
+
+// Per ray, the partial sums of the K box ranges in range order.
+template <bool AONLY>
+__global__ __launch_bounds__(kBlock) void k_walk_merge(const Partial* __restrict__ parts, int K, int64_t nrays,
+                                                      const uint32_t* __restrict__ rperm, WalkOut out)
+{
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nrays) return;
+    double a1 = 0.0, a2 = 0.0, g1 = 0.0, g2 = 0.0;
+    float ka = 0.0f;
+    int c[4] = {0, 0, 0, 0};
+    for (int k = 0; k < K; ++k) {
+        const Partial& q = parts[(int64_t)k * nrays + r];
+        a1 += ((double)q.a1 - (double)q.c1) + q.b1;
+        a2 += ((double)q.a2 - (double)q.c2) + q.b2;
+        ka += q.k;
+        g1 += (double)q.g1 + q.bg1;
+        g2 += (double)q.g2 + q.bg2;
+        for (int i = 0; i < 4; ++i) c[i] += q.cnt[i];
+    }
+    const int64_t o = rperm ? (int64_t)rperm[r] : r;
+    out.a1[o] = (float)a1;
+    out.a2[o] = (float)a2;
+    if (!AONLY) {
+        if (out.k) out.k[o] = ka;
+        if (out.g1) out.g1[o] = (float)g1;
+        if (out.g2) out.g2[o] = (float)g2;
+    }
+    if (out.counts)
+        for (int i = 0; i < 4; ++i) out.counts[4 * o + i] = c[i];
 }
 
 // Persistent walk over many lenses: every wavefront takes (lens, 64-ray group)
@@ -170,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __rest
         const double X = valid ? xs[gi] : 0.0, Y = valid ? ys[gi] : 0.0;
         Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
         int cnt[4];
-        walk_group<P, AONLY, MODE>(L.tree, X, Y, valid, lane, A, cnt);
+        walk_group<P, AONLY, MODE>(L.tree, X, Y, valid, lane, A, cnt, 0, L.tree.ncells);
         if (valid) write_out<AONLY, false>(A, cnt, (int64_t)perm[gi] - L.ray_off, L.out);
     }
 }
@@ -268,25 +338,57 @@ __global__ __launch_bounds__(kBlock) void k_ray_gather(const uint32_t* __restric
     ys[k] = y[perm[k]];
 }
 
+// The deepest box whose square holds the rays' bounding box (one thread);
+// -1 when the rays cover under 5% of the root square: their work then sits in
+// a small part of the tree and splitting by box ranges would not spread it.
+__global__ void k_split_box(BoxArrays b, const int32_t* __restrict__ next, double x0, double y0, double S,
+                            const double* __restrict__ bb, int ncells, int* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if ((bb[1] - bb[0]) * (bb[3] - bb[2]) < 0.05 * S * S) {
+        *out = -1;
+        return;
+    }
+    int c = 0;
+    for (int guard = 0; guard <= kMaxLevel; ++guard) {
+        if (b.leaf[c]) break;
+        int found = -1;
+        for (int ch = c + 1, n = 0; ch < next[c] && n < 4; ch = next[ch] > ch ? next[ch] : ch + 1, ++n) {
+            const double side = ldexp(S, -b.level[ch]);
+            const double bx0 = x0 + (double)b.ix[ch] * side, by0 = y0 + (double)b.iy[ch] * side;
+            if (bb[0] >= bx0 && bb[1] < bx0 + side && bb[2] >= by0 && bb[3] < by0 + side) {
+                found = ch;
+                break;
+            }
+        }
+        if (found < 0) break;
+        c = found;
+    }
+    *out = c < ncells ? c : 0;
+}
+
 template <int P, bool AONLY>
 void launch_walk(const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm, int64_t nrays,
-                 const WalkOut& out, int mode, hipStream_t st)
+                 const WalkOut& out, int mode, int K, Partial* parts, const int* split_box, hipStream_t st)
 {
-    const dim3 g(ceil_div(nrays, kBlock)), b(kBlock);
+    const dim3 g((unsigned)walk_grid_blocks((nrays + kWave - 1) / kWave, K)), b(kBlock);
     if (mode == 1)
-        hipLaunchKernelGGL((k_walk<P, AONLY, 1>), g, b, 0, st, T, rxs, rys, rperm, nrays, out);
+        hipLaunchKernelGGL((k_walk<P, AONLY, 1>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, K, parts, split_box);
     else if (mode == 2)
-        hipLaunchKernelGGL((k_walk<P, AONLY, 2>), g, b, 0, st, T, rxs, rys, rperm, nrays, out);
+        hipLaunchKernelGGL((k_walk<P, AONLY, 2>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, K, parts, split_box);
     else
-        hipLaunchKernelGGL((k_walk<P, AONLY, 0>), g, b, 0, st, T, rxs, rys, rperm, nrays, out);
+        hipLaunchKernelGGL((k_walk<P, AONLY, 0>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, K, parts, split_box);
+    if (K > 1)
+        hipLaunchKernelGGL((k_walk_merge<AONLY>), dim3(ceil_div(nrays, kBlock)), b, 0, st, parts, K, nrays, rperm, out);
 }
 
 template <bool AONLY>
 void dispatch_walk(int p, const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm,
-                   int64_t nrays, const WalkOut& out, int mode, hipStream_t st)
+                   int64_t nrays, const WalkOut& out, int mode, int K, Partial* parts, const int* split_box,
+                   hipStream_t st)
 {
 #define GLM_CASE(PP) \
-    case PP: launch_walk<PP, AONLY>(T, rxs, rys, rperm, nrays, out, mode, st); break;
+    case PP: launch_walk<PP, AONLY>(T, rxs, rys, rperm, nrays, out, mode, K, parts, split_box, st); break;
     switch (p) {
         GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
         GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
@@ -309,6 +411,9 @@ RayLayout ray_layout(int64_t nrays)
     L.ys = a.take(8ull * nrays);
     L.hist = a.take(4ull * radix_hist_words(nrays));
     L.part = a.take(sizeof(double) * 4 * 257);
+    L.sbox = a.take(64);
+    L.split = walk_split(nrays);
+    L.parts = a.take(sizeof(Partial) * (size_t)split_slots(nrays));
     L.bytes = a.size;
     return L;
 }
@@ -538,25 +643,53 @@ glm_status shoot_batched_device(const BatchLens* host_table, int nlens, int orde
     return GLM_OK;
 }
 
+glm_status split_box_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, void* ws,
+                            const RayLayout& L, bool have_bbox, int** out, hipStream_t st)
+{
+    char* W = static_cast<char*>(ws);
+    double* part = reinterpret_cast<double*>(W + L.part);
+    const int nbb = 256;
+    if (!have_bbox) {
+        hipLaunchKernelGGL(k_ray_bbox, dim3(nbb), dim3(kBlock), 0, st, rx, ry, nrays, part);
+        hipLaunchKernelGGL(k_ray_root, dim3(1), dim3(kBlock), 0, st, part, nbb, part + 4 * nbb);
+    }
+    int* sb = reinterpret_cast<int*>(W + L.sbox);
+    hipLaunchKernelGGL(k_split_box, dim3(1), dim3(1), 0, st, ts.b, ts.b.next, ts.x0, ts.y0, ts.side, part + 4 * nbb,
+                       ts.ncells, sb);
+    GLM_HIP(hipGetLastError());
+    *out = sb;
+    return GLM_OK;
+}
+
 glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, float* a1,
                         float* a2, float* k, float* g1, float* g2, int32_t* counts, uint32_t flags, void* ws,
                         hipStream_t st)
 {
     if (nrays == 0) return GLM_OK;
     StagedRays sr{rx, ry, nullptr};
+    const RayLayout L = ray_layout(nrays);
     if (!(flags & GLM_RAYS_ORDERED)) {
-        const RayLayout L = ray_layout(nrays);
         glm_status rc = stage_rays(rx, ry, nrays, ws, L, &sr, st);
+        if (rc != GLM_OK) return rc;
+    }
+    // box ranges per group: never more than one range per 64 boxes
+    int K = L.split;
+    while (K > 1 && (int64_t)K * 64 > ts.ncells) --K;
+    if (K < 4) K = 1;
+    Partial* parts = K > 1 ? reinterpret_cast<Partial*>(static_cast<char*>(ws) + L.parts) : nullptr;
+    int* split_box = nullptr;
+    if (K > 1) {
+        glm_status rc = split_box_device(ts, rx, ry, nrays, ws, L, !(flags & GLM_RAYS_ORDERED), &split_box, st);
         if (rc != GLM_OK) return rc;
     }
     // counts requested: Kahan walk with counters; else plain or Kahan walk
     const int mode = counts ? 1 : ((flags & GLM_NO_KAHAN) ? 2 : 0);
     if (flags & GLM_ALPHA_ONLY)
         dispatch_walk<true>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays,
-                            WalkOut{a1, a2, nullptr, nullptr, nullptr, counts}, mode, st);
+                            WalkOut{a1, a2, nullptr, nullptr, nullptr, counts}, mode, K, parts, split_box, st);
     else
         dispatch_walk<false>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays, WalkOut{a1, a2, k, g1, g2, counts},
-                             mode, st);
+                             mode, K, parts, split_box, st);
     GLM_HIP(hipGetLastError());
     return GLM_OK;
 }

@@ -32,9 +32,47 @@ glm_status refine_round_device(double* cx, double* cy, double* side, const float
                                const float* g2, int64_t ncells, int64_t nrefine, int32_t* refined, void* ws,
                                hipStream_t st);
 
+// Wavefronts per 64-ray group.  A small launch (few groups) splits the
+// preorder box array into K ranges walked by separate wavefronts, so that
+// about kSplitWaves wavefronts keep the chip busy; their partial sums are
+// merged per ray in range order.  A split has a range before, K - 2 slices
+// of, and a range after one box: below kMinSplit ranges it rarely spreads the
+// work, so there is none.
+constexpr int64_t kSplitWaves = 16384;
+constexpr int64_t kMinSplit = 4;
+constexpr int64_t kMaxSplit = 32;
+
+inline int walk_split(int64_t nrays)
+{
+    const int64_t groups = (nrays + 63) / 64;
+    if (groups <= 0) return 1;
+    int64_t k = (kSplitWaves + groups - 1) / groups;
+    if (k > kMaxSplit) k = kMaxSplit;
+    if (k < kMinSplit) k = 1;
+    return (int)k;
+}
+
+// Partial-sum slots (K x rays) to reserve for up to nrays rays: a bound that
+// grows with nrays, so that a workspace sized for a launch also fits every
+// smaller one (K * groups < kSplitWaves + kSplitWaves / kMinSplit).
+inline int64_t split_slots(int64_t nrays)
+{
+    const int64_t groups = (nrays + 63) / 64;
+    const int64_t cap = kSplitWaves + kSplitWaves / kMinSplit;
+    return 64 * (kMaxSplit * groups < cap ? kMaxSplit * groups : cap);
+}
+
+// Partial sums of one ray over one range of boxes (merged by k_walk_merge).
+struct alignas(16) Partial {
+    float a1, c1, a2, c2, k, g1, g2, pad;
+    double b1, b2, bg1, bg2;
+    int32_t cnt[4];
+};
+
 // Byte offsets of the ray workspace pieces.
 struct RayLayout {
-    size_t k0, k1, v0, v1, xs, ys, hist, part, bytes;
+    size_t k0, k1, v0, v1, xs, ys, hist, part, sbox, parts, bytes;
+    int split;
 };
 RayLayout ray_layout(int64_t nrays);
 
@@ -48,6 +86,11 @@ struct StagedRays {
 // each 64-ray group is spatially compact.
 glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* ws, const RayLayout& L,
                       StagedRays* out, hipStream_t st);
+
+// Index of the deepest box holding the rays' bounding box, written to the
+// workspace (computes the box unless stage_rays did).
+glm_status split_box_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, void* ws,
+                            const RayLayout& L, bool have_bbox, int** out, hipStream_t st);
 
 glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, float* a1,
                         float* a2, float* k, float* g1, float* g2, int32_t* counts, uint32_t flags, void* ws,

@@ -30,7 +30,12 @@ def test_batched_equals_per_lens_and_oracle(ora):
         if rx.size == 0:
             continue
         got = to_np(o)
-        np.testing.assert_array_equal(got, shoot(t, rx, ry))  # identical per-ray work
+        # the same per-ray decisions; a single small walk may split the box
+        # array over several wavefronts, which only regroups the FP32 sums
+        single, cnt = shoot(t, rx, ry, counts=True)
+        np.testing.assert_allclose(got[:, :2], single[:, :2], rtol=2e-6, atol=1e-7 * np.abs(single[:, :2]).max())
+        np.testing.assert_allclose(got[:, 2], single[:, 2], rtol=2e-6, atol=1e-7 * np.abs(single[:, 2]).max())
+        np.testing.assert_allclose(got[:, 3:], single[:, 3:], rtol=1e-5, atol=1e-6 * np.abs(single[:, 3:]).max())
         idx = synth.sample_rays(rx, ry, 128, 5)
         ref = ora.direct(l.x, l.y, l.m, l.s, l.q, rx[idx], ry[idx])
         ea, ek, eg = rel_err(got[idx], ref)

@@ -158,6 +158,41 @@ def test_edge_cases(ora):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("leaf,order", [(64, 12), (8, 0), (2, 1)])
+def test_parameter_extremes(ora, leaf, order):
+    """Largest leaf and order, the monopole alone, and near-singleton leaves."""
+    lens = mixed_lens(6000, 27)
+    say(f"[gpu] parameter extremes: leaf={leaf} p={order}")
+    T, tree = compare_topology(ora, lens, 0.45, leaf, order)
+    rx, ry = synth.ray_grid(45)
+    ref, rcnt = T.shoot(rx, ry, counts=True)
+    got, gcnt = shoot(tree, rx, ry, counts=True)
+    np.testing.assert_array_equal(gcnt, rcnt[:, [0, 1, 2, 4]])
+    ea, ek, eg = rel_err(got, ref)
+    stats("alpha vs oracle tree", ea)
+    assert np.quantile(ea, 0.999) < 1e-5 and ea.max() < 1e-4
+    ok = np.abs(ref[:, 2]) > 0
+    assert np.all(ek[ok] < 1e-4)
+
+
+def test_point_masses_without_smoothing_array(ora):
+    """s = NULL: every particle is a point mass; kappa is exactly zero."""
+    import paper_1312_1128_amd as g
+
+    lens = synth.point_masses(3000, 29)
+    say("[gpu] point masses, s = NULL")
+    tree = g.Tree().build(dev(lens.x), dev(lens.y), dev(lens.m), None, theta=0.5, q=3.0, leaf_size=8, order=4)
+    assert tree.info()["nlisted"] == 0
+    rx, ry = synth.ray_grid(40)
+    got, gcnt = shoot(tree, rx, ry, counts=True)
+    T = ora.Tree(lens.x, lens.y, lens.m, np.zeros(lens.n), 3.0, 0.5, 8, 4)
+    ref, rcnt = T.shoot(rx, ry, counts=True)
+    np.testing.assert_array_equal(gcnt, rcnt[:, [0, 1, 2, 4]])
+    assert np.all(got[:, 2] == 0.0)
+    ea, _, eg = rel_err(got, ref)
+    assert ea.max() < 1e-5 and eg.max() < 1e-4
+
+
 def test_determinism_and_flags(ora):
     import paper_1312_1128_amd as g
 
@@ -178,6 +213,26 @@ def test_determinism_and_flags(ora):
     nk = shoot(tree, rx, ry, kahan=False)  # plain FP32 summation of alpha: ~sqrt(terms) eps
     ea = np.linalg.norm(nk[:, :2] - a[:, :2], axis=1) / np.linalg.norm(a[:, :2], axis=1)
     assert ea.max() < 1e-5
+
+
+def test_split_walk_matches_single_range(ora):
+    """Few rays: the walk splits the box array over several wavefronts per ray
+    group; same decisions and counts as the oracle tree, sums regrouped only."""
+    lens = synth.nfw_halo(30000, 45)
+    rx, ry = synth.uniform_points(700, 46)
+    say("[gpu] split walk (700 rays)")
+    tree = build(lens, 0.3, 8, 6)
+    got, cnt = shoot(tree, rx, ry, counts=True)
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.3, 8, 6)
+    ref, rc = T.shoot(rx, ry, counts=True)
+    np.testing.assert_array_equal(cnt, rc[:, [0, 1, 2, 4]])
+    ea, ek, eg = rel_err(got, ref)
+    assert ea.max() < 1e-5 and ek.max() < 1e-5
+    # the split walk inside one big launch gives the same values per ray
+    big_x = np.concatenate([rx, synth.uniform_points(2_000_000, 47)[0]])
+    big_y = np.concatenate([ry, synth.uniform_points(2_000_000, 47)[1]])
+    got_big = shoot(tree, big_x, big_y)[: rx.size]
+    np.testing.assert_allclose(got_big[:, :2], got[:, :2], rtol=2e-6, atol=1e-7 * np.abs(got[:, :2]).max())
 
 
 def test_bad_inputs_are_rejected():
