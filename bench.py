@@ -18,11 +18,19 @@ Printed as one JSON line, with:
                   counts times fixed per-interaction weights;
   cpu_baseline -- the FP64 brute-force oracle on a bounded ray sample on the
                   host cores (also yields the sample's error vs FP64);
-  extras       -- build time, walk-only rate, plain GPU direct sum rates.
+  extras       -- build time, walk-only rate, plain GPU direct sum rates, and
+                  the fitting (forward + adjoint), refinement and 64-lens
+                  workloads (--no-extras leaves these out).
+
+`roofline.traffic` is the walk's HBM bytes per launch from the committed
+rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the counters'
+reading for a plain 1 GiB device copy, which every run performs last); it is
+null when the walk's sources differ from those the counters were taken on.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -41,6 +49,35 @@ THETA, ORDER, LEAF = 0.3, 8, 8
 # order p, leaf particle, big-particle correction
 def flops_per_ray(counts: np.ndarray, p: int) -> np.ndarray:
     return 5.0 * counts[:, 0] + (20.0 + 16.0 * p) * counts[:, 1] + 22.0 * counts[:, 2] + 60.0 * counts[:, 3]
+
+
+WALK_SOURCES = ["walk.hip", "walk.hpp", "eval.hpp", "common.hpp"]
+HBM_PROFILE = os.path.join(ROOT, "profiles", "k_walk_nfw1e6_grid2048_hbm.txt")
+
+
+def walk_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        with open(os.path.join(ROOT, "paper_1312_1128_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per walk launch from the committed counter summary, or None
+    when there is none or the walk has changed since it was taken."""
+    try:
+        with open(HBM_PROFILE) as fh:
+            kv = dict(l.split(":", 1) for l in fh.read().splitlines() if ":" in l and not l.startswith(" "))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("walk_sources_sha256") != walk_sources_sha256():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -62,6 +99,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary workloads (direct sum, fitting, refinement, 64 lenses)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -129,101 +168,118 @@ def main():
     log(f"walk: {walk_ms:.3f} ms, {flop:.3e} algorithmic FLOP -> {achieved:.2f} TFLOP/s "
         f"({achieved / PEAK_FP32_TFLOPS:.3f} of FP32 peak); counts/ray {cnt.mean(0)}")
 
-    # plain GPU direct sum on a slice of the rays
-    nd = 262144
-    res = {}
-    for fp64 in (False, True):
-        g.shoot_direct(x, y, m, s, lens.q, rx[:256], ry[:256], fp64=fp64)
+    extras = {}
+    if not args.no_extras:
+        # plain GPU direct sum on a slice of the rays
+        nd = 262144
+        res = {}
+        for fp64 in (False, True):
+            g.shoot_direct(x, y, m, s, lens.q, rx[:256], ry[:256], fp64=fp64)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            g.shoot_direct(x, y, m, s, lens.q, rx[:nd], ry[:nd], fp64=fp64)
+            torch.cuda.synchronize()
+            res[fp64] = nd / (time.perf_counter() - t)
+        log(f"direct sum: fp32 {res[False]:.3e} rays/s, fp64 {res[True]:.3e} rays/s")
+
+        # forward + adjoint on the lens-fitting workload: 1e5 particles, 1e5 rays,
+        # L = sum |x - alpha - beta*|^2 (step = build + alpha walk + adjoint walk)
+        lens5 = synth.nfw_halo(100_000, synth.BASE_SEED + 5)
+        r5x, r5y = synth.uniform_points(100_000, synth.BASE_SEED + 6)
+        x5, y5, m5, s5, rx5, ry5 = (d(a) for a in (lens5.x, lens5.y, lens5.m, lens5.s, r5x, r5y))
+        bx5 = rx5 - 0.1 * rx5  # fixed target source positions (only the data flow matters for timing)
+        by5 = ry5 - 0.1 * ry5
+        tree5 = g.Tree()
+        ws5 = torch.empty(g.workspace_bytes(rx5.numel()), dtype=torch.uint8, device=dev)
+        out5 = {k: torch.empty(rx5.numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2"]}
+        grads5 = [torch.zeros(lens5.n, dtype=torch.float64, device=dev) for _ in range(4)]
+
+        def step5():
+            tree5.build(x5, y5, m5, s5, theta=THETA, q=lens5.q, leaf_size=LEAF, order=ORDER)
+            g.shoot(tree5, rx5, ry5, out=out5, workspace=ws5, alpha_only=True)
+            ga1 = (-2.0 * (rx5 - out5["a1"] - bx5)).float()
+            ga2 = (-2.0 * (ry5 - out5["a2"] - by5)).float()
+            for t_ in grads5:
+                t_.zero_()
+            g.shoot_adjoint(tree5, rx5, ry5, ga1, ga2, *grads5, workspace=ws5)
+
+        for _ in range(2):
+            step5()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        g.shoot_direct(x, y, m, s, lens.q, rx[:nd], ry[:nd], fp64=fp64)
+        n5 = max(3, args.steps)
+        for _ in range(n5):
+            step5()
         torch.cuda.synchronize()
-        res[fp64] = nd / (time.perf_counter() - t)
-    log(f"direct sum: fp32 {res[False]:.3e} rays/s, fp64 {res[True]:.3e} rays/s")
+        fa_ms = 1e3 * (time.perf_counter() - t) / n5
+        log(f"fwd+adjoint (1e5 particles, 1e5 rays): {fa_ms:.3f} ms -> {rx5.numel() / (fa_ms * 1e-3):.4e} rays/s")
 
-    # forward + adjoint on the lens-fitting workload: 1e5 particles, 1e5 rays,
-    # L = sum |x - alpha - beta*|^2 (step = build + alpha walk + adjoint walk)
-    lens5 = synth.nfw_halo(100_000, synth.BASE_SEED + 5)
-    r5x, r5y = synth.uniform_points(100_000, synth.BASE_SEED + 6)
-    x5, y5, m5, s5, rx5, ry5 = (d(a) for a in (lens5.x, lens5.y, lens5.m, lens5.s, r5x, r5y))
-    bx5 = rx5 - 0.1 * rx5  # fixed target source positions (only the data flow matters for timing)
-    by5 = ry5 - 0.1 * ry5
-    tree5 = g.Tree()
-    ws5 = torch.empty(g.workspace_bytes(rx5.numel()), dtype=torch.uint8, device=dev)
-    out5 = {k: torch.empty(rx5.numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2"]}
-    grads5 = [torch.zeros(lens5.n, dtype=torch.float64, device=dev) for _ in range(4)]
-
-    def step5():
-        tree5.build(x5, y5, m5, s5, theta=THETA, q=lens5.q, leaf_size=LEAF, order=ORDER)
-        g.shoot(tree5, rx5, ry5, out=out5, workspace=ws5, alpha_only=True)
-        ga1 = (-2.0 * (rx5 - out5["a1"] - bx5)).float()
-        ga2 = (-2.0 * (ry5 - out5["a2"] - by5)).float()
-        for t_ in grads5:
-            t_.zero_()
-        g.shoot_adjoint(tree5, rx5, ry5, ga1, ga2, *grads5, workspace=ws5)
-
-    for _ in range(2):
-        step5()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    n5 = max(3, args.steps)
-    for _ in range(n5):
-        step5()
-    torch.cuda.synchronize()
-    fa_ms = 1e3 * (time.perf_counter() - t) / n5
-    log(f"fwd+adjoint (1e5 particles, 1e5 rays): {fa_ms:.3f} ms -> {rx5.numel() / (fa_ms * 1e-3):.4e} rays/s")
-
-    # microlensing refinement: halo + 1e5 stars, 256^2 base cells over the star
-    # patch, 6 rounds refining the top 10% by 3x3, all rounds in one HIP graph
-    lens3, cx3, cy3, side3 = synth.workload_microlensing()
-    x3, y3, m3, s3 = d(lens3.x), d(lens3.y), d(lens3.m), d(lens3.s)
-    tree3 = g.Tree().build(x3, y3, m3, s3, theta=THETA, q=lens3.q, leaf_size=LEAF, order=ORDER)
-    run3 = g.RefinementRun(tree3, d(cx3), d(cy3), d(side3), g.refine_schedule(cx3.size))
-    n3 = run3.run()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(3):
-        run3.run()
-    torch.cuda.synchronize()
-    eager3 = (time.perf_counter() - t) / 3
-    graph3 = run3.capture()
-    graph3.replay()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(3):
+        # microlensing refinement: halo + 1e5 stars, 256^2 base cells over the star
+        # patch, 6 rounds refining the top 10% by 3x3, all rounds in one HIP graph
+        lens3, cx3, cy3, side3 = synth.workload_microlensing()
+        x3, y3, m3, s3 = d(lens3.x), d(lens3.y), d(lens3.m), d(lens3.s)
+        tree3 = g.Tree().build(x3, y3, m3, s3, theta=THETA, q=lens3.q, leaf_size=LEAF, order=ORDER)
+        run3 = g.RefinementRun(tree3, d(cx3), d(cy3), d(side3), g.refine_schedule(cx3.size))
+        n3 = run3.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            run3.run()
+        torch.cuda.synchronize()
+        eager3 = (time.perf_counter() - t) / 3
+        graph3 = run3.capture()
         graph3.replay()
-    torch.cuda.synchronize()
-    graph3_s = (time.perf_counter() - t) / 3
-    log(f"refinement (6 rounds, {n3} rays): graph {1e3 * graph3_s:.2f} ms, eager {1e3 * eager3:.2f} ms "
-        f"-> {n3 / graph3_s:.4e} rays/s")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            graph3.replay()
+        torch.cuda.synchronize()
+        graph3_s = (time.perf_counter() - t) / 3
+        log(f"refinement (6 rounds, {n3} rays): graph {1e3 * graph3_s:.2f} ms, eager {1e3 * eager3:.2f} ms "
+            f"-> {n3 / graph3_s:.4e} rays/s")
 
-    # 64 independent lenses in one persistent launch
-    lenses4 = synth.workload_batched_lenses(64)
-    trees4, rays4 = [], []
-    for l4, r4x, r4y in lenses4:
-        trees4.append(g.Tree().build(d(l4.x), d(l4.y), d(l4.m), d(l4.s), theta=THETA, q=l4.q, leaf_size=LEAF,
-                                     order=ORDER))
-        rays4.append((d(r4x), d(r4y)))
-    R4 = sum(r[0].numel() for r in rays4)
-    outs4 = [{k: torch.empty(r[0].numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2", "kappa", "g1", "g2"]}
-             for r in rays4]
-    ws4 = torch.empty(g.batch.batched_workspace_bytes([r[0].numel() for r in rays4]), dtype=torch.uint8, device=dev)
-    g.shoot_batched(trees4, rays4, outs=outs4, workspace=ws4)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(3):
+        # 64 independent lenses in one persistent launch
+        lenses4 = synth.workload_batched_lenses(64)
+        trees4, rays4 = [], []
+        for l4, r4x, r4y in lenses4:
+            trees4.append(g.Tree().build(d(l4.x), d(l4.y), d(l4.m), d(l4.s), theta=THETA, q=l4.q, leaf_size=LEAF,
+                                         order=ORDER))
+            rays4.append((d(r4x), d(r4y)))
+        R4 = sum(r[0].numel() for r in rays4)
+        outs4 = [{k: torch.empty(r[0].numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2", "kappa", "g1", "g2"]}
+                 for r in rays4]
+        ws4 = torch.empty(g.batch.batched_workspace_bytes([r[0].numel() for r in rays4]), dtype=torch.uint8, device=dev)
         g.shoot_batched(trees4, rays4, outs=outs4, workspace=ws4)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            g.shoot_batched(trees4, rays4, outs=outs4, workspace=ws4)
+        torch.cuda.synchronize()
+        b4 = (time.perf_counter() - t) / 3
+        ws4b = torch.empty(g.workspace_bytes(max(r[0].numel() for r in rays4)), dtype=torch.uint8, device=dev)
+        t = time.perf_counter()
+        for _ in range(3):
+            for tr, (r4x, r4y), o4 in zip(trees4, rays4, outs4):
+                g.shoot(tr, r4x, r4y, out=o4, workspace=ws4b)
+        torch.cuda.synchronize()
+        l4 = (time.perf_counter() - t) / 3
+        log(f"64 lenses ({R4} rays): one persistent launch {1e3 * b4:.2f} ms ({R4 / b4:.4e} rays/s), "
+            f"per-lens launches {1e3 * l4:.2f} ms")
+        extras = {"direct_fp32_rays_per_s": res[False], "direct_fp64_rays_per_s": res[True],
+                  "fwd_adjoint_rays_per_s": rx5.numel() / (fa_ms * 1e-3), "fwd_adjoint_ms": fa_ms,
+                  "fwd_adjoint_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2",
+                  "refinement_rays": n3, "refinement_graph_ms": 1e3 * graph3_s, "refinement_eager_ms": 1e3 * eager3,
+                  "refinement_rays_per_s": n3 / graph3_s,
+                  "refinement_workload": "nfw_1e6 + 1e5 Salpeter stars, 256^2 base, 6 rounds top-10% 3x3",
+                  "batched_lenses": len(lenses4), "batched_rays": R4, "batched_ms": 1e3 * b4,
+                  "batched_rays_per_s": R4 / b4, "per_lens_launches_ms": 1e3 * l4}
+
+    # counter calibration: a plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB)
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
-    b4 = (time.perf_counter() - t) / 3
-    ws4b = torch.empty(g.workspace_bytes(max(r[0].numel() for r in rays4)), dtype=torch.uint8, device=dev)
-    t = time.perf_counter()
-    for _ in range(3):
-        for tr, (r4x, r4y), o4 in zip(trees4, rays4, outs4):
-            g.shoot(tr, r4x, r4y, out=o4, workspace=ws4b)
-    torch.cuda.synchronize()
-    l4 = (time.perf_counter() - t) / 3
-    log(f"64 lenses ({R4} rays): one persistent launch {1e3 * b4:.2f} ms ({R4 / b4:.4e} rays/s), "
-        f"per-lens launches {1e3 * l4:.2f} ms")
+    del src, dst
 
     line = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
@@ -232,19 +288,12 @@ def main():
         "config": {"workload": "nfw_1e6_particles_grid2048", "particles": lens.n, "rays": R, "theta": THETA,
                    "order": ORDER, "leaf_size": LEAF, "q": lens.q, "step": "build_tree + shoot (alpha, kappa, gamma)"},
         "roofline": {"bound": "alu", "kernel": "k_walk", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                      "kernel_ms": walk_ms, "flop_per_launch": flop},
         "extras": {"build_ms": build_ms, "walk_only_rays_per_s": R / (walk_ms * 1e-3),
                    "ncells": info["ncells"], "nlisted": info["nlisted"],
                    "counts_per_ray": dict(zip(["visited", "accepted", "leaf", "list_hits"], cnt.mean(0).tolist())),
-                   "direct_fp32_rays_per_s": res[False], "direct_fp64_rays_per_s": res[True],
-                   "fwd_adjoint_rays_per_s": rx5.numel() / (fa_ms * 1e-3), "fwd_adjoint_ms": fa_ms,
-                   "fwd_adjoint_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2",
-                   "refinement_rays": n3, "refinement_graph_ms": 1e3 * graph3_s, "refinement_eager_ms": 1e3 * eager3,
-                   "refinement_rays_per_s": n3 / graph3_s,
-                   "refinement_workload": "nfw_1e6 + 1e5 Salpeter stars, 256^2 base, 6 rounds top-10% 3x3",
-                   "batched_lenses": len(lenses4), "batched_rays": R4, "batched_ms": 1e3 * b4,
-                   "batched_rays_per_s": R4 / b4, "per_lens_launches_ms": 1e3 * l4},
+                   **extras},
     }
 
     if not args.no_cpu:
