@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_direct32(const double* __restrict__ 
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool valid = r < nr;
     const double X = valid ? rx[r] : 0.0, Y = valid ? ry[r] : 0.0;
-    Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+    Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
     int dummy = 0;
     for (int base = 0; base < n; base += kBlock) {
         const int j = base + threadIdx.x;
@@ -54,8 +54,8 @@ __global__ __launch_bounds__(kBlock) void k_direct32(const double* __restrict__ 
     a2[r] = A.a2;
     if (!AONLY) {
         ka[r] = A.k;
-        g1[r] = A.g1;
-        g2[r] = A.g2;
+        g1[r] = (float)A.g1;
+        g2[r] = (float)A.g2;
     }
     (void)A.b1;
 }

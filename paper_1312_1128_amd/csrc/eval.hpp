@@ -10,11 +10,14 @@ namespace glm {
 
 // Per-lane accumulators.  alpha is summed in FP32 with Kahan compensation;
 // the point-mass terms of big-list particles that a ray lies inside (added
-// once with each sign, see eval_particle) go to an FP64 balance where they
-// cancel without leaving FP32 rounding of size m / r behind.
+// once with each sign, see eval_particle) go to an FP64 balance (b1, b2)
+// where they cancel without leaving FP32 rounding of size m / r behind.  The
+// shear, a sum of large terms of both signs that nearly cancel near a mass
+// concentration, takes its FP32 terms into FP64 accumulators (the balanced
+// point terms included); kappa, a sum of positive terms, stays FP32.
 struct Acc {
-    float a1, c1, a2, c2, k, g1, g2;
-    double b1, b2, bg1, bg2;
+    float a1, c1, a2, c2, k;
+    double g1, g2, b1, b2;
 };
 
 // compensated (Kahan) summation step; plain FP32 addition when KAHAN is false
@@ -114,15 +117,15 @@ __device__ inline void eval_particle(const PRec& pr, double X, double Y, int mod
             A.b1 += (double)P[0];
             A.b2 += (double)P[1];
             if (!AONLY) {
-                A.bg1 += (double)P[2];
-                A.bg2 += (double)P[3];
+                A.g1 += (double)P[2];
+                A.g2 += (double)P[3];
             }
         } else {
             kadd<KAHAN>(A.a1, A.c1, P[0]);
             kadd<KAHAN>(A.a2, A.c2, P[1]);
             if (!AONLY) {
-                A.g1 += P[2];
-                A.g2 += P[3];
+                A.g1 += (double)P[2];
+                A.g2 += (double)P[3];
             }
         }
         return;
@@ -138,16 +141,16 @@ __device__ inline void eval_particle(const PRec& pr, double X, double Y, int mod
     if (!AONLY) {
         A.k += mh * e;
         const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = 2.0f * f1 * f2 * ir2;
-        A.g1 -= Gam * c2;
-        A.g2 -= Gam * s2;
+        A.g1 -= (double)(Gam * c2);
+        A.g2 -= (double)(Gam * s2);
     }
     if (mode == 1) {
         hits++;
         A.b1 -= (double)P[0];
         A.b2 -= (double)P[1];
         if (!AONLY) {
-            A.bg1 -= (double)P[2];
-            A.bg2 -= (double)P[3];
+            A.g1 -= (double)P[2];
+            A.g2 -= (double)P[3];
         }
     }
 }
@@ -198,8 +201,8 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
         const float S1 = fmaf(t1, c1, fmaf(-t2, c2, b1)), S2 = fmaf(t1, c2, fmaf(t2, c1, b2));
         const float w21 = fmaf(v1, v1, -v2 * v2), w22 = 2.0f * v1 * v2;
         const float G1 = M * fmaf(w21, S1, -w22 * S2), G2 = M * fmaf(w21, S2, w22 * S1);
-        A.g1 -= G1;
-        A.g2 += G2;
+        A.g1 -= (double)G1;
+        A.g2 += (double)G2;
     }
 }
 

@@ -114,8 +114,8 @@ __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, cons
     out.a2[o] = (float)(((double)A.a2 - (double)A.c2) + A.b2);
     if (!AONLY) {
         if (out.k) out.k[o] = A.k;
-        if (out.g1) out.g1[o] = (float)((double)A.g1 + A.bg1);
-        if (out.g2) out.g2[o] = (float)((double)A.g2 + A.bg2);
+        if (out.g1) out.g1[o] = (float)A.g1;
+        if (out.g2) out.g2[o] = (float)A.g2;
     }
     if (STATS && out.counts) {
         out.counts[4 * o + 0] = cnt[0];
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __rest
         c0 = 0;
         c1 = nc;
     }
-    Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+    Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
     int cnt[4];
     walk_group<P, AONLY, MODE>(T, X, Y, valid, lane, A, cnt, c0, c1);
     if (!valid) return;
@@ -169,13 +169,11 @@ __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __rest
     q.a2 = A.a2;
     q.c2 = A.c2;
     q.k = A.k;
+    q.pad = 0.0f;
     q.g1 = A.g1;
     q.g2 = A.g2;
-    q.pad = 0.0f;
     q.b1 = A.b1;
     q.b2 = A.b2;
-    q.bg1 = A.bg1;
-    q.bg2 = A.bg2;
     for (int i = 0; i < 4; ++i) q.cnt[i] = WalkMode<MODE>::stats ? cnt[i] : 0;
     parts[(int64_t)k * nrays + r] = q;
 }
@@ -195,8 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_merge(const Partial* __restrict
         a1 += ((double)q.a1 - (double)q.c1) + q.b1;
         a2 += ((double)q.a2 - (double)q.c2) + q.b2;
         ka += q.k;
-        g1 += (double)q.g1 + q.bg1;
-        g2 += (double)q.g2 + q.bg2;
+        g1 += q.g1;
+        g2 += q.g2;
         for (int i = 0; i < 4; ++i) c[i] += q.cnt[i];
     }
     const int64_t o = rperm ? (int64_t)rperm[r] : r;
@@ -238,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __rest
         const bool valid = rl < L.nrays;
         const int64_t gi = L.ray_off + (valid ? rl : 0);
         const double X = valid ? xs[gi] : 0.0, Y = valid ? ys[gi] : 0.0;
-        Acc A = {0, 0, 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+        Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
         int cnt[4];
         walk_group<P, AONLY, MODE>(L.tree, X, Y, valid, lane, A, cnt, 0, L.tree.ncells);
         if (valid) write_out<AONLY, false>(A, cnt, (int64_t)perm[gi] - L.ray_off, L.out);
