@@ -32,7 +32,7 @@ __device__ inline double wave_sum_d(double v) { return wave_sum<double>(v); }
 __device__ inline float wave_sum_f(float v) { return wave_sum<float>(v); }
 
 // Gradient terms of one particle for this lane, per the same cases as the
-// forward's eval_particle.  Returns FP64 (m, x, y, s) contributions in G.
+// forward's leaf_particle and list_particle.  Returns FP64 (m, x, y, s) contributions in G.
 // mode 0: leaf sum; mode 1: big-particle correction (Gaussian - point).
 __device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mode, bool act, float g1, float g2,
                                      float invC, double G[4])

@@ -37,7 +37,6 @@ __global__ __launch_bounds__(kBlock) void k_direct32(const double* __restrict__ 
     const bool valid = r < nr;
     const double X = valid ? rx[r] : 0.0, Y = valid ? ry[r] : 0.0;
     Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
-    int dummy = 0;
     for (int base = 0; base < n; base += kBlock) {
         const int j = base + threadIdx.x;
         PRec t;
@@ -46,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_direct32(const double* __restrict__ 
         tile[threadIdx.x] = t;
         __syncthreads();
         const int cnt = min(kBlock, n - base);
-        for (int k = 0; k < cnt; ++k) eval_particle<AONLY, true>(tile[k], X, Y, 0, A, dummy);
+        for (int k = 0; k < cnt; ++k) leaf_particle<AONLY, true>(tile[k], X, Y, A);
         __syncthreads();
     }
     if (!valid) return;

@@ -10,7 +10,7 @@ namespace glm {
 
 // Per-lane accumulators.  alpha is summed in FP32 with Kahan compensation;
 // the point-mass terms of big-list particles that a ray lies inside (added
-// once with each sign, see eval_particle) go to an FP64 balance (b1, b2)
+// once with each sign, see leaf_particle) go to an FP64 balance (b1, b2)
 // where they cancel without leaving FP32 rounding of size m / r behind.  The
 // shear, a sum of large terms of both signs that nearly cancel near a mass
 // concentration, takes its FP32 terms into FP64 accumulators (the balanced
@@ -91,67 +91,92 @@ __device__ inline void point_terms(float m, float f1, float f2, float ir2, float
     P[3] = -(pm * s2);
 }
 
-// One particle for this lane.
-//  mode 0 (leaf sum): an unlisted particle enters with the Gaussian kernel if
-//    the ray is inside its support, as a point mass otherwise; a listed
-//    particle enters as a point mass (its moments and leaf treat it as one).
-//  mode 1 (big-particle list of a visited box): if the ray is inside the
-//    support, add Gaussian - point (Sec. 3.2: listed particles are added
-//    individually and removed from the tree part).
-// The point part of every "inside" pair (mode 1, and mode 0 for a listed
-// particle) goes to the FP64 balance so the pair cancels exactly.
+// Accumulate alpha += coef * (f1, f2) and gamma -= Gam * (cos 2phi, sin 2phi)
+// (with ir2 = 1 / r^2: cos 2phi = (f1^2 - f2^2) ir2, sin 2phi = 2 f1 f2 ir2).
 template <bool AONLY, bool KAHAN>
-__device__ inline void eval_particle(const PRec& pr, double X, double Y, int mode, Acc& A, int& hits)
+__device__ inline void add_radial(float coef, float Gam, float f1, float f2, float ir2, Acc& A)
 {
-    double d1, d2;
-    const double r2 = sqdist(X, Y, pr.x, pr.y, &d1, &d2);
-    const bool inside = r2 < pr.qs2;
-    const bool listed = (pr.meta >> 31) != 0;
-    if (mode == 1 && !inside) return;
-    const float f1 = (float)d1, f2 = (float)d2, r2f = (float)r2;
-    const float ir2 = r2f > 0.0f ? __builtin_amdgcn_rcpf(r2f) : 0.0f;
-    float P[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (!inside || mode == 1 || listed) point_terms(pr.m, f1, f2, ir2, P);
-    if (!inside || (mode == 0 && listed)) {
-        if (inside) { // listed and inside: the list box already added Gaussian - point
-            A.b1 += (double)P[0];
-            A.b2 += (double)P[1];
-            if (!AONLY) {
-                A.g1 += (double)P[2];
-                A.g2 += (double)P[3];
-            }
-        } else {
-            kadd<KAHAN>(A.a1, A.c1, P[0]);
-            kadd<KAHAN>(A.a2, A.c2, P[1]);
-            if (!AONLY) {
-                A.g1 += (double)P[2];
-                A.g2 += (double)P[3];
-            }
-        }
-        return;
-    }
-    // Gaussian kernel (Sec. 3.1)
-    const float u = r2f * pr.h;
-    const float e = __expf(-u);
-    const float mh = pr.mC * pr.h;
-    float Acoef, Gam;
-    gauss_terms(u, e, ir2, pr.mC, mh, &Acoef, &Gam);
-    kadd<KAHAN>(A.a1, A.c1, Acoef * f1);
-    kadd<KAHAN>(A.a2, A.c2, Acoef * f2);
+    kadd<KAHAN>(A.a1, A.c1, coef * f1);
+    kadd<KAHAN>(A.a2, A.c2, coef * f2);
     if (!AONLY) {
-        A.k += mh * e;
         const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = 2.0f * f1 * f2 * ir2;
         A.g1 -= (double)(Gam * c2);
         A.g2 -= (double)(Gam * s2);
     }
-    if (mode == 1) {
-        hits++;
-        A.b1 -= (double)P[0];
-        A.b2 -= (double)P[1];
-        if (!AONLY) {
-            A.g1 -= (double)P[2];
-            A.g2 -= (double)P[3];
-        }
+}
+
+// One particle of a leaf for this lane (a direct-sum term).
+//  - listed particle: a point mass (its box's moments and leaf treat it as
+//    one).  A lane inside its support also gets Gaussian - point from the
+//    list of the box that holds it, so that lane's point part goes to the
+//    FP64 balance, where it cancels exactly.
+//  - unlisted particle: the truncated Gaussian of Sec. 3.1 inside the
+//    support, a point mass outside.
+// All cases share one select-based path (no divergent branches).  The point
+// terms are formed without FMA contraction, exactly as in point_terms, so a
+// balanced pair cancels bit for bit.
+template <bool AONLY, bool KAHAN>
+__device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A)
+{
+#pragma clang fp contract(off)
+    double d1, d2;
+    const double r2 = sqdist(X, Y, pr.x, pr.y, &d1, &d2);
+    const bool inside = r2 < pr.qs2;
+    const bool listed = (pr.meta >> 31) != 0;
+    const bool gauss = inside && !listed;  // the Gaussian kernel applies here
+    const bool balance = inside && listed; // the box list adds Gaussian - point
+    const float f1 = (float)d1, f2 = (float)d2, r2f = (float)r2;
+    const float ir2 = r2f > 0.0f ? __builtin_amdgcn_rcpf(r2f) : 0.0f;
+    const float pm = pr.m * ir2;
+    float coef = pm, Gam = pm;
+    if (__any(gauss)) {
+        const float u = r2f * pr.h;
+        const float e = __expf(-u);
+        const float mh = pr.mC * pr.h;
+        float Ag, Gg;
+        gauss_terms(u, e, ir2, pr.mC, mh, &Ag, &Gg);
+        coef = gauss ? Ag : pm;
+        Gam = gauss ? Gg : pm;
+        if (!AONLY) A.k += gauss ? mh * e : 0.0f;
+    }
+    const float v1 = coef * f1, v2 = coef * f2;
+    kadd<KAHAN>(A.a1, A.c1, balance ? 0.0f : v1);
+    kadd<KAHAN>(A.a2, A.c2, balance ? 0.0f : v2);
+    A.b1 += (double)(balance ? v1 : 0.0f);
+    A.b2 += (double)(balance ? v2 : 0.0f);
+    if (!AONLY) {
+        const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = (2.0f * f1 * f2) * ir2;
+        A.g1 -= (double)(Gam * c2);
+        A.g2 -= (double)(Gam * s2);
+    }
+}
+
+// One entry of the big-particle list of a visited box (Sec. 3.2): a lane
+// inside the particle's support adds Gaussian - point (the tree part counted
+// the particle as a point mass); the point part goes to the FP64 balance.
+template <bool AONLY, bool KAHAN>
+__device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A, int& hits)
+{
+    double d1, d2;
+    const double r2 = sqdist(X, Y, pr.x, pr.y, &d1, &d2);
+    if (!(r2 < pr.qs2)) return;
+    const float f1 = (float)d1, f2 = (float)d2, r2f = (float)r2;
+    const float ir2 = r2f > 0.0f ? __builtin_amdgcn_rcpf(r2f) : 0.0f;
+    float P[4];
+    point_terms(pr.m, f1, f2, ir2, P);
+    const float u = r2f * pr.h;
+    const float e = __expf(-u);
+    const float mh = pr.mC * pr.h;
+    float Ag, Gg;
+    gauss_terms(u, e, ir2, pr.mC, mh, &Ag, &Gg);
+    add_radial<AONLY, KAHAN>(Ag, Gg, f1, f2, ir2, A);
+    hits++;
+    A.b1 -= (double)P[0];
+    A.b2 -= (double)P[1];
+    if (!AONLY) {
+        A.k += mh * e;
+        A.g1 -= (double)P[2];
+        A.g2 -= (double)P[3];
     }
 }
 

@@ -68,7 +68,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                     const int k = __ffsll((unsigned long long)cm) - 1;
                     cm &= cm - 1;
                     const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
-                    if (act) eval_particle<AONLY, KAHAN>(pr, X, Y, 1, A, n_hit);
+                    if (act) list_particle<AONLY, KAHAN>(pr, X, Y, A, n_hit);
                 }
             }
         }
@@ -86,10 +86,9 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                 if constexpr (STATS) {
                     if (opn) n_dir += e.pend - e.pbeg;
                 }
-                int dummy = 0;
                 for (int j = e.pbeg; j < e.pend; ++j) {
                     const PRec pr = T.prt[j];
-                    if (opn) eval_particle<AONLY, KAHAN>(pr, X, Y, 0, A, dummy);
+                    if (opn) leaf_particle<AONLY, KAHAN>(pr, X, Y, A);
                 }
             }
             cur = cur + 1;
