@@ -27,10 +27,6 @@ namespace glm {
 
 namespace {
 
-__device__ inline double wave_sum_d(double v) { return wave_sum<double>(v); }
-
-__device__ inline float wave_sum_f(float v) { return wave_sum<float>(v); }
-
 // Gradient terms of one particle for this lane, per the same cases as the
 // forward's leaf_particle and list_particle.  Returns FP64 (m, x, y, s) contributions in G.
 // mode 0: leaf sum; mode 1: big-particle correction (Gaussian - point).
@@ -86,19 +82,23 @@ __device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mod
     return true;
 }
 
+// Sum one particle's per-lane gradient terms over the wavefront and add them
+// to the particle: lanes 0..3 each issue the atomic of one quantity (m, x,
+// y, s), so the wave issues one atomic instruction per particle.
 __device__ inline void reduce_and_add(const double G[4], bool any_s, uint32_t meta, double* __restrict__ dm,
                                       double* __restrict__ dx, double* __restrict__ dy, double* __restrict__ ds,
                                       int lane)
 {
-    const double s0 = wave_sum_d(G[0]), s1 = wave_sum_d(G[1]), s2 = wave_sum_d(G[2]);
-    const double s3 = any_s ? wave_sum_d(G[3]) : 0.0;
-    if (lane == 0) {
-        const uint32_t i = meta & 0x7fffffffu;
-        if (dm) unsafeAtomicAdd(dm + i, s0);
-        if (dx) unsafeAtomicAdd(dx + i, s1);
-        if (dy) unsafeAtomicAdd(dy + i, s2);
-        if (ds && any_s) unsafeAtomicAdd(ds + i, s3);
+    double S[4] = {G[0], G[1], G[2], G[3]};
+    if (any_s) {
+        wave_sum_n<4>(S);
+    } else {
+        wave_sum_n<3>(S);
+        S[3] = 0.0;
     }
+    const double mine = lane == 0 ? S[0] : lane == 1 ? S[1] : lane == 2 ? S[2] : S[3];
+    double* base = lane == 0 ? dm : lane == 1 ? dx : lane == 2 ? dy : ds;
+    if (lane < (any_s ? 4 : 3) && base != nullptr) unsafeAtomicAdd(base + (meta & 0x7fffffffu), mine);
 }
 
 template <int P>
@@ -221,13 +221,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 a[NA - 2] = g1 * V1 - g2 * V2;
                 a[NA - 1] = g1 * V2 + g2 * V1;
             }
+            wave_sum_n<NA>(a);
+            // lane k adds total k: one atomic instruction over NA adjacent words
+            float mine = 0.0f;
 #pragma unroll
-            for (int k = 0; k < NA; ++k) a[k] = wave_sum_f(a[k]);
-            if (lane == 0) {
-                double* dst = abar + (size_t)cur * NA;
-#pragma unroll
-                for (int k = 0; k < NA; ++k) unsafeAtomicAdd(dst + k, (double)a[k]);
-            }
+            for (int k = 0; k < NA; ++k) mine = lane == k ? a[k] : mine;
+            if (lane < NA) unsafeAtomicAdd(abar + (size_t)cur * NA + lane, (double)mine);
         }
         if (h.info & kInfoLeaf) {
             if (__any(opn)) {

@@ -363,4 +363,35 @@ __device__ inline T wave_sum(T v)
     }
 }
 
+// N independent wavefront sums, interleaved step by step (each DPP step runs
+// over all N values, so no step waits on the lane move just before it);
+// every lane gets the N totals.  Same order of additions as wave_sum.
+template <int N, class T>
+__device__ inline void wave_sum_n(T* v)
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = dpp_step<0xB1, 0xF>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = dpp_step<0x4E, 0xF>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = dpp_step<0x141, 0xF>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = dpp_step<0x140, 0xF>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = dpp_step<0x142, 0xA>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = dpp_step<0x143, 0xC>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        if constexpr (sizeof(T) == 4) {
+            v[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[k]), 63));
+        } else {
+            const long long b = __builtin_bit_cast(long long, v[k]);
+            const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+            const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+            v[k] = __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
+        }
+    }
+}
+
 } // namespace glm
