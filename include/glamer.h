@@ -174,8 +174,8 @@ GLM_API glm_status glm_shoot_direct(const double* x, const double* y, const doub
  * nullable; ds is zero for point masses).  Moment contributions are pushed
  * down from boxes to particles through dQ_k/dm_i, dQ_k/dz_i and dz_cm.
  * Uses FP64 atomics: results are reproducible to rounding, not bitwise.
- *   workspace: at least glm_shoot_workspace_bytes(nrays) plus the tree's
- *   box-adjoint scratch, which the handle owns.
+ *   workspace: at least glm_shoot_workspace_bytes(nrays); the scratch for
+ *   box adjoints and per-particle sums is device memory the handle owns.
  */
 GLM_API glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* ry,
                              int64_t nrays, const float* ga1, const float* ga2, double* dm,

@@ -82,23 +82,29 @@ __device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mod
     return true;
 }
 
-// Sum one particle's per-lane gradient terms over the wavefront and add them
-// to the particle: lanes 0..3 each issue the atomic of one quantity (m, x,
-// y, s), so the wave issues one atomic instruction per particle.
-__device__ inline void reduce_and_add(const double G[4], bool any_s, uint32_t meta, double* __restrict__ dm,
-                                      double* __restrict__ dx, double* __restrict__ dy, double* __restrict__ ds,
-                                      int lane)
+// Sums of one particle's per-lane gradient terms (m, x, y, s) over the
+// wavefront; every lane gets the totals.
+__device__ inline void particle_sums(const double G[4], bool any_s, double S[4])
 {
-    double S[4] = {G[0], G[1], G[2], G[3]};
+    S[0] = G[0];
+    S[1] = G[1];
+    S[2] = G[2];
+    S[3] = G[3];
     if (any_s) {
         wave_sum_n<4>(S);
     } else {
         wave_sum_n<3>(S);
         S[3] = 0.0;
     }
+}
+
+// The particle's four interleaved FP64 accumulators (m, x, y, s) sit at
+// pg + 4 * (Morton position); lanes 0..3 add one each, so the wave issues a
+// single atomic instruction that touches one cache line.
+__device__ inline void add_particle(const double S[4], uint32_t meta, double* __restrict__ pg, int lane)
+{
     const double mine = lane == 0 ? S[0] : lane == 1 ? S[1] : lane == 2 ? S[2] : S[3];
-    double* base = lane == 0 ? dm : lane == 1 ? dx : lane == 2 ? dy : ds;
-    if (lane < (any_s ? 4 : 3) && base != nullptr) unsafeAtomicAdd(base + (meta & 0x7fffffffu), mine);
+    if (lane < 4) unsafeAtomicAdd(pg + 4 * (size_t)(meta & 0x7fffffffu) + lane, mine);
 }
 
 template <int P>
@@ -106,9 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                                                         const double* __restrict__ rys,
                                                         const uint32_t* __restrict__ rperm, int64_t nrays,
                                                         const float* __restrict__ ga1, const float* __restrict__ ga2,
-                                                        double* __restrict__ dm, double* __restrict__ dx,
-                                                        double* __restrict__ dy, double* __restrict__ ds,
-                                                        double* __restrict__ abar, int K,
+                                                        double* __restrict__ pg, double* __restrict__ abar, int K,
                                                         const int* __restrict__ split_box)
 {
     constexpr int NA = 2 * (P + 1) + 2; // (Re, Im) of Abar_0..Abar_P, Bbar
@@ -164,7 +168,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                     cm &= cm - 1;
                     const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
                     const bool hit = particle_grad(pr, X, Y, 1, act, g1, g2, invC, G);
-                    if (__any(hit)) reduce_and_add(G, true, pr.meta, dm, dx, dy, ds, lane);
+                    if (__any(hit)) {
+                        double S[4];
+                        particle_sums(G, true, S);
+                        add_particle(S, pr.meta, pg, lane);
+                    }
                 }
             }
         }
@@ -235,7 +243,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                     const PRec pr = T.prt[j];
                     const bool hit = particle_grad(pr, X, Y, 0, opn, g1, g2, invC, G);
                     const bool any_s = __any(hit && G[3] != 0.0);
-                    reduce_and_add(G, any_s, pr.meta, dm, dx, dy, ds, lane);
+                    double S[4];
+                    particle_sums(G, any_s, S);
+                    add_particle(S, pr.meta, pg, lane);
                 }
             }
             cur = cur + 1;
@@ -248,17 +258,19 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
     }
 }
 
-// Box adjoints -> particles.  One thread per particle walks its ancestors.
+// Box adjoints -> particles.  One thread per particle walks its ancestors,
+// then adds the direct-term gradients the walk gathered.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __restrict__ ms,
-                                                    const double* __restrict__ abar, double* __restrict__ dm,
-                                                    double* __restrict__ dx, double* __restrict__ dy)
+                                                    const double* __restrict__ abar, const double* __restrict__ pg,
+                                                    double* __restrict__ dm, double* __restrict__ dx,
+                                                    double* __restrict__ dy, double* __restrict__ ds)
 {
     constexpr int NA = 2 * (P + 1) + 2;
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= T.n) return;
     const PRec pr = T.prt[k];
-    const uint32_t i = pr.meta & 0x7fffffffu;
+    const int32_t i = T.perm[k]; // original index
     const double mi = ms[k];
     double gm = 0.0, gzr = 0.0, gzi = 0.0;
     int c = 0;
@@ -319,9 +331,12 @@ __global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __
         if (ch >= h.next) break;
         c = ch;
     }
-    if (dm) dm[i] += gm;
-    if (dx) dx[i] += gzr;
-    if (dy) dy[i] -= gzi;
+    // plus the direct terms the walk gathered for this particle
+    const double* q = pg + 4 * (size_t)k;
+    if (dm) dm[i] += gm + q[0];
+    if (dx) dx[i] += gzr + q[1];
+    if (dy) dy[i] += q[2] - gzi;
+    if (ds) ds[i] += q[3];
 }
 
 __global__ void k_fill_zero(double* p, int64_t n)
@@ -335,16 +350,18 @@ glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, 
                           double* dm, double* dx, double* dy, double* ds, int K, const int* split_box, hipStream_t st)
 {
     constexpr int NA = 2 * (P + 1) + 2;
-    const size_t words = (size_t)ts.ncells * NA;
+    // scratch: box adjoints (NA per box), then 4 direct-term gradients per particle
+    const size_t words = (size_t)ts.ncells * NA + 4 * (size_t)ts.n;
     glm_status rc = ts.abuf.ensure(words * sizeof(double));
     if (rc != GLM_OK) return rc;
     double* abar = ts.abuf.as<double>();
+    double* pg = abar + (size_t)ts.ncells * NA;
     hipLaunchKernelGGL(k_fill_zero, dim3(ceil_div((int64_t)words, kBlock)), dim3(kBlock), 0, st, abar, (int64_t)words);
     const int64_t blocks = walk_grid_blocks((nrays + kWave - 1) / kWave, K);
     hipLaunchKernelGGL((k_adjoint_walk<P>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ts.dev, sr.xs,
-                       sr.ys, sr.perm, nrays, ga1, ga2, dm, dx, dy, ds, abar, K, split_box);
-    hipLaunchKernelGGL((k_pushdown<P>), dim3(ceil_div(ts.n, kBlock)), dim3(kBlock), 0, st, ts.dev, ts.ms, abar, dm, dx,
-                       dy);
+                       sr.ys, sr.perm, nrays, ga1, ga2, pg, abar, K, split_box);
+    hipLaunchKernelGGL((k_pushdown<P>), dim3(ceil_div(ts.n, kBlock)), dim3(kBlock), 0, st, ts.dev, ts.ms, abar, pg, dm,
+                       dx, dy, ds);
     GLM_HIP(hipGetLastError());
     return GLM_OK;
 }

@@ -160,7 +160,9 @@ glm_status glm_tree_export(const glm_tree* t, int32_t* level, uint32_t* ix, uint
         std::vector<PRec> l((size_t)hs.nlisted);
         if (hs.nlisted > 0)
             GLM_HIP(hipMemcpy(l.data(), ts.dev.lst, sizeof(PRec) * l.size(), hipMemcpyDeviceToHost));
-        for (size_t k = 0; k < l.size(); ++k) list_idx[k] = (int32_t)(l[k].meta & 0x7fffffffu);
+        std::vector<int32_t> pm((size_t)n);
+        GLM_HIP(hipMemcpy(pm.data(), ts.perm, 4 * n, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < l.size(); ++k) list_idx[k] = pm[l[k].meta & 0x7fffffffu];
     }
     return GLM_OK;
 }

@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_list_assign(const uint64_t* __restri
 }
 
 __device__ inline void fill_rec(PRec& r, double x, double y, double m, double s, double q, double invC, bool listed,
-                                uint32_t orig)
+                                uint32_t pos)
 {
 #pragma clang fp contract(off)
     const double qs = q * s;
@@ -362,19 +362,19 @@ __device__ inline void fill_rec(PRec& r, double x, double y, double m, double s,
     r.m = (float)m;
     r.mC = (float)(m * invC);
     r.h = s > 0.0 ? (float)(1.0 / (2.0 * s * s)) : 0.0f;
-    r.meta = orig | (listed ? 0x80000000u : 0u);
+    r.meta = pos | (listed ? 0x80000000u : 0u);
 }
 
 __global__ __launch_bounds__(kBlock) void k_particle_records(int n, const double* __restrict__ xs,
                                                             const double* __restrict__ ys, const double* __restrict__ ms,
-                                                            const double* __restrict__ ss, const uint32_t* __restrict__ perm,
+                                                            const double* __restrict__ ss,
                                                             const uint32_t* __restrict__ lkey, uint32_t unlisted,
                                                             double q, double invC, PRec* __restrict__ prt)
 {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     PRec r;
-    fill_rec(r, xs[j], ys[j], ms[j], ss[j], q, invC, lkey[j] != unlisted, perm[j]);
+    fill_rec(r, xs[j], ys[j], ms[j], ss[j], q, invC, lkey[j] != unlisted, (uint32_t)j);
     prt[j] = r;
 }
 
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_list_ranges(int n, const uint32_t* _
                                                        const uint32_t* __restrict__ lval, uint32_t unlisted,
                                                        const double* __restrict__ xs, const double* __restrict__ ys,
                                                        const double* __restrict__ ms, const double* __restrict__ ss,
-                                                       const uint32_t* __restrict__ perm, double q, double invC,
+                                                       double q, double invC,
                                                        BoxArrays b, PRec* __restrict__ lst,
                                                        BuildSync* __restrict__ sync)
 {
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_list_ranges(int n, const uint32_t* _
     if (k == n - 1 || lkey[k + 1] == unlisted) sync->nlisted = k + 1;
     const uint32_t j = lval[k];
     PRec r;
-    fill_rec(r, xs[j], ys[j], ms[j], ss[j], q, invC, true, perm[j]);
+    fill_rec(r, xs[j], ys[j], ms[j], ss[j], q, invC, true, j);
     lst[k] = r;
 }
 
@@ -707,11 +707,11 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     }
     hipLaunchKernelGGL(k_list_assign, dim3(gb), dim3(kBlock), 0, st, K, n, ss, q, sync, nc, leaf_of, b, cnt, lstart,
                        unlisted, lk0, lv0);
-    hipLaunchKernelGGL(k_particle_records, dim3(gb), dim3(kBlock), 0, st, n, xs, ys, ms, ss, perm, lk0, unlisted, q,
-                       invC, prt);
+    hipLaunchKernelGGL(k_particle_records, dim3(gb), dim3(kBlock), 0, st, n, xs, ys, ms, ss, lk0, unlisted, q, invC,
+                       prt);
     const int lw = radix_sort_u32(lk0, lv0, lk1, lv1, n, passes, hist, st);
     hipLaunchKernelGGL(k_list_ranges, dim3(gb), dim3(kBlock), 0, st, n, lw ? lk1 : lk0, lw ? lv1 : lv0, unlisted, xs,
-                       ys, ms, ss, perm, q, invC, b, lst, sync);
+                       ys, ms, ss, q, invC, b, lst, sync);
     for (int l = kMaxLevel; l >= 0; --l)
         if (lt.cnt[l] > 0)
             hipLaunchKernelGGL(k_moments_level, dim3(ceil_div(lt.cnt[l], kBlock)), dim3(kBlock), 0, st, levidx + lt.off[l],

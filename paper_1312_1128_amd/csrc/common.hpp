@@ -43,7 +43,7 @@ struct alignas(8) PRec {
     float m;       // mass
     float mC;      // m / (1 - exp(-q^2/2))
     float h;       // 1 / (2 s^2), 0 for point masses
-    uint32_t meta; // original particle index | (listed in a big-particle list) << 31
+    uint32_t meta; // Morton position of the particle | (listed in a big-particle list) << 31
 };
 
 constexpr uint32_t kInfoLeaf = 1u;
