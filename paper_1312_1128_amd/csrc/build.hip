@@ -402,21 +402,14 @@ __global__ __launch_bounds__(kBlock) void k_list_ranges(int n, const uint32_t* _
 
 // ---------------------------------------------------------------- moments
 
-__constant__ double c_binom[kMaxOrder + 1][kMaxOrder + 1] = {
-    {1},
-    {1, 1},
-    {1, 2, 1},
-    {1, 3, 3, 1},
-    {1, 4, 6, 4, 1},
-    {1, 5, 10, 10, 5, 1},
-    {1, 6, 15, 20, 15, 6, 1},
-    {1, 7, 21, 35, 35, 21, 7, 1},
-    {1, 8, 28, 56, 70, 56, 28, 8, 1},
-    {1, 9, 36, 84, 126, 126, 84, 36, 9, 1},
-    {1, 10, 45, 120, 210, 252, 210, 120, 45, 10, 1},
-    {1, 11, 55, 165, 330, 462, 462, 330, 165, 55, 11, 1},
-    {1, 12, 66, 220, 495, 792, 924, 792, 495, 220, 66, 12, 1},
-};
+// Binomial coefficient C(n, k) (exact in FP64 for n <= 12); folds to a
+// constant inside the unrolled moment loops.
+__host__ __device__ constexpr double binomial(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
 
 __device__ inline void box_bounds(const BoxArrays& b, int c, const BuildSync* sync, double* bx0, double* bx1,
                                   double* by0, double* by1)
@@ -433,7 +426,8 @@ __device__ inline void box_bounds(const BoxArrays& b, int c, const BuildSync* sy
 // Internal boxes: centre of mass of the children, then the children's moments
 // translated, Q_k = sum_children sum_j C(k, j) Q_j(child) t^(k-j) with
 // t = z_child - z_cm (exact re-expansion of sum m (z - z_cm)^k).
-__global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restrict__ levidx, int count, int p, BoxArrays b,
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restrict__ levidx, int count, BoxArrays b,
                                                          const double* __restrict__ xs, const double* __restrict__ ys,
                                                          const double* __restrict__ ms,
                                                          const BuildSync* __restrict__ sync, double* __restrict__ cM,
@@ -443,9 +437,10 @@ __global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restr
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= count) return;
     const int c = levidx[t];
-    const int P = p + 1;
-    double Qr[kMaxOrder + 1], Qi[kMaxOrder + 1];
-    for (int k = 0; k < P; ++k) Qr[k] = Qi[k] = 0.0;
+    constexpr int P1 = P + 1; // Q_0 .. Q_P
+    double Qr[P1], Qi[P1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) Qr[k] = Qi[k] = 0.0;
     double M = 0.0, cx, cy;
     if (b.leaf[c]) {
         double sx = 0.0, sy = 0.0;
@@ -466,7 +461,8 @@ __global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restr
         for (int j = b.beg[c]; j < b.end[c]; ++j) {
             const double dr = xs[j] - cx, di = ys[j] - cy;
             double pr = ms[j], pi = 0.0;
-            for (int k = 0; k < P; ++k) {
+#pragma unroll
+            for (int k = 0; k < P1; ++k) {
                 Qr[k] += pr;
                 Qi[k] += pi;
                 const double t = pr * dr - pi * di;
@@ -492,18 +488,27 @@ __global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restr
         }
         for (int ch = c + 1; ch < b.next[c]; ch = b.next[ch] > ch ? b.next[ch] : ch + 1) {
             const double tr = ccx[ch] - cx, ti = ccy[ch] - cy;
-            double tpr[kMaxOrder + 1], tpi[kMaxOrder + 1];
+            double tpr[P1], tpi[P1];
             tpr[0] = 1.0;
             tpi[0] = 0.0;
-            for (int k = 1; k < P; ++k) {
+#pragma unroll
+            for (int k = 1; k < P1; ++k) {
                 tpr[k] = tpr[k - 1] * tr - tpi[k - 1] * ti;
                 tpi[k] = tpr[k - 1] * ti + tpi[k - 1] * tr;
             }
-            const double* q = cQ + (size_t)ch * P * 2;
-            for (int k = 0; k < P; ++k) {
+            const double* q = cQ + (size_t)ch * P1 * 2;
+            double qr[P1], qi[P1];
+#pragma unroll
+            for (int k = 0; k < P1; ++k) {
+                qr[k] = q[2 * k];
+                qi[k] = q[2 * k + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < P1; ++k) {
                 double sr = 0.0, si = 0.0;
+#pragma unroll
                 for (int j = 0; j <= k; ++j) {
-                    const double br = c_binom[k][j] * q[2 * j], bi = c_binom[k][j] * q[2 * j + 1];
+                    const double br = binomial(k, j) * qr[j], bi = binomial(k, j) * qi[j];
                     sr += br * tpr[k - j] - bi * tpi[k - j];
                     si += br * tpi[k - j] + bi * tpr[k - j];
                 }
@@ -515,8 +520,9 @@ __global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restr
     cM[c] = M;
     ccx[c] = cx;
     ccy[c] = cy;
-    double* q = cQ + (size_t)c * P * 2;
-    for (int k = 0; k < P; ++k) {
+    double* q = cQ + (size_t)c * P1 * 2;
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
         q[2 * k] = Qr[k];
         q[2 * k + 1] = Qi[k];
     }
@@ -713,9 +719,20 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     hipLaunchKernelGGL(k_list_ranges, dim3(gb), dim3(kBlock), 0, st, n, lw ? lk1 : lk0, lw ? lv1 : lv0, unlisted, xs,
                        ys, ms, ss, q, invC, b, lst, sync);
     for (int l = kMaxLevel; l >= 0; --l)
-        if (lt.cnt[l] > 0)
-            hipLaunchKernelGGL(k_moments_level, dim3(ceil_div(lt.cnt[l], kBlock)), dim3(kBlock), 0, st, levidx + lt.off[l],
-                               lt.cnt[l], p, b, xs, ys, ms, sync, cM, ccx, ccy, cQ);
+        if (lt.cnt[l] > 0) {
+            const dim3 g(ceil_div(lt.cnt[l], kBlock)), blk(kBlock);
+#define GLM_CASE(PP)                                                                                          \
+    case PP:                                                                                                  \
+        hipLaunchKernelGGL((k_moments_level<PP>), g, blk, 0, st, levidx + lt.off[l], lt.cnt[l], b, xs, ys, ms, \
+                           sync, cM, ccx, ccy, cQ);                                                           \
+        break;
+            switch (p) {
+                GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
+                GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
+                default: break;
+            }
+#undef GLM_CASE
+        }
     hipLaunchKernelGGL(k_finalize, dim3(gc), dim3(kBlock), 0, st, nc, p, prm.theta, b, sync, cM, ccx, ccy, cQ, hdr, ext,
                        mom);
     GLM_HIP(hipGetLastError());
