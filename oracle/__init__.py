@@ -6,7 +6,9 @@ Python access (ctypes) to the plain FP64 C implementations in this folder:
   particle, the theta_force = 0 limit of Sec. 5.1;
 * oracle B (``Tree``): the modified quad-tree solver of Sec. 3.2, recursive and
   in FP64, with per-ray interaction counts and a decision tape for frozen-walk
-  finite differences.
+  finite differences;
+* ``knn``: smoothing lengths (Sec. 3.1), the distance to the k-th nearest
+  other particle, by brute force.
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the GPU library.
@@ -21,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = ["direct.c", "tree.c"]
+SOURCES = ["direct.c", "tree.c", "knn.c"]
 
 _lib = None
 
@@ -55,6 +57,7 @@ def _load():
     lib.ora_unit_terms.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, d]
     lib.ora_kernel_norm.argtypes = [ctypes.c_double]
     lib.ora_kernel_norm.restype = ctypes.c_double
+    lib.ora_knn.argtypes = [d, d, i64, ctypes.c_int, d, ctypes.c_int]
     lib.ora_tree_build.argtypes = [d, d, d, d, i64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int]
     lib.ora_tree_build.restype = vp
@@ -113,6 +116,16 @@ def direct(x, y, m, s, q, rx, ry, threads: int | None = None) -> np.ndarray:
     lib.ora_direct(_p(x), _p(y), _p(m), _p(s), x.shape[0], float(q), _p(rx), _p(ry), nr,
                    *[_p(o) for o in out], threads or default_threads())
     return np.stack(out, axis=1)
+
+
+def knn(x, y, k: int = 32, threads: int | None = None) -> np.ndarray:
+    """Smoothing lengths: distance from each particle to its k-th nearest other particle."""
+    lib = _load()
+    x, y = _f64(x), _f64(y)
+    out = np.zeros(x.shape[0])
+    if lib.ora_knn(_p(x), _p(y), x.shape[0], int(k), _p(out), threads or default_threads()) != 0:
+        raise ValueError("need 1 <= k <= n - 1")
+    return out
 
 
 def direct_grad(x, y, m, s, q, rx, ry, ga, threads: int | None = None):

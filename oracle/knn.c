@@ -1,0 +1,59 @@
+/*
+ * Oracle for the smoothing lengths (Sec. 3.1) -- TEST INFRASTRUCTURE ONLY.
+ *
+ * The smoothing length of a particle is the radius that holds its N_sph
+ * nearest neighbours; in 2D it is the distance to its k-th nearest other
+ * particle (the particle itself excluded, coincident particles counted at
+ * distance 0).  Written as the definition: every squared distance, then the
+ * k-th smallest by selection, then its square root.  O(n^2).
+ */
+#include <math.h>
+#include <stdlib.h>
+
+#include "oracle.h"
+
+/* k-th smallest (1-based) of a[0..n-1] by quickselect (a is reordered). */
+static double kth_smallest(double* a, int64_t n, int64_t k)
+{
+    int64_t lo = 0, hi = n - 1, want = k - 1;
+    while (lo < hi) {
+        const double pivot = a[lo + (hi - lo) / 2];
+        int64_t i = lo, j = hi;
+        while (i <= j) {
+            while (a[i] < pivot) ++i;
+            while (a[j] > pivot) --j;
+            if (i <= j) {
+                const double t = a[i];
+                a[i] = a[j];
+                a[j] = t;
+                ++i;
+                --j;
+            }
+        }
+        if (want <= j) hi = j;
+        else if (want >= i) lo = i;
+        else return a[want];
+    }
+    return a[want];
+}
+
+int ora_knn(const double* x, const double* y, int64_t n, int k, double* s_out, int nthreads)
+{
+    if (n < 2 || k < 1 || k > n - 1) return -1;
+#pragma omp parallel num_threads(nthreads)
+    {
+        double* d2 = (double*)malloc(sizeof(double) * (size_t)(n - 1));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t m = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                const double dx = x[i] - x[j], dy = y[i] - y[j];
+                d2[m++] = dx * dx + dy * dy;
+            }
+            s_out[i] = sqrt(kth_smallest(d2, n - 1, k));
+        }
+        free(d2);
+    }
+    return 0;
+}

@@ -46,6 +46,11 @@ int ora_direct_grad(const double* x, const double* y, const double* m, const dou
                     const double* ga1, const double* ga2,
                     double* dm, double* dx, double* dy, double* ds, int nthreads);
 
+/* Smoothing lengths (Sec. 3.1): for each particle the 2D distance to its
+ * k-th nearest other particle, by brute force.  Returns -1 unless
+ * 1 <= k <= n - 1. */
+int ora_knn(const double* x, const double* y, int64_t n, int k, double* s_out, int nthreads);
+
 /* Oracle B: reference tree. */
 typedef struct ora_tree ora_tree;
 
