@@ -198,6 +198,18 @@ def main():
         log(f"tree vs GPU FP64 direct over all {R} rays: max rel err alpha {full_err['alpha_max']:.2e} "
             f"kappa {full_err['kappa_max']:.2e} gamma {full_err['gamma_max']:.2e}")
 
+        # smoothing lengths of the 1e6 particles on the GPU (tree of the positions + k = 32 walk)
+        g.smoothing_lengths(x, y, k=32)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            s_gpu = g.smoothing_lengths(x, y, k=32)
+        torch.cuda.synchronize()
+        knn_ms = 1e3 * (time.perf_counter() - t) / 3
+        knn_diff = float(((s_gpu - s).abs() / s).max())
+        log(f"smoothing lengths (k = 32, 1e6 particles): {knn_ms:.3f} ms; max rel diff vs the inputs' host k-d tree "
+            f"{knn_diff:.1e}")
+
         # forward + adjoint on the lens-fitting workload: 1e5 particles, 1e5 rays,
         # L = sum |x - alpha - beta*|^2 (step = build + alpha walk + adjoint walk)
         lens5 = synth.nfw_halo(100_000, synth.BASE_SEED + 5)
@@ -283,6 +295,7 @@ def main():
             f"per-lens launches {1e3 * l4:.2f} ms")
         extras = {"direct_fp32_rays_per_s": res[False], "direct_fp64_rays_per_s": res[True],
                   "full_grid_err_vs_gpu_fp64_direct": full_err,
+                  "knn_smoothing_1e6_ms": knn_ms, "knn_max_rel_diff_vs_host_kdtree": knn_diff,
                   "fwd_adjoint_rays_per_s": rx5.numel() / (fa_ms * 1e-3), "fwd_adjoint_ms": fa_ms,
                   "fwd_adjoint_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2",
                   "refinement_rays": n3, "refinement_graph_ms": 1e3 * graph3_s, "refinement_eager_ms": 1e3 * eager3,

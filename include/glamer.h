@@ -132,6 +132,19 @@ GLM_API glm_status glm_tree_export(const glm_tree* t, int32_t* level, uint32_t* 
                            double* rcut2, double* Q, int32_t* perm, uint64_t* key,
                            int32_t* list_idx);
 
+/*
+ * Smoothing lengths (Sec. 3.1: the smoothing scale of a particle is the
+ * radius holding its N_sph nearest neighbours) of the tree's n particles, in
+ * 2D: for each particle the distance to its k-th nearest other particle
+ * (itself excluded; coincident particles count, at distance 0), from the FP64
+ * positions given to glm_build_tree, by a pruned walk of the tree's boxes.
+ *   s_out: device FP64, n values, original particle order (overwritten)
+ *   k    : 1 .. 64 and at most n - 1, else GLM_EINVAL
+ * Masses, moments and lists are not used: a tree built with unit masses and
+ * s = NULL serves.  Enqueued on `stream`; no workspace.
+ */
+GLM_API glm_status glm_tree_knn(const glm_tree* t, int32_t k, double* s_out, void* stream);
+
 /* Bytes of device workspace glm_shoot / glm_shoot_adjoint need for nrays rays. */
 GLM_API glm_status glm_shoot_workspace_bytes(int64_t nrays, size_t* bytes);
 

@@ -58,6 +58,7 @@ def _load():
     lib.ora_kernel_norm.argtypes = [ctypes.c_double]
     lib.ora_kernel_norm.restype = ctypes.c_double
     lib.ora_knn.argtypes = [d, d, i64, ctypes.c_int, d, ctypes.c_int]
+    lib.ora_knn_at.argtypes = [d, d, i64, ctypes.c_int, vp, i64, d, ctypes.c_int]
     lib.ora_tree_build.argtypes = [d, d, d, d, i64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int]
     lib.ora_tree_build.restype = vp
@@ -118,12 +119,20 @@ def direct(x, y, m, s, q, rx, ry, threads: int | None = None) -> np.ndarray:
     return np.stack(out, axis=1)
 
 
-def knn(x, y, k: int = 32, threads: int | None = None) -> np.ndarray:
-    """Smoothing lengths: distance from each particle to its k-th nearest other particle."""
+def knn(x, y, k: int = 32, at=None, threads: int | None = None) -> np.ndarray:
+    """Smoothing lengths: distance from each particle (or from the particles
+    listed in ``at``) to its k-th nearest other particle."""
     lib = _load()
     x, y = _f64(x), _f64(y)
-    out = np.zeros(x.shape[0])
-    if lib.ora_knn(_p(x), _p(y), x.shape[0], int(k), _p(out), threads or default_threads()) != 0:
+    if at is None:
+        out = np.zeros(x.shape[0])
+        rc = lib.ora_knn(_p(x), _p(y), x.shape[0], int(k), _p(out), threads or default_threads())
+    else:
+        q = np.ascontiguousarray(at, dtype=np.int64)
+        out = np.zeros(q.shape[0])
+        rc = lib.ora_knn_at(_p(x), _p(y), x.shape[0], int(k), q.ctypes.data, q.shape[0], _p(out),
+                            threads or default_threads())
+    if rc != 0:
         raise ValueError("need 1 <= k <= n - 1")
     return out
 

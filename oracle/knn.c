@@ -39,19 +39,26 @@ static double kth_smallest(double* a, int64_t n, int64_t k)
 
 int ora_knn(const double* x, const double* y, int64_t n, int k, double* s_out, int nthreads)
 {
+    return ora_knn_at(x, y, n, k, NULL, n, s_out, nthreads);
+}
+
+int ora_knn_at(const double* x, const double* y, int64_t n, int k, const int64_t* queries, int64_t nq,
+               double* s_out, int nthreads)
+{
     if (n < 2 || k < 1 || k > n - 1) return -1;
 #pragma omp parallel num_threads(nthreads)
     {
         double* d2 = (double*)malloc(sizeof(double) * (size_t)(n - 1));
 #pragma omp for schedule(dynamic, 16)
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t t = 0; t < nq; ++t) {
+            const int64_t i = queries ? queries[t] : t;
             int64_t m = 0;
             for (int64_t j = 0; j < n; ++j) {
                 if (j == i) continue;
                 const double dx = x[i] - x[j], dy = y[i] - y[j];
                 d2[m++] = dx * dx + dy * dy;
             }
-            s_out[i] = sqrt(kth_smallest(d2, n - 1, k));
+            s_out[t] = sqrt(kth_smallest(d2, n - 1, k));
         }
         free(d2);
     }

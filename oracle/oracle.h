@@ -50,6 +50,9 @@ int ora_direct_grad(const double* x, const double* y, const double* m, const dou
  * k-th nearest other particle, by brute force.  Returns -1 unless
  * 1 <= k <= n - 1. */
 int ora_knn(const double* x, const double* y, int64_t n, int k, double* s_out, int nthreads);
+/* The same for the particles queries[0..nq-1] only (out[t] for queries[t]). */
+int ora_knn_at(const double* x, const double* y, int64_t n, int k, const int64_t* queries, int64_t nq,
+               double* s_out, int nthreads);
 
 /* Oracle B: reference tree. */
 typedef struct ora_tree ora_tree;

@@ -19,7 +19,7 @@ from ._capi import (GLM_ALPHA_ONLY, GLM_NO_KAHAN, GLM_RAYS_ORDERED, GlamerError,
 
 __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
            "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
-           "refine_schedule", "RefinementRun", "autotune"]
+           "refine_schedule", "RefinementRun", "autotune", "smoothing_lengths"]
 
 
 def _ptr(t):
@@ -84,6 +84,14 @@ class Tree:
         _capi.check(self._lib.glm_tree_get_info(self._h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in GlmTreeInfo._fields_}
 
+    def knn(self, k: int = 32, out=None):
+        """Smoothing lengths (Sec. 3.1) of the tree's particles: float64 tensor of
+        the distance from each particle to its k-th nearest other particle."""
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _capi.check(self._lib.glm_tree_knn(self._h, int(k), _ptr(out), _stream()))
+        return out
+
     def export(self) -> dict:
         """Host copy of the boxes (preorder), the Morton order and the lists."""
         import numpy as np
@@ -128,6 +136,15 @@ def shoot(tree: Tree, rx, ry, counts: bool = False, alpha_only: bool = False, ka
     if counts:
         out["counts"] = cnt
     return out
+
+
+def smoothing_lengths(x, y, k: int = 32, leaf_size: int = 16):
+    """Smoothing lengths of particles at (x, y) (float64 CUDA tensors): the 2D
+    distance from each to its k-th nearest other particle (Sec. 3.1), on a
+    tree built from the positions alone."""
+    x, y = _f64(x, "x"), _f64(y, "y")
+    tree = Tree().build(x, y, torch.ones_like(x), None, theta=0.5, q=3.0, leaf_size=leaf_size, order=0)
+    return tree.knn(k)
 
 
 def shoot_direct(x, y, m, s, q, rx, ry, fp64: bool = False, alpha_only: bool = False):

@@ -23,7 +23,7 @@ EXPORTED = [
     "glm_tree_create", "glm_tree_destroy", "glm_build_tree", "glm_tree_get_info", "glm_tree_export",
     "glm_shoot_workspace_bytes", "glm_shoot", "glm_shoot_direct", "glm_shoot_adjoint",
     "glm_last_error", "glm_version", "glm_shoot_batched_workspace_bytes", "glm_shoot_batched",
-    "glm_refine_workspace_bytes", "glm_refine_round",
+    "glm_refine_workspace_bytes", "glm_refine_round", "glm_tree_knn",
 ]
 
 
@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
     lib.glm_refine_workspace_bytes.restype = st
     lib.glm_refine_round.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, vp, vp, ctypes.c_size_t, vp]
     lib.glm_refine_round.restype = st
+    lib.glm_tree_knn.argtypes = [vp, ctypes.c_int32, vp, vp]
+    lib.glm_tree_knn.restype = st
     lib.glm_last_error.argtypes = []
     lib.glm_last_error.restype = ctypes.c_char_p
     lib.glm_version.argtypes = []

@@ -167,6 +167,15 @@ glm_status glm_tree_export(const glm_tree* t, int32_t* level, uint32_t* ix, uint
     return GLM_OK;
 }
 
+glm_status glm_tree_knn(const glm_tree* t, int32_t k, double* s_out, void* stream)
+{
+    if (!t || !s_out) return fail(GLM_EINVAL, "NULL argument");
+    if (!t->ts.built) return fail(GLM_ESTATE, "tree not built");
+    if (k < 1 || k > 64) return fail(GLM_EINVAL, "k must be in 1..64");
+    if ((int64_t)k > (int64_t)t->ts.n - 1) return fail(GLM_EINVAL, "k must be at most n - 1");
+    return knn_device(t->ts, k, s_out, static_cast<hipStream_t>(stream));
+}
+
 glm_status glm_shoot_workspace_bytes(int64_t nrays, size_t* bytes)
 {
     if (!bytes || nrays < 0) return fail(GLM_EINVAL, "bad argument");

@@ -62,4 +62,8 @@ struct TreeStorage {
 glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, const double* m, const double* s,
                              int64_t n, const glm_params& prm, hipStream_t st);
 
+// Smoothing lengths of the tree's particles (knn.hip): distance to the k-th
+// nearest other particle, written in original order.
+glm_status knn_device(const TreeStorage& ts, int k, double* s_out, hipStream_t st);
+
 } // namespace glm

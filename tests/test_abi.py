@@ -68,6 +68,8 @@ def test_host_validation(lib):
     assert rc == _capi.GLM_ESTATE
     info = _capi.GlmTreeInfo()
     assert lib.glm_tree_get_info(h, ctypes.byref(info)) == _capi.GLM_ESTATE
+    assert lib.glm_tree_knn(h, 32, buf, None) == _capi.GLM_ESTATE
+    assert lib.glm_tree_knn(None, 32, buf, None) == _capi.GLM_EINVAL
     # workspace size is a host-side function of the ray count
     b = ctypes.c_size_t()
     assert lib.glm_shoot_workspace_bytes(1 << 20, ctypes.byref(b)) == 0 and b.value > (1 << 20) * 32

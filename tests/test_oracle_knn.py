@@ -50,3 +50,10 @@ def test_two_particles_and_bad_k(ora):
     assert np.all(s == 5.0)
     with pytest.raises(ValueError):
         ora.knn(np.array([0.0, 1.0]), np.array([0.0, 0.0]), 2)
+
+
+def test_query_subset_matches_full(ora):
+    g = synth.rng(73)
+    x, y = g.normal(size=1500), g.normal(size=1500)
+    at = np.array([0, 7, 1499, 7, 300])
+    np.testing.assert_array_equal(ora.knn(x, y, 16, at=at), ora.knn(x, y, 16)[at])
