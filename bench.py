@@ -266,6 +266,30 @@ def main():
         log(f"refinement (6 rounds, {n3} rays): graph {1e3 * graph3_s:.2f} ms, eager {1e3 * eager3:.2f} ms "
             f"-> {n3 / graph3_s:.4e} rays/s")
 
+        # refinement with the interpolation shortcut on a smooth patch of the 1e6 halo
+        # (0.0002 square at (0.3, 0.05), 256^2 base cells, 6 rounds): plain vs interpolated
+        pa, pc = 0.0002, (0.3, 0.05)
+        ix6, iy6 = synth.ray_grid(256, 0.0, pa)
+        run6 = g.RefinementRun(tree3, d(ix6 + pc[0] - pa / 2), d(iy6 + pc[1] - pa / 2),
+                               d(np.full(ix6.size, pa / 256)), g.refine_schedule(ix6.size))
+        for _ in range(2):
+            n6 = run6.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            run6.run()
+        torch.cuda.synchronize()
+        plain6 = (time.perf_counter() - t) / 3
+        run6.run_interp(pc[0] - pa / 2, pc[1] - pa / 2, pa / 256, 256, tol=1e-4)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            _, walked6 = run6.run_interp(pc[0] - pa / 2, pc[1] - pa / 2, pa / 256, 256, tol=1e-4)
+        torch.cuda.synchronize()
+        interp6 = (time.perf_counter() - t) / 3
+        log(f"refinement of a smooth patch ({n6} cells): plain {1e3 * plain6:.2f} ms, with interpolation "
+            f"{1e3 * interp6:.2f} ms, walking {walked6} rays")
+
         # 64 independent lenses in one persistent launch
         lenses4 = synth.workload_batched_lenses(64)
         trees4, rays4 = [], []
@@ -301,6 +325,10 @@ def main():
                   "refinement_rays": n3, "refinement_graph_ms": 1e3 * graph3_s, "refinement_eager_ms": 1e3 * eager3,
                   "refinement_rays_per_s": n3 / graph3_s,
                   "refinement_workload": "nfw_1e6 + 1e5 Salpeter stars, 256^2 base, 6 rounds top-10% 3x3",
+                  "interp_refinement_cells": n6, "interp_refinement_walked": walked6,
+                  "interp_refinement_plain_ms": 1e3 * plain6, "interp_refinement_ms": 1e3 * interp6,
+                  "interp_refinement_workload": "nfw_1e6 + stars tree, smooth 0.0002 patch at (0.3, 0.05), "
+                                                "256^2 base, 6 rounds, tol 1e-4",
                   "batched_lenses": len(lenses4), "batched_rays": R4, "batched_ms": 1e3 * b4,
                   "batched_rays_per_s": R4 / b4, "per_lens_launches_ms": 1e3 * l4}
 

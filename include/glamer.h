@@ -244,6 +244,69 @@ GLM_API glm_status glm_refine_round(double* cx, double* cy, double* side, const 
                                     int32_t* refined, void* workspace, size_t workspace_bytes,
                                     void* stream);
 
+/*
+ * Interpolation shortcut of refinement (Sec. 3.4).  The cells of a refined
+ * grid form a nested grid: an nbase x nbase base grid of side h0 with
+ * lower-left corner (x0, y0) at level 0, every split 3 x 3 one level deeper,
+ * a cell named by its level l and integer coordinates (i, j) with centre
+ * (x0 + (i + 1/2) h0 / 3^l, y0 + (j + 1/2) h0 / 3^l).  The caller-owned state
+ * holds per cell its level and coordinates and a hash (l, i, j) -> cell.
+ * Levels are supported while nbase * 3^l <= 2^28.
+ */
+
+/* Bytes of the interpolation state for grids of up to capacity cells. */
+GLM_API glm_status glm_interp_state_bytes(int64_t capacity, size_t* bytes);
+
+/* Bytes of device workspace for one glm_refine_interp_round. */
+GLM_API glm_status glm_interp_round_workspace_bytes(int64_t ncells, int64_t nrefine, size_t* bytes);
+
+/*
+ * Index the base grid: the ncells cells centred at (cx, cy) (device FP64) are
+ * cells of the base grid described above.  state: device buffer of at least
+ * glm_interp_state_bytes(capacity); capacity >= the largest cell count the
+ * rounds will reach.  No host synchronisation.
+ */
+GLM_API glm_status glm_interp_init(const double* cx, const double* cy, int64_t ncells, double x0, double y0,
+                                   double h0, int64_t capacity, void* state, size_t state_bytes, void* stream);
+
+/*
+ * One refinement round with the interpolation shortcut.  Ranks and splits the
+ * cells exactly as glm_refine_round (same cx, cy, side and `refined`).  Before
+ * a cell is split, its neighbours (on each of the 8 sides the cell of the same
+ * level, else the coarser cell covering that spot; none outside the grid) are
+ * compared with it: if there is at least one and every neighbour's kappa, g1
+ * and g2 differ from the cell's by at most tol (FP32 differences), the
+ * magnification matrix is taken as uniform over the cell, and its 8 new
+ * cells get, at their centres x (FP64 arithmetic, stored FP32),
+ *   alpha = alpha_c + [[k + g1, g2], [g2, k - g1]] (x - x_c),
+ *   kappa, g1, g2 = those of the cell,
+ * in a1, a2, kappa, g1, g2 (device FP32, capacity).  The new cells of the
+ * other refined cells are listed in shoot_idx (device int32, >= 8 nrefine), 8
+ * per cell in rank order and row order, and their number is written to
+ * *shoot_count (device int32): shoot them with glm_shoot_indexed.
+ * 1 <= nrefine <= ncells, ncells + 8 nrefine <= capacity.  No host
+ * synchronisation.
+ */
+GLM_API glm_status glm_refine_interp_round(double* cx, double* cy, double* side, float* a1, float* a2,
+                                           float* kappa, float* g1, float* g2, int64_t ncells, int64_t nrefine,
+                                           int64_t nbase, float tol, int32_t* refined, int32_t* shoot_idx,
+                                           int32_t* shoot_count, int64_t capacity, void* state,
+                                           size_t state_bytes, void* workspace, size_t workspace_bytes,
+                                           void* stream);
+
+/* Bytes of device workspace for glm_shoot_indexed of count rays. */
+GLM_API glm_status glm_shoot_indexed_workspace_bytes(int64_t count, size_t* bytes);
+
+/*
+ * glm_shoot of the rays at (cx[idx[t]], cy[idx[t]]), t < count, with the
+ * outputs written at index idx[t] of a1, a2, kappa, g1, g2 (device arrays
+ * indexed like cx; kappa, g1, g2 unused with GLM_ALPHA_ONLY).  idx: device
+ * int32, distinct indices.  workspace >= glm_shoot_indexed_workspace_bytes.
+ */
+GLM_API glm_status glm_shoot_indexed(const glm_tree* t, const double* cx, const double* cy, const int32_t* idx,
+                                     int64_t count, float* a1, float* a2, float* kappa, float* g1, float* g2,
+                                     uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 GLM_API const char* glm_last_error(void);
 

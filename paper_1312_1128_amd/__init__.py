@@ -19,7 +19,8 @@ from ._capi import (GLM_ALPHA_ONLY, GLM_NO_KAHAN, GLM_RAYS_ORDERED, GlamerError,
 
 __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
            "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
-           "refine_schedule", "RefinementRun", "autotune", "smoothing_lengths"]
+           "refine_schedule", "RefinementRun", "autotune", "smoothing_lengths", "interp_init",
+           "refine_interp_round", "shoot_indexed"]
 
 
 def _ptr(t):
@@ -209,4 +210,5 @@ class ShootFn(torch.autograd.Function):
         return None, None, dm, dx, dy, (ds if ctx.has_s else None), None
 
 
-from .batch import RefinementRun, autotune, refine_round, refine_schedule, shoot_batched  # noqa: E402
+from .batch import (RefinementRun, autotune, interp_init, refine_interp_round, refine_round,  # noqa: E402
+                    refine_schedule, shoot_batched, shoot_indexed)

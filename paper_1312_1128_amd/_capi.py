@@ -23,7 +23,9 @@ EXPORTED = [
     "glm_tree_create", "glm_tree_destroy", "glm_build_tree", "glm_tree_get_info", "glm_tree_export",
     "glm_shoot_workspace_bytes", "glm_shoot", "glm_shoot_direct", "glm_shoot_adjoint",
     "glm_last_error", "glm_version", "glm_shoot_batched_workspace_bytes", "glm_shoot_batched",
-    "glm_refine_workspace_bytes", "glm_refine_round", "glm_tree_knn",
+    "glm_refine_workspace_bytes", "glm_refine_round", "glm_tree_knn", "glm_interp_state_bytes",
+    "glm_interp_round_workspace_bytes", "glm_interp_init", "glm_refine_interp_round",
+    "glm_shoot_indexed_workspace_bytes", "glm_shoot_indexed",
 ]
 
 
@@ -94,6 +96,20 @@ def load(path: str = LIB_PATH):
     lib.glm_refine_workspace_bytes.restype = st
     lib.glm_refine_round.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, vp, vp, ctypes.c_size_t, vp]
     lib.glm_refine_round.restype = st
+    sz = ctypes.c_size_t
+    lib.glm_interp_state_bytes.argtypes = [i64, P(sz)]
+    lib.glm_interp_state_bytes.restype = st
+    lib.glm_interp_round_workspace_bytes.argtypes = [i64, i64, P(sz)]
+    lib.glm_interp_round_workspace_bytes.restype = st
+    lib.glm_interp_init.argtypes = [vp, vp, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, vp, sz, vp]
+    lib.glm_interp_init.restype = st
+    lib.glm_refine_interp_round.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i64, ctypes.c_float, vp, vp,
+                                            vp, i64, vp, sz, vp, sz, vp]
+    lib.glm_refine_interp_round.restype = st
+    lib.glm_shoot_indexed_workspace_bytes.argtypes = [i64, P(sz)]
+    lib.glm_shoot_indexed_workspace_bytes.restype = st
+    lib.glm_shoot_indexed.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, u32, vp, sz, vp]
+    lib.glm_shoot_indexed.restype = st
     lib.glm_tree_knn.argtypes = [vp, ctypes.c_int32, vp, vp]
     lib.glm_tree_knn.restype = st
     lib.glm_last_error.argtypes = []

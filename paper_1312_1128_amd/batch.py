@@ -71,6 +71,49 @@ def refine_round(cx, cy, side, kappa, g1, g2, ncells: int, nrefine: int, refined
                                      ctypes.c_void_p(_ptr(workspace)), workspace.numel(), _stream()))
 
 
+def _size(fn, *args) -> int:
+    b = ctypes.c_size_t(0)
+    _capi.check(fn(*args, ctypes.byref(b)))
+    return int(b.value)
+
+
+def interp_init(cx, cy, ncells: int, x0: float, y0: float, h0: float, capacity: int, state):
+    """Index the base grid (nbase x nbase cells of side h0, lower-left corner
+    (x0, y0)) for the interpolation shortcut; state: uint8 CUDA tensor."""
+    lib = _capi.load()
+    _capi.check(lib.glm_interp_init(ctypes.c_void_p(_ptr(cx)), ctypes.c_void_p(_ptr(cy)), int(ncells), float(x0),
+                                    float(y0), float(h0), int(capacity), ctypes.c_void_p(_ptr(state)), state.numel(),
+                                    _stream()))
+
+
+def refine_interp_round(cx, cy, side, out, ncells: int, nrefine: int, nbase: int, tol: float, capacity: int, state,
+                        shoot_idx, shoot_count, refined=None, workspace=None):
+    """One refinement round with the interpolation shortcut (Sec. 3.4): new
+    cells of uniform cells are filled in `out`, the others are listed in
+    shoot_idx with their number in shoot_count (device)."""
+    lib = _capi.load()
+    if workspace is None:
+        workspace = torch.empty(_size(lib.glm_interp_round_workspace_bytes, int(ncells), int(nrefine)),
+                                dtype=torch.uint8, device=cx.device)
+    v = lambda t: ctypes.c_void_p(_ptr(t))
+    _capi.check(lib.glm_refine_interp_round(v(cx), v(cy), v(side), v(out["a1"]), v(out["a2"]), v(out["kappa"]),
+                                            v(out["g1"]), v(out["g2"]), int(ncells), int(nrefine), int(nbase),
+                                            float(tol), v(refined), v(shoot_idx), v(shoot_count), int(capacity),
+                                            v(state), state.numel(), v(workspace), workspace.numel(), _stream()))
+
+
+def shoot_indexed(tree, cx, cy, idx, count: int, out, workspace=None, alpha_only: bool = False):
+    """Walk the rays (cx[idx[t]], cy[idx[t]]), t < count, writing out[...][idx[t]]."""
+    lib = _capi.load()
+    if workspace is None:
+        workspace = torch.empty(max(_size(lib.glm_shoot_indexed_workspace_bytes, int(count)), 1), dtype=torch.uint8,
+                                device=cx.device)
+    v = lambda t: ctypes.c_void_p(_ptr(t))
+    _capi.check(lib.glm_shoot_indexed(tree.handle.value, v(cx), v(cy), v(idx), int(count), v(out["a1"]), v(out["a2"]),
+                                      v(out.get("kappa")), v(out.get("g1")), v(out.get("g2")),
+                                      GLM_ALPHA_ONLY if alpha_only else 0, v(workspace), workspace.numel(), _stream()))
+
+
 def refine_schedule(n0: int, rounds: int = 6, frac: float = 0.1, max_new_rays: int = 600_000):
     """Cells refined per round: floor(frac * cells), with 8 new rays per refined
     cell capped at max_new_rays."""
@@ -126,6 +169,48 @@ class RefinementRun:
             self._shoot_range(n, n + 8 * k)
             n += 8 * k
         return n
+
+    def run_interp(self, x0: float, y0: float, h0: float, nbase: int, tol: float = 1e-4):
+        """The same schedule with the interpolation shortcut (Sec. 3.4): the
+        base cells (an nbase x nbase grid of side h0 from (x0, y0)) are shot,
+        then each round fills the new cells of uniform cells by the linear lens
+        equation and walks only the others.  Reads the number of rays to walk
+        once per round (a host synchronisation), so it is not graph-captured.
+        Returns (cells, rays walked)."""
+        lib = _capi.load()
+        dev = self.cx.device
+        if not hasattr(self, "_interp"):
+            self._interp = dict(
+                state=torch.empty(_size(lib.glm_interp_state_bytes, self.cap), dtype=torch.uint8, device=dev),
+                idx=torch.zeros(max(8 * max(self.schedule + [1]), 1), dtype=torch.int32, device=dev),
+                count=torch.zeros(1, dtype=torch.int32, device=dev),
+                ws_round=torch.empty(max(_size(lib.glm_interp_round_workspace_bytes, n, max(k, 1))
+                                         for n, k in self._rounds()), dtype=torch.uint8, device=dev),
+                ws_idx=torch.empty(_size(lib.glm_shoot_indexed_workspace_bytes, 8 * max(self.schedule + [1])),
+                                   dtype=torch.uint8, device=dev))
+        it = self._interp
+        bx, by, bs = self.base
+        self.cx[: self.n0].copy_(bx)
+        self.cy[: self.n0].copy_(by)
+        self.side[: self.n0].copy_(bs)
+        self._shoot_range(0, self.n0)
+        interp_init(self.cx, self.cy, self.n0, x0, y0, h0, self.cap, it["state"])
+        n, walked = self.n0, self.n0
+        for k in self.schedule:
+            if k > 0:
+                refine_interp_round(self.cx, self.cy, self.side, self.out, n, k, nbase, tol, self.cap, it["state"],
+                                    it["idx"], it["count"], refined=self.refined, workspace=it["ws_round"])
+                cnt = int(it["count"].item())
+                shoot_indexed(self.tree, self.cx, self.cy, it["idx"], cnt, self.out, workspace=it["ws_idx"])
+                walked += cnt
+            n += 8 * k
+        return n, walked
+
+    def _rounds(self):
+        n = self.n0
+        for k in self.schedule:
+            yield n, k
+            n += 8 * k
 
     def capture(self):
         s = torch.cuda.Stream()

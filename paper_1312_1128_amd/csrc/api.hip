@@ -315,4 +315,79 @@ glm_status glm_refine_round(double* cx, double* cy, double* side, const float* k
                                static_cast<hipStream_t>(stream));
 }
 
+glm_status glm_interp_state_bytes(int64_t capacity, size_t* bytes)
+{
+    if (!bytes || capacity < 1 || capacity > 0x7fffff00) return fail(GLM_EINVAL, "bad argument");
+    *bytes = interp_layout(capacity).bytes;
+    return GLM_OK;
+}
+
+glm_status glm_interp_round_workspace_bytes(int64_t ncells, int64_t nrefine, size_t* bytes)
+{
+    if (!bytes || ncells < 1 || nrefine < 0 || nrefine > ncells || ncells > 0x7fffff00)
+        return fail(GLM_EINVAL, "bad argument");
+    *bytes = interp_round_workspace_bytes(ncells, nrefine);
+    return GLM_OK;
+}
+
+glm_status glm_interp_init(const double* cx, const double* cy, int64_t ncells, double x0, double y0, double h0,
+                           int64_t capacity, void* state, size_t state_bytes, void* stream)
+{
+    if (!cx || !cy || !state) return fail(GLM_EINVAL, "NULL device pointer");
+    if (ncells < 1 || capacity < ncells || capacity > 0x7fffff00) return fail(GLM_EINVAL, "need 1 <= ncells <= capacity");
+    if (!(h0 > 0.0) || !isfinite(h0) || !isfinite(x0) || !isfinite(y0)) return fail(GLM_EINVAL, "bad base grid");
+    const size_t need = interp_layout(capacity).bytes;
+    if (state_bytes < need) return fail(GLM_ENOMEM, "state smaller than glm_interp_state_bytes = " + std::to_string(need));
+    return interp_init_device(cx, cy, ncells, x0, y0, h0, capacity, state, static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_refine_interp_round(double* cx, double* cy, double* side, float* a1, float* a2, float* kappa,
+                                   float* g1, float* g2, int64_t ncells, int64_t nrefine, int64_t nbase, float tol,
+                                   int32_t* refined, int32_t* shoot_idx, int32_t* shoot_count, int64_t capacity,
+                                   void* state, size_t state_bytes, void* workspace, size_t workspace_bytes,
+                                   void* stream)
+{
+    if (!cx || !cy || !side || !a1 || !a2 || !kappa || !g1 || !g2 || !shoot_idx || !shoot_count || !state)
+        return fail(GLM_EINVAL, "NULL device pointer");
+    if (ncells < 1 || nrefine < 0 || nrefine > ncells) return fail(GLM_EINVAL, "need 0 <= nrefine <= ncells");
+    if (ncells + 8 * nrefine > capacity || capacity > 0x7fffff00) return fail(GLM_EINVAL, "capacity too small");
+    if (nbase < 1 || nbase > (1 << 28)) return fail(GLM_EINVAL, "nbase out of range");
+    if (!(tol >= 0.0f) || !isfinite(tol)) return fail(GLM_EINVAL, "tol must be finite and >= 0");
+    const size_t sneed = interp_layout(capacity).bytes;
+    if (state_bytes < sneed) return fail(GLM_ENOMEM, "state smaller than glm_interp_state_bytes = " + std::to_string(sneed));
+    const size_t need = interp_round_workspace_bytes(ncells, nrefine);
+    if (!workspace || workspace_bytes < need)
+        return fail(GLM_ENOMEM, "workspace smaller than glm_interp_round_workspace_bytes = " + std::to_string(need));
+    if (nrefine == 0) return fail(GLM_EINVAL, "nrefine must be >= 1");
+    return interp_round_device(cx, cy, side, a1, a2, kappa, g1, g2, ncells, nrefine, nbase, tol, refined, shoot_idx,
+                               shoot_count, capacity, state, workspace, static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_shoot_indexed_workspace_bytes(int64_t count, size_t* bytes)
+{
+    if (!bytes || count < 0 || count > 0x7fffff00) return fail(GLM_EINVAL, "bad argument");
+    *bytes = shoot_indexed_workspace_bytes(count);
+    return GLM_OK;
+}
+
+glm_status glm_shoot_indexed(const glm_tree* t, const double* cx, const double* cy, const int32_t* idx, int64_t count,
+                             float* a1, float* a2, float* kappa, float* g1, float* g2, uint32_t flags, void* workspace,
+                             size_t workspace_bytes, void* stream)
+{
+    if (!t) return fail(GLM_EINVAL, "tree handle is NULL");
+    if (!t->ts.built) return fail(GLM_ESTATE, "tree not built");
+    if (count < 0 || count > 0x7fffff00) return fail(GLM_EINVAL, "count out of range");
+    if (count == 0) return GLM_OK;
+    if (!cx || !cy || !idx || !a1 || !a2) return fail(GLM_EINVAL, "NULL device pointer");
+    if (flags & ~(GLM_ALPHA_ONLY | GLM_NO_KAHAN)) return fail(GLM_EINVAL, "unknown flag bits");
+    flags |= t->ts.params.flags;
+    if (!(flags & GLM_ALPHA_ONLY) && (!kappa || !g1 || !g2))
+        return fail(GLM_EINVAL, "kappa, g1, g2 are required unless GLM_ALPHA_ONLY");
+    const size_t need = shoot_indexed_workspace_bytes(count);
+    if (!workspace || workspace_bytes < need)
+        return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_indexed_workspace_bytes = " + std::to_string(need));
+    return shoot_indexed_device(t->ts, cx, cy, idx, count, a1, a2, kappa, g1, g2, flags, workspace,
+                                static_cast<hipStream_t>(stream));
+}
+
 } // extern "C"

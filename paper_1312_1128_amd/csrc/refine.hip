@@ -72,11 +72,9 @@ RefineLayout refine_layout(int64_t n)
 
 size_t refine_workspace_bytes(int64_t ncells) { return refine_layout(ncells).bytes; }
 
-glm_status refine_round_device(double* cx, double* cy, double* side, const float* ka, const float* g1,
-                               const float* g2, int64_t ncells, int64_t nrefine, int32_t* refined, void* ws,
-                               hipStream_t st)
+glm_status refine_rank_device(const double* side, const float* ka, const float* g1, const float* g2,
+                              int64_t ncells, void* ws, const uint32_t** order, hipStream_t st)
 {
-    if (nrefine == 0) return GLM_OK;
     const RefineLayout R = refine_layout(ncells);
     char* W = static_cast<char*>(ws);
     uint32_t* k0 = reinterpret_cast<uint32_t*>(W + R.k0);
@@ -87,10 +85,29 @@ glm_status refine_round_device(double* cx, double* cy, double* side, const float
     hipLaunchKernelGGL(k_refine_keys, dim3(ceil_div(ncells, kBlock)), dim3(kBlock), 0, st, side, ka, g1, g2, ncells,
                        k0, v0);
     const int w = radix_sort_u32(k0, v0, k1, v1, ncells, 4, hist, st);
-    hipLaunchKernelGGL(k_refine_spawn, dim3(ceil_div(nrefine, kBlock)), dim3(kBlock), 0, st, w ? v1 : v0, nrefine,
-                       ncells, cx, cy, side, refined);
+    *order = w ? v1 : v0;
     GLM_HIP(hipGetLastError());
     return GLM_OK;
+}
+
+glm_status refine_spawn_device(const uint32_t* order, int64_t nrefine, int64_t ncells, double* cx, double* cy,
+                               double* side, int32_t* refined, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_refine_spawn, dim3(ceil_div(nrefine, kBlock)), dim3(kBlock), 0, st, order, nrefine, ncells,
+                       cx, cy, side, refined);
+    GLM_HIP(hipGetLastError());
+    return GLM_OK;
+}
+
+glm_status refine_round_device(double* cx, double* cy, double* side, const float* ka, const float* g1,
+                               const float* g2, int64_t ncells, int64_t nrefine, int32_t* refined, void* ws,
+                               hipStream_t st)
+{
+    if (nrefine == 0) return GLM_OK;
+    const uint32_t* order = nullptr;
+    glm_status rc = refine_rank_device(side, ka, g1, g2, ncells, ws, &order, st);
+    if (rc != GLM_OK) return rc;
+    return refine_spawn_device(order, nrefine, ncells, cx, cy, side, refined, st);
 }
 
 } // namespace glm

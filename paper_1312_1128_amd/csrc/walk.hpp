@@ -31,6 +31,28 @@ size_t refine_workspace_bytes(int64_t ncells);
 glm_status refine_round_device(double* cx, double* cy, double* side, const float* ka, const float* g1,
                                const float* g2, int64_t ncells, int64_t nrefine, int32_t* refined, void* ws,
                                hipStream_t st);
+// The two halves of a round: rank the cells (order = cell indices by
+// descending score, in ws), then split the first nrefine of them.
+glm_status refine_rank_device(const double* side, const float* ka, const float* g1, const float* g2,
+                              int64_t ncells, void* ws, const uint32_t** order, hipStream_t st);
+glm_status refine_spawn_device(const uint32_t* order, int64_t nrefine, int64_t ncells, double* cx, double* cy,
+                               double* side, int32_t* refined, hipStream_t st);
+
+// Interpolation shortcut of refinement (interp.hip): per-cell level and
+// integer coordinates plus a (level, i, j) -> cell hash, in a caller buffer.
+struct InterpLayout {
+    size_t lev, ci, cj, keys, vals, bytes;
+    int64_t table_cap;
+};
+InterpLayout interp_layout(int64_t capacity);
+size_t interp_round_workspace_bytes(int64_t ncells, int64_t nrefine);
+glm_status interp_init_device(const double* cx, const double* cy, int64_t ncells, double x0, double y0, double h0,
+                              int64_t capacity, void* state, hipStream_t st);
+glm_status interp_round_device(double* cx, double* cy, double* side, float* a1, float* a2, float* ka, float* g1,
+                               float* g2, int64_t ncells, int64_t nrefine, int64_t nbase, float tol,
+                               int32_t* refined, int32_t* shoot_idx, int32_t* shoot_count, int64_t capacity,
+                               void* state, void* ws, hipStream_t st);
+size_t shoot_indexed_workspace_bytes(int64_t count);
 
 // Wavefronts per 64-ray group.  A small launch (few groups) splits the
 // preorder box array into K ranges walked by separate wavefronts, so that
@@ -95,6 +117,10 @@ glm_status split_box_device(const TreeStorage& ts, const double* rx, const doubl
 glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, float* a1,
                         float* a2, float* k, float* g1, float* g2, int32_t* counts, uint32_t flags, void* ws,
                         hipStream_t st);
+
+glm_status shoot_indexed_device(const TreeStorage& ts, const double* cx, const double* cy, const int32_t* idx,
+                                int64_t count, float* a1, float* a2, float* ka, float* g1, float* g2, uint32_t flags,
+                                void* ws, hipStream_t st);
 
 glm_status direct_device(const double* x, const double* y, const double* m, const double* s, int64_t n, double q,
                          const double* rx, const double* ry, int64_t nrays, int fp64, void* const out5[5],

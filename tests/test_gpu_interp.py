@@ -1,0 +1,223 @@
+"""Interpolation shortcut of refinement (Sec. 3.4) on the device, against a
+plain numpy restatement of the rule (decisions, neighbours, shoot lists
+bit for bit; filled values to FP32 rounding), and against the tree walk at
+the interpolated points (the paper finds interpolation and direct shooting
+agree to a part in 1e4 for the deflection)."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import build, dev, say
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["a1", "a2", "kappa", "g1", "g2"]
+
+
+def locate(table, level, i, j, nbase):
+    """The cell at (level, i, j), else the nearest coarser cell covering it."""
+    for l in range(level, -1, -1):
+        span = 3 ** l
+        if i < 0 or j < 0 or i >= nbase * span or j >= nbase * span:
+            return -1
+        c = table.get((l, i, j), -1)
+        if c >= 0:
+            return c
+        i //= 3
+        j //= 3
+    return -1
+
+
+def numpy_round(S, n, k, nbase, tol):
+    """One round of the rule on host copies S (cx, cy, side, outputs, lev, ci,
+    cj, table).  Returns the shoot list."""
+    f32 = np.float32
+    h = S["side"][:n].astype(f32)
+    ka, g1, g2 = (S[q][:n].astype(f32) for q in ("kappa", "g1", "g2"))
+    sc = (h * h) * ((ka * ka + g1 * g1) + g2 * g2)
+    key = np.uint32(0xFFFFFFFF) - sc.astype(f32).view(np.uint32)
+    order = np.argsort(key, kind="stable")[:k]
+    uniform = []
+    for c in order:
+        found, ok = 0, True
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == 0 and dy == 0:
+                    continue
+                nb = locate(S["table"], S["lev"][c], S["ci"][c] + dx, S["cj"][c] + dy, nbase)
+                if nb < 0 or nb == c:
+                    continue
+                found += 1
+                ok = ok and all(abs(f32(S[q][nb]) - f32(S[q][c])) <= f32(tol) for q in ("kappa", "g1", "g2"))
+        uniform.append(ok and found > 0)
+    shoot = []
+    for t, c in enumerate(order):
+        h3 = S["side"][c] / 3.0
+        l, i, j = S["lev"][c] + 1, 3 * S["ci"][c] + 1, 3 * S["cj"][c] + 1
+        A1, A2, K, G1, G2 = (float(S[q][c]) for q in NAMES)
+        q = 0
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == 0 and dy == 0:
+                    continue
+                o = n + 8 * t + q
+                S["cx"][o] = S["cx"][c] + float(dx) * h3
+                S["cy"][o] = S["cy"][c] + float(dy) * h3
+                S["side"][o] = h3
+                S["lev"][o], S["ci"][o], S["cj"][o] = l, i + dx, j + dy
+                S["table"][(l, i + dx, j + dy)] = o
+                if uniform[t]:
+                    ux, uy = S["cx"][o] - S["cx"][c], S["cy"][o] - S["cy"][c]
+                    S["a1"][o] = A1 + (K + G1) * ux + G2 * uy
+                    S["a2"][o] = A2 + G2 * ux + (K - G1) * uy
+                    S["kappa"][o], S["g1"][o], S["g2"][o] = K, G1, G2
+                else:
+                    shoot.append(o)
+                q += 1
+        S["side"][c] = h3
+        S["lev"][c], S["ci"][c], S["cj"][c] = l, i, j
+        S["table"][(l, i, j)] = int(c)
+    return np.array(order), np.array(uniform), np.array(shoot, dtype=np.int64)
+
+
+def micro_lens(nhalo, nstars, seed):
+    halo = synth.nfw_halo(nhalo, seed)
+    stars = synth.star_patch(nstars, seed + 2)
+    return synth.Lens(np.concatenate([halo.x, stars.x]), np.concatenate([halo.y, stars.y]),
+                      np.concatenate([halo.m, stars.m]), np.concatenate([halo.s, stars.s]))
+
+
+def smooth_lens(nhalo, seed):
+    return synth.nfw_halo(nhalo, seed)
+
+
+# (lens, base cells per side, patch side, patch centre): a smooth halo, where
+# the refined cells are mostly uniform, and a star field, where they are not
+CASES = {
+    "smooth_halo": (lambda: smooth_lens(50_000, 503), 48, 0.0002, (0.3, 0.05)),
+    "star_field": (lambda: micro_lens(50_000, 2_000, 501), 48, 0.01, (0.25, 0.0)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_interp_rounds_match_rule_and_walk(ora, case):
+    import paper_1312_1128_amd as g
+    import torch
+
+    make, nbase, patch, (xc, yc) = CASES[case]
+    lens = make()
+    x0, y0 = xc - patch / 2, yc - patch / 2
+    h0 = patch / nbase
+    bx, by = synth.ray_grid(nbase, 0.0, patch)
+    bx, by = bx + x0, by + y0
+    sched = g.refine_schedule(bx.size, rounds=4)
+    cap = bx.size + 8 * sum(sched)
+    say(f"[gpu] interpolation rounds: n={lens.n} base={nbase}^2 schedule={sched}")
+    tree = build(lens, 0.3, 16, 8)
+    cx = torch.zeros(cap, dtype=torch.float64, device="cuda")
+    cy, side = torch.zeros_like(cx), torch.zeros_like(cx)
+    cx[: bx.size], cy[: bx.size], side[: bx.size] = dev(bx), dev(by), h0
+    out = {q: torch.zeros(cap, dtype=torch.float32, device="cuda") for q in NAMES}
+    n = bx.size
+    o0 = g.shoot(tree, cx[:n], cy[:n])
+    for q in NAMES:
+        out[q][:n] = o0[q]
+    lib = g._capi.load()
+    import ctypes
+
+    sbytes = ctypes.c_size_t()
+    lib.glm_interp_state_bytes(cap, ctypes.byref(sbytes))
+    state = torch.empty(sbytes.value, dtype=torch.uint8, device="cuda")
+    g.interp_init(cx, cy, n, x0, y0, h0, cap, state)
+    idx = torch.zeros(8 * max(sched), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    refined = torch.zeros(max(sched), dtype=torch.int32, device="cuda")
+    # host mirror of the state
+    S = {"cx": cx.cpu().numpy().copy(), "cy": cy.cpu().numpy().copy(), "side": side.cpu().numpy().copy()}
+    for q in NAMES:
+        S[q] = out[q].cpu().numpy().astype(np.float64)
+    S["lev"] = np.zeros(cap, dtype=np.int64)
+    S["ci"] = np.zeros(cap, dtype=np.int64)
+    S["cj"] = np.zeros(cap, dtype=np.int64)
+    ii = np.floor((S["cx"][:n] - x0) / h0).astype(np.int64)
+    jj = np.floor((S["cy"][:n] - y0) / h0).astype(np.int64)
+    S["ci"][:n], S["cj"][:n] = ii, jj
+    S["table"] = {(0, int(a), int(b)): c for c, (a, b) in enumerate(zip(ii, jj))}
+    interpolated = []
+    for r, k in enumerate(sched):
+        order, uniform, shoot = numpy_round(S, n, k, nbase, 1e-4)
+        g.refine_interp_round(cx, cy, side, out, n, k, nbase, 1e-4, cap, state, idx, count, refined=refined)
+        cnt = int(count.item())
+        say(f"  round {r}: refine {k}, uniform {int(uniform.sum())}, walk {cnt}")
+        np.testing.assert_array_equal(refined[:k].cpu().numpy(), order)
+        assert cnt == shoot.size
+        np.testing.assert_array_equal(idx[:cnt].cpu().numpy(), shoot)
+        m = n + 8 * k
+        np.testing.assert_array_equal(cx[:m].cpu().numpy(), S["cx"][:m])
+        np.testing.assert_array_equal(cy[:m].cpu().numpy(), S["cy"][:m])
+        np.testing.assert_array_equal(side[:m].cpu().numpy(), S["side"][:m])
+        filled = np.setdiff1d(np.arange(n, m), shoot)
+        for q in NAMES:
+            if filled.size == 0:
+                break
+            got = out[q][:m].cpu().numpy()[filled].astype(np.float64)
+            np.testing.assert_allclose(got, S[q][filled], rtol=1e-6, atol=1e-7 * np.abs(S[q][filled]).max())
+        g.shoot_indexed(tree, cx, cy, idx, cnt, out)
+        for q in NAMES:  # the device values (walked, and filled up to rounding) carry over to the mirror
+            S[q][n:m] = out[q][n:m].cpu().numpy().astype(np.float64)
+        interpolated.append(filled)
+        n = m
+    interpolated = np.concatenate(interpolated)
+    say(f"  {interpolated.size} of {n - bx.size} new cells interpolated")
+    if case == "smooth_halo":
+        assert interpolated.size > (n - bx.size) // 2
+    if interpolated.size == 0:
+        return
+    # interpolated cells against walking the same points
+    walked = g.shoot(tree, dev(S["cx"][interpolated]), dev(S["cy"][interpolated]))
+    a_int = np.stack([out["a1"].cpu().numpy()[interpolated], out["a2"].cpu().numpy()[interpolated]], 1)
+    a_w = np.stack([walked["a1"].cpu().numpy(), walked["a2"].cpu().numpy()], 1).astype(np.float64)
+    err = np.linalg.norm(a_int - a_w, axis=1) / np.linalg.norm(a_w, axis=1)
+    say(f"  {interpolated.size} interpolated rays: alpha vs walk max {err.max():.2e} median {np.median(err):.2e}")
+    assert err.max() <= 1e-4
+    dk = np.abs(out["kappa"].cpu().numpy()[interpolated] - walked["kappa"].cpu().numpy())
+    say(f"  kappa vs walk max {dk.max():.2e}")
+
+
+def test_interp_tol_zero_walks_everything():
+    import paper_1312_1128_amd as g
+    import torch
+
+    lens = micro_lens(20_000, 500, 511)
+    nbase, patch = 32, 0.01
+    x0, y0 = 0.25 - patch / 2, -patch / 2
+    bx, by = synth.ray_grid(nbase, 0.0, patch)
+    tree = build(lens, 0.3, 16, 8)
+    sched = g.refine_schedule(bx.size, rounds=3)
+    run = g.RefinementRun(tree, dev(bx + x0), dev(by + y0), dev(np.full(bx.size, patch / nbase)), sched)
+    n = run.run()
+    torch.cuda.synchronize()
+    plain = {q: v[:n].cpu().numpy().copy() for q, v in run.out.items()}
+    pos = (run.cx[:n].cpu().numpy().copy(), run.cy[:n].cpu().numpy().copy(), run.side[:n].cpu().numpy().copy())
+    n2, walked = run.run_interp(x0, y0, patch / nbase, nbase, tol=0.0)
+    torch.cuda.synchronize()
+    say(f"[gpu] tol 0: {n2} cells, {walked} walked")
+    assert n2 == n
+    np.testing.assert_array_equal(run.cx[:n].cpu().numpy(), pos[0])
+    np.testing.assert_array_equal(run.side[:n].cpu().numpy(), pos[2])
+    # with tol 0 only exactly equal neighbourhoods are interpolated
+    for q in NAMES:
+        np.testing.assert_allclose(run.out[q][:n].cpu().numpy(), plain[q], rtol=2e-5,
+                                   atol=1e-6 * np.abs(plain[q]).max())
+
+
+def test_interp_invalid_arguments():
+    import paper_1312_1128_amd as g
+    import torch
+
+    x = torch.zeros(16, dtype=torch.float64, device="cuda")
+    st = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(g.GlamerError):  # state too small
+        g.interp_init(x, x, 16, 0.0, 0.0, 1.0, 16, st)
+    with pytest.raises(g.GlamerError):  # bad base grid
+        g.interp_init(x, x, 16, 0.0, 0.0, 0.0, 16, torch.empty(1 << 16, dtype=torch.uint8, device="cuda"))
