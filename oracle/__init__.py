@@ -58,6 +58,12 @@ def _load():
     lib.ora_kernel_norm.argtypes = [ctypes.c_double]
     lib.ora_kernel_norm.restype = ctypes.c_double
     lib.ora_knn.argtypes = [d, d, i64, ctypes.c_int, d, ctypes.c_int]
+    lib.ora_unit_psi.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int]
+    lib.ora_unit_psi.restype = ctypes.c_double
+    lib.ora_ein.argtypes = [ctypes.c_double]
+    lib.ora_ein.restype = ctypes.c_double
+    lib.ora_direct_psi.argtypes = [d, d, d, d, i64, ctypes.c_double, d, d, i64, d, ctypes.c_int]
+    lib.ora_tree_shoot_psi.argtypes = [vp, d, d, i64, d, ctypes.c_int]
     lib.ora_knn_at.argtypes = [d, d, i64, ctypes.c_int, vp, i64, d, ctypes.c_int]
     lib.ora_tree_build.argtypes = [d, d, d, d, i64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int]
@@ -117,6 +123,26 @@ def direct(x, y, m, s, q, rx, ry, threads: int | None = None) -> np.ndarray:
     lib.ora_direct(_p(x), _p(y), _p(m), _p(s), x.shape[0], float(q), _p(rx), _p(ry), nr,
                    *[_p(o) for o in out], threads or default_threads())
     return np.stack(out, axis=1)
+
+
+def unit_psi(d1: float, d2: float, s: float, q: float, inside: bool) -> float:
+    return _load().ora_unit_psi(d1, d2, s, q, int(inside))
+
+
+def ein(z: float) -> float:
+    return _load().ora_ein(z)
+
+
+def direct_psi(x, y, m, s, q, rx, ry, threads: int | None = None) -> np.ndarray:
+    """Oracle A for the lensing potential psi (alpha = grad psi)."""
+    lib = _load()
+    x, y, m = _f64(x), _f64(y), _f64(m)
+    s = _f64(s) if s is not None else np.zeros_like(x)
+    rx, ry = _f64(rx), _f64(ry)
+    out = np.zeros(rx.shape[0])
+    lib.ora_direct_psi(_p(x), _p(y), _p(m), _p(s), x.shape[0], float(q), _p(rx), _p(ry), rx.shape[0], _p(out),
+                       threads or default_threads())
+    return out
 
 
 def knn(x, y, k: int = 32, at=None, threads: int | None = None) -> np.ndarray:
@@ -212,6 +238,13 @@ class Tree:
                                  cnt.ctypes.data if counts else None, threads or default_threads())
         res = np.stack(out, axis=1)
         return (res, cnt) if counts else res
+
+    def shoot_psi(self, rx, ry, threads: int | None = None):
+        """The potential psi along the same walk."""
+        rx, ry = _f64(rx), _f64(ry)
+        out = np.zeros(rx.shape[0])
+        self._lib.ora_tree_shoot_psi(self._h, _p(rx), _p(ry), rx.shape[0], _p(out), threads or default_threads())
+        return out
 
     def record(self, rx, ry):
         rx, ry = _f64(rx), _f64(ry)

@@ -58,6 +58,38 @@ void ora_unit_terms(double d1, double d2, double s, double q, int inside, double
     out[6] = dG * d2;
 }
 
+/* Ein(z) = int_0^z (1 - e^-t) / t dt = sum_{k>=1} (-1)^(k+1) z^k / (k k!), an
+ * entire function; the series is summed until its terms stop changing the
+ * sum (z <= q^2 / 2 here, a few dozen terms). */
+double ora_ein(double z)
+{
+    double term = z, sum = 0.0; /* term = (-1)^(k+1) z^k / k! */
+    for (int k = 1; k < 400; ++k) {
+        const double add = term / (double)k;
+        const double next = sum + add;
+        if (next == sum && k > 1) break;
+        sum = next;
+        term *= -z / (double)(k + 1);
+    }
+    return sum;
+}
+
+/*
+ * Lensing potential of one particle, per unit mass, at offset d (Sec. 3.2:
+ * alpha = grad psi).  A point mass has psi = ln r.  The truncated Gaussian
+ * equals the point mass outside its support R = q s (its alpha does, and psi
+ * is fixed to agree there); inside, integrating d psi / d r = G(r) / r from R,
+ *   psi = ln R - (Ein(q^2/2) - Ein(u)) / (2 C),  u = r^2 / (2 s^2).
+ * A point mass exactly at the ray contributes 0, like its deflection.
+ */
+double ora_unit_psi(double d1, double d2, double s, double q, int inside)
+{
+    const double r2 = d1 * d1 + d2 * d2;
+    if (!inside) return r2 > 0.0 ? 0.5 * log(r2) : 0.0;
+    const double C = ora_kernel_norm(q);
+    return log(q * s) - (ora_ein(0.5 * q * q) - ora_ein(r2 / (2.0 * s * s))) / (2.0 * C);
+}
+
 /* inside iff s > 0 and r^2 < (q s)^2 (strict, Sec. 3.1). */
 int ora_inside(double d1, double d2, double s, double q)
 {
@@ -86,6 +118,23 @@ int ora_direct(const double* x, const double* y, const double* m, const double* 
         kap[r] = acc[2];
         g1[r] = acc[3];
         g2[r] = acc[4];
+    }
+    return 0;
+}
+
+int ora_direct_psi(const double* x, const double* y, const double* m, const double* s, int64_t n, double q,
+                   const double* rx, const double* ry, int64_t nr, double* psi, int nthreads)
+{
+    if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t r = 0; r < nr; ++r) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const double d1 = rx[r] - x[i], d2 = ry[r] - y[i];
+            const double si = s ? s[i] : 0.0;
+            acc += m[i] * ora_unit_psi(d1, d2, si, q, ora_inside(d1, d2, si, q));
+        }
+        psi[r] = acc;
     }
     return 0;
 }

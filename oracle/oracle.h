@@ -28,6 +28,13 @@ extern "C" {
  * point-mass form.  out: a1 a2 kappa g1 g2 da1/ds da2/ds. */
 void ora_unit_terms(double d1, double d2, double s, double q, int inside, double out[7]);
 
+/* Lensing potential of one particle per unit mass (point mass: ln r; the
+ * truncated Gaussian inside its support: ln(q s) - (Ein(q^2/2) - Ein(u)) / (2C)). */
+double ora_unit_psi(double d1, double d2, double s, double q, int inside);
+
+/* Ein(z) = integral_0^z (1 - exp(-t)) / t dt. */
+double ora_ein(double z);
+
 /* inside the truncated support: s > 0 and r^2 < (q s)^2 (Sec. 3.1) */
 int ora_inside(double d1, double d2, double s, double q);
 
@@ -38,6 +45,10 @@ double ora_kernel_norm(double q);
 int ora_direct(const double* x, const double* y, const double* m, const double* s, int64_t n,
                double q, const double* rx, const double* ry, int64_t nr,
                double* a1, double* a2, double* kap, double* g1, double* g2, int nthreads);
+
+/* Oracle A for the potential psi (alpha = grad psi, Sec. 3.2). */
+int ora_direct_psi(const double* x, const double* y, const double* m, const double* s, int64_t n, double q,
+                   const double* rx, const double* ry, int64_t nr, double* psi, int nthreads);
 
 /* Oracle A adjoint: gradient of L = sum_r ga_r . alpha_r with respect to the
  * particle masses, positions and smoothing lengths (FP64 brute force). */
@@ -77,6 +88,11 @@ int64_t ora_tree_list(const ora_tree* t, int64_t cell, int32_t* out);
 int ora_tree_shoot(const ora_tree* t, const double* rx, const double* ry, int64_t nr,
                    double* a1, double* a2, double* kap, double* g1, double* g2,
                    int64_t* counts, int nthreads);
+
+/* The potential psi along the same walk (boxes: Re[Q_0 ln w - sum Q_k / (k w^k)];
+ * leaves and list corrections from ora_unit_psi). */
+int ora_tree_shoot_psi(const ora_tree* t, const double* rx, const double* ry, int64_t nr, double* psi,
+                       int nthreads);
 
 /* Decision tape: record every branch of the walk for these rays, then replay
  * it after ora_tree_set_particles has changed masses/positions/smoothing

@@ -375,6 +375,20 @@ static void multipole(const double complex* Q, int p, double w1, double w2, doub
     acc[4] -= cimag(Gm);
 }
 
+/* potential of a box (Sec. 3.2, alpha = grad psi): for point masses,
+ * psi = Re sum_i m_i ln(w - d_i) = Re [Q_0 ln w - sum_{k>=1} Q_k / (k w^k)]. */
+static double multipole_psi(const double complex* Q, int p, double w1, double w2)
+{
+    const double complex w = w1 + I * w2;
+    const double complex iw = 1.0 / w;
+    double complex pw = iw, S = Q[0] * clog(w);
+    for (int k = 1; k <= p; ++k) {
+        S -= Q[k] * pw / (double)k;
+        pw *= iw;
+    }
+    return creal(S);
+}
+
 typedef struct {
     const double* ga; /* cotangent of alpha for the adjoint walk, or NULL */
     double *dm, *dx, *dy, *ds;
@@ -399,7 +413,7 @@ static void particle_term(const ora_tree* t, int64_t i, const double tt[7], doub
 }
 
 static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5], int64_t cnt[5],
-                  tape_t* tp, adj_t* adj)
+                  tape_t* tp, adj_t* adj, double* psi)
 {
     const ocell* cl = &t->cells[c];
     cnt[0]++;
@@ -414,6 +428,8 @@ static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5
             ora_unit_terms(d1, d2, t->s[i], t->q, 0, tpnt);
             particle_term(t, i, te, 1.0, acc, adj);
             particle_term(t, i, tpnt, -1.0, acc, adj);
+            if (psi)
+                *psi += t->m[i] * (ora_unit_psi(d1, d2, t->s[i], t->q, 1) - ora_unit_psi(d1, d2, t->s[i], t->q, 0));
         }
     }
     const double w1 = X - cl->cx, w2 = Y - cl->cy;
@@ -422,6 +438,7 @@ static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5
         const double complex* Q = t->Q + c * (t->p + 1);
         if (!adj) {
             multipole(Q, t->p, w1, w2, acc);
+            if (psi) *psi += multipole_psi(Q, t->p, w1, w2);
         } else {
             const double complex w = w1 + I * w2, iw = 1.0 / w;
             const double complex gh = adj->ga[0] + I * adj->ga[1];
@@ -441,9 +458,10 @@ static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5
             cnt[2]++;
             ora_unit_terms(d1, d2, t->s[j], t->q, in, tt);
             particle_term(t, j, tt, 1.0, acc, adj);
+            if (psi) *psi += t->m[j] * ora_unit_psi(d1, d2, t->s[j], t->q, in);
         }
     } else {
-        for (int k = 0; k < cl->nchild; ++k) visit(t, cl->child[k], X, Y, acc, cnt, tp, adj);
+        for (int k = 0; k < cl->nchild; ++k) visit(t, cl->child[k], X, Y, acc, cnt, tp, adj, psi);
     }
 }
 
@@ -455,7 +473,7 @@ int ora_tree_shoot(const ora_tree* t, const double* rx, const double* ry, int64_
     for (int64_t r = 0; r < nr; ++r) {
         double acc[5] = {0, 0, 0, 0, 0};
         int64_t cnt[5] = {0, 0, 0, 0, 0};
-        visit(t, 0, rx[r], ry[r], acc, cnt, NULL, NULL);
+        visit(t, 0, rx[r], ry[r], acc, cnt, NULL, NULL, NULL);
         a1[r] = acc[0];
         a2[r] = acc[1];
         kap[r] = acc[2];
@@ -463,6 +481,19 @@ int ora_tree_shoot(const ora_tree* t, const double* rx, const double* ry, int64_
         g2[r] = acc[4];
         if (counts)
             for (int k = 0; k < 5; ++k) counts[r * 5 + k] = cnt[k];
+    }
+    return 0;
+}
+
+int ora_tree_shoot_psi(const ora_tree* t, const double* rx, const double* ry, int64_t nr, double* psi, int nthreads)
+{
+    if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t r = 0; r < nr; ++r) {
+        double acc[5] = {0, 0, 0, 0, 0}, ps = 0.0;
+        int64_t cnt[5] = {0, 0, 0, 0, 0};
+        visit(t, 0, rx[r], ry[r], acc, cnt, NULL, NULL, &ps);
+        psi[r] = ps;
     }
     return 0;
 }
@@ -477,7 +508,7 @@ int ora_tree_record(ora_tree* t, const double* rx, const double* ry, int64_t nr)
         double acc[5] = {0, 0, 0, 0, 0};
         int64_t cnt[5] = {0, 0, 0, 0, 0};
         t->tapes[r].mode = 1;
-        visit(t, 0, rx[r], ry[r], acc, cnt, &t->tapes[r], NULL);
+        visit(t, 0, rx[r], ry[r], acc, cnt, &t->tapes[r], NULL, NULL);
         t->tapes[r].mode = 2;
     }
     return 0;
@@ -503,7 +534,7 @@ int ora_tree_shoot_frozen(const ora_tree* t, const double* rx, const double* ry,
         int64_t cnt[5] = {0, 0, 0, 0, 0};
         tape_t tp = t->tapes[r];
         tp.pos = 0;
-        visit(t, 0, rx[r], ry[r], acc, cnt, &tp, NULL);
+        visit(t, 0, rx[r], ry[r], acc, cnt, &tp, NULL, NULL);
         a1[r] = acc[0];
         a2[r] = acc[1];
         kap[r] = acc[2];
@@ -547,7 +578,7 @@ int ora_tree_grad(const ora_tree* t, const double* rx, const double* ry, int64_t
         int64_t cnt[5] = {0, 0, 0, 0, 0};
         double g[2] = {ga1[r], ga2[r]};
         adj.ga = g;
-        visit(t, 0, rx[r], ry[r], acc, cnt, NULL, &adj);
+        visit(t, 0, rx[r], ry[r], acc, cnt, NULL, &adj, NULL);
     }
     for (int64_t c = 0; c < t->nc; ++c) {
         const ocell* cl = &t->cells[c];
