@@ -198,6 +198,18 @@ def main():
         log(f"tree vs GPU FP64 direct over all {R} rays: max rel err alpha {full_err['alpha_max']:.2e} "
             f"kappa {full_err['kappa_max']:.2e} gamma {full_err['gamma_max']:.2e}")
 
+        # deflection + potential + time delay of the headline grid in one walk
+        pot = g.shoot_potential(tree, rx, ry, ordered=True, workspace=ws)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(3):
+            pot = g.shoot_potential(tree, rx, ry, ordered=True, workspace=ws)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        pot_ms = ev0.elapsed_time(ev1) / 3
+        log(f"alpha + potential + time delay walk: {pot_ms:.3f} ms -> {R / (pot_ms * 1e-3):.4e} rays/s")
+        del pot
+
         # smoothing lengths of the 1e6 particles on the GPU (tree of the positions + k = 32 walk)
         g.smoothing_lengths(x, y, k=32)
         torch.cuda.synchronize()
@@ -319,6 +331,7 @@ def main():
             f"per-lens launches {1e3 * l4:.2f} ms")
         extras = {"direct_fp32_rays_per_s": res[False], "direct_fp64_rays_per_s": res[True],
                   "full_grid_err_vs_gpu_fp64_direct": full_err,
+                  "potential_walk_ms": pot_ms, "potential_walk_rays_per_s": R / (pot_ms * 1e-3),
                   "knn_smoothing_1e6_ms": knn_ms, "knn_max_rel_diff_vs_host_kdtree": knn_diff,
                   "fwd_adjoint_rays_per_s": rx5.numel() / (fa_ms * 1e-3), "fwd_adjoint_ms": fa_ms,
                   "fwd_adjoint_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2",

@@ -169,6 +169,23 @@ GLM_API glm_status glm_shoot(const glm_tree* t, const double* rx, const double* 
                      uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Deflection and lensing potential (Sec. 3.2: alpha = grad psi; the time
+ * delay of a single plane is |alpha|^2 / 2 - psi), in one tree walk with the
+ * decisions of glm_shoot.  A point mass contributes m ln r (0 for a ray
+ * exactly on it), a truncated Gaussian the point-mass value outside its
+ * support and, inside, m [ln(q s) - (Ein(q^2/2) - Ein(u)) / (2C)] with
+ * Ein(z) = integral_0^z (1 - e^-t) / t dt; a box contributes
+ * Re[Q_0 ln w - sum_k Q_k / (k w^k)].  FP32 terms, FP64 sums.
+ *   a1, a2, psi: device FP32 outputs (nrays, input order);
+ *   tdelay: device FP32 |alpha|^2 / 2 - psi, or NULL;
+ *   flags: GLM_RAYS_ORDERED or 0; workspace as for glm_shoot.
+ * One wavefront per 64-ray group (small launches are not split).
+ */
+GLM_API glm_status glm_shoot_potential(const glm_tree* t, const double* rx, const double* ry, int64_t nrays,
+                                       float* a1, float* a2, float* psi, float* tdelay, uint32_t flags,
+                                       void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Plain direct sum over all n particles (theta = 0 equivalent; Sec. 5.1), for
  * rays (device FP64).  fp64 != 0: outputs are device double arrays; else
  * float arrays with FP32 evaluation and compensated accumulation.

@@ -20,7 +20,7 @@ from ._capi import (GLM_ALPHA_ONLY, GLM_NO_KAHAN, GLM_RAYS_ORDERED, GlamerError,
 __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
            "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
            "refine_schedule", "RefinementRun", "autotune", "smoothing_lengths", "interp_init",
-           "refine_interp_round", "shoot_indexed"]
+           "refine_interp_round", "shoot_indexed", "shoot_potential"]
 
 
 def _ptr(t):
@@ -136,6 +136,21 @@ def shoot(tree: Tree, rx, ry, counts: bool = False, alpha_only: bool = False, ka
                               _ptr(workspace), ws_bytes, _stream()))
     if counts:
         out["counts"] = cnt
+    return out
+
+
+def shoot_potential(tree: Tree, rx, ry, ordered: bool = False, workspace=None):
+    """Deflection, lensing potential and time delay (Sec. 3.2) in one walk:
+    dict of float32 tensors a1, a2, psi, tdelay (|alpha|^2 / 2 - psi)."""
+    rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
+    R = rx.shape[0]
+    out = {k: torch.empty(R, dtype=torch.float32, device=rx.device) for k in ["a1", "a2", "psi", "tdelay"]}
+    if workspace is None:
+        workspace = torch.empty(max(workspace_bytes(R), 1), dtype=torch.uint8, device=rx.device)
+    lib = _capi.load()
+    _capi.check(lib.glm_shoot_potential(tree.handle, _ptr(rx), _ptr(ry), R, _ptr(out["a1"]), _ptr(out["a2"]),
+                                        _ptr(out["psi"]), _ptr(out["tdelay"]), GLM_RAYS_ORDERED if ordered else 0,
+                                        _ptr(workspace), workspace.numel(), _stream()))
     return out
 
 

@@ -25,7 +25,7 @@ EXPORTED = [
     "glm_last_error", "glm_version", "glm_shoot_batched_workspace_bytes", "glm_shoot_batched",
     "glm_refine_workspace_bytes", "glm_refine_round", "glm_tree_knn", "glm_interp_state_bytes",
     "glm_interp_round_workspace_bytes", "glm_interp_init", "glm_refine_interp_round",
-    "glm_shoot_indexed_workspace_bytes", "glm_shoot_indexed",
+    "glm_shoot_indexed_workspace_bytes", "glm_shoot_indexed", "glm_shoot_potential",
 ]
 
 
@@ -110,6 +110,8 @@ def load(path: str = LIB_PATH):
     lib.glm_shoot_indexed_workspace_bytes.restype = st
     lib.glm_shoot_indexed.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, u32, vp, sz, vp]
     lib.glm_shoot_indexed.restype = st
+    lib.glm_shoot_potential.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, u32, vp, sz, vp]
+    lib.glm_shoot_potential.restype = st
     lib.glm_tree_knn.argtypes = [vp, ctypes.c_int32, vp, vp]
     lib.glm_tree_knn.restype = st
     lib.glm_last_error.argtypes = []

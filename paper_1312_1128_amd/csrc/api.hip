@@ -205,6 +205,23 @@ glm_status glm_shoot(const glm_tree* t, const double* rx, const double* ry, int6
                         static_cast<hipStream_t>(stream));
 }
 
+glm_status glm_shoot_potential(const glm_tree* t, const double* rx, const double* ry, int64_t nrays, float* a1,
+                               float* a2, float* psi, float* tdelay, uint32_t flags, void* workspace,
+                               size_t workspace_bytes, void* stream)
+{
+    if (!t) return fail(GLM_EINVAL, "tree handle is NULL");
+    if (!t->ts.built) return fail(GLM_ESTATE, "tree not built");
+    if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays must be in 0 .. 2^31 - 256");
+    if (nrays == 0) return GLM_OK;
+    if (!rx || !ry || !a1 || !a2 || !psi) return fail(GLM_EINVAL, "rx, ry, a1, a2, psi must be device pointers");
+    if (flags & ~GLM_RAYS_ORDERED) return fail(GLM_EINVAL, "unknown flag bits");
+    const size_t need = ray_layout(nrays).bytes;
+    if (!workspace || workspace_bytes < need)
+        return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_workspace_bytes(nrays) = " + std::to_string(need));
+    return potential_device(t->ts, rx, ry, nrays, a1, a2, psi, tdelay, flags, workspace,
+                            static_cast<hipStream_t>(stream));
+}
+
 glm_status glm_shoot_direct(const double* x, const double* y, const double* m, const double* s, int64_t n, double q,
                             const double* rx, const double* ry, int64_t nrays, int fp64, void* const out5[5],
                             void* stream)

@@ -583,6 +583,31 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int ncells, int p, double t
 
 // ------------------------------------------------------------------- host
 
+// Ein(z) = integral_0^z (1 - e^-t) / t dt by its power series (host).
+static double ein_host(double z)
+{
+    double term = z, sum = 0.0;
+    for (int k = 1; k < 400; ++k) {
+        const double next = sum + term / (double)k;
+        if (next == sum && k > 1) break;
+        sum = next;
+        term *= -z / (double)(k + 1);
+    }
+    return sum;
+}
+
+// Terms of the Ein series that reach FP64 accuracy on [0, U] (at most 100,
+// which covers q up to about 7).
+static int32_t ein_terms(double U)
+{
+    double term = U; // U^k / k!
+    for (int k = 1; k < 100; ++k) {
+        if (term / (double)k < 1e-17 && k > 2) return k;
+        term *= U / (double)(k + 1);
+    }
+    return 100;
+}
+
 glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, const double* m, const double* s,
                              int64_t n64, const glm_params& prm, hipStream_t st)
 {
@@ -763,6 +788,8 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     ts.dev.order = p;
     ts.dev.invC = (float)invC;
     ts.dev.q = q;
+    ts.dev.einU = ein_host(0.5 * q * q);
+    ts.dev.einTerms = ein_terms(0.5 * q * q);
     ts.ccx = ccx;
     ts.ms = ms;
     ts.ccy = ccy;

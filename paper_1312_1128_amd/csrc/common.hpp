@@ -70,8 +70,9 @@ struct TreeDev {
     int32_t nlisted;
     int32_t order;
     float invC;             // 1 / (1 - exp(-q^2/2))
-    float pad;
+    int32_t einTerms;       // series terms of Ein on [0, q^2/2]
     double q;
+    double einU;            // Ein(q^2/2), for the potential of the truncated Gaussian
 };
 
 // ---------------------------------------------------------------------------

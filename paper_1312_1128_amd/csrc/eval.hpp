@@ -18,7 +18,43 @@ namespace glm {
 struct Acc {
     float a1, c1, a2, c2, k;
     double g1, g2, b1, b2;
+    double ps; // lensing potential (FP64 sum of FP32 terms), when asked for
 };
+
+// Ein(u) = integral_0^u (1 - e^-t) / t dt = sum_k c_k u^k with
+// c_k = (-1)^(k+1) / (k k!), by Horner in FP64 over the first `terms`
+// coefficients (chosen per tree so the series is converged for u <= q^2/2).
+constexpr int kEinTerms = 100;
+struct EinTable {
+    double c[kEinTerms];
+};
+constexpr EinTable make_ein_table()
+{
+    EinTable t{};
+    double f = 1.0;
+    for (int k = 1; k <= kEinTerms; ++k) {
+        f *= (double)k;
+        t.c[k - 1] = ((k & 1) ? 1.0 : -1.0) / ((double)k * f);
+    }
+    return t;
+}
+__constant__ inline EinTable c_ein = make_ein_table();
+
+__device__ inline double ein(double u, int terms)
+{
+    double s = c_ein.c[terms - 1];
+    for (int k = terms - 2; k >= 0; --k) s = fma(s, u, c_ein.c[k]);
+    return s * u;
+}
+
+// Potential of a truncated Gaussian inside its support, per unit mass
+// (alpha = grad psi, Sec. 3.2; equal to the point mass's ln r at the edge):
+//   ln(q s) - (Ein(q^2/2) - Ein(u)) / (2C),  u = r^2 / (2 s^2).
+__device__ inline float gauss_psi(const PRec& pr, double r2, double einU, int terms, float invC)
+{
+    const double u = r2 * (double)pr.h;
+    return 0.5f * __logf((float)pr.qs2) - (float)((einU - ein(u, terms)) * (0.5 * (double)invC));
+}
 
 // compensated (Kahan) summation step; plain FP32 addition when KAHAN is false
 template <bool KAHAN>
@@ -115,8 +151,9 @@ __device__ inline void add_radial(float coef, float Gam, float f1, float f2, flo
 // All cases share one select-based path (no divergent branches).  The point
 // terms are formed without FMA contraction, exactly as in point_terms, so a
 // balanced pair cancels bit for bit.
-template <bool AONLY, bool KAHAN>
-__device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A)
+template <bool AONLY, bool KAHAN, bool PSI = false>
+__device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A, double einU = 0.0,
+                                     int terms = 1, float invC = 0.0f)
 {
 #pragma clang fp contract(off)
     double d1, d2;
@@ -149,13 +186,19 @@ __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A)
         A.g1 -= (double)(Gam * c2);
         A.g2 -= (double)(Gam * s2);
     }
+    if constexpr (PSI) {
+        // point mass m ln r (0 at r = 0), or the Gaussian inside its support
+        const float lnr = r2f > 0.0f ? 0.5f * __logf(r2f) : 0.0f;
+        A.ps += (double)(pr.m * (gauss ? gauss_psi(pr, r2, einU, terms, invC) : lnr));
+    }
 }
 
 // One entry of the big-particle list of a visited box (Sec. 3.2): a lane
 // inside the particle's support adds Gaussian - point (the tree part counted
 // the particle as a point mass); the point part goes to the FP64 balance.
-template <bool AONLY, bool KAHAN>
-__device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A, int& hits)
+template <bool AONLY, bool KAHAN, bool PSI = false>
+__device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A, int& hits, double einU = 0.0,
+                                     int terms = 1, float invC = 0.0f)
 {
     double d1, d2;
     const double r2 = sqdist(X, Y, pr.x, pr.y, &d1, &d2);
@@ -178,12 +221,16 @@ __device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A,
         A.g1 -= (double)P[2];
         A.g2 -= (double)P[3];
     }
+    if constexpr (PSI) {
+        const float lnr = r2f > 0.0f ? 0.5f * __logf(r2f) : 0.0f;
+        A.ps += (double)(pr.m * gauss_psi(pr, r2, einU, terms, invC)) - (double)(pr.m * lnr);
+    }
 }
 
 // Multipole expansion of an accepted box about its centre of mass (Sec. 3.2):
 //   alpha1 - i alpha2 = M v P(t),  gamma1 - i gamma2 = -M v^2 (P(t) + t P'(t)),
 // v = 1/w, t = r_cm v, P(t) = 1 + sum_{k>=2} Qn_k t^k, Qn_k = Q_k / (M r_cm^k).
-template <int P, bool AONLY, bool KAHAN>
+template <int P, bool AONLY, bool KAHAN, bool PSI = false>
 __device__ inline void eval_box(const float* __restrict__ mo, double w1, double w2, Acc& A)
 {
     const float M = mo[0], rcm = mo[1];
@@ -228,6 +275,24 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
         const float G1 = M * fmaf(w21, S1, -w22 * S2), G2 = M * fmaf(w21, S2, w22 * S1);
         A.g1 -= (double)G1;
         A.g2 += (double)G2;
+    }
+    if constexpr (PSI) {
+        // psi = Re[Q_0 ln w - sum_k Q_k / (k w^k)] = M (ln|w| - Re sum_{k>=2} (Qn_k / k) t^k)
+        float re = 0.0f;
+        if constexpr (P >= 2) {
+            float s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
+            for (int k = P; k >= 2; --k) {
+                const float q1 = mo[2 + 2 * (k - 2)] * (1.0f / (float)k);
+                const float q2 = mo[3 + 2 * (k - 2)] * (1.0f / (float)k);
+                const float n1 = fmaf(s1, t1, fmaf(-s2, t2, q1)), n2 = fmaf(s1, t2, fmaf(s2, t1, q2));
+                s1 = n1;
+                s2 = n2;
+            }
+            const float u1 = fmaf(t1, t1, -t2 * t2), u2 = 2.0f * t1 * t2; // t^2
+            re = fmaf(s1, u1, -s2 * u2);
+        }
+        A.ps += (double)(M * (0.5f * __logf(fmaf(f1, f1, f2 * f2)) - re));
     }
 }
 

@@ -35,7 +35,7 @@ struct WalkMode {
     static constexpr bool stats = MODE == 1;
 };
 
-template <int P, bool AONLY, int MODE>
+template <int P, bool AONLY, int MODE, bool PSI = false>
 __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool valid, int lane, Acc& A, int cnt[4],
                                   int c0, int c1)
 {
@@ -68,7 +68,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                     const int k = __ffsll((unsigned long long)cm) - 1;
                     cm &= cm - 1;
                     const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
-                    if (act) list_particle<AONLY, KAHAN>(pr, X, Y, A, n_hit);
+                    if (act) list_particle<AONLY, KAHAN, PSI>(pr, X, Y, A, n_hit, T.einU, T.einTerms, T.invC);
                 }
             }
         }
@@ -78,7 +78,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
         const bool opn = act && !acc;
         if constexpr (STATS) n_acc += acc;
         if (__any(acc)) {
-            if (acc) eval_box<P, AONLY, KAHAN>(T.mom + (size_t)cur * mom_stride(P), w1, w2, A);
+            if (acc) eval_box<P, AONLY, KAHAN, PSI>(T.mom + (size_t)cur * mom_stride(P), w1, w2, A);
         }
         if (h.info & kInfoLeaf) {
             if (__any(opn)) {
@@ -88,7 +88,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                 }
                 for (int j = e.pbeg; j < e.pend; ++j) {
                     const PRec pr = T.prt[j];
-                    if (opn) leaf_particle<AONLY, KAHAN>(pr, X, Y, A);
+                    if (opn) leaf_particle<AONLY, KAHAN, PSI>(pr, X, Y, A, T.einU, T.einTerms, T.invC);
                 }
             }
             cur = cur + 1;
@@ -105,12 +105,17 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
     cnt[3] = n_hit;
 }
 
-template <bool AONLY, bool STATS>
+template <bool AONLY, bool STATS, bool PSI = false>
 __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, const WalkOut& out)
 {
     // fold the FP64 balance of the big-particle point terms into the result
-    out.a1[o] = (float)(((double)A.a1 - (double)A.c1) + A.b1);
-    out.a2[o] = (float)(((double)A.a2 - (double)A.c2) + A.b2);
+    const double a1 = ((double)A.a1 - (double)A.c1) + A.b1, a2 = ((double)A.a2 - (double)A.c2) + A.b2;
+    out.a1[o] = (float)a1;
+    out.a2[o] = (float)a2;
+    if constexpr (PSI) {
+        out.psi[o] = (float)A.ps;
+        if (out.td) out.td[o] = (float)(0.5 * (a1 * a1 + a2 * a2) - A.ps); // Sec. 3.2: |alpha|^2 / 2 - psi
+    }
     if (!AONLY) {
         if (out.k) out.k[o] = A.k;
         if (out.g1) out.g1[o] = (float)A.g1;
@@ -124,7 +129,7 @@ __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, cons
     }
 }
 
-template <int P, bool AONLY, int MODE>
+template <int P, bool AONLY, int MODE, bool PSI = false>
 __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __restrict__ rxs,
                                                 const double* __restrict__ rys, const uint32_t* __restrict__ rperm,
                                                 int64_t nrays, WalkOut out, int K, Partial* __restrict__ parts,
@@ -154,12 +159,12 @@ __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __rest
         c0 = 0;
         c1 = nc;
     }
-    Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+    Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int cnt[4];
-    walk_group<P, AONLY, MODE>(T, X, Y, valid, lane, A, cnt, c0, c1);
+    walk_group<P, AONLY, MODE, PSI>(T, X, Y, valid, lane, A, cnt, c0, c1);
     if (!valid) return;
     if (K == 1) {
-        write_out<AONLY, WalkMode<MODE>::stats>(A, cnt, rperm ? (int64_t)rperm[r] : r, out);
+        write_out<AONLY, WalkMode<MODE>::stats, PSI>(A, cnt, rperm ? (int64_t)rperm[r] : r, out);
         return;
     }
     Partial q;
@@ -235,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __rest
         const bool valid = rl < L.nrays;
         const int64_t gi = L.ray_off + (valid ? rl : 0);
         const double X = valid ? xs[gi] : 0.0, Y = valid ? ys[gi] : 0.0;
-        Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+        Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int cnt[4];
         walk_group<P, AONLY, MODE>(L.tree, X, Y, valid, lane, A, cnt, 0, L.tree.ncells);
         if (valid) write_out<AONLY, false>(A, cnt, (int64_t)perm[gi] - L.ray_off, L.out);
@@ -379,6 +384,15 @@ void launch_walk(const TreeDev& T, const double* rxs, const double* rys, const u
         hipLaunchKernelGGL((k_walk_merge<AONLY>), dim3(ceil_div(nrays, kBlock)), b, 0, st, parts, K, nrays, rperm, out);
 }
 
+// alpha and psi in one walk, no split (K = 1)
+template <int P>
+void launch_potential(const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm, int64_t nrays,
+                      const WalkOut& out, hipStream_t st)
+{
+    const dim3 g((unsigned)walk_grid_blocks((nrays + kWave - 1) / kWave, 1)), b(kBlock);
+    hipLaunchKernelGGL((k_walk<P, true, 0, true>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, 1, nullptr, nullptr);
+}
+
 template <bool AONLY>
 void dispatch_walk(int p, const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm,
                    int64_t nrays, const WalkOut& out, int mode, int K, Partial* parts, const int* split_box,
@@ -386,6 +400,19 @@ void dispatch_walk(int p, const TreeDev& T, const double* rxs, const double* rys
 {
 #define GLM_CASE(PP) \
     case PP: launch_walk<PP, AONLY>(T, rxs, rys, rperm, nrays, out, mode, K, parts, split_box, st); break;
+    switch (p) {
+        GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
+        GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
+        default: break;
+    }
+#undef GLM_CASE
+}
+
+void dispatch_potential(int p, const TreeDev& T, const double* rxs, const double* rys, const uint32_t* rperm,
+                        int64_t nrays, const WalkOut& out, hipStream_t st)
+{
+#define GLM_CASE(PP) \
+    case PP: launch_potential<PP>(T, rxs, rys, rperm, nrays, out, st); break;
     switch (p) {
         GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
         GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
@@ -687,6 +714,24 @@ glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* r
     else
         dispatch_walk<false>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays, WalkOut{a1, a2, k, g1, g2, counts},
                              mode, K, parts, split_box, st);
+    GLM_HIP(hipGetLastError());
+    return GLM_OK;
+}
+
+glm_status potential_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, float* a1,
+                            float* a2, float* psi, float* td, uint32_t flags, void* ws, hipStream_t st)
+{
+    if (nrays == 0) return GLM_OK;
+    StagedRays sr{rx, ry, nullptr};
+    const RayLayout L = ray_layout(nrays);
+    if (!(flags & GLM_RAYS_ORDERED)) {
+        glm_status rc = stage_rays(rx, ry, nrays, ws, L, &sr, st);
+        if (rc != GLM_OK) return rc;
+    }
+    WalkOut out{a1, a2, nullptr, nullptr, nullptr, nullptr};
+    out.psi = psi;
+    out.td = td;
+    dispatch_potential(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays, out, st);
     GLM_HIP(hipGetLastError());
     return GLM_OK;
 }

@@ -9,6 +9,8 @@ namespace glm {
 struct WalkOut {
     float *a1, *a2, *k, *g1, *g2;
     int32_t* counts;
+    float* psi = nullptr; // potential walk only
+    float* td = nullptr;  // time delay |alpha|^2 / 2 - psi (nullable)
 };
 
 // One lens of a batched walk (device table entry).
@@ -121,6 +123,11 @@ glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* r
 glm_status shoot_indexed_device(const TreeStorage& ts, const double* cx, const double* cy, const int32_t* idx,
                                 int64_t count, float* a1, float* a2, float* ka, float* g1, float* g2, uint32_t flags,
                                 void* ws, hipStream_t st);
+
+// alpha and the potential psi (and the time delay when td is not NULL) of
+// the rays; one wavefront per 64-ray group (no split).
+glm_status potential_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, float* a1,
+                            float* a2, float* psi, float* td, uint32_t flags, void* ws, hipStream_t st);
 
 glm_status direct_device(const double* x, const double* y, const double* m, const double* s, int64_t n, double q,
                          const double* rx, const double* ry, int64_t nrays, int fp64, void* const out5[5],
