@@ -23,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = ["direct.c", "tree.c", "knn.c"]
+SOURCES = ["direct.c", "tree.c", "knn.c", "nfw.c"]
 
 _lib = None
 
@@ -58,6 +58,15 @@ def _load():
     lib.ora_kernel_norm.argtypes = [ctypes.c_double]
     lib.ora_kernel_norm.restype = ctypes.c_double
     lib.ora_knn.argtypes = [d, d, i64, ctypes.c_int, d, ctypes.c_int]
+    for fn in ("ora_nfw_F", "ora_nfw_f", "ora_nfw_g"):
+        getattr(lib, fn).argtypes = [ctypes.c_double]
+        getattr(lib, fn).restype = ctypes.c_double
+    lib.ora_nfw_terms.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, d]
+    lib.ora_direct_nfw.argtypes = [d, d, d, d, i64, ctypes.c_double, d, d, i64, d, d, d, d, d, ctypes.c_int]
+    lib.ora_tree_build_nfw.argtypes = [d, d, d, d, i64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_int]
+    lib.ora_tree_build_nfw.restype = vp
+    lib.ora_tree_shoot_psi.restype = ctypes.c_int
     lib.ora_unit_psi.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int]
     lib.ora_unit_psi.restype = ctypes.c_double
     lib.ora_ein.argtypes = [ctypes.c_double]
@@ -125,6 +134,36 @@ def direct(x, y, m, s, q, rx, ry, threads: int | None = None) -> np.ndarray:
     return np.stack(out, axis=1)
 
 
+def nfw_F(x: float) -> float:
+    return _load().ora_nfw_F(x)
+
+
+def nfw_f(x: float) -> float:
+    return _load().ora_nfw_f(x)
+
+
+def nfw_g(x: float) -> float:
+    return _load().ora_nfw_g(x)
+
+
+def nfw_terms(d1: float, d2: float, R: float, c: float, inside: bool) -> np.ndarray:
+    out = np.zeros(7)
+    _load().ora_nfw_terms(d1, d2, R, c, int(inside), _p(out))
+    return out
+
+
+def direct_nfw(x, y, m, R, c, rx, ry, threads: int | None = None) -> np.ndarray:
+    """Oracle A for truncated NFW halos (size R, concentration c)."""
+    lib = _load()
+    x, y, m, R = _f64(x), _f64(y), _f64(m), _f64(R)
+    rx, ry = _f64(rx), _f64(ry)
+    nr = rx.shape[0]
+    out = [np.zeros(nr) for _ in range(5)]
+    lib.ora_direct_nfw(_p(x), _p(y), _p(m), _p(R), x.shape[0], float(c), _p(rx), _p(ry), nr,
+                       *[_p(o) for o in out], threads or default_threads())
+    return np.stack(out, axis=1)
+
+
 def unit_psi(d1: float, d2: float, s: float, q: float, inside: bool) -> float:
     return _load().ora_unit_psi(d1, d2, s, q, int(inside))
 
@@ -181,14 +220,16 @@ def direct_grad(x, y, m, s, q, rx, ry, ga, threads: int | None = None):
 class Tree:
     """Oracle B: FP64 reference quad-tree (Sec. 3.2)."""
 
-    def __init__(self, x, y, m, s, q=3.0, theta=0.5, leaf_size=8, order=2):
+    def __init__(self, x, y, m, s, q=3.0, theta=0.5, leaf_size=8, order=2, nfw: bool = False):
+        """nfw: the particles are truncated NFW halos, s their sizes and q
+        their concentration."""
         lib = _load()
         self._keep = [_f64(x), _f64(y), _f64(m),
                       _f64(s) if s is not None else np.zeros(np.asarray(x).shape[0])]
         self.n = self._keep[0].shape[0]
         self.q, self.theta, self.leaf_size, self.order = float(q), float(theta), int(leaf_size), int(order)
-        self._h = lib.ora_tree_build(*[_p(a) for a in self._keep], self.n, self.q, self.theta,
-                                     self.leaf_size, self.order)
+        build = lib.ora_tree_build_nfw if nfw else lib.ora_tree_build
+        self._h = build(*[_p(a) for a in self._keep], self.n, self.q, self.theta, self.leaf_size, self.order)
         if not self._h:
             raise ValueError("oracle tree build rejected its arguments")
         self._lib = lib

@@ -1,0 +1,115 @@
+/*
+ * Oracle for truncated NFW halos as "particles" (Sec. 3.2: every particle
+ * type has its own expressions for the lensing quantities; outside its outer
+ * radius a spherically symmetric profile lenses like a point mass) --
+ * TEST INFRASTRUCTURE ONLY.
+ *
+ * A halo of mass m, size (truncation radius) R and concentration c has the
+ * projected NFW surface density, cut at projected radius R and normalised so
+ * that its mass inside R is m.  With r_s = R / c and x = r / r_s:
+ *   F(x) = arccosh(1/x) / sqrt(1 - x^2) (x < 1), arccos(1/x) / sqrt(x^2 - 1) (x > 1), 1 at x = 1;
+ *   f(x) = (1 - F(x)) / (x^2 - 1)   (surface-density shape, f(1) = 1/3);
+ *   g(x) = ln(x / 2) + F(x)         (enclosed-mass shape, g' = x f, g(0) = 0).
+ * Inside R: alpha = m G d / r^2 with G = g(x) / g(c); kappa = m f(x) / (2 r_s^2 g(c));
+ * gamma = -(m G / r^2 - kappa)(cos 2phi, sin 2phi).  Outside: a point mass.
+ * Near x = 1 the formulas are 0/0: there the series F = sum_k (-e)^k / (2k + 1),
+ * e = x^2 - 1, is used.  For x < 1 the two large logarithms of g cancel; g is
+ * regrouped so that they do not (see ora_nfw_g).
+ */
+#include <math.h>
+#include <string.h>
+
+#include "oracle.h"
+
+double ora_nfw_F(double x)
+{
+    const double e = (x - 1.0) * (x + 1.0); /* x^2 - 1 without cancellation near x = 1 */
+    if (fabs(e) < 1e-3) {
+        double s = 0.0, p = 1.0;
+        for (int k = 0; k < 12; ++k) {
+            s += p / (double)(2 * k + 1);
+            p *= -e;
+        }
+        return s;
+    }
+    if (x < 1.0) return acosh(1.0 / x) / sqrt(-e);
+    return acos(1.0 / x) / sqrt(e);
+}
+
+double ora_nfw_f(double x)
+{
+    const double e = (x - 1.0) * (x + 1.0); /* x^2 - 1 without cancellation near x = 1 */
+    if (fabs(e) < 1e-3) { /* (1 - F) / e = sum_{k>=1} (-1)^(k+1) e^(k-1) / (2k + 1) */
+        double s = 0.0, p = 1.0;
+        for (int k = 1; k < 13; ++k) {
+            s += p / (double)(2 * k + 1);
+            p *= -e;
+        }
+        return s;
+    }
+    return (1.0 - ora_nfw_F(x)) / e;
+}
+
+double ora_nfw_g(double x)
+{
+    if (x <= 0.0) return 0.0;
+    const double e = (x - 1.0) * (x + 1.0); /* x^2 - 1 without cancellation near x = 1 */
+    if (x < 1.0 && fabs(e) >= 1e-3) {
+        /* ln(x/2) + arccosh(1/x)/y with y = sqrt(1 - x^2), arccosh(1/x) = L + ln((1+y)/2),
+         * L = ln(2/x): both large terms cancel; regrouped without cancellation as
+         * [L x^2 / (1 + y) + log1p(-x^2 / (2 (1 + y)))] / y */
+        const double y = sqrt(-e), L = log(2.0 / x), x2 = x * x;
+        return (L * x2 / (1.0 + y) + log1p(-x2 / (2.0 * (1.0 + y)))) / y;
+    }
+    return log(0.5 * x) + ora_nfw_F(x);
+}
+
+int ora_nfw_inside(double d1, double d2, double R)
+{
+    return R > 0.0 && d1 * d1 + d2 * d2 < R * R;
+}
+
+/* per unit mass: out = a1 a2 kappa g1 g2 (0 0); a ray exactly at the centre
+ * gets nothing (alpha and gamma vanish by symmetry; kappa diverges there) */
+void ora_nfw_terms(double d1, double d2, double R, double c, int inside, double out[7])
+{
+    memset(out, 0, 7 * sizeof(double));
+    const double r2 = d1 * d1 + d2 * d2;
+    if (r2 == 0.0) return;
+    double G = 1.0, K = 0.0;
+    if (inside) {
+        const double rs = R / c, x = sqrt(r2) / rs, gc = ora_nfw_g(c);
+        G = ora_nfw_g(x) / gc;
+        K = ora_nfw_f(x) / (2.0 * rs * rs * gc);
+    }
+    const double h = G / r2;
+    out[0] = h * d1;
+    out[1] = h * d2;
+    out[2] = K;
+    const double Gam = h - K;
+    out[3] = -Gam * (d1 * d1 - d2 * d2) / r2;
+    out[4] = -Gam * 2.0 * d1 * d2 / r2;
+}
+
+int ora_direct_nfw(const double* x, const double* y, const double* m, const double* R, int64_t n, double c,
+                   const double* rx, const double* ry, int64_t nr, double* a1, double* a2, double* kap,
+                   double* g1, double* g2, int nthreads)
+{
+    if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t r = 0; r < nr; ++r) {
+        double acc[5] = {0, 0, 0, 0, 0};
+        for (int64_t i = 0; i < n; ++i) {
+            const double d1 = rx[r] - x[i], d2 = ry[r] - y[i];
+            double t[7];
+            ora_nfw_terms(d1, d2, R[i], c, ora_nfw_inside(d1, d2, R[i]), t);
+            for (int k = 0; k < 5; ++k) acc[k] += m[i] * t[k];
+        }
+        a1[r] = acc[0];
+        a2[r] = acc[1];
+        kap[r] = acc[2];
+        g1[r] = acc[3];
+        g2[r] = acc[4];
+    }
+    return 0;
+}

@@ -65,11 +65,26 @@ int ora_knn(const double* x, const double* y, int64_t n, int k, double* s_out, i
 int ora_knn_at(const double* x, const double* y, int64_t n, int k, const int64_t* queries, int64_t nq,
                double* s_out, int nthreads);
 
+/* Truncated NFW halos (nfw.c): shape functions of the projected profile,
+ * per-unit-mass terms (a1 a2 kappa g1 g2, 0 0) of a halo of size R and
+ * concentration c, inside test r < R, and the brute force. */
+double ora_nfw_F(double x);
+double ora_nfw_f(double x);
+double ora_nfw_g(double x);
+int ora_nfw_inside(double d1, double d2, double R);
+void ora_nfw_terms(double d1, double d2, double R, double c, int inside, double out[7]);
+int ora_direct_nfw(const double* x, const double* y, const double* m, const double* R, int64_t n, double c,
+                   const double* rx, const double* ry, int64_t nr, double* a1, double* a2, double* kap,
+                   double* g1, double* g2, int nthreads);
+
 /* Oracle B: reference tree. */
 typedef struct ora_tree ora_tree;
 
 ora_tree* ora_tree_build(const double* x, const double* y, const double* m, const double* s,
                          int64_t n, double q, double theta, int leaf_size, int order);
+/* The same tree of truncated NFW halos: sizes R (support), concentration c. */
+ora_tree* ora_tree_build_nfw(const double* x, const double* y, const double* m, const double* R, int64_t n,
+                             double c, double theta, int leaf_size, int order);
 void ora_tree_free(ora_tree* t);
 int64_t ora_tree_ncells(const ora_tree* t);
 /* root square: x0, y0, side */

@@ -17,8 +17,9 @@
  *  - moments are the complex multipoles Q_k = sum_j m_j (z_j - z_cm)^k,
  *    k = 0..p ("monopole and quadrupole" is p = 2);
  *  - r_cm is the distance from the centre of mass to the farthest box corner;
- *  - a particle's "size" is its support radius q s; it is listed in the
- *    highest box where q s > side / 2, if that box is not below its leaf;
+ *  - a particle's "size" is its support radius (q s for a Gaussian, the
+ *    truncation radius for an NFW halo); it is listed in the highest box where
+ *    size > side / 2, if that box is not below its leaf;
  *  - listed particles are points inside moments and leaf sums; every visited
  *    box (accepted or opened) adds "exact kernel - point" for each of its
  *    listed particles that the ray falls inside.
@@ -50,7 +51,8 @@ typedef struct {
 
 struct ora_tree {
     int64_t n;
-    double q, theta;
+    int kind;   /* 0: Gaussian particles and point masses; 1: truncated NFW halos */
+    double q, theta; /* q: Gaussian cutoff, or the NFW concentration */
     int L, p;
     double *x, *y, *m, *s;
     double x0, y0, S, scale;
@@ -64,6 +66,21 @@ struct ora_tree {
     tape_t* tapes;
     int64_t ntapes;
 };
+
+/* The particle type of the tree: support radius ("size"), inside test and
+ * per-unit-mass terms. */
+static double support(const ora_tree* t, int64_t i) { return t->kind ? t->s[i] : t->q * t->s[i]; }
+
+static int inside_of(const ora_tree* t, int64_t i, double d1, double d2)
+{
+    return t->kind ? ora_nfw_inside(d1, d2, t->s[i]) : ora_inside(d1, d2, t->s[i], t->q);
+}
+
+static void terms_of(const ora_tree* t, int64_t i, double d1, double d2, int in, double out[7])
+{
+    if (t->kind) ora_nfw_terms(d1, d2, t->s[i], t->q, in, out);
+    else ora_unit_terms(d1, d2, t->s[i], t->q, in, out);
+}
 
 /* ---------------------------------------------------------------- build */
 
@@ -177,7 +194,7 @@ static void assign_lists(ora_tree* t)
     for (int64_t i = 0; i < n; ++i) {
         t->listed_at[i] = -1;
         if (!(t->s[i] > 0)) continue;
-        const double qs = t->q * t->s[i];
+        const double qs = support(t, i);
         int l = 0;
         while (l <= 32 && !(qs > ldexp(t->S, -(l + 1)))) ++l;
         if (l > 32 || l > t->cells[leaf_of[i]].level) continue;
@@ -213,12 +230,13 @@ static void assign_lists(ora_tree* t)
     free(leaf_of);
 }
 
-ora_tree* ora_tree_build(const double* x, const double* y, const double* m, const double* s,
-                         int64_t n, double q, double theta, int leaf_size, int order)
+static ora_tree* build_kind(const double* x, const double* y, const double* m, const double* s, int64_t n,
+                            double q, double theta, int leaf_size, int order, int kind)
 {
     if (n <= 0 || leaf_size < 1 || order < 0) return NULL;
     ora_tree* t = (ora_tree*)calloc(1, sizeof(ora_tree));
     t->n = n;
+    t->kind = kind;
     t->q = q;
     t->theta = theta;
     t->L = leaf_size;
@@ -263,6 +281,18 @@ ora_tree* ora_tree_build(const double* x, const double* y, const double* m, cons
     for (int64_t c = 0; c < t->nc; ++c) cell_moments(t, c);
     assign_lists(t);
     return t;
+}
+
+ora_tree* ora_tree_build(const double* x, const double* y, const double* m, const double* s,
+                         int64_t n, double q, double theta, int leaf_size, int order)
+{
+    return build_kind(x, y, m, s, n, q, theta, leaf_size, order, 0);
+}
+
+ora_tree* ora_tree_build_nfw(const double* x, const double* y, const double* m, const double* R, int64_t n,
+                             double c, double theta, int leaf_size, int order)
+{
+    return build_kind(x, y, m, R, n, c, theta, leaf_size, order, 1);
 }
 
 void ora_tree_free(ora_tree* t)
@@ -421,11 +451,11 @@ static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5
         const int64_t i = t->lst[k];
         const double d1 = X - t->x[i], d2 = Y - t->y[i];
         cnt[3]++;
-        if (decide(tp, ora_inside(d1, d2, t->s[i], t->q))) {
+        if (decide(tp, inside_of(t, i, d1, d2))) {
             double te[7], tpnt[7];
             cnt[4]++;
-            ora_unit_terms(d1, d2, t->s[i], t->q, 1, te);
-            ora_unit_terms(d1, d2, t->s[i], t->q, 0, tpnt);
+            terms_of(t, i, d1, d2, 1, te);
+            terms_of(t, i, d1, d2, 0, tpnt);
             particle_term(t, i, te, 1.0, acc, adj);
             particle_term(t, i, tpnt, -1.0, acc, adj);
             if (psi)
@@ -453,10 +483,10 @@ static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5
         for (int64_t k = cl->beg; k < cl->end; ++k) {
             const int64_t j = t->perm[k];
             const double d1 = X - t->x[j], d2 = Y - t->y[j];
-            const int in = t->listed_at[j] >= 0 ? 0 : decide(tp, ora_inside(d1, d2, t->s[j], t->q));
+            const int in = t->listed_at[j] >= 0 ? 0 : decide(tp, inside_of(t, j, d1, d2));
             double tt[7];
             cnt[2]++;
-            ora_unit_terms(d1, d2, t->s[j], t->q, in, tt);
+            terms_of(t, j, d1, d2, in, tt);
             particle_term(t, j, tt, 1.0, acc, adj);
             if (psi) *psi += t->m[j] * ora_unit_psi(d1, d2, t->s[j], t->q, in);
         }
@@ -487,6 +517,7 @@ int ora_tree_shoot(const ora_tree* t, const double* rx, const double* ry, int64_
 
 int ora_tree_shoot_psi(const ora_tree* t, const double* rx, const double* ry, int64_t nr, double* psi, int nthreads)
 {
+    if (t->kind) return -1; /* the potential is written for Gaussians and point masses */
     if (nthreads <= 0) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
     for (int64_t r = 0; r < nr; ++r) {

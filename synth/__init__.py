@@ -166,6 +166,20 @@ def gaussian_blobs(n: int, seed: int, s_lo: float = 0.01, s_hi: float = 0.1,
     return Lens(x, y, m, s, q=q, meta={"kind": "blobs"})
 
 
+def nfw_halo_field(n: int, seed: int, rmax: float = 0.3, c: float = 3.0, mmin: float = 1e-3,
+                   mmax: float = 1.0, radius: float = 1.0):
+    """The paper's halo convergence test (Sec. 5.1): n truncated NFW halos
+    uniform in a disk, sizes uniform up to rmax, masses dN/dm ~ m^-2 on
+    [mmin, mmax], all of concentration c.  Returns (Lens with s = sizes, c)."""
+    g = rng(seed)
+    r = radius * np.sqrt(g.uniform(0.0, 1.0, n))
+    ph = g.uniform(0.0, 2.0 * math.pi, n)
+    size = g.uniform(0.0, rmax, n)
+    u = g.uniform(0.0, 1.0, n)
+    m = 1.0 / (1.0 / mmin - u * (1.0 / mmin - 1.0 / mmax))
+    return Lens(r * np.cos(ph), r * np.sin(ph), m, size, q=c, meta={"kind": "nfw_halos", "c": c}), c
+
+
 # --------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------

@@ -1,0 +1,80 @@
+"""Pins of the truncated-NFW halo oracle (halos as "particles", Sec. 3.2;
+the paper's halo convergence test of Sec. 5.1)."""
+import numpy as np
+import pytest
+
+import synth
+
+
+def F_direct(x):
+    return np.arccosh(1 / x) / np.sqrt(1 - x * x) if x < 1 else np.arccos(1 / x) / np.sqrt(x * x - 1)
+
+
+def test_shape_functions(ora):
+    from scipy.integrate import quad
+
+    for x in (0.05, 0.3, 0.9, 0.97, 1.03, 1.5, 3.0, 8.0):
+        assert abs(ora.nfw_F(x) - F_direct(x)) <= 1e-13 * F_direct(x), x
+    # both sides of the series switch near x = 1
+    for e in (-1.01e-3, -0.99e-3, 0.99e-3, 1.01e-3):
+        x = np.sqrt(1 + e)
+        assert abs(ora.nfw_F(x) - F_direct(x)) <= 2e-12, e
+    assert ora.nfw_f(1.0) == pytest.approx(1 / 3, rel=1e-15)
+    # g is the enclosed-mass shape: g(x) = integral_0^x t f(t) dt, g' = x f
+    for x in (2e-4, 1e-3, 0.02, 0.5, 0.999, 1.0, 1.001, 2.0, 3.0):
+        ref = quad(lambda t: t * ora.nfw_f(t), 0, x, limit=400, epsabs=1e-30, epsrel=1e-12)[0]
+        assert abs(ora.nfw_g(x) - ref) <= 1e-10 * ref, x
+        h = 1e-6 * x
+        dg = (ora.nfw_g(x + h) - ora.nfw_g(x - h)) / (2 * h)
+        assert abs(dg - x * ora.nfw_f(x)) <= 1e-7 * x * ora.nfw_f(x), x
+
+
+@pytest.mark.parametrize("r_over_R", [0.001, 0.1, 0.33, 0.5, 0.9, 1.2])
+def test_kappa_gamma_from_alpha(ora, r_over_R):
+    R, c, phi = 0.3, 3.0, 0.4
+    r = r_over_R * R
+    d1, d2 = r * np.cos(phi), r * np.sin(phi)
+
+    def a(u, v):
+        return ora.nfw_terms(u, v, R, c, u * u + v * v < R * R)[:2]
+
+    h = 1e-6 * r
+    dx = (a(d1 + h, d2) - a(d1 - h, d2)) / (2 * h)
+    dy = (a(d1, d2 + h) - a(d1, d2 - h)) / (2 * h)
+    t = ora.nfw_terms(d1, d2, R, c, r < R)
+    scale = np.abs([dx, dy]).max()
+    assert abs(0.5 * (dx[0] + dy[1]) - t[2]) <= 1e-6 * scale  # kappa = div(alpha) / 2
+    assert abs(0.5 * (dx[0] - dy[1]) - t[3]) <= 1e-6 * scale  # gamma1
+    assert abs(dx[1] - t[4]) <= 1e-6 * scale and abs(dy[0] - t[4]) <= 1e-6 * scale  # gamma2, curl-free
+
+
+def test_mass_and_continuity(ora):
+    from scipy.integrate import quad
+
+    R, c = 0.2, 3.0
+    mass = quad(lambda r: 2 * np.pi * r * ora.nfw_terms(r, 0.0, R, c, True)[2], 0, R, limit=400,
+                epsabs=1e-14, epsrel=1e-11)[0]
+    assert mass == pytest.approx(np.pi, rel=1e-9)  # integral of kappa = pi m (m in units of pi Sigma_crit)
+    inner = ora.nfw_terms(R * (1 - 1e-13), 0.0, R, c, True)
+    outer = ora.nfw_terms(R * (1 + 1e-13), 0.0, R, c, False)
+    assert abs(inner[0] - outer[0]) <= 1e-10 * outer[0]  # alpha continuous; a point mass outside
+
+
+def test_halo_field_kappa_exact_for_any_theta(ora):
+    """The paper's halo test: kappa from halos intersecting the ray only, so
+    the tree's kappa has no error at any theta; alpha and gamma converge."""
+    lens, c = synth.nfw_halo_field(3000, 97)
+    rx, ry = synth.uniform_points(200, 98, -0.8, 0.8)
+    rx[:4], ry[:4] = [0.0, 1e-3, -0.01, 0.02], [0.0, 2e-3, 0.005, -0.01]
+    ref = ora.direct_nfw(lens.x, lens.y, lens.m, lens.s, c, rx, ry)
+    T0 = ora.Tree(lens.x, lens.y, lens.m, lens.s, c, 0.0, 8, 4, nfw=True)
+    np.testing.assert_allclose(T0.shoot(rx, ry), ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+    prev = None
+    for theta in (0.5, 0.3, 0.1):
+        got = ora.Tree(lens.x, lens.y, lens.m, lens.s, c, theta, 8, 4, nfw=True).shoot(rx, ry)
+        assert np.abs(got[:, 2] - ref[:, 2]).max() <= 1e-12 * np.abs(ref[:, 2]).max()
+        ea = (np.linalg.norm(got[:, :2] - ref[:, :2], axis=1) / np.linalg.norm(ref[:, :2], axis=1)).max()
+        if prev is not None:
+            assert ea < prev
+        prev = ea
+    assert prev < 1e-6
