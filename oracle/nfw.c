@@ -12,8 +12,9 @@
  *   g(x) = ln(x / 2) + F(x)         (enclosed-mass shape, g' = x f, g(0) = 0).
  * Inside R: alpha = m G d / r^2 with G = g(x) / g(c); kappa = m f(x) / (2 r_s^2 g(c));
  * gamma = -(m G / r^2 - kappa)(cos 2phi, sin 2phi).  Outside: a point mass.
- * Near x = 1 the formulas are 0/0: there the series F = sum_k (-e)^k / (2k + 1),
- * e = x^2 - 1, is used.  For x < 1 the two large logarithms of g cancel; g is
+ * Near x = 1 the formulas are 0/0: there (|e| < 1e-2) the series
+ * F = sum_k (-e)^k / (2k + 1), e = x^2 - 1, is used, converged to rounding by
+ * 12 terms.  For x < 1 the two large logarithms of g cancel; g is
  * regrouped so that they do not (see ora_nfw_g).
  */
 #include <math.h>
@@ -24,7 +25,7 @@
 double ora_nfw_F(double x)
 {
     const double e = (x - 1.0) * (x + 1.0); /* x^2 - 1 without cancellation near x = 1 */
-    if (fabs(e) < 1e-3) {
+    if (fabs(e) < 1e-2) {
         double s = 0.0, p = 1.0;
         for (int k = 0; k < 12; ++k) {
             s += p / (double)(2 * k + 1);
@@ -32,14 +33,21 @@ double ora_nfw_F(double x)
         }
         return s;
     }
-    if (x < 1.0) return acosh(1.0 / x) / sqrt(-e);
-    return acos(1.0 / x) / sqrt(e);
+    /* arccosh(1/x) = ln((1 + y) / x) = log1p((y + (1 - x)) / x) and
+     * arccos(1/x) = atan(y): the same values as the textbook forms, without
+     * arguments near 1 where those lose digits */
+    if (x < 1.0) {
+        const double y = sqrt(-e);
+        return log1p((y + (1.0 - x)) / x) / y;
+    }
+    const double y = sqrt(e);
+    return atan(y) / y;
 }
 
 double ora_nfw_f(double x)
 {
     const double e = (x - 1.0) * (x + 1.0); /* x^2 - 1 without cancellation near x = 1 */
-    if (fabs(e) < 1e-3) { /* (1 - F) / e = sum_{k>=1} (-1)^(k+1) e^(k-1) / (2k + 1) */
+    if (fabs(e) < 1e-2) { /* (1 - F) / e = sum_{k>=1} (-1)^(k+1) e^(k-1) / (2k + 1) */
         double s = 0.0, p = 1.0;
         for (int k = 1; k < 13; ++k) {
             s += p / (double)(2 * k + 1);
@@ -54,7 +62,7 @@ double ora_nfw_g(double x)
 {
     if (x <= 0.0) return 0.0;
     const double e = (x - 1.0) * (x + 1.0); /* x^2 - 1 without cancellation near x = 1 */
-    if (x < 1.0 && fabs(e) >= 1e-3) {
+    if (x < 1.0 && fabs(e) >= 1e-2) {
         /* ln(x/2) + arccosh(1/x)/y with y = sqrt(1 - x^2), arccosh(1/x) = L + ln((1+y)/2),
          * L = ln(2/x): both large terms cancel; regrouped without cancellation as
          * [L x^2 / (1 + y) + log1p(-x^2 / (2 (1 + y)))] / y */

@@ -16,9 +16,9 @@ def test_shape_functions(ora):
     for x in (0.05, 0.3, 0.9, 0.97, 1.03, 1.5, 3.0, 8.0):
         assert abs(ora.nfw_F(x) - F_direct(x)) <= 1e-13 * F_direct(x), x
     # both sides of the series switch near x = 1
-    for e in (-1.01e-3, -0.99e-3, 0.99e-3, 1.01e-3):
+    for e in (-1.01e-2, -0.99e-2, 0.99e-2, 1.01e-2):
         x = np.sqrt(1 + e)
-        assert abs(ora.nfw_F(x) - F_direct(x)) <= 2e-12, e
+        assert abs(ora.nfw_F(x) - F_direct(x)) <= 2e-13, e
     assert ora.nfw_f(1.0) == pytest.approx(1 / 3, rel=1e-15)
     # g is the enclosed-mass shape: g(x) = integral_0^x t f(t) dt, g' = x f
     for x in (2e-4, 1e-3, 0.02, 0.5, 0.999, 1.0, 1.001, 2.0, 3.0):
@@ -27,6 +27,29 @@ def test_shape_functions(ora):
         h = 1e-6 * x
         dg = (ora.nfw_g(x + h) - ora.nfw_g(x - h)) / (2 * h)
         assert abs(dg - x * ora.nfw_f(x)) <= 1e-7 * x * ora.nfw_f(x), x
+
+
+def test_shapes_near_one_against_series():
+    """Around x = 1, F = sum (-e)^k / (2k + 1) and f = (1 - F) / e =
+    sum (-e)^k / (2k + 3) with e = x^2 - 1 (the Taylor series of atan(y)/y
+    and atanh(y)/y in y^2 = +-e), summed in 50-digit decimal arithmetic for the
+    exact binary x: both sides of the series switch and the closed forms just
+    beyond it, where F's digits cancel in f."""
+    from decimal import Decimal, getcontext
+
+    import oracle as ora
+
+    getcontext().prec = 50
+    for x in (0.9, 0.95, 0.994, 0.99499, 0.995, 0.999, 0.9999, 1.0, 1.0001, 1.001, 1.00499, 1.005, 1.006, 1.05, 1.1):
+        e = Decimal(x) * Decimal(x) - 1
+        F = f = Decimal(0)
+        p = Decimal(1)
+        for k in range(400):
+            F += p / (2 * k + 1)
+            f += p / (2 * k + 3)
+            p *= -e
+        assert abs(ora.nfw_F(x) - float(F)) <= 4e-16 * float(F), x
+        assert abs(ora.nfw_f(x) - float(f)) <= 1e-13 * float(f), x
 
 
 @pytest.mark.parametrize("r_over_R", [0.001, 0.1, 0.33, 0.5, 0.9, 1.2])
