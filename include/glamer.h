@@ -55,11 +55,24 @@ typedef enum {
 #define GLM_ALPHA_ONLY 1u   /* skip kappa and gamma (Sec. 3.2: the solver's option) */
 #define GLM_NO_KAHAN 2u     /* plain FP32 accumulation of alpha (debug) */
 #define GLM_RAYS_ORDERED 4u /* rays already in a spatially coherent order: skip the ray sort */
+/* build: the particles are truncated NFW halos (Sec. 3.2: analytic halos as
+ * particles), not Gaussians.  A halo of mass m, size s = R (its truncation
+ * radius, the support) and concentration c = q has the projected NFW surface
+ * density with scale radius r_s = R / c, cut at projected radius R and
+ * normalised to mass m inside R; beyond R it is a point mass.  With x = r / r_s,
+ * F = arccosh(1/x)/sqrt(1-x^2) (x < 1), arccos(1/x)/sqrt(x^2-1) (x > 1),
+ * f = (1 - F)/(x^2 - 1), g = ln(x/2) + F:  alpha = m g(x)/g(c) d/r^2,
+ * kappa = m f(x) / (2 r_s^2 g(c)).  A ray exactly at a halo's centre gets
+ * nothing from it.  s = 0 is a point mass.  Same big-particle lists (a halo is
+ * listed where R > side / 2) and the same walk; the potential and adjoint walks
+ * reject such a tree with GLM_ESTATE. */
+#define GLM_NFW_HALOS 8u
 
 /* Solver parameters (Sec. 3.2 and 3.1). */
 typedef struct {
     double theta;      /* opening parameter theta_force, 0 <= theta < 1 (0 = direct sum) */
-    double q;          /* Gaussian cutoff in smoothing lengths, q > 0 (Sec. 3.1) */
+    double q;          /* Gaussian cutoff in smoothing lengths, q > 0 (Sec. 3.1); the halo
+                          concentration c with GLM_NFW_HALOS */
     int32_t leaf_size; /* a box is a leaf when it holds <= leaf_size particles, 1..64 */
     int32_t order;     /* multipole order p: moments Q_0..Q_p, 0..12 ("monopole and quadrupole" = 2) */
     uint32_t flags;    /* GLM_* flags */
@@ -197,6 +210,17 @@ GLM_API glm_status glm_shoot_direct(const double* x, const double* y, const doub
                             int64_t nrays, int fp64, void* const out5[5], void* stream);
 
 /*
+ * Plain direct sum over n truncated NFW halos (the profile of GLM_NFW_HALOS;
+ * Sec. 3.2 and the halo tests of Sec. 5.1): R = sizes (device FP64, >= 0,
+ * 0 = point mass), c = concentration > 0, other arguments as glm_shoot_direct.
+ * fp64 != 0 evaluates the profile in FP64; else FP32 terms with compensated
+ * alpha, as the tree walk does.
+ */
+GLM_API glm_status glm_shoot_direct_nfw(const double* x, const double* y, const double* m, const double* R,
+                                int64_t n, double c, const double* rx, const double* ry,
+                                int64_t nrays, int fp64, void* const out5[5], void* stream);
+
+/*
  * Adjoint of glm_shoot for L with cotangents ga1 = dL/dalpha1, ga2 = dL/dalpha2
  * (device FP32, length nrays, input order).  Replays the forward walk's
  * decisions on the same tree and rays, and ACCUMULATES (+=) into the device
@@ -214,7 +238,7 @@ GLM_API glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const 
 
 /* One lens of a batched walk. */
 typedef struct {
-    const glm_tree* tree; /* built tree; every tree of a batch has the same order */
+    const glm_tree* tree; /* built tree; every tree of a batch has the same order and particle kind */
     const double* rx;     /* device FP64 ray positions, nrays each */
     const double* ry;
     int64_t nrays;        /* >= 0 */

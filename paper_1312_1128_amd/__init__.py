@@ -14,11 +14,11 @@ import ctypes
 import torch
 
 from . import _capi
-from ._capi import (GLM_ALPHA_ONLY, GLM_NO_KAHAN, GLM_RAYS_ORDERED, GlamerError, GlmParams,  # noqa: F401
-                    GlmTreeInfo)
+from ._capi import (GLM_ALPHA_ONLY, GLM_NFW_HALOS, GLM_NO_KAHAN, GLM_RAYS_ORDERED, GlamerError,  # noqa: F401
+                    GlmParams, GlmTreeInfo)
 
 __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
-           "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
+           "GLM_NFW_HALOS", "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
            "refine_schedule", "RefinementRun", "autotune", "smoothing_lengths", "interp_init",
            "refine_interp_round", "shoot_indexed", "shoot_potential"]
 
@@ -67,7 +67,10 @@ class Tree:
     def handle(self):
         return self._h
 
-    def build(self, x, y, m, s=None, theta=0.3, q=3.0, leaf_size=8, order=8, flags=0):
+    def build(self, x, y, m, s=None, theta=0.3, q=3.0, leaf_size=8, order=8, flags=0, nfw: bool = False):
+        """nfw: the particles are truncated NFW halos of sizes s and concentration q."""
+        if nfw:
+            flags |= GLM_NFW_HALOS
         x, y, m = _f64(x, "x"), _f64(y, "y"), _f64(m, "m")
         s = _f64(s, "s") if s is not None else None
         n = x.shape[0]
@@ -163,8 +166,11 @@ def smoothing_lengths(x, y, k: int = 32, leaf_size: int = 16):
     return tree.knn(k)
 
 
-def shoot_direct(x, y, m, s, q, rx, ry, fp64: bool = False, alpha_only: bool = False):
-    """Plain direct sum over all particles on the GPU."""
+def shoot_direct(x, y, m, s, q, rx, ry, fp64: bool = False, alpha_only: bool = False, nfw: bool = False):
+    """Plain direct sum over all particles on the GPU (nfw: truncated NFW halos
+    of sizes s and concentration q)."""
+    if nfw and s is None:
+        raise ValueError("NFW halos need their sizes s")
     x, y, m = _f64(x, "x"), _f64(y, "y"), _f64(m, "m")
     s = _f64(s, "s") if s is not None else None
     rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
@@ -175,8 +181,9 @@ def shoot_direct(x, y, m, s, q, rx, ry, fp64: bool = False, alpha_only: bool = F
     arr = (ctypes.c_void_p * 5)(*[out[k].data_ptr() if k in out else None
                                   for k in ["a1", "a2", "kappa", "g1", "g2"]])
     lib = _capi.load()
-    _capi.check(lib.glm_shoot_direct(_ptr(x), _ptr(y), _ptr(m), _ptr(s), x.shape[0], float(q), _ptr(rx), _ptr(ry),
-                                     R, 1 if fp64 else 0, arr, _stream()))
+    fn = lib.glm_shoot_direct_nfw if nfw else lib.glm_shoot_direct
+    _capi.check(fn(_ptr(x), _ptr(y), _ptr(m), _ptr(s), x.shape[0], float(q), _ptr(rx), _ptr(ry),
+                   R, 1 if fp64 else 0, arr, _stream()))
     return out
 
 

@@ -17,6 +17,7 @@ GLM_EDATA = -5
 GLM_ALPHA_ONLY = 1
 GLM_NO_KAHAN = 2
 GLM_RAYS_ORDERED = 4
+GLM_NFW_HALOS = 8
 
 # every symbol include/glamer.h declares
 EXPORTED = [
@@ -25,7 +26,7 @@ EXPORTED = [
     "glm_last_error", "glm_version", "glm_shoot_batched_workspace_bytes", "glm_shoot_batched",
     "glm_refine_workspace_bytes", "glm_refine_round", "glm_tree_knn", "glm_interp_state_bytes",
     "glm_interp_round_workspace_bytes", "glm_interp_init", "glm_refine_interp_round",
-    "glm_shoot_indexed_workspace_bytes", "glm_shoot_indexed", "glm_shoot_potential",
+    "glm_shoot_indexed_workspace_bytes", "glm_shoot_indexed", "glm_shoot_potential", "glm_shoot_direct_nfw",
 ]
 
 
@@ -86,6 +87,8 @@ def load(path: str = LIB_PATH):
     lib.glm_shoot.restype = st
     lib.glm_shoot_direct.argtypes = [vp, vp, vp, vp, i64, ctypes.c_double, vp, vp, i64, i32, P(vp), vp]
     lib.glm_shoot_direct.restype = st
+    lib.glm_shoot_direct_nfw.argtypes = [vp, vp, vp, vp, i64, ctypes.c_double, vp, vp, i64, i32, P(vp), vp]
+    lib.glm_shoot_direct_nfw.restype = st
     lib.glm_shoot_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp]
     lib.glm_shoot_adjoint.restype = st
     lib.glm_shoot_batched_workspace_bytes.argtypes = [P(ctypes.c_int64), i32, P(ctypes.c_size_t)]

@@ -52,7 +52,8 @@ static glm_status check_params(const glm_params* p)
     if (!(p->q > 0.0) || !isfinite(p->q)) return fail(GLM_EINVAL, "q must be finite and > 0");
     if (p->leaf_size < 1 || p->leaf_size > 64) return fail(GLM_EINVAL, "leaf_size must be in 1..64");
     if (p->order < 0 || p->order > kMaxOrder) return fail(GLM_EINVAL, "order must be in 0..12");
-    if (p->flags & ~(GLM_ALPHA_ONLY | GLM_NO_KAHAN | GLM_RAYS_ORDERED)) return fail(GLM_EINVAL, "unknown flag bits");
+    if (p->flags & ~(GLM_ALPHA_ONLY | GLM_NO_KAHAN | GLM_RAYS_ORDERED | GLM_NFW_HALOS))
+        return fail(GLM_EINVAL, "unknown flag bits");
     return GLM_OK;
 }
 
@@ -215,6 +216,7 @@ glm_status glm_shoot_potential(const glm_tree* t, const double* rx, const double
     if (nrays == 0) return GLM_OK;
     if (!rx || !ry || !a1 || !a2 || !psi) return fail(GLM_EINVAL, "rx, ry, a1, a2, psi must be device pointers");
     if (flags & ~GLM_RAYS_ORDERED) return fail(GLM_EINVAL, "unknown flag bits");
+    if (t->ts.dev.kind != kKindGauss) return fail(GLM_ESTATE, "the potential walk is for Gaussian particles and point masses");
     const size_t need = ray_layout(nrays).bytes;
     if (!workspace || workspace_bytes < need)
         return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_workspace_bytes(nrays) = " + std::to_string(need));
@@ -231,7 +233,19 @@ glm_status glm_shoot_direct(const double* x, const double* y, const double* m, c
     if (n < 1 || n > 0x7ffffff0) return fail(GLM_EINVAL, "n must be in 1 .. 2^31 - 16");
     if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays out of range");
     if (!(q > 0.0) || !isfinite(q)) return fail(GLM_EINVAL, "q must be finite and > 0");
-    return direct_device(x, y, m, s, n, q, rx, ry, nrays, fp64, out5, static_cast<hipStream_t>(stream));
+    return direct_device(x, y, m, s, n, q, kKindGauss, rx, ry, nrays, fp64, out5, static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_shoot_direct_nfw(const double* x, const double* y, const double* m, const double* R, int64_t n,
+                                double c, const double* rx, const double* ry, int64_t nrays, int fp64,
+                                void* const out5[5], void* stream)
+{
+    if (!x || !y || !m || !R || !rx || !ry || !out5 || !out5[0] || !out5[1])
+        return fail(GLM_EINVAL, "NULL device pointer");
+    if (n < 1 || n > 0x7ffffff0) return fail(GLM_EINVAL, "n must be in 1 .. 2^31 - 16");
+    if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays out of range");
+    if (!(c > 0.0) || !isfinite(c)) return fail(GLM_EINVAL, "c must be finite and > 0");
+    return direct_device(x, y, m, R, n, c, kKindNfw, rx, ry, nrays, fp64, out5, static_cast<hipStream_t>(stream));
 }
 
 glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* ry, int64_t nrays, const float* ga1,
@@ -244,6 +258,7 @@ glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* 
     if (nrays == 0) return GLM_OK;
     if (!rx || !ry || !ga1 || !ga2) return fail(GLM_EINVAL, "rx, ry, ga1, ga2 must be device pointers");
     if (flags & ~(GLM_NO_KAHAN | GLM_RAYS_ORDERED | GLM_ALPHA_ONLY)) return fail(GLM_EINVAL, "unknown flag bits");
+    if (t->ts.dev.kind != kKindGauss) return fail(GLM_ESTATE, "the adjoint walk is for Gaussian particles and point masses");
     {
         const size_t need = ray_layout(nrays).bytes;
         if (!workspace || workspace_bytes < need)
@@ -285,6 +300,8 @@ glm_status glm_shoot_batched(const glm_lens_rays* lenses, int nlens, uint32_t fl
             return fail(GLM_EINVAL, "lens " + std::to_string(l) + ": kappa, g1, g2 required unless GLM_ALPHA_ONLY");
         const int p = e.tree->ts.params.order;
         if (order >= 0 && p != order) return fail(GLM_EINVAL, "all trees of a batch must have the same order");
+        if (l > 0 && e.tree->ts.dev.kind != lenses[0].tree->ts.dev.kind)
+            return fail(GLM_EINVAL, "all trees of a batch must hold the same particle kind");
         order = p;
         counts[l] = e.nrays;
         total += e.nrays;

@@ -12,6 +12,7 @@
 #include <math.h>
 
 #include "build.hpp"
+#include "eval.hpp"
 
 namespace glm {
 
@@ -318,11 +319,12 @@ __global__ __launch_bounds__(kBlock) void k_leaf_of(BoxArrays b, int ncells, int
     for (int j = b.beg[c]; j < b.end[c]; ++j) leaf_of[j] = c;
 }
 
-// Big-particle lists (Sec. 3.2): a smoothed particle of support radius q s is
-// listed in the highest box where q s > side / 2, provided that box is not
+// Big-particle lists (Sec. 3.2): a smoothed particle of support radius
+// supp * s (q s for a Gaussian, the size s for an NFW halo) is listed in the
+// highest box where the support exceeds side / 2, provided that box is not
 // below the particle's leaf.  Key = box index (kUnlisted otherwise).
 __global__ __launch_bounds__(kBlock) void k_list_assign(const uint64_t* __restrict__ K, int n, const double* __restrict__ ss,
-                                                       double q, BuildSync* __restrict__ sync, int ncells,
+                                                       double supp, BuildSync* __restrict__ sync, int ncells,
                                                        const int32_t* __restrict__ leaf_of, BoxArrays b,
                                                        const int32_t* __restrict__ cs, const int8_t* __restrict__ lstart,
                                                        uint32_t unlisted, uint32_t* __restrict__ lkey,
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_list_assign(const uint64_t* __restri
     uint32_t key = unlisted;
     const double sj = ss[j];
     if (sj > 0.0) {
-        const double qs = q * sj;
+        const double qs = supp * sj;
         int l = 0;
         while (l <= kMaxLevel && !(qs > ldexp(sync->side, -(l + 1)))) ++l;
         const int lf = leaf_of[j];
@@ -351,17 +353,19 @@ __global__ __launch_bounds__(kBlock) void k_list_assign(const uint64_t* __restri
     lval[j] = (uint32_t)j;
 }
 
-__device__ inline void fill_rec(PRec& r, double x, double y, double m, double s, double q, double invC, bool listed,
-                                uint32_t pos)
+// Walk record of one particle of the tree's kind.  q: the Gaussian cutoff or
+// the halo concentration; norm: 1 / C for Gaussians, 1 / g(c) for halos.
+__device__ inline void fill_rec(PRec& r, double x, double y, double m, double s, int kind, double q, double norm,
+                                bool listed, uint32_t pos)
 {
 #pragma clang fp contract(off)
-    const double qs = q * s;
+    const double qs = kind == kKindNfw ? s : q * s;
     r.x = x;
     r.y = y;
     r.qs2 = s > 0.0 ? qs * qs : 0.0;
     r.m = (float)m;
-    r.mC = (float)(m * invC);
-    r.h = s > 0.0 ? (float)(1.0 / (2.0 * s * s)) : 0.0f;
+    r.mC = (float)(m * norm);
+    r.h = s > 0.0 ? (float)(kind == kKindNfw ? q / s : 1.0 / (2.0 * s * s)) : 0.0f;
     r.meta = pos | (listed ? 0x80000000u : 0u);
 }
 
@@ -369,12 +373,12 @@ __global__ __launch_bounds__(kBlock) void k_particle_records(int n, const double
                                                             const double* __restrict__ ys, const double* __restrict__ ms,
                                                             const double* __restrict__ ss,
                                                             const uint32_t* __restrict__ lkey, uint32_t unlisted,
-                                                            double q, double invC, PRec* __restrict__ prt)
+                                                            int kind, double q, double norm, PRec* __restrict__ prt)
 {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     PRec r;
-    fill_rec(r, xs[j], ys[j], ms[j], ss[j], q, invC, lkey[j] != unlisted, (uint32_t)j);
+    fill_rec(r, xs[j], ys[j], ms[j], ss[j], kind, q, norm, lkey[j] != unlisted, (uint32_t)j);
     prt[j] = r;
 }
 
@@ -382,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_list_ranges(int n, const uint32_t* _
                                                        const uint32_t* __restrict__ lval, uint32_t unlisted,
                                                        const double* __restrict__ xs, const double* __restrict__ ys,
                                                        const double* __restrict__ ms, const double* __restrict__ ss,
-                                                       double q, double invC,
+                                                       int kind, double q, double norm,
                                                        BoxArrays b, PRec* __restrict__ lst,
                                                        BuildSync* __restrict__ sync)
 {
@@ -396,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_list_ranges(int n, const uint32_t* _
     if (k == n - 1 || lkey[k + 1] == unlisted) sync->nlisted = k + 1;
     const uint32_t j = lval[k];
     PRec r;
-    fill_rec(r, xs[j], ys[j], ms[j], ss[j], q, invC, true, j);
+    fill_rec(r, xs[j], ys[j], ms[j], ss[j], kind, q, norm, true, j);
     lst[k] = r;
 }
 
@@ -615,6 +619,11 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     const int p = prm.order, L = prm.leaf_size;
     const double q = prm.q;
     const double invC = 1.0 / (-expm1(-0.5 * q * q));
+    // particle kind: truncated Gaussians (support q s), or NFW halos of size s
+    // and concentration q (support s, mass normalised by g(q))
+    const int kind = (prm.flags & GLM_NFW_HALOS) ? kKindNfw : kKindGauss;
+    const double supp = kind == kKindNfw ? 1.0 : q;
+    const double norm = kind == kKindNfw ? 1.0 / nfw_g_at(q) : invC;
 
     // ---- per-particle arena
     Arena pa;
@@ -736,13 +745,13 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
         lk0 = reinterpret_cast<uint32_t*>(k0);
         lk1 = reinterpret_cast<uint32_t*>(k0) + n;
     }
-    hipLaunchKernelGGL(k_list_assign, dim3(gb), dim3(kBlock), 0, st, K, n, ss, q, sync, nc, leaf_of, b, cnt, lstart,
-                       unlisted, lk0, lv0);
-    hipLaunchKernelGGL(k_particle_records, dim3(gb), dim3(kBlock), 0, st, n, xs, ys, ms, ss, lk0, unlisted, q, invC,
-                       prt);
+    hipLaunchKernelGGL(k_list_assign, dim3(gb), dim3(kBlock), 0, st, K, n, ss, supp, sync, nc, leaf_of, b, cnt,
+                       lstart, unlisted, lk0, lv0);
+    hipLaunchKernelGGL(k_particle_records, dim3(gb), dim3(kBlock), 0, st, n, xs, ys, ms, ss, lk0, unlisted, kind, q,
+                       norm, prt);
     const int lw = radix_sort_u32(lk0, lv0, lk1, lv1, n, passes, hist, st);
     hipLaunchKernelGGL(k_list_ranges, dim3(gb), dim3(kBlock), 0, st, n, lw ? lk1 : lk0, lw ? lv1 : lv0, unlisted, xs,
-                       ys, ms, ss, q, invC, b, lst, sync);
+                       ys, ms, ss, kind, q, norm, b, lst, sync);
     for (int l = kMaxLevel; l >= 0; --l)
         if (lt.cnt[l] > 0) {
             const dim3 g(ceil_div(lt.cnt[l], kBlock)), blk(kBlock);
@@ -786,6 +795,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     ts.dev.n = n;
     ts.dev.nlisted = -1; // read on demand (sync->nlisted)
     ts.dev.order = p;
+    ts.dev.kind = kind;
     ts.dev.invC = (float)invC;
     ts.dev.q = q;
     ts.dev.einU = ein_host(0.5 * q * q);

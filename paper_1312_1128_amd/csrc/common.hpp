@@ -36,13 +36,23 @@ struct alignas(16) CellExt {
     int32_t lbeg, lend; // big-particle list entries
 };
 
+// Particle kinds of a tree (one per tree): truncated Gaussians of Sec. 3.1,
+// or truncated NFW halos (Sec. 3.2: a halo type with its own closed forms).
+// Point masses (s = 0) go with either.
+constexpr int kKindGauss = 0;
+constexpr int kKindNfw = 1;
+
 // 40 B: one particle as the walk evaluates it.
+//   Gaussian: qs2 = (q s)^2, mC = m / (1 - exp(-q^2/2)), h = 1 / (2 s^2);
+//   NFW halo of size R = s and concentration c: qs2 = R^2, mC = m / g(c),
+//     h = c / R (the inverse scale radius);
+//   point mass: qs2 = 0, h = 0.
 struct alignas(8) PRec {
     double x, y;   // position (FP64)
-    double qs2;    // (q s)^2 in FP64, the support of the Gaussian; 0 for point masses
+    double qs2;    // squared support radius in FP64 (outside it the particle is a point mass)
     float m;       // mass
-    float mC;      // m / (1 - exp(-q^2/2))
-    float h;       // 1 / (2 s^2), 0 for point masses
+    float mC;      // mass scaled by the profile's normalisation
+    float h;       // profile scale
     uint32_t meta; // Morton position of the particle | (listed in a big-particle list) << 31
 };
 
@@ -69,6 +79,7 @@ struct TreeDev {
     int32_t n;
     int32_t nlisted;
     int32_t order;
+    int32_t kind;           // kKindGauss or kKindNfw
     float invC;             // 1 / (1 - exp(-q^2/2))
     int32_t einTerms;       // series terms of Ein on [0, q^2/2]
     double q;

@@ -113,6 +113,101 @@ __device__ inline void gauss_terms(float u, float e, float ir2, float mC, float 
     *G = small ? Gs : Gl;
 }
 
+// ---------------------------------------------------------------------------
+// Truncated NFW halo (Sec. 3.2: analytic halos are particles with their own
+// closed forms; outside its size a halo lenses as a point mass).  A halo of
+// mass m inside its size R and concentration c has scale radius r_s = R / c;
+// at x = r / r_s, with e = x^2 - 1,
+//   F(x) = atan(y) / y  (x > 1, y = sqrt(e)),   atanh(y) / y  (x < 1, y = sqrt(-e)),
+//   f(x) = (1 - F) / e        projected density shape (f(1) = 1/3),
+//   g(x) = ln(x / 2) + F      enclosed-mass shape (g' = x f, g(c) normalises m),
+// and with mC = m / g(c), h = 1 / r_s:
+//   alpha = mC h^2 (g / x^2) d,   kappa = mC h^2 f / 2,   gamma from both.
+// nfw_shape returns g / x^2 and f from x^2 and e, both of which the caller
+// forms in FP64 from r^2, so that e has no cancellation near x = 1:
+//  - |e| < eps: F = sum_k (-e)^k / (2k + 1), f = sum_k (-e)^k / (2k + 3),
+//    g = ln x - ln 2 + F with ln x = log1p(e) / 2;
+//  - x > 1 beyond: F = atan(y) / y, f = (1 - F) / e, g as above;
+//  - x < 1 beyond: atanh(y) = log1p(2 y (1 + y) / x^2) / 2 (as 1 - y = x^2 / (1 + y)),
+//    f = (F - 1) / y^2, and g / x^2 = [ln(2 / x) / (1 + y) + log1p(-a) / x^2] / y
+//    with a = x^2 / (2 (1 + y)), which keeps ln(x / 2) and F from cancelling.
+// NSER series terms suit eps: 12 at 0.25 for FP32, 17 at 0.1 for FP64.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline float nfw_log1p(float v) { return log1pf(v); }
+__host__ __device__ inline double nfw_log1p(double v) { return log1p(v); }
+__host__ __device__ inline float nfw_log(float v) { return logf(v); }
+__host__ __device__ inline double nfw_log(double v) { return log(v); }
+__host__ __device__ inline float nfw_atan(float v) { return atanf(v); }
+__host__ __device__ inline double nfw_atan(double v) { return atan(v); }
+__host__ __device__ inline float nfw_sqrt(float v) { return sqrtf(v); }
+__host__ __device__ inline double nfw_sqrt(double v) { return sqrt(v); }
+
+// sum_{k < N} z^k / (2k + OFF) by Horner
+template <class T, int N, int OFF>
+__host__ __device__ inline T odd_series(T z)
+{
+    T s = (T)(1.0 / (double)(2 * (N - 1) + OFF));
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) s = s * z + (T)(1.0 / (double)(2 * k + OFF));
+    return s;
+}
+
+template <class T, int NSER>
+__host__ __device__ inline void nfw_shape(T x2, T e, T eps, T* gx2, T* f)
+{
+    const T ln2 = (T)0.693147180559945309417;
+    if (e > -eps && e < eps) {
+        const T F = odd_series<T, NSER, 1>(-e);
+        *f = odd_series<T, NSER + 1, 3>(-e);
+        *gx2 = ((T)0.5 * nfw_log1p(e) - ln2 + F) / x2;
+    } else if (e > (T)0) {
+        const T y = nfw_sqrt(e);
+        const T F = nfw_atan(y) / y;
+        *f = ((T)1 - F) / e;
+        *gx2 = ((T)0.5 * nfw_log1p(e) - ln2 + F) / x2;
+    } else {
+        // x^2 is kept above a tiny floor, so that a ray at the centre gives finite values
+        const T tiny = sizeof(T) == 4 ? (T)1e-30 : (T)1e-300;
+        const T xx = x2 > tiny ? x2 : tiny;
+        const T y = nfw_sqrt(-e), opy = (T)1 + y;
+        const T F = (T)0.5 * nfw_log1p((T)2 * y * opy / xx) / y;
+        *f = (F - (T)1) / (-e);
+        const T L = ln2 - (T)0.5 * nfw_log(xx);
+        *gx2 = (L / opy + nfw_log1p(-xx / ((T)2 * opy)) / xx) / y;
+    }
+}
+
+// g(c) on the host (FP64), for the mass normalisation of a halo of concentration c
+inline double nfw_g_at(double c)
+{
+    double gx2, f;
+    nfw_shape<double, 17>(c * c, (c - 1.0) * (c + 1.0), 0.1, &gx2, &f);
+    return gx2 * (c * c);
+}
+
+// Profile terms of one smoothed particle for a lane inside its support (r^2
+// in FP64 and FP32, ir2 = 1 / r^2): alpha = A d, kappa = K and
+// gamma = -G (cos 2phi, sin 2phi) with G = A - K.
+template <int KIND>
+__device__ inline void profile_terms(const PRec& pr, double r2, float r2f, float ir2, float* A, float* G, float* K)
+{
+    if constexpr (KIND == kKindNfw) {
+        const double x2 = r2 * ((double)pr.h * (double)pr.h);
+        float gx2, f;
+        nfw_shape<float, 12>((float)x2, (float)(x2 - 1.0), 0.25f, &gx2, &f);
+        const float mh2 = (pr.mC * pr.h) * pr.h;
+        *A = mh2 * gx2;
+        *K = r2 > 0.0 ? 0.5f * mh2 * f : 0.0f; // a ray at the centre gets nothing
+        *G = *A - *K;
+    } else {
+        const float u = r2f * pr.h;
+        const float e = __expf(-u);
+        const float mh = pr.mC * pr.h;
+        gauss_terms(u, e, ir2, pr.mC, mh, A, G);
+        *K = mh * e;
+    }
+}
+
 // Point-mass terms of one particle (Sec. 3.5): alpha = m d / r^2 and
 // gamma = -(m / r^2) (cos 2phi, sin 2phi).  Kept free of FMA contraction so
 // that the two call sites of a balanced pair produce identical values.
@@ -151,7 +246,7 @@ __device__ inline void add_radial(float coef, float Gam, float f1, float f2, flo
 // All cases share one select-based path (no divergent branches).  The point
 // terms are formed without FMA contraction, exactly as in point_terms, so a
 // balanced pair cancels bit for bit.
-template <bool AONLY, bool KAHAN, bool PSI = false>
+template <bool AONLY, bool KAHAN, bool PSI = false, int KIND = kKindGauss>
 __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A, double einU = 0.0,
                                      int terms = 1, float invC = 0.0f)
 {
@@ -167,14 +262,11 @@ __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A,
     const float pm = pr.m * ir2;
     float coef = pm, Gam = pm;
     if (__any(gauss)) {
-        const float u = r2f * pr.h;
-        const float e = __expf(-u);
-        const float mh = pr.mC * pr.h;
-        float Ag, Gg;
-        gauss_terms(u, e, ir2, pr.mC, mh, &Ag, &Gg);
+        float Ag, Gg, Kg;
+        profile_terms<KIND>(pr, r2, r2f, ir2, &Ag, &Gg, &Kg);
         coef = gauss ? Ag : pm;
         Gam = gauss ? Gg : pm;
-        if (!AONLY) A.k += gauss ? mh * e : 0.0f;
+        if (!AONLY) A.k += gauss ? Kg : 0.0f;
     }
     const float v1 = coef * f1, v2 = coef * f2;
     kadd<KAHAN>(A.a1, A.c1, balance ? 0.0f : v1);
@@ -196,7 +288,7 @@ __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A,
 // One entry of the big-particle list of a visited box (Sec. 3.2): a lane
 // inside the particle's support adds Gaussian - point (the tree part counted
 // the particle as a point mass); the point part goes to the FP64 balance.
-template <bool AONLY, bool KAHAN, bool PSI = false>
+template <bool AONLY, bool KAHAN, bool PSI = false, int KIND = kKindGauss>
 __device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A, int& hits, double einU = 0.0,
                                      int terms = 1, float invC = 0.0f)
 {
@@ -207,17 +299,14 @@ __device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A,
     const float ir2 = r2f > 0.0f ? __builtin_amdgcn_rcpf(r2f) : 0.0f;
     float P[4];
     point_terms(pr.m, f1, f2, ir2, P);
-    const float u = r2f * pr.h;
-    const float e = __expf(-u);
-    const float mh = pr.mC * pr.h;
-    float Ag, Gg;
-    gauss_terms(u, e, ir2, pr.mC, mh, &Ag, &Gg);
+    float Ag, Gg, Kg;
+    profile_terms<KIND>(pr, r2, r2f, ir2, &Ag, &Gg, &Kg);
     add_radial<AONLY, KAHAN>(Ag, Gg, f1, f2, ir2, A);
     hits++;
     A.b1 -= (double)P[0];
     A.b2 -= (double)P[1];
     if (!AONLY) {
-        A.k += mh * e;
+        A.k += Kg;
         A.g1 -= (double)P[2];
         A.g2 -= (double)P[3];
     }

@@ -35,7 +35,7 @@ struct WalkMode {
     static constexpr bool stats = MODE == 1;
 };
 
-template <int P, bool AONLY, int MODE, bool PSI = false>
+template <int P, bool AONLY, int MODE, bool PSI = false, int KIND = kKindGauss>
 __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool valid, int lane, Acc& A, int cnt[4],
                                   int c0, int c1)
 {
@@ -68,7 +68,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                     const int k = __ffsll((unsigned long long)cm) - 1;
                     cm &= cm - 1;
                     const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
-                    if (act) list_particle<AONLY, KAHAN, PSI>(pr, X, Y, A, n_hit, T.einU, T.einTerms, T.invC);
+                    if (act) list_particle<AONLY, KAHAN, PSI, KIND>(pr, X, Y, A, n_hit, T.einU, T.einTerms, T.invC);
                 }
             }
         }
@@ -88,7 +88,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                 }
                 for (int j = e.pbeg; j < e.pend; ++j) {
                     const PRec pr = T.prt[j];
-                    if (opn) leaf_particle<AONLY, KAHAN, PSI>(pr, X, Y, A, T.einU, T.einTerms, T.invC);
+                    if (opn) leaf_particle<AONLY, KAHAN, PSI, KIND>(pr, X, Y, A, T.einU, T.einTerms, T.invC);
                 }
             }
             cur = cur + 1;
@@ -129,7 +129,7 @@ __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, cons
     }
 }
 
-template <int P, bool AONLY, int MODE, bool PSI = false>
+template <int P, bool AONLY, int MODE, bool PSI = false, int KIND = kKindGauss>
 __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __restrict__ rxs,
                                                 const double* __restrict__ rys, const uint32_t* __restrict__ rperm,
                                                 int64_t nrays, WalkOut out, int K, Partial* __restrict__ parts,
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __rest
     }
     Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int cnt[4];
-    walk_group<P, AONLY, MODE, PSI>(T, X, Y, valid, lane, A, cnt, c0, c1);
+    walk_group<P, AONLY, MODE, PSI, KIND>(T, X, Y, valid, lane, A, cnt, c0, c1);
     if (!valid) return;
     if (K == 1) {
         write_out<AONLY, WalkMode<MODE>::stats, PSI>(A, cnt, rperm ? (int64_t)rperm[r] : r, out);
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_merge(const Partial* __restrict
 // Persistent walk over many lenses: every wavefront takes (lens, 64-ray group)
 // items from a device counter until the queue is empty.  Lenses are ranked by
 // estimated cost, so the largest ray groups start first.
-template <int P, bool AONLY, int MODE>
+template <int P, bool AONLY, int MODE, int KIND>
 __global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __restrict__ lenses, int nlens,
                                                         const int64_t* __restrict__ gprefix, int* __restrict__ counter,
                                                         const double* __restrict__ xs, const double* __restrict__ ys,
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __rest
         const double X = valid ? xs[gi] : 0.0, Y = valid ? ys[gi] : 0.0;
         Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int cnt[4];
-        walk_group<P, AONLY, MODE>(L.tree, X, Y, valid, lane, A, cnt, 0, L.tree.ncells);
+        walk_group<P, AONLY, MODE, false, KIND>(L.tree, X, Y, valid, lane, A, cnt, 0, L.tree.ncells);
         if (valid) write_out<AONLY, false>(A, cnt, (int64_t)perm[gi] - L.ray_off, L.out);
     }
 }
@@ -374,12 +374,18 @@ void launch_walk(const TreeDev& T, const double* rxs, const double* rys, const u
                  const WalkOut& out, int mode, int K, Partial* parts, const int* split_box, hipStream_t st)
 {
     const dim3 g((unsigned)walk_grid_blocks((nrays + kWave - 1) / kWave, K)), b(kBlock);
-    if (mode == 1)
-        hipLaunchKernelGGL((k_walk<P, AONLY, 1>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, K, parts, split_box);
-    else if (mode == 2)
-        hipLaunchKernelGGL((k_walk<P, AONLY, 2>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, K, parts, split_box);
-    else
-        hipLaunchKernelGGL((k_walk<P, AONLY, 0>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, K, parts, split_box);
+#define GLM_WALK(MD, KD) \
+    hipLaunchKernelGGL((k_walk<P, AONLY, MD, false, KD>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, K, parts, split_box)
+    if (T.kind == kKindNfw) {
+        if (mode == 1) GLM_WALK(1, kKindNfw);
+        else if (mode == 2) GLM_WALK(2, kKindNfw);
+        else GLM_WALK(0, kKindNfw);
+    } else {
+        if (mode == 1) GLM_WALK(1, kKindGauss);
+        else if (mode == 2) GLM_WALK(2, kKindGauss);
+        else GLM_WALK(0, kKindGauss);
+    }
+#undef GLM_WALK
     if (K > 1)
         hipLaunchKernelGGL((k_walk_merge<AONLY>), dim3(ceil_div(nrays, kBlock)), b, 0, st, parts, K, nrays, rperm, out);
 }
@@ -588,15 +594,20 @@ BatchLayout batch_layout(int nlens, int64_t total)
 
 template <int P, bool AONLY>
 void launch_batched(const BatchLens* table, int nlens, const int64_t* gpre, int* counter, const double* xs,
-                    const double* ys, const uint32_t* perm, int64_t items, int kahan, hipStream_t st)
+                    const double* ys, const uint32_t* perm, int64_t items, int kahan, int kind, hipStream_t st)
 {
     const int blocks = (int)std::min<int64_t>((items + 3) / 4, 256 * 8);
-    if (kahan)
-        hipLaunchKernelGGL((k_walk_batched<P, AONLY, 0>), dim3(blocks), dim3(kBlock), 0, st, table, nlens, gpre,
-                           counter, xs, ys, perm);
-    else
-        hipLaunchKernelGGL((k_walk_batched<P, AONLY, 2>), dim3(blocks), dim3(kBlock), 0, st, table, nlens, gpre,
-                           counter, xs, ys, perm);
+#define GLM_WALK(MD, KD)                                                                                    \
+    hipLaunchKernelGGL((k_walk_batched<P, AONLY, MD, KD>), dim3(blocks), dim3(kBlock), 0, st, table, nlens, gpre, \
+                       counter, xs, ys, perm)
+    if (kind == kKindNfw) {
+        if (kahan) GLM_WALK(0, kKindNfw);
+        else GLM_WALK(2, kKindNfw);
+    } else {
+        if (kahan) GLM_WALK(0, kKindGauss);
+        else GLM_WALK(2, kKindGauss);
+    }
+#undef GLM_WALK
 }
 
 } // namespace
@@ -650,12 +661,13 @@ glm_status shoot_batched_device(const BatchLens* host_table, int nlens, int orde
     const uint32_t* perm = w ? v1 : v0;
     hipLaunchKernelGGL(k_batch_gather, dim3(g), dim3(kBlock), 0, st, dtab, droff, ks, perm, total, xs, ys);
     const int kahan = (flags & GLM_NO_KAHAN) ? 0 : 1;
+    const int kind = host_table[0].tree.kind; // every lens of a batch has the same particle kind
 #define GLM_CASE(PP)                                                                                     \
     case PP:                                                                                             \
         if (flags & GLM_ALPHA_ONLY)                                                                      \
-            launch_batched<PP, true>(dtab, nlens, dgpre, counter, xs, ys, perm, items, kahan, st);       \
+            launch_batched<PP, true>(dtab, nlens, dgpre, counter, xs, ys, perm, items, kahan, kind, st); \
         else                                                                                             \
-            launch_batched<PP, false>(dtab, nlens, dgpre, counter, xs, ys, perm, items, kahan, st);      \
+            launch_batched<PP, false>(dtab, nlens, dgpre, counter, xs, ys, perm, items, kahan, kind, st);\
         break;
     switch (order) {
         GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)

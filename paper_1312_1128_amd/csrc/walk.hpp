@@ -129,8 +129,9 @@ glm_status shoot_indexed_device(const TreeStorage& ts, const double* cx, const d
 glm_status potential_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, float* a1,
                             float* a2, float* psi, float* td, uint32_t flags, void* ws, hipStream_t st);
 
+// kind: kKindGauss (q = cutoff) or kKindNfw (s = sizes, q = concentration)
 glm_status direct_device(const double* x, const double* y, const double* m, const double* s, int64_t n, double q,
-                         const double* rx, const double* ry, int64_t nrays, int fp64, void* const out5[5],
+                         int kind, const double* rx, const double* ry, int64_t nrays, int fp64, void* const out5[5],
                          hipStream_t st);
 
 glm_status adjoint_device(TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, const float* ga1,
