@@ -329,6 +329,65 @@ def main():
         l4 = (time.perf_counter() - t) / 3
         log(f"64 lenses ({R4} rays): one persistent launch {1e3 * b4:.2f} ms ({R4 / b4:.4e} rays/s), "
             f"per-lens launches {1e3 * l4:.2f} ms")
+        del trees4, rays4, outs4, ws4, ws4b
+
+        # truncated NFW halos as particles: the halo convergence test's field (1e4 halos
+        # in the unit disk, sizes U(0, 0.3), dN/dm ~ m^-2 on [1e-3, 1], c = 3) under a
+        # 2048^2 grid over [-1, 1]^2; tree at the headline theta / order / leaf size
+        lh, ch = synth.nfw_halo_field(10_000, synth.BASE_SEED + 7)
+        xh, yh, mh, sh = d(lh.x), d(lh.y), d(lh.m), d(lh.s)
+        hx, hy = synth.ray_grid_tiled(2048, -1.0, 1.0)
+        hxd, hyd = d(hx), d(hy)
+        treeh = g.Tree()
+
+        def steph():
+            treeh.build(xh, yh, mh, sh, theta=THETA, q=ch, leaf_size=LEAF, order=ORDER, nfw=True)
+            g.shoot(treeh, hxd, hyd, out=out, workspace=ws)
+
+        for _ in range(2):
+            steph()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            steph()
+        torch.cuda.synchronize()
+        nfw_ms = 1e3 * (time.perf_counter() - t) / 5
+        ev0.record(stream)
+        for _ in range(5):
+            g.shoot(treeh, hxd, hyd, out=out, ordered=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        nfw_walk_ms = ev0.elapsed_time(ev1) / 5
+        cnth = g.shoot(treeh, hxd, hyd, counts=True, ordered=True)["counts"].cpu().numpy().astype(np.float64)
+        g.shoot(treeh, hxd, hyd, out=out, workspace=ws)
+        resh = {}
+        for fp64 in (False, True):
+            g.shoot_direct(xh, yh, mh, sh, ch, hxd[:256], hyd[:256], fp64=fp64, nfw=True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fullh = g.shoot_direct(xh, yh, mh, sh, ch, hxd, hyd, fp64=fp64, nfw=True)
+            torch.cuda.synchronize()
+            resh[fp64] = R / (time.perf_counter() - t)
+        ref_a = torch.stack([fullh["a1"], fullh["a2"]], 1)
+        ref_g = torch.stack([fullh["g1"], fullh["g2"]], 1)
+        e_a = (torch.stack([out["a1"], out["a2"]], 1).double() - ref_a).norm(dim=1) / ref_a.norm(dim=1)
+        e_g = (torch.stack([out["g1"], out["g2"]], 1).double() - ref_g).norm(dim=1) / ref_g.norm(dim=1)
+        inside = fullh["kappa"] > 0
+        e_k = (out["kappa"].double() - fullh["kappa"]).abs()[inside] / fullh["kappa"][inside]
+        gnorm = ref_g.norm(dim=1)
+        worst = int(e_g.argmax())
+        nfw_err = {"alpha_max": float(e_a.max()), "alpha_median": float(e_a.median()),
+                   "kappa_max": float(e_k.max()), "gamma_max": float(e_g.max()),
+                   "gamma_p999": float(torch.quantile(e_g.float(), 0.999)),
+                   "gamma_rays_above_1e-4": int((e_g > 1e-4).sum()),
+                   "gamma_worst_ray_abs_over_median_abs": float(gnorm[worst] / gnorm.median()),
+                   "kappa_zero_outside_exact": bool((out["kappa"][~inside] == 0).all())}
+        del fullh, ref_a, ref_g, e_a, e_g, e_k, gnorm
+        log(f"NFW halo field (1e4 halos, 2048^2 rays): build + shoot {nfw_ms:.2f} ms -> {R / (nfw_ms * 1e-3):.4e} "
+            f"rays/s (walk {nfw_walk_ms:.2f} ms); direct fp32 {resh[False]:.3e}, fp64 {resh[True]:.3e} rays/s; "
+            f"vs GPU FP64 direct: alpha max {nfw_err['alpha_max']:.2e} kappa max {nfw_err['kappa_max']:.2e} "
+            f"gamma max {nfw_err['gamma_max']:.2e} (p99.9 {nfw_err['gamma_p999']:.2e}, "
+            f"{nfw_err['gamma_rays_above_1e-4']} rays above 1e-4); counts/ray {cnth.mean(0)}")
         extras = {"direct_fp32_rays_per_s": res[False], "direct_fp64_rays_per_s": res[True],
                   "full_grid_err_vs_gpu_fp64_direct": full_err,
                   "potential_walk_ms": pot_ms, "potential_walk_rays_per_s": R / (pot_ms * 1e-3),
@@ -343,7 +402,14 @@ def main():
                   "interp_refinement_workload": "nfw_1e6 + stars tree, smooth 0.0002 patch at (0.3, 0.05), "
                                                 "256^2 base, 6 rounds, tol 1e-4",
                   "batched_lenses": len(lenses4), "batched_rays": R4, "batched_ms": 1e3 * b4,
-                  "batched_rays_per_s": R4 / b4, "per_lens_launches_ms": 1e3 * l4}
+                  "batched_rays_per_s": R4 / b4, "per_lens_launches_ms": 1e3 * l4,
+                  "nfw_halos": {"workload": "1e4 truncated NFW halos (unit disk, sizes U(0, 0.3), dN/dm ~ m^-2 "
+                                            "on [1e-3, 1], c = 3), 2048^2 grid over [-1, 1]^2",
+                                "step_ms": nfw_ms, "rays_per_s": R / (nfw_ms * 1e-3), "walk_ms": nfw_walk_ms,
+                                "direct_fp32_rays_per_s": resh[False], "direct_fp64_rays_per_s": resh[True],
+                                "err_vs_gpu_fp64_direct": nfw_err,
+                                "counts_per_ray": dict(zip(["visited", "accepted", "leaf", "list_hits"],
+                                                           cnth.mean(0).tolist()))}}
 
     # counter calibration: a plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB)
     src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
