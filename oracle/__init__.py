@@ -74,6 +74,7 @@ def _load():
     lib.ora_direct_psi.argtypes = [d, d, d, d, i64, ctypes.c_double, d, d, i64, d, ctypes.c_int]
     lib.ora_tree_shoot_psi.argtypes = [vp, d, d, i64, d, ctypes.c_int]
     lib.ora_knn_at.argtypes = [d, d, i64, ctypes.c_int, vp, i64, d, ctypes.c_int]
+    lib.ora_knn_ex.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int, vp, i64, d, ctypes.c_int]
     lib.ora_tree_build.argtypes = [d, d, d, d, i64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int]
     lib.ora_tree_build.restype = vp
@@ -184,21 +185,22 @@ def direct_psi(x, y, m, s, q, rx, ry, threads: int | None = None) -> np.ndarray:
     return out
 
 
-def knn(x, y, k: int = 32, at=None, threads: int | None = None) -> np.ndarray:
+def knn(x, y, k: int = 32, at=None, threads: int | None = None, z=None, species=None) -> np.ndarray:
     """Smoothing lengths: distance from each particle (or from the particles
-    listed in ``at``) to its k-th nearest other particle."""
+    listed in ``at``) to its k-th nearest other particle; in 3D when z is
+    given, and among the particle's own species when species is given."""
     lib = _load()
     x, y = _f64(x), _f64(y)
-    if at is None:
-        out = np.zeros(x.shape[0])
-        rc = lib.ora_knn(_p(x), _p(y), x.shape[0], int(k), _p(out), threads or default_threads())
-    else:
-        q = np.ascontiguousarray(at, dtype=np.int64)
-        out = np.zeros(q.shape[0])
-        rc = lib.ora_knn_at(_p(x), _p(y), x.shape[0], int(k), q.ctypes.data, q.shape[0], _p(out),
-                            threads or default_threads())
+    zz = _f64(z) if z is not None else None
+    sp = np.ascontiguousarray(species, dtype=np.int32) if species is not None else None
+    q = np.ascontiguousarray(at, dtype=np.int64) if at is not None else None
+    out = np.zeros(q.shape[0] if q is not None else x.shape[0])
+    rc = lib.ora_knn_ex(_p(x), _p(y), _p(zz) if zz is not None else None,
+                        sp.ctypes.data if sp is not None else None, x.shape[0], int(k),
+                        q.ctypes.data if q is not None else None, out.shape[0], _p(out),
+                        threads or default_threads())
     if rc != 0:
-        raise ValueError("need 1 <= k <= n - 1")
+        raise ValueError("need 1 <= k <= n - 1 and at least k + 1 particles of every queried species")
     return out
 
 

@@ -64,6 +64,12 @@ int ora_knn(const double* x, const double* y, int64_t n, int k, double* s_out, i
 /* The same for the particles queries[0..nq-1] only (out[t] for queries[t]). */
 int ora_knn_at(const double* x, const double* y, int64_t n, int k, const int64_t* queries, int64_t nq,
                double* s_out, int nthreads);
+/* General form: 3D distances when z is not NULL, and only particles of the
+ * same species when species is not NULL (queries may be NULL: all n).
+ * Returns -1 unless 1 <= k <= n - 1 and every queried particle has at least k
+ * others of its species (those get NaN). */
+int ora_knn_ex(const double* x, const double* y, const double* z, const int32_t* species, int64_t n, int k,
+               const int64_t* queries, int64_t nq, double* s_out, int nthreads);
 
 /* Truncated NFW halos (nfw.c): shape functions of the projected profile,
  * per-unit-mass terms (a1 a2 kappa g1 g2, 0 0) of a halo of size R and

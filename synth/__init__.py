@@ -63,7 +63,14 @@ def uniform_points(n: int, seed: int, lo: float = -0.5, hi: float = 0.5):
 # particle sets
 # --------------------------------------------------------------------------
 def nfw_projected(n: int, seed: int, c: float = 5.0, r200: float = 1.0):
-    """Projected positions of n particles drawn from a 3D NFW profile.
+    """Projected positions of n particles drawn from a 3D NFW profile
+    (nfw_3d without its z coordinate)."""
+    x, y, _ = nfw_3d(n, seed, c, r200)
+    return x, y
+
+
+def nfw_3d(n: int, seed: int, c: float = 5.0, r200: float = 1.0):
+    """3D positions (x, y, z) of n particles drawn from an NFW profile.
 
     Radii follow the enclosed-mass fraction mu(x) = ln(1+x) - x/(1+x) on
     x = r/r_s in [0, c] (truncated at r200 = c r_s), inverted through the
@@ -81,7 +88,7 @@ def nfw_projected(n: int, seed: int, c: float = 5.0, r200: float = 1.0):
     cost = g.uniform(-1.0, 1.0, n)
     phi = g.uniform(0.0, 2.0 * math.pi, n)
     sint = np.sqrt(np.maximum(0.0, 1.0 - cost * cost))
-    return r * sint * np.cos(phi), r * sint * np.sin(phi)
+    return r * sint * np.cos(phi), r * sint * np.sin(phi), r * cost
 
 
 def knn_smoothing(x, y, k: int = 32):
