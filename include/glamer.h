@@ -158,6 +158,26 @@ GLM_API glm_status glm_tree_export(const glm_tree* t, int32_t* level, uint32_t* 
  */
 GLM_API glm_status glm_tree_knn(const glm_tree* t, int32_t k, double* s_out, void* stream);
 
+/*
+ * Smoothing lengths from raw positions (Sec. 3.1): for each particle the
+ * distance to its k-th nearest other particle (itself excluded, coincident
+ * particles at distance 0), counted in projection when z is NULL and in space
+ * (the paper's preferred 3D smoothing) otherwise; with species != NULL only
+ * particles of the same species count (each species is smoothed on its own).
+ * The squared distance is (dx^2 + dy^2) + dz^2 in FP64, so the result is the
+ * square root of the k-th smallest FP64 squared distance.
+ *   x, y, z : device FP64 positions, length n (z nullable); n in 2 .. 2^31 - 1
+ *   species : device int32 ids in [0, 65535], nullable
+ *   k       : 1 .. 64, and every species must hold at least k + 1 particles
+ *   s_out   : device FP64, length n, original order (written)
+ *   workspace: at least glm_knn_workspace_bytes(n, species != NULL) bytes
+ * Synchronises `stream` once (twice with species). GLM_EDATA for a non-finite
+ * position, a species id out of range or a species with <= k particles.
+ */
+GLM_API glm_status glm_knn_workspace_bytes(int64_t n, int32_t with_species, size_t* bytes);
+GLM_API glm_status glm_knn(const double* x, const double* y, const double* z, const int32_t* species, int64_t n,
+                   int32_t k, double* s_out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Bytes of device workspace glm_shoot / glm_shoot_adjoint need for nrays rays. */
 GLM_API glm_status glm_shoot_workspace_bytes(int64_t nrays, size_t* bytes);
 

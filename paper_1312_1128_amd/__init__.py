@@ -20,7 +20,7 @@ from ._capi import (GLM_ALPHA_ONLY, GLM_NFW_HALOS, GLM_NO_KAHAN, GLM_RAYS_ORDERE
 __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
            "GLM_NFW_HALOS", "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
            "refine_schedule", "RefinementRun", "autotune", "smoothing_lengths", "interp_init",
-           "refine_interp_round", "shoot_indexed", "shoot_potential"]
+           "refine_interp_round", "shoot_indexed", "shoot_potential", "knn"]
 
 
 def _ptr(t):
@@ -157,13 +157,37 @@ def shoot_potential(tree: Tree, rx, ry, ordered: bool = False, workspace=None):
     return out
 
 
-def smoothing_lengths(x, y, k: int = 32, leaf_size: int = 16):
-    """Smoothing lengths of particles at (x, y) (float64 CUDA tensors): the 2D
-    distance from each to its k-th nearest other particle (Sec. 3.1), on a
-    tree built from the positions alone."""
+def smoothing_lengths(x, y, k: int = 32, leaf_size: int = 16, z=None, species=None, workspace=None):
+    """Smoothing lengths of particles at (x, y) (float64 CUDA tensors): the
+    distance from each to its k-th nearest other particle (Sec. 3.1).  In 2D
+    without species, on a quad-tree built from the positions alone; with z
+    (3D smoothing) or species (int32 ids, each species smoothed on its own),
+    on the bounding-box hierarchy of glm_knn."""
     x, y = _f64(x, "x"), _f64(y, "y")
-    tree = Tree().build(x, y, torch.ones_like(x), None, theta=0.5, q=3.0, leaf_size=leaf_size, order=0)
-    return tree.knn(k)
+    if z is None and species is None:
+        tree = Tree().build(x, y, torch.ones_like(x), None, theta=0.5, q=3.0, leaf_size=leaf_size, order=0)
+        return tree.knn(k)
+    return knn(x, y, k, z=z, species=species, workspace=workspace)
+
+
+def knn(x, y, k: int = 32, z=None, species=None, out=None, workspace=None):
+    """glm_knn: k-th nearest-neighbour distances from raw positions, 2D or 3D
+    (z), optionally per species (int32 ids)."""
+    x, y = _f64(x, "x"), _f64(y, "y")
+    z = _f64(z, "z") if z is not None else None
+    if species is not None:
+        assert species.dtype == torch.int32 and species.is_contiguous() and species.is_cuda
+    n = x.shape[0]
+    lib = _capi.load()
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=x.device)
+    nb = ctypes.c_size_t()
+    _capi.check(lib.glm_knn_workspace_bytes(n, 1 if species is not None else 0, ctypes.byref(nb)))
+    if workspace is None:
+        workspace = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=x.device)
+    _capi.check(lib.glm_knn(_ptr(x), _ptr(y), _ptr(z), _ptr(species), n, int(k), _ptr(out), _ptr(workspace),
+                            workspace.numel(), _stream()))
+    return out
 
 
 def shoot_direct(x, y, m, s, q, rx, ry, fp64: bool = False, alpha_only: bool = False, nfw: bool = False):

@@ -27,6 +27,7 @@ EXPORTED = [
     "glm_refine_workspace_bytes", "glm_refine_round", "glm_tree_knn", "glm_interp_state_bytes",
     "glm_interp_round_workspace_bytes", "glm_interp_init", "glm_refine_interp_round",
     "glm_shoot_indexed_workspace_bytes", "glm_shoot_indexed", "glm_shoot_potential", "glm_shoot_direct_nfw",
+    "glm_knn_workspace_bytes", "glm_knn",
 ]
 
 
@@ -117,6 +118,10 @@ def load(path: str = LIB_PATH):
     lib.glm_shoot_potential.restype = st
     lib.glm_tree_knn.argtypes = [vp, ctypes.c_int32, vp, vp]
     lib.glm_tree_knn.restype = st
+    lib.glm_knn_workspace_bytes.argtypes = [i64, i32, P(ctypes.c_size_t)]
+    lib.glm_knn_workspace_bytes.restype = st
+    lib.glm_knn.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
+    lib.glm_knn.restype = st
     lib.glm_last_error.argtypes = []
     lib.glm_last_error.restype = ctypes.c_char_p
     lib.glm_version.argtypes = []

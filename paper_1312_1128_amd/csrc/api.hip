@@ -224,6 +224,25 @@ glm_status glm_shoot_potential(const glm_tree* t, const double* rx, const double
                             static_cast<hipStream_t>(stream));
 }
 
+glm_status glm_knn_workspace_bytes(int64_t n, int32_t with_species, size_t* bytes)
+{
+    if (!bytes || n < 0 || n > 0x7fffffff) return fail(GLM_EINVAL, "bad argument");
+    *bytes = knn_workspace_bytes(n, with_species != 0);
+    return GLM_OK;
+}
+
+glm_status glm_knn(const double* x, const double* y, const double* z, const int32_t* species, int64_t n, int32_t k,
+                   double* s_out, void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!x || !y || !s_out) return fail(GLM_EINVAL, "x, y, s_out must be device pointers");
+    if (n < 2 || n > 0x7fffffff) return fail(GLM_EINVAL, "n must be in 2 .. 2^31 - 1");
+    if (k < 1 || k > 64 || k > n - 1) return fail(GLM_EINVAL, "k must be in 1 .. min(64, n - 1)");
+    const size_t need = knn_workspace_bytes(n, species != nullptr);
+    if (!workspace || workspace_bytes < need)
+        return fail(GLM_ENOMEM, "workspace smaller than glm_knn_workspace_bytes = " + std::to_string(need));
+    return knn_positions_device(x, y, z, species, n, k, s_out, workspace, static_cast<hipStream_t>(stream));
+}
+
 glm_status glm_shoot_direct(const double* x, const double* y, const double* m, const double* s, int64_t n, double q,
                             const double* rx, const double* ry, int64_t nrays, int fp64, void* const out5[5],
                             void* stream)

@@ -66,4 +66,13 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
 // nearest other particle, written in original order.
 glm_status knn_device(const TreeStorage& ts, int k, double* s_out, hipStream_t st);
 
+// Smoothing lengths from raw positions (knn3.hip): 2D (z NULL) or 3D, and per
+// species when species is not NULL; the caller's workspace holds
+// knn_workspace_bytes(n, species != NULL) bytes.  Synchronises the stream
+// once (twice with species) to validate the inputs and read the species
+// segments.
+size_t knn_workspace_bytes(int64_t n, bool species);
+glm_status knn_positions_device(const double* x, const double* y, const double* z, const int32_t* species,
+                                int64_t n, int k, double* s_out, void* ws, hipStream_t st);
+
 } // namespace glm
