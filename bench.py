@@ -221,6 +221,30 @@ def main():
         knn_diff = float(((s_gpu - s).abs() / s).max())
         log(f"smoothing lengths (k = 32, 1e6 particles): {knn_ms:.3f} ms; max rel diff vs the inputs' host k-d tree "
             f"{knn_diff:.1e}")
+        # the same from raw positions on the bounding-box hierarchy: 2D, 3D (the positions
+        # before projection), and two species (the halo plus 1e5 stars around (0.25, 0))
+        x3d, y3d, z3d = (d(a) for a in synth.nfw_3d(1_000_000, synth.BASE_SEED + 2))
+        stars_b = synth.star_patch(100_000, synth.BASE_SEED + 20)
+        xs2, ys2 = torch.cat([x, d(stars_b.x)]), torch.cat([y, d(stars_b.y)])
+        sp2 = torch.cat([torch.zeros(lens.n, dtype=torch.int32), torch.ones(100_000, dtype=torch.int32)]).to(dev)
+        knn_pos = {}
+        for name, args_k in (("2d", (x, y, None, None)), ("3d", (x3d, y3d, z3d, None)),
+                             ("2d_two_species", (xs2, ys2, None, sp2))):
+            wsk = torch.empty(max(1, g.knn_workspace_bytes(args_k[0].numel(), args_k[3] is not None)),
+                              dtype=torch.uint8, device=dev)
+            g.knn(args_k[0], args_k[1], 32, z=args_k[2], species=args_k[3], workspace=wsk)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                sk = g.knn(args_k[0], args_k[1], 32, z=args_k[2], species=args_k[3], workspace=wsk)
+            torch.cuda.synchronize()
+            knn_pos[name] = 1e3 * (time.perf_counter() - t) / 3
+            if name == "2d":
+                knn_pos["2d_equals_quadtree"] = bool(torch.equal(sk, s_gpu))
+        del x3d, y3d, z3d, xs2, ys2, sp2, wsk, sk
+        log(f"smoothing lengths from positions (k = 32): 2D {knn_pos['2d']:.2f} ms (same as the quad-tree: "
+            f"{knn_pos['2d_equals_quadtree']}), 3D {knn_pos['3d']:.2f} ms, 2D with two species (1.1e6) "
+            f"{knn_pos['2d_two_species']:.2f} ms")
 
         # forward + adjoint on the lens-fitting workload: 1e5 particles, 1e5 rays,
         # L = sum |x - alpha - beta*|^2 (step = build + alpha walk + adjoint walk)
@@ -392,6 +416,7 @@ def main():
                   "full_grid_err_vs_gpu_fp64_direct": full_err,
                   "potential_walk_ms": pot_ms, "potential_walk_rays_per_s": R / (pot_ms * 1e-3),
                   "knn_smoothing_1e6_ms": knn_ms, "knn_max_rel_diff_vs_host_kdtree": knn_diff,
+                  "knn_from_positions_ms": knn_pos,
                   "fwd_adjoint_rays_per_s": rx5.numel() / (fa_ms * 1e-3), "fwd_adjoint_ms": fa_ms,
                   "fwd_adjoint_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2",
                   "refinement_rays": n3, "refinement_graph_ms": 1e3 * graph3_s, "refinement_eager_ms": 1e3 * eager3,

@@ -20,7 +20,7 @@ from ._capi import (GLM_ALPHA_ONLY, GLM_NFW_HALOS, GLM_NO_KAHAN, GLM_RAYS_ORDERE
 __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
            "GLM_NFW_HALOS", "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
            "refine_schedule", "RefinementRun", "autotune", "smoothing_lengths", "interp_init",
-           "refine_interp_round", "shoot_indexed", "shoot_potential", "knn"]
+           "refine_interp_round", "shoot_indexed", "shoot_potential", "knn", "knn_workspace_bytes"]
 
 
 def _ptr(t):
@@ -170,6 +170,12 @@ def smoothing_lengths(x, y, k: int = 32, leaf_size: int = 16, z=None, species=No
     return knn(x, y, k, z=z, species=species, workspace=workspace)
 
 
+def knn_workspace_bytes(n: int, species: bool = False) -> int:
+    nb = ctypes.c_size_t()
+    _capi.check(_capi.load().glm_knn_workspace_bytes(int(n), 1 if species else 0, ctypes.byref(nb)))
+    return nb.value
+
+
 def knn(x, y, k: int = 32, z=None, species=None, out=None, workspace=None):
     """glm_knn: k-th nearest-neighbour distances from raw positions, 2D or 3D
     (z), optionally per species (int32 ids)."""
@@ -181,10 +187,9 @@ def knn(x, y, k: int = 32, z=None, species=None, out=None, workspace=None):
     lib = _capi.load()
     if out is None:
         out = torch.empty(n, dtype=torch.float64, device=x.device)
-    nb = ctypes.c_size_t()
-    _capi.check(lib.glm_knn_workspace_bytes(n, 1 if species is not None else 0, ctypes.byref(nb)))
     if workspace is None:
-        workspace = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=x.device)
+        workspace = torch.empty(max(knn_workspace_bytes(n, species is not None), 1), dtype=torch.uint8,
+                                device=x.device)
     _capi.check(lib.glm_knn(_ptr(x), _ptr(y), _ptr(z), _ptr(species), n, int(k), _ptr(out), _ptr(workspace),
                             workspace.numel(), _stream()))
     return out
