@@ -93,6 +93,11 @@ def _load():
     lib.ora_tree_shoot_frozen.argtypes = [vp, d, d, i64, d, d, d, d, d]
     lib.ora_tree_shoot_frozen.restype = ctypes.c_int
     lib.ora_tree_grad.argtypes = [vp, d, d, i64, d, d, d, d, d, d]
+    lib.ora_tree_grad_kg.argtypes = [vp, d, d, i64, d, d, d, d, d, d, d, d, d]
+    lib.ora_tree_grad_kg.restype = ctypes.c_int
+    lib.ora_direct_grad_kg.argtypes = [d, d, d, d, i64, ctypes.c_double, d, d, i64, d, d, d, d, d, d, d, d, d,
+                                       ctypes.c_int]
+    lib.ora_unit_dterms.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, d]
     _lib = lib
     return lib
 
@@ -204,19 +209,42 @@ def knn(x, y, k: int = 32, at=None, threads: int | None = None, z=None, species=
     return out
 
 
-def direct_grad(x, y, m, s, q, rx, ry, ga, threads: int | None = None):
-    """Oracle A adjoint for L = sum_r ga_r . alpha_r.  Returns (dm, dx, dy, ds)."""
+def _cot(gk, gg):
+    """kappa and gamma cotangents as (gk, gg1, gg2) arrays or None."""
+    k = _f64(gk) if gk is not None else None
+    if gg is None:
+        return k, None, None
+    gg = np.ascontiguousarray(gg, dtype=np.float64)
+    return k, _f64(gg[:, 0]), _f64(gg[:, 1])
+
+
+def _pn(a):
+    return _p(a) if a is not None else None
+
+
+def direct_grad(x, y, m, s, q, rx, ry, ga, threads: int | None = None, gk=None, gg=None):
+    """Oracle A adjoint for L = sum_r ga_r . alpha_r (+ gk_r kappa_r + gg_r . gamma_r
+    when gk [nr] / gg [nr, 2] are given).  Returns (dm, dx, dy, ds)."""
     lib = _load()
     x, y, m = _f64(x), _f64(y), _f64(m)
     s = _f64(s) if s is not None else np.zeros_like(x)
     rx, ry = _f64(rx), _f64(ry)
     ga = np.ascontiguousarray(ga, dtype=np.float64)
     g1, g2 = _f64(ga[:, 0]), _f64(ga[:, 1])
+    k, h1, h2 = _cot(gk, gg)
     n = x.shape[0]
     out = [np.zeros(n) for _ in range(4)]
-    lib.ora_direct_grad(_p(x), _p(y), _p(m), _p(s), n, float(q), _p(rx), _p(ry), rx.shape[0],
-                        _p(g1), _p(g2), *[_p(o) for o in out], threads or default_threads())
+    lib.ora_direct_grad_kg(_p(x), _p(y), _p(m), _p(s), n, float(q), _p(rx), _p(ry), rx.shape[0],
+                           _p(g1), _p(g2), _pn(k), _pn(h1), _pn(h2), *[_p(o) for o in out],
+                           threads or default_threads())
     return tuple(out)
+
+
+def unit_dterms(d1: float, d2: float, s: float, q: float, inside: bool) -> np.ndarray:
+    """Per unit mass: d(kappa, gamma1, gamma2) / d(d1, d2) and / d s."""
+    out = np.zeros(9)
+    _load().ora_unit_dterms(float(d1), float(d2), float(s), float(q), int(inside), _p(out))
+    return out
 
 
 class Tree:
@@ -306,11 +334,14 @@ class Tree:
             raise ValueError("record() the same rays first")
         return np.stack(out, axis=1)
 
-    def grad(self, rx, ry, ga):
+    def grad(self, rx, ry, ga, gk=None, gg=None):
         rx, ry = _f64(rx), _f64(ry)
         ga = np.ascontiguousarray(ga, dtype=np.float64)
         g1, g2 = _f64(ga[:, 0]), _f64(ga[:, 1])
+        k, h1, h2 = _cot(gk, gg)
         out = [np.zeros(self.n) for _ in range(4)]
-        self._lib.ora_tree_grad(self._h, _p(rx), _p(ry), rx.shape[0], _p(g1), _p(g2),
-                                *[_p(o) for o in out])
+        rc = self._lib.ora_tree_grad_kg(self._h, _p(rx), _p(ry), rx.shape[0], _p(g1), _p(g2), _pn(k), _pn(h1),
+                                        _pn(h2), *[_p(o) for o in out])
+        if rc != 0:
+            raise ValueError("the kappa and gamma adjoint is written for Gaussians and point masses")
         return tuple(out)

@@ -27,6 +27,10 @@ extern "C" {
  * Per unit mass; `inside` selects the truncated Gaussian kernel, otherwise the
  * point-mass form.  out: a1 a2 kappa g1 g2 da1/ds da2/ds. */
 void ora_unit_terms(double d1, double d2, double s, double q, int inside, double out[7]);
+/* Per unit mass: derivatives of kappa, gamma1, gamma2 with respect to the
+ * offset (d1, d2) and to s: dk/dd1, dk/dd2, dg1/dd1, dg1/dd2, dg2/dd1,
+ * dg2/dd2, dk/ds, dg1/ds, dg2/ds. */
+void ora_unit_dterms(double d1, double d2, double s, double q, int inside, double out[9]);
 
 /* Lensing potential of one particle per unit mass (point mass: ln r; the
  * truncated Gaussian inside its support: ln(q s) - (Ein(q^2/2) - Ein(u)) / (2C)). */
@@ -56,6 +60,12 @@ int ora_direct_grad(const double* x, const double* y, const double* m, const dou
                     double q, const double* rx, const double* ry, int64_t nr,
                     const double* ga1, const double* ga2,
                     double* dm, double* dx, double* dy, double* ds, int nthreads);
+/* The same for L = sum_r ga_r . alpha_r + gk_r kappa_r + gg_r . gamma_r
+ * (gk, gg1, gg2 nullable: zero). */
+int ora_direct_grad_kg(const double* x, const double* y, const double* m, const double* s, int64_t n,
+                       double q, const double* rx, const double* ry, int64_t nr,
+                       const double* ga1, const double* ga2, const double* gk, const double* gg1,
+                       const double* gg2, double* dm, double* dx, double* dy, double* ds, int nthreads);
 
 /* Smoothing lengths (Sec. 3.1): for each particle the 2D distance to its
  * k-th nearest other particle, by brute force.  Returns -1 unless
@@ -129,6 +139,12 @@ int ora_tree_shoot_frozen(const ora_tree* t, const double* rx, const double* ry,
 int ora_tree_grad(const ora_tree* t, const double* rx, const double* ry, int64_t nr,
                   const double* ga1, const double* ga2,
                   double* dm, double* dx, double* dy, double* ds);
+/* The same for L = sum_r ga_r . alpha_r + gk_r kappa_r + gg_r . gamma_r
+ * (gk, gg1, gg2 nullable).  Gaussian particles and point masses only (-1 for
+ * a tree of NFW halos). */
+int ora_tree_grad_kg(const ora_tree* t, const double* rx, const double* ry, int64_t nr,
+                     const double* ga1, const double* ga2, const double* gk, const double* gg1,
+                     const double* gg2, double* dm, double* dx, double* dy, double* ds);
 
 #ifdef __cplusplus
 }

@@ -420,26 +420,33 @@ static double multipole_psi(const double complex* Q, int p, double w1, double w2
 }
 
 typedef struct {
-    const double* ga; /* cotangent of alpha for the adjoint walk, or NULL */
+    const double* ga; /* cotangents of the ray: alpha (2), kappa, gamma (2) */
     double *dm, *dx, *dy, *ds;
     double complex *Abar, *Bbar;
 } adj_t;
 
 /* particle i enters with weight m_i: forward accumulation, or the adjoint of
- * sign * (its per-unit-mass terms t) */
-static void particle_term(const ora_tree* t, int64_t i, const double tt[7], double sign, double acc[5],
-                          adj_t* adj)
+ * sign * (its per-unit-mass terms t; dt their kappa and gamma derivatives) */
+static void particle_term(const ora_tree* t, int64_t i, const double tt[7], const double dt[9], double sign,
+                          double acc[5], adj_t* adj)
 {
     const double mi = t->m[i];
     if (!adj) {
         for (int k = 0; k < 5; ++k) acc[k] += sign * mi * tt[k];
         return;
     }
-    const double g1 = adj->ga[0], g2 = adj->ga[1];
-    adj->dm[i] += sign * (g1 * tt[0] + g2 * tt[1]);
-    adj->dx[i] -= sign * mi * (g1 * (tt[2] + tt[3]) + g2 * tt[4]);
-    adj->dy[i] -= sign * mi * (g1 * tt[4] + g2 * (tt[2] - tt[3]));
-    adj->ds[i] += sign * mi * (g1 * tt[5] + g2 * tt[6]);
+    const double g1 = adj->ga[0], g2 = adj->ga[1], gk = adj->ga[2], h1 = adj->ga[3], h2 = adj->ga[4];
+    adj->dm[i] += sign * (g1 * tt[0] + g2 * tt[1] + gk * tt[2] + h1 * tt[3] + h2 * tt[4]);
+    adj->dx[i] -= sign * mi * (g1 * (tt[2] + tt[3]) + g2 * tt[4] + gk * dt[0] + h1 * dt[2] + h2 * dt[4]);
+    adj->dy[i] -= sign * mi * (g1 * tt[4] + g2 * (tt[2] - tt[3]) + gk * dt[1] + h1 * dt[3] + h2 * dt[5]);
+    adj->ds[i] += sign * mi * (g1 * tt[5] + g2 * tt[6] + gk * dt[6] + h1 * dt[7] + h2 * dt[8]);
+}
+
+/* kappa and gamma derivatives of particle i (zero unless the adjoint needs them) */
+static void dterms_of(const ora_tree* t, int64_t i, double d1, double d2, int in, const adj_t* adj, double out[9])
+{
+    if (adj && !t->kind) ora_unit_dterms(d1, d2, t->s[i], t->q, in, out);
+    else memset(out, 0, 9 * sizeof(double));
 }
 
 static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5], int64_t cnt[5],
@@ -452,12 +459,14 @@ static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5
         const double d1 = X - t->x[i], d2 = Y - t->y[i];
         cnt[3]++;
         if (decide(tp, inside_of(t, i, d1, d2))) {
-            double te[7], tpnt[7];
+            double te[7], tpnt[7], de[9], dpnt[9];
             cnt[4]++;
             terms_of(t, i, d1, d2, 1, te);
             terms_of(t, i, d1, d2, 0, tpnt);
-            particle_term(t, i, te, 1.0, acc, adj);
-            particle_term(t, i, tpnt, -1.0, acc, adj);
+            dterms_of(t, i, d1, d2, 1, adj, de);
+            dterms_of(t, i, d1, d2, 0, adj, dpnt);
+            particle_term(t, i, te, de, 1.0, acc, adj);
+            particle_term(t, i, tpnt, dpnt, -1.0, acc, adj);
             if (psi)
                 *psi += t->m[i] * (ora_unit_psi(d1, d2, t->s[i], t->q, 1) - ora_unit_psi(d1, d2, t->s[i], t->q, 0));
         }
@@ -470,12 +479,17 @@ static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5
             multipole(Q, t->p, w1, w2, acc);
             if (psi) *psi += multipole_psi(Q, t->p, w1, w2);
         } else {
+            /* L = Re[gh F + gg F'] with F = sum_k Q_k w^-(k+1) = alpha1 - i alpha2,
+             * F' = gamma1 - i gamma2, gh = ga1 + i ga2, gg = gg1 + i gg2; w = z - z_cm, so
+             * dL/dQ_k = gh w^-(k+1) - gg (k+1) w^-(k+2), dL/dz_cm = -(gh F' + gg F'') */
             const double complex w = w1 + I * w2, iw = 1.0 / w;
             const double complex gh = adj->ga[0] + I * adj->ga[1];
+            const double complex gg = adj->ga[3] + I * adj->ga[4];
             double complex pw = iw;
             for (int k = 0; k <= t->p; ++k) {
-                adj->Abar[c * (t->p + 1) + k] += gh * pw;
+                adj->Abar[c * (t->p + 1) + k] += gh * pw - gg * (double)(k + 1) * pw * iw;
                 adj->Bbar[c] += gh * (double)(k + 1) * Q[k] * pw * iw;
+                adj->Bbar[c] -= gg * (double)((k + 1) * (k + 2)) * Q[k] * pw * iw * iw;
                 pw *= iw;
             }
         }
@@ -484,10 +498,11 @@ static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5
             const int64_t j = t->perm[k];
             const double d1 = X - t->x[j], d2 = Y - t->y[j];
             const int in = t->listed_at[j] >= 0 ? 0 : decide(tp, inside_of(t, j, d1, d2));
-            double tt[7];
+            double tt[7], dt[9];
             cnt[2]++;
             terms_of(t, j, d1, d2, in, tt);
-            particle_term(t, j, tt, 1.0, acc, adj);
+            dterms_of(t, j, d1, d2, in, adj, dt);
+            particle_term(t, j, tt, dt, 1.0, acc, adj);
             if (psi) *psi += t->m[j] * ora_unit_psi(d1, d2, t->s[j], t->q, in);
         }
     } else {
@@ -591,6 +606,14 @@ int ora_tree_grad(const ora_tree* t, const double* rx, const double* ry, int64_t
                   const double* ga1, const double* ga2, double* dm, double* dx, double* dy,
                   double* ds)
 {
+    return ora_tree_grad_kg(t, rx, ry, nr, ga1, ga2, NULL, NULL, NULL, dm, dx, dy, ds);
+}
+
+int ora_tree_grad_kg(const ora_tree* t, const double* rx, const double* ry, int64_t nr,
+                     const double* ga1, const double* ga2, const double* gk, const double* gg1,
+                     const double* gg2, double* dm, double* dx, double* dy, double* ds)
+{
+    if (t->kind && (gk || gg1 || gg2)) return -1;
     const int P = t->p + 1;
     adj_t adj;
     double* ds_local = ds ? ds : (double*)malloc((size_t)t->n * sizeof(double));
@@ -607,7 +630,7 @@ int ora_tree_grad(const ora_tree* t, const double* rx, const double* ry, int64_t
     for (int64_t r = 0; r < nr; ++r) {
         double acc[5] = {0, 0, 0, 0, 0};
         int64_t cnt[5] = {0, 0, 0, 0, 0};
-        double g[2] = {ga1[r], ga2[r]};
+        double g[5] = {ga1[r], ga2[r], gk ? gk[r] : 0.0, gg1 ? gg1[r] : 0.0, gg2 ? gg2[r] : 0.0};
         adj.ga = g;
         visit(t, 0, rx[r], ry[r], acc, cnt, NULL, &adj, NULL);
     }
