@@ -241,20 +241,25 @@ GLM_API glm_status glm_shoot_direct_nfw(const double* x, const double* y, const 
                                 int64_t nrays, int fp64, void* const out5[5], void* stream);
 
 /*
- * Adjoint of glm_shoot for L with cotangents ga1 = dL/dalpha1, ga2 = dL/dalpha2
- * (device FP32, length nrays, input order).  Replays the forward walk's
- * decisions on the same tree and rays, and ACCUMULATES (+=) into the device
- * FP64 arrays (original particle order, length n): dm, dx, dy, ds (each
- * nullable; ds is zero for point masses).  Moment contributions are pushed
- * down from boxes to particles through dQ_k/dm_i, dQ_k/dz_i and dz_cm.
- * Uses FP64 atomics: results are reproducible to rounding, not bitwise.
+ * Adjoint of glm_shoot for L with cotangents ga1 = dL/dalpha1, ga2 = dL/dalpha2,
+ * gk = dL/dkappa, gg1 = dL/dgamma1, gg2 = dL/dgamma2 (device FP32, length
+ * nrays, input order; each may be NULL, meaning zero, but not all five).
+ * Replays the forward walk's decisions on the same tree and rays, and
+ * ACCUMULATES (+=) into the device FP64 arrays (original particle order,
+ * length n): dm, dx, dy, ds (each nullable; ds is zero for point masses).
+ * Moment contributions are pushed down from boxes to particles through
+ * dQ_k/dm_i, dQ_k/dz_i and dz_cm (kappa has no box term; gamma1 - i gamma2 of
+ * a box is the derivative of its alpha1 - i alpha2 series).  Uses FP64
+ * atomics: results are reproducible to rounding, not bitwise.  Trees of
+ * GLM_NFW_HALOS are refused (GLM_ESTATE).
  *   workspace: at least glm_shoot_workspace_bytes(nrays); the scratch for
  *   box adjoints and per-particle sums is device memory the handle owns.
  */
 GLM_API glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* ry,
-                             int64_t nrays, const float* ga1, const float* ga2, double* dm,
-                             double* dx, double* dy, double* ds, uint32_t flags, void* workspace,
-                             size_t workspace_bytes, void* stream);
+                             int64_t nrays, const float* ga1, const float* ga2, const float* gk,
+                             const float* gg1, const float* gg2, double* dm, double* dx, double* dy,
+                             double* ds, uint32_t flags, void* workspace, size_t workspace_bytes,
+                             void* stream);
 
 /* One lens of a batched walk. */
 typedef struct {

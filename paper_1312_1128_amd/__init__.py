@@ -217,14 +217,15 @@ def shoot_direct(x, y, m, s, q, rx, ry, fp64: bool = False, alpha_only: bool = F
 
 
 def shoot_adjoint(tree: Tree, rx, ry, ga1, ga2, dm=None, dx=None, dy=None, ds=None, ordered: bool = False,
-                  workspace=None):
+                  workspace=None, gk=None, gg1=None, gg2=None):
     """Adjoint walk: accumulates dL/d(m, x, y, s) (float64, original particle
-    order) for cotangents ga = dL/dalpha (float32).  Returns (dm, dx, dy, ds)."""
+    order) for cotangents ga = dL/dalpha and optionally gk = dL/dkappa,
+    gg = dL/dgamma (float32; any may be None).  Returns (dm, dx, dy, ds)."""
     rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
     R = rx.shape[0]
     dev = rx.device
-    ga1 = ga1.to(torch.float32).contiguous()
-    ga2 = ga2.to(torch.float32).contiguous()
+    f32 = lambda t: t.to(torch.float32).contiguous() if t is not None else None
+    ga1, ga2, gk, gg1, gg2 = f32(ga1), f32(ga2), f32(gk), f32(gg1), f32(gg2)
     n = tree.n
     dm = torch.zeros(n, dtype=torch.float64, device=dev) if dm is None else dm
     dx = torch.zeros(n, dtype=torch.float64, device=dev) if dx is None else dx
@@ -235,30 +236,35 @@ def shoot_adjoint(tree: Tree, rx, ry, ga1, ga2, dm=None, dx=None, dy=None, ds=No
     ws_bytes = workspace.numel()
     flags = GLM_RAYS_ORDERED if ordered else 0
     lib = _capi.load()
-    _capi.check(lib.glm_shoot_adjoint(tree.handle, _ptr(rx), _ptr(ry), R, _ptr(ga1), _ptr(ga2), _ptr(dm), _ptr(dx),
-                                      _ptr(dy), _ptr(ds), flags, _ptr(workspace), ws_bytes, _stream()))
+    _capi.check(lib.glm_shoot_adjoint(tree.handle, _ptr(rx), _ptr(ry), R, _ptr(ga1), _ptr(ga2), _ptr(gk), _ptr(gg1),
+                                      _ptr(gg2), _ptr(dm), _ptr(dx), _ptr(dy), _ptr(ds), flags, _ptr(workspace),
+                                      ws_bytes, _stream()))
     return dm, dx, dy, ds
 
 
 class ShootFn(torch.autograd.Function):
-    """alpha(rays; m, x, y, s) through the tree, differentiable in the particle
-    masses, positions and smoothing lengths (the tree topology and every walk
-    decision are those of the forward call)."""
+    """alpha(rays; m, x, y, s) through the tree -- or (a1, a2, kappa, g1, g2)
+    with lensing=True -- differentiable in the particle masses, positions and
+    smoothing lengths (the tree topology and every walk decision are those of
+    the forward call)."""
 
     @staticmethod
-    def forward(ctx, rx, ry, m, x, y, s, params: dict):
+    def forward(ctx, rx, ry, m, x, y, s, params: dict, lensing: bool = False):
         tree = Tree().build(x.detach(), y.detach(), m.detach(), s.detach() if s is not None else None, **params)
-        out = shoot(tree, rx, ry, alpha_only=True)
+        out = shoot(tree, rx, ry, alpha_only=not lensing)
         ctx.tree = tree
         ctx.save_for_backward(rx, ry)
         ctx.has_s = s is not None
+        ctx.lensing = lensing
+        if lensing:
+            return out["a1"], out["a2"], out["kappa"], out["g1"], out["g2"]
         return out["a1"], out["a2"]
 
     @staticmethod
-    def backward(ctx, g1, g2):
+    def backward(ctx, g1, g2, gk=None, gg1=None, gg2=None):
         rx, ry = ctx.saved_tensors
-        dm, dx, dy, ds = shoot_adjoint(ctx.tree, rx, ry, g1, g2)
-        return None, None, dm, dx, dy, (ds if ctx.has_s else None), None
+        dm, dx, dy, ds = shoot_adjoint(ctx.tree, rx, ry, g1, g2, gk=gk, gg1=gg1, gg2=gg2)
+        return None, None, dm, dx, dy, (ds if ctx.has_s else None), None, None
 
 
 from .batch import (RefinementRun, autotune, interp_init, refine_interp_round, refine_round,  # noqa: E402

@@ -90,7 +90,7 @@ def load(path: str = LIB_PATH):
     lib.glm_shoot_direct.restype = st
     lib.glm_shoot_direct_nfw.argtypes = [vp, vp, vp, vp, i64, ctypes.c_double, vp, vp, i64, i32, P(vp), vp]
     lib.glm_shoot_direct_nfw.restype = st
-    lib.glm_shoot_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp]
+    lib.glm_shoot_adjoint.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp]
     lib.glm_shoot_adjoint.restype = st
     lib.glm_shoot_batched_workspace_bytes.argtypes = [P(ctypes.c_int64), i32, P(ctypes.c_size_t)]
     lib.glm_shoot_batched_workspace_bytes.restype = st

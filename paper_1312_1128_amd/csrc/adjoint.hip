@@ -1,7 +1,7 @@
 // Adjoint of the forward tree walk: dL/d(m, x, y, s) of the particles for
-// cotangents ga = dL/dalpha of the rays, on the frozen topology and decisions
-// of the forward walk (the same traversal runs again and takes the same FP64
-// decisions).
+// cotangents ga = dL/dalpha of the rays, and optionally gk = dL/dkappa and
+// gg = dL/dgamma, on the frozen topology and decisions of the forward walk
+// (the same traversal runs again and takes the same FP64 decisions).
 //
 // Direct terms (leaf particles, big-particle corrections) give particle
 // gradients directly:
@@ -12,7 +12,17 @@
 // with g_hat = ga1 + i ga2 the walk accumulates per box
 //   Abar_k r_cm^k = sum_r g_hat v t^k   (v = 1/w, t = r_cm v)
 //   Bbar          = sum_r g_hat M v^2 (P(t) + t P'(t))     (= g_hat dF/dz_cm)
-// and a push-down pass gives every particle its share through
+// A gamma cotangent adds, with gg_hat = gg1 + i gg2 (gamma1 - i gamma2 = F'(w)),
+//   Abar_k r_cm^k -= (k + 1) gg_hat v^2 t^k,   Bbar -= gg_hat F''(w) = gg_hat M v^3 T(t),
+//   T(t) = sum (k+1)(k+2) Qn_k t^k;  kappa gets nothing from a box.
+// Direct terms of a circular profile, with u = r^2, A = alpha / d, kappa(u):
+//   gamma1 - i gamma2 = a conj(w)^2,  a = (kappa - A)/u,  b = u A'' = dkappa/du - 2a,
+//   d kappa / d d_j = 2 (dkappa/du) d_j,
+//   d gamma1/d d1 = 2 d1 (b c + a), d gamma1/d d2 = 2 d2 (b c - a),
+//   d gamma2/d d1 = 2 d2 (b (1 + c) + a), d gamma2/d d2 = 2 d1 (b (1 - c) + a),  c = cos 2phi;
+// for the Gaussian a = -m h^2 (Gam-series / x) (no cancellation at small x = h u),
+// dkappa/du = -h kappa, d kappa/ds - dA/ds = m e^-x x / (C s^3).
+// A push-down pass gives every particle its share through
 //   dQ_k/dm_i = d^k - k Q_{k-1} d / M,  dQ_k/dz_i = k m_i d^(k-1) - k Q_{k-1} m_i / M,
 //   dz_cm/dm_i = d / M,  dz_cm/dz_i = m_i / M  (d = z_i - z_cm; all holomorphic).
 // Per-lane terms are reduced across the wavefront before one FP64 atomic per
@@ -27,14 +37,36 @@ namespace glm {
 
 namespace {
 
+// Cotangents of one ray: alpha (g1, g2), kappa (k), gamma (h1, h2).
+struct Cot {
+    float g1, g2, k, h1, h2;
+};
+
+// kappa and gamma part of a term's gradient, per unit mass (m, then d/d d1,
+// d/d d2 of L, the s part separately): kap = kappa, Am = A = alpha / d,
+// dk = dkappa/du, a = (kappa - A) / u.
+__device__ inline void kg_grad(const Cot& cg, float f1, float f2, float ir2, float kap, float a, float dk, float* em,
+                               float* e1, float* e2)
+{
+    const float c = (f1 * f1 - f2 * f2) * ir2, sn = 2.0f * f1 * f2 * ir2;
+    const float b = dk - 2.0f * a;
+    const float u = (f1 * f1 + f2 * f2);
+    // gamma1 = a (d1^2 - d2^2) = a u c, gamma2 = a u sn
+    *em = cg.k * kap + (cg.h1 * c + cg.h2 * sn) * (a * u);
+    *e1 = 2.0f * (cg.k * dk * f1 + cg.h1 * f1 * fmaf(b, c, a) + cg.h2 * f2 * fmaf(b, 1.0f + c, a));
+    *e2 = 2.0f * (cg.k * dk * f2 + cg.h1 * f2 * fmaf(b, c, -a) + cg.h2 * f1 * fmaf(b, 1.0f - c, a));
+}
+
 // Gradient terms of one particle for this lane, per the same cases as the
 // forward's leaf_particle and list_particle.  Returns FP64 (m, x, y, s) contributions in G.
 // mode 0: leaf sum; mode 1: big-particle correction (Gaussian - point).
-__device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mode, bool act, float g1, float g2,
+template <bool KG>
+__device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mode, bool act, const Cot& cg,
                                      float invC, double G[4])
 {
     G[0] = G[1] = G[2] = G[3] = 0.0;
     if (!act) return false;
+    const float g1 = cg.g1, g2 = cg.g2;
     double d1, d2;
     const double r2 = sqdist(X, Y, pr.x, pr.y, &d1, &d2);
     const bool inside = r2 < pr.qs2;
@@ -46,9 +78,17 @@ __device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mod
     // point mass, per unit mass: alpha = d / r^2, gamma = -(cos 2phi, sin 2phi) / r^2, kappa = 0
     float P[4];
     point_terms(1.0f, f1, f2, ir2, P);
-    const float pm_m = g1 * P[0] + g2 * P[1];
-    const float pm_x = -(g1 * P[2] + g2 * P[3]) * pr.m;
-    const float pm_y = -(g1 * P[3] - g2 * P[2]) * pr.m;
+    float pm_m = g1 * P[0] + g2 * P[1];
+    float pm_x = -(g1 * P[2] + g2 * P[3]) * pr.m;
+    float pm_y = -(g1 * P[3] - g2 * P[2]) * pr.m;
+    if constexpr (KG) {
+        // point mass: kappa = 0, A = 1/u, a = -1/u^2, dkappa/du = 0
+        float km, k1, k2;
+        kg_grad(cg, f1, f2, ir2, 0.0f, -(ir2 * ir2), 0.0f, &km, &k1, &k2);
+        pm_m += km;
+        pm_x -= k1 * pr.m;
+        pm_y -= k2 * pr.m;
+    }
     const bool gauss = inside && !(mode == 0 && listed);
     if (!gauss) { // point mass (a listed+inside point pairs with the list box's -point)
         G[0] = (double)pm_m;
@@ -64,11 +104,33 @@ __device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mod
     const float Ku = hu * e;
     const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = 2.0f * f1 * f2 * ir2;
     const float ga1 = -Gu * c2, ga2 = -Gu * s2; // gamma per unit mass
-    const float em = Au * gd;
-    const float ex = -(g1 * (Ku + ga1) + g2 * ga2) * pr.m;
-    const float ey = -(g1 * ga2 + g2 * (Ku - ga1)) * pr.m;
+    float em = Au * gd;
+    float ex = -(g1 * (Ku + ga1) + g2 * ga2) * pr.m;
+    float ey = -(g1 * ga2 + g2 * (Ku - ga1)) * pr.m;
     // d alpha / d s = -m d e^-u / (s^3 C), 1/s^3 = 2h sqrt(2h)
-    const float es = -pr.m * hu * e * 2.0f * __builtin_sqrtf(2.0f * pr.h) * gd;
+    float es = -pr.m * hu * e * 2.0f * __builtin_sqrtf(2.0f * pr.h) * gd;
+    if constexpr (KG) {
+        // a = -Gam / u with Gam = hu * sd(x), x = u_gauss: a = -hu * h * sd(x) / x
+        float sdx;
+        if (u < 0.5f) {
+            sdx = 1.0f / 2 + u * (-1.0f / 3 + u * (1.0f / 8 + u * (-1.0f / 30 + u * (1.0f / 144 + u * (-1.0f / 840 + u * (1.0f / 5760 + u * (-1.0f / 45360 + u * (1.0f / 403200))))))));
+        } else {
+            const float iu = __builtin_amdgcn_rcpf(u);
+            sdx = ((1.0f - e) * iu - e) * iu;
+        }
+        const float a = -hu * pr.h * sdx;
+        const float dk = -pr.h * Ku;
+        float km, k1, k2;
+        kg_grad(cg, f1, f2, ir2, Ku, a, dk, &km, &k1, &k2);
+        em += km;
+        ex -= k1 * pr.m;
+        ey -= k2 * pr.m;
+        // d/ds: kappa_s and (kappa_s - A_s) = invC e x / s^3 (per unit mass)
+        const float is3 = 2.0f * pr.h * __builtin_sqrtf(2.0f * pr.h);
+        const float ks = invC * e * (u - 1.0f) * is3;
+        const float gs = invC * e * u * is3;
+        es += pr.m * (cg.k * ks + (cg.h1 * c2 + cg.h2 * s2) * gs);
+    }
     if (mode == 1) {
         G[0] = (double)em - (double)pm_m;
         G[1] = (double)ex - (double)pm_x;
@@ -107,13 +169,17 @@ __device__ inline void add_particle(const double S[4], uint32_t meta, double* __
     if (lane < 4) unsafeAtomicAdd(pg + 4 * (size_t)(meta & 0x7fffffffu) + lane, mine);
 }
 
-template <int P>
+// Cotangent arrays of the rays (input order); any may be NULL (zero).
+struct CotIn {
+    const float *ga1, *ga2, *gk, *gg1, *gg2;
+};
+
+template <int P, bool KG>
 __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double* __restrict__ rxs,
                                                         const double* __restrict__ rys,
                                                         const uint32_t* __restrict__ rperm, int64_t nrays,
-                                                        const float* __restrict__ ga1, const float* __restrict__ ga2,
-                                                        double* __restrict__ pg, double* __restrict__ abar, int K,
-                                                        const int* __restrict__ split_box)
+                                                        CotIn ci, double* __restrict__ pg, double* __restrict__ abar,
+                                                        int K, const int* __restrict__ split_box)
 {
     constexpr int NA = 2 * (P + 1) + 2; // (Re, Im) of Abar_0..Abar_P, Bbar
     const int lane = threadIdx.x & (kWave - 1);
@@ -127,7 +193,17 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
     const bool valid = r < nrays;
     const double X = valid ? rxs[r] : 0.0, Y = valid ? rys[r] : 0.0;
     const int64_t o = valid ? (rperm ? (int64_t)rperm[r] : r) : 0;
-    const float g1 = valid ? ga1[o] : 0.0f, g2 = valid ? ga2[o] : 0.0f;
+    Cot cg{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (valid) {
+        cg.g1 = ci.ga1 ? ci.ga1[o] : 0.0f;
+        cg.g2 = ci.ga2 ? ci.ga2[o] : 0.0f;
+        if constexpr (KG) {
+            cg.k = ci.gk ? ci.gk[o] : 0.0f;
+            cg.h1 = ci.gg1 ? ci.gg1[o] : 0.0f;
+            cg.h2 = ci.gg2 ? ci.gg2[o] : 0.0f;
+        }
+    }
+    const float g1 = cg.g1, g2 = cg.g2;
     const double gx0 = wave_min(valid ? X : INFINITY), gx1 = wave_max(valid ? X : -INFINITY);
     const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
     const float invC = T.invC;
@@ -167,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                     const int k = __ffsll((unsigned long long)cm) - 1;
                     cm &= cm - 1;
                     const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
-                    const bool hit = particle_grad(pr, X, Y, 1, act, g1, g2, invC, G);
+                    const bool hit = particle_grad<KG>(pr, X, Y, 1, act, cg, invC, G);
                     if (__any(hit)) {
                         double S[4];
                         particle_sums(G, true, S);
@@ -228,6 +304,34 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 const float V1 = M * fmaf(w21, S1, -w22 * S2), V2 = M * fmaf(w21, S2, w22 * S1);
                 a[NA - 2] = g1 * V1 - g2 * V2;
                 a[NA - 1] = g1 * V2 + g2 * V1;
+                if constexpr (KG) {
+                    // gamma: Abar_k r_cm^k -= (k+1) gg v^2 t^k, Bbar -= gg M v^3 T(t)
+                    const float h1 = cg.h1, h2 = cg.h2;
+                    float q1 = fmaf(h1, w21, -h2 * w22), q2 = fmaf(h1, w22, h2 * w21); // gg v^2
+#pragma unroll
+                    for (int k = 0; k <= P; ++k) {
+                        a[2 * k] -= (float)(k + 1) * q1;
+                        a[2 * k + 1] -= (float)(k + 1) * q2;
+                        const float n1 = fmaf(q1, t1, -q2 * t2), n2 = fmaf(q1, t2, q2 * t1);
+                        q1 = n1;
+                        q2 = n2;
+                    }
+                    // T(t) = sum_k (k+1)(k+2) Qn_k t^k by Horner (Qn_0 = 1, Qn_1 = 0)
+                    float T1 = 0.0f, T2 = 0.0f;
+#pragma unroll
+                    for (int k = P; k >= 0; --k) {
+                        const float cf = (float)((k + 1) * (k + 2));
+                        const float q1k = k >= 2 ? cf * mo[2 + 2 * (k - 2)] : (k == 0 ? cf : 0.0f);
+                        const float q2k = k >= 2 ? cf * mo[3 + 2 * (k - 2)] : 0.0f;
+                        const float n1 = fmaf(T1, t1, fmaf(-T2, t2, q1k)), n2 = fmaf(T1, t2, fmaf(T2, t1, q2k));
+                        T1 = n1;
+                        T2 = n2;
+                    }
+                    const float w31 = fmaf(w21, v1, -w22 * v2), w32 = fmaf(w21, v2, w22 * v1); // v^3
+                    const float U1 = M * fmaf(w31, T1, -w32 * T2), U2 = M * fmaf(w31, T2, w32 * T1);
+                    a[NA - 2] -= h1 * U1 - h2 * U2;
+                    a[NA - 1] -= h1 * U2 + h2 * U1;
+                }
             }
             wave_sum_n<NA>(a);
             // lane k adds total k: one atomic instruction over NA adjacent words
@@ -241,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 const CellExt e = T.ext[cur];
                 for (int j = e.pbeg; j < e.pend; ++j) {
                     const PRec pr = T.prt[j];
-                    const bool hit = particle_grad(pr, X, Y, 0, opn, g1, g2, invC, G);
+                    const bool hit = particle_grad<KG>(pr, X, Y, 0, opn, cg, invC, G);
                     const bool any_s = __any(hit && G[3] != 0.0);
                     double S[4];
                     particle_sums(G, any_s, S);
@@ -346,8 +450,8 @@ __global__ void k_fill_zero(double* p, int64_t n)
 }
 
 template <int P>
-glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, const float* ga1, const float* ga2,
-                          double* dm, double* dx, double* dy, double* ds, int K, const int* split_box, hipStream_t st)
+glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, const CotIn& ci, double* dm,
+                          double* dx, double* dy, double* ds, int K, const int* split_box, hipStream_t st)
 {
     constexpr int NA = 2 * (P + 1) + 2;
     // scratch: box adjoints (NA per box), then 4 direct-term gradients per particle
@@ -358,8 +462,12 @@ glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, 
     double* pg = abar + (size_t)ts.ncells * NA;
     hipLaunchKernelGGL(k_fill_zero, dim3(ceil_div((int64_t)words, kBlock)), dim3(kBlock), 0, st, abar, (int64_t)words);
     const int64_t blocks = walk_grid_blocks((nrays + kWave - 1) / kWave, K);
-    hipLaunchKernelGGL((k_adjoint_walk<P>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ts.dev, sr.xs,
-                       sr.ys, sr.perm, nrays, ga1, ga2, pg, abar, K, split_box);
+    if (ci.gk || ci.gg1 || ci.gg2)
+        hipLaunchKernelGGL((k_adjoint_walk<P, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ts.dev, sr.xs,
+                           sr.ys, sr.perm, nrays, ci, pg, abar, K, split_box);
+    else
+        hipLaunchKernelGGL((k_adjoint_walk<P, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ts.dev, sr.xs,
+                           sr.ys, sr.perm, nrays, ci, pg, abar, K, split_box);
     hipLaunchKernelGGL((k_pushdown<P>), dim3(ceil_div(ts.n, kBlock)), dim3(kBlock), 0, st, ts.dev, ts.ms, abar, pg, dm,
                        dx, dy, ds);
     GLM_HIP(hipGetLastError());
@@ -369,8 +477,8 @@ glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, 
 } // namespace
 
 glm_status adjoint_device(TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, const float* ga1,
-                          const float* ga2, double* dm, double* dx, double* dy, double* ds, uint32_t flags, void* ws,
-                          hipStream_t st)
+                          const float* ga2, const float* gk, const float* gg1, const float* gg2, double* dm,
+                          double* dx, double* dy, double* ds, uint32_t flags, void* ws, hipStream_t st)
 {
     if (nrays == 0) return GLM_OK;
     StagedRays sr{rx, ry, nullptr};
@@ -388,7 +496,7 @@ glm_status adjoint_device(TreeStorage& ts, const double* rx, const double* ry, i
         if (rc != GLM_OK) return rc;
     }
 #define GLM_CASE(PP) \
-    case PP: return launch_adjoint<PP>(ts, sr, nrays, ga1, ga2, dm, dx, dy, ds, K, split_box, st);
+    case PP: return launch_adjoint<PP>(ts, sr, nrays, CotIn{ga1, ga2, gk, gg1, gg2}, dm, dx, dy, ds, K, split_box, st);
     switch (ts.params.order) {
         GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
         GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)

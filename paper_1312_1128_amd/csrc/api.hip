@@ -268,14 +268,16 @@ glm_status glm_shoot_direct_nfw(const double* x, const double* y, const double* 
 }
 
 glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* ry, int64_t nrays, const float* ga1,
-                             const float* ga2, double* dm, double* dx, double* dy, double* ds, uint32_t flags,
-                             void* workspace, size_t workspace_bytes, void* stream)
+                             const float* ga2, const float* gk, const float* gg1, const float* gg2, double* dm,
+                             double* dx, double* dy, double* ds, uint32_t flags, void* workspace,
+                             size_t workspace_bytes, void* stream)
 {
     if (!t) return fail(GLM_EINVAL, "tree handle is NULL");
     if (!t->ts.built) return fail(GLM_ESTATE, "tree not built");
     if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays out of range");
     if (nrays == 0) return GLM_OK;
-    if (!rx || !ry || !ga1 || !ga2) return fail(GLM_EINVAL, "rx, ry, ga1, ga2 must be device pointers");
+    if (!rx || !ry) return fail(GLM_EINVAL, "rx, ry must be device pointers");
+    if (!ga1 && !ga2 && !gk && !gg1 && !gg2) return fail(GLM_EINVAL, "every cotangent is NULL");
     if (flags & ~(GLM_NO_KAHAN | GLM_RAYS_ORDERED | GLM_ALPHA_ONLY)) return fail(GLM_EINVAL, "unknown flag bits");
     if (t->ts.dev.kind != kKindGauss) return fail(GLM_ESTATE, "the adjoint walk is for Gaussian particles and point masses");
     {
@@ -283,8 +285,8 @@ glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* 
         if (!workspace || workspace_bytes < need)
             return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_workspace_bytes(nrays) = " + std::to_string(need));
     }
-    return adjoint_device(const_cast<glm_tree*>(t)->ts, rx, ry, nrays, ga1, ga2, dm, dx, dy, ds, flags, workspace,
-                          static_cast<hipStream_t>(stream));
+    return adjoint_device(const_cast<glm_tree*>(t)->ts, rx, ry, nrays, ga1, ga2, gk, gg1, gg2, dm, dx, dy, ds, flags,
+                          workspace, static_cast<hipStream_t>(stream));
 }
 
 glm_status glm_shoot_batched_workspace_bytes(const int64_t* nrays, int nlens, size_t* bytes)

@@ -134,8 +134,9 @@ glm_status direct_device(const double* x, const double* y, const double* m, cons
                          int kind, const double* rx, const double* ry, int64_t nrays, int fp64, void* const out5[5],
                          hipStream_t st);
 
+// Cotangents: ga1, ga2 = dL/dalpha, gk = dL/dkappa, gg1, gg2 = dL/dgamma (each nullable: zero).
 glm_status adjoint_device(TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, const float* ga1,
-                          const float* ga2, double* dm, double* dx, double* dy, double* ds, uint32_t flags, void* ws,
-                          hipStream_t st);
+                          const float* ga2, const float* gk, const float* gg1, const float* gg2, double* dm,
+                          double* dx, double* dy, double* ds, uint32_t flags, void* ws, hipStream_t st);
 
 } // namespace glm

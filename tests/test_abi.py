@@ -64,7 +64,7 @@ def test_host_validation(lib):
     # an unbuilt tree cannot be walked
     rc = lib.glm_shoot(h, buf, buf, 4, buf, buf, buf, buf, buf, None, 0, None, 0, None)
     assert rc == _capi.GLM_ESTATE
-    rc = lib.glm_shoot_adjoint(h, buf, buf, 4, buf, buf, None, None, None, None, 0, None, 0, None)
+    rc = lib.glm_shoot_adjoint(h, buf, buf, 4, buf, buf, None, None, None, None, None, None, None, 0, None, 0, None)
     assert rc == _capi.GLM_ESTATE
     info = _capi.GlmTreeInfo()
     assert lib.glm_tree_get_info(h, ctypes.byref(info)) == _capi.GLM_ESTATE
