@@ -278,6 +278,29 @@ def main():
         fa_ms = 1e3 * (time.perf_counter() - t) / n5
         log(f"fwd+adjoint (1e5 particles, 1e5 rays): {fa_ms:.3f} ms -> {rx5.numel() / (fa_ms * 1e-3):.4e} rays/s")
 
+        # the same with kappa and gamma in the loss: L += sum (kappa - 1/2)^2 + |gamma|^2
+        out5k = {k: torch.empty(rx5.numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2", "kappa", "g1", "g2"]}
+
+        def step5kg():
+            tree5.build(x5, y5, m5, s5, theta=THETA, q=lens5.q, leaf_size=LEAF, order=ORDER)
+            g.shoot(tree5, rx5, ry5, out=out5k, workspace=ws5)
+            ga1 = (-2.0 * (rx5 - out5k["a1"] - bx5)).float()
+            ga2 = (-2.0 * (ry5 - out5k["a2"] - by5)).float()
+            for t_ in grads5:
+                t_.zero_()
+            g.shoot_adjoint(tree5, rx5, ry5, ga1, ga2, *grads5, workspace=ws5, gk=2.0 * (out5k["kappa"] - 0.5),
+                            gg1=2.0 * out5k["g1"], gg2=2.0 * out5k["g2"])
+
+        for _ in range(2):
+            step5kg()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n5):
+            step5kg()
+        torch.cuda.synchronize()
+        fak_ms = 1e3 * (time.perf_counter() - t) / n5
+        log(f"fwd+adjoint with kappa and gamma in the loss: {fak_ms:.3f} ms -> {rx5.numel() / (fak_ms * 1e-3):.4e} rays/s")
+
         # microlensing refinement: halo + 1e5 stars, 256^2 base cells over the star
         # patch, 6 rounds refining the top 10% by 3x3, all rounds in one HIP graph
         lens3, cx3, cy3, side3 = synth.workload_microlensing()
@@ -419,6 +442,8 @@ def main():
                   "knn_from_positions_ms": knn_pos,
                   "fwd_adjoint_rays_per_s": rx5.numel() / (fa_ms * 1e-3), "fwd_adjoint_ms": fa_ms,
                   "fwd_adjoint_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2",
+                  "fwd_adjoint_kappa_gamma_ms": fak_ms,
+                  "fwd_adjoint_kappa_gamma_rays_per_s": rx5.numel() / (fak_ms * 1e-3),
                   "refinement_rays": n3, "refinement_graph_ms": 1e3 * graph3_s, "refinement_eager_ms": 1e3 * eager3,
                   "refinement_rays_per_s": n3 / graph3_s,
                   "refinement_workload": "nfw_1e6 + 1e5 Salpeter stars, 256^2 base, 6 rounds top-10% 3x3",
