@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
         cur = __builtin_amdgcn_readfirstlane(cur);
         const CellHdr h = T.hdr[cur];
         const bool act = cur >= skip;
-        if (h.info & kInfoList) {
+        if ((h.info & kInfoList) && list_reaches(T, cur, gx0, gx1, gy0, gy1)) {
             const CellExt e = T.ext[cur];
             for (int base = e.lbeg; base < e.lend; base += kWave) {
                 const int j = base + lane;

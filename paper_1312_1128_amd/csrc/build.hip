@@ -404,6 +404,30 @@ __global__ __launch_bounds__(kBlock) void k_list_ranges(int n, const uint32_t* _
     lst[k] = r;
 }
 
+// Reach of each box's big-particle list: the bounding box of its particles'
+// supports, widened by far more than the rounding of any distance test, so
+// that a ray group whose bounding box misses it cannot be inside any of them.
+__global__ __launch_bounds__(kBlock) void k_list_reach(BoxArrays b, int ncells, const PRec* __restrict__ lst,
+                                                      double* __restrict__ lreach)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncells) return;
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (int k = b.lbeg[c]; k < b.lend[c]; ++k) {
+        const PRec pr = lst[k];
+        const double r = sqrt(pr.qs2) * (1.0 + 4e-9);
+        const double mx = r + 4.5e-16 * fabs(pr.x), my = r + 4.5e-16 * fabs(pr.y);
+        x0 = fmin(x0, pr.x - mx);
+        x1 = fmax(x1, pr.x + mx);
+        y0 = fmin(y0, pr.y - my);
+        y1 = fmax(y1, pr.y + my);
+    }
+    lreach[4 * (size_t)c + 0] = x0;
+    lreach[4 * (size_t)c + 1] = x1;
+    lreach[4 * (size_t)c + 2] = y0;
+    lreach[4 * (size_t)c + 3] = y1;
+}
+
 // ---------------------------------------------------------------- moments
 
 // Binomial coefficient C(n, k) (exact in FP64 for n <= 12); folds to a
@@ -697,6 +721,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     const size_t o_ext = ca.take(sizeof(CellExt) * (size_t)nc);
     const size_t o_mom = ca.take(4ull * stride * nc);
     const size_t o_levidx = ca.take(4ull * nc);
+    const size_t o_lreach = ca.take(32ull * nc);
     rc = ts.cbuf.ensure(ca.size);
     if (rc != GLM_OK) return rc;
     char* C0 = ts.cbuf.as<char>();
@@ -718,6 +743,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     CellExt* ext = reinterpret_cast<CellExt*>(C0 + o_ext);
     float* mom = reinterpret_cast<float*>(C0 + o_mom);
     int32_t* levidx = reinterpret_cast<int32_t*>(C0 + o_levidx);
+    double* lreach = reinterpret_cast<double*>(C0 + o_lreach);
     LevelTable lt;
     {
         int off = 0;
@@ -752,6 +778,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     const int lw = radix_sort_u32(lk0, lv0, lk1, lv1, n, passes, hist, st);
     hipLaunchKernelGGL(k_list_ranges, dim3(gb), dim3(kBlock), 0, st, n, lw ? lk1 : lk0, lw ? lv1 : lv0, unlisted, xs,
                        ys, ms, ss, kind, q, norm, b, lst, sync);
+    hipLaunchKernelGGL(k_list_reach, dim3(gc), dim3(kBlock), 0, st, b, nc, lst, lreach);
     for (int l = kMaxLevel; l >= 0; --l)
         if (lt.cnt[l] > 0) {
             const dim3 g(ceil_div(lt.cnt[l], kBlock)), blk(kBlock);
@@ -791,6 +818,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     ts.dev.cbeg = b.beg;
     ts.dev.cend = b.end;
     ts.dev.perm = reinterpret_cast<int32_t*>(perm);
+    ts.dev.lreach = lreach;
     ts.dev.ncells = nc;
     ts.dev.n = n;
     ts.dev.nlisted = -1; // read on demand (sync->nlisted)

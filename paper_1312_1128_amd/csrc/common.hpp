@@ -75,6 +75,7 @@ struct TreeDev {
     const int32_t* cbeg;    // box particle range (Morton order)
     const int32_t* cend;
     const int32_t* perm;    // Morton position -> original index
+    const double* lreach;   // per box with a list: x0, x1, y0, y1 of the union of its list particles' supports
     int32_t ncells;
     int32_t n;
     int32_t nlisted;

@@ -385,6 +385,14 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
     }
 }
 
+// Whether some ray of the group (bounding box [gx0, gx1] x [gy0, gy1]) can
+// lie inside a particle of box c's big-particle list (see the list reach).
+__device__ inline bool list_reaches(const TreeDev& T, int c, double gx0, double gx1, double gy0, double gy1)
+{
+    const double* lr = T.lreach + 4 * (size_t)c;
+    return !(gx1 < lr[0] || gx0 > lr[1] || gy1 < lr[2] || gy0 > lr[3]);
+}
+
 // The walk of a preorder range [c0, c1) of boxes: every ancestor of a box in
 // the range is either in the range or an ancestor of c0.  A lane that accepts
 // an ancestor of c0 skips that ancestor's whole subtree; returns the preorder

@@ -52,7 +52,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
         const CellHdr h = T.hdr[cur];
         const bool act = cur >= skip;
         if constexpr (STATS) n_vis += act;
-        if (h.info & kInfoList) {
+        if ((h.info & kInfoList) && list_reaches(T, cur, gx0, gx1, gy0, gy1)) {
             const CellExt e = T.ext[cur];
             for (int base = e.lbeg; base < e.lend; base += kWave) {
                 const int j = base + lane;
