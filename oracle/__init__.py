@@ -68,6 +68,11 @@ def _load():
     lib.ora_tree_build_nfw.restype = vp
     lib.ora_tree_shoot_psi.restype = ctypes.c_int
     lib.ora_unit_psi.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int]
+    lib.ora_nfw_H.argtypes = [ctypes.c_double]
+    lib.ora_nfw_H.restype = ctypes.c_double
+    lib.ora_nfw_psi.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int]
+    lib.ora_nfw_psi.restype = ctypes.c_double
+    lib.ora_direct_nfw_psi.argtypes = [d, d, d, d, i64, ctypes.c_double, d, d, i64, d, ctypes.c_int]
     lib.ora_unit_psi.restype = ctypes.c_double
     lib.ora_ein.argtypes = [ctypes.c_double]
     lib.ora_ein.restype = ctypes.c_double
@@ -176,6 +181,25 @@ def unit_psi(d1: float, d2: float, s: float, q: float, inside: bool) -> float:
 
 def ein(z: float) -> float:
     return _load().ora_ein(z)
+
+
+def nfw_H(x: float) -> float:
+    return _load().ora_nfw_H(x)
+
+
+def nfw_psi(d1: float, d2: float, R: float, c: float, inside: bool) -> float:
+    return _load().ora_nfw_psi(d1, d2, R, c, int(inside))
+
+
+def direct_nfw_psi(x, y, m, R, c, rx, ry, threads: int | None = None) -> np.ndarray:
+    """Oracle A for the potential of truncated NFW halos (sizes R, concentration c)."""
+    lib = _load()
+    x, y, m, R = _f64(x), _f64(y), _f64(m), _f64(R)
+    rx, ry = _f64(rx), _f64(ry)
+    out = np.zeros(rx.shape[0])
+    lib.ora_direct_nfw_psi(_p(x), _p(y), _p(m), _p(R), x.shape[0], float(c), _p(rx), _p(ry), rx.shape[0], _p(out),
+                           threads or default_threads())
+    return out
 
 
 def direct_psi(x, y, m, s, q, rx, ry, threads: int | None = None) -> np.ndarray:

@@ -121,3 +121,47 @@ int ora_direct_nfw(const double* x, const double* y, const double* m, const doub
     }
     return 0;
 }
+
+/* Potential (alpha = grad psi, Sec. 3.2).  H(x) = ln^2(x/2)/2 - arccosh^2(1/x)/2 for
+ * x < 1 and ln^2(x/2)/2 + arccos^2(1/x)/2 for x > 1 has H' = g(x)/x, so inside R
+ *   psi = m [H(x) - H(c)] / g(c) + m ln R,
+ * which joins the point mass's m ln r at r = R; outside, psi = m ln r.  The two
+ * inverse functions are taken as log1p((y + 1 - x)/x) and atan(y) with
+ * y = sqrt|x^2 - 1| (the same values, without arguments near 1). */
+double ora_nfw_H(double x)
+{
+    const double e = (x - 1.0) * (x + 1.0), L = log(0.5 * x);
+    if (x < 1.0) {
+        const double y = sqrt(-e), a = log1p((y + (1.0 - x)) / x);
+        return 0.5 * L * L - 0.5 * a * a;
+    }
+    const double y = sqrt(e), a = atan(y);
+    return 0.5 * L * L + 0.5 * a * a;
+}
+
+/* per unit mass; a ray exactly at the centre gets the value of the limit x -> 0
+ * would be -inf there, so 0 is returned for r = 0 as for alpha */
+double ora_nfw_psi(double d1, double d2, double R, double c, int inside)
+{
+    const double r2 = d1 * d1 + d2 * d2;
+    if (r2 == 0.0) return 0.0;
+    if (!inside) return 0.5 * log(r2);
+    const double x = sqrt(r2) * c / R;
+    return (ora_nfw_H(x) - ora_nfw_H(c)) / ora_nfw_g(c) + log(R);
+}
+
+int ora_direct_nfw_psi(const double* x, const double* y, const double* m, const double* R, int64_t n, double c,
+                       const double* rx, const double* ry, int64_t nr, double* psi, int nthreads)
+{
+    if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t r = 0; r < nr; ++r) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const double d1 = rx[r] - x[i], d2 = ry[r] - y[i];
+            acc += m[i] * ora_nfw_psi(d1, d2, R[i], c, ora_nfw_inside(d1, d2, R[i]));
+        }
+        psi[r] = acc;
+    }
+    return 0;
+}

@@ -89,6 +89,11 @@ double ora_nfw_f(double x);
 double ora_nfw_g(double x);
 int ora_nfw_inside(double d1, double d2, double R);
 void ora_nfw_terms(double d1, double d2, double R, double c, int inside, double out[7]);
+/* NFW potential: H(x) with H' = g(x)/x, psi per unit mass, and the direct sum. */
+double ora_nfw_H(double x);
+double ora_nfw_psi(double d1, double d2, double R, double c, int inside);
+int ora_direct_nfw_psi(const double* x, const double* y, const double* m, const double* R, int64_t n, double c,
+                       const double* rx, const double* ry, int64_t nr, double* psi, int nthreads);
 int ora_direct_nfw(const double* x, const double* y, const double* m, const double* R, int64_t n, double c,
                    const double* rx, const double* ry, int64_t nr, double* a1, double* a2, double* kap,
                    double* g1, double* g2, int nthreads);

@@ -76,6 +76,11 @@ static int inside_of(const ora_tree* t, int64_t i, double d1, double d2)
     return t->kind ? ora_nfw_inside(d1, d2, t->s[i]) : ora_inside(d1, d2, t->s[i], t->q);
 }
 
+static double psi_of(const ora_tree* t, int64_t i, double d1, double d2, int in)
+{
+    return t->kind ? ora_nfw_psi(d1, d2, t->s[i], t->q, in) : ora_unit_psi(d1, d2, t->s[i], t->q, in);
+}
+
 static void terms_of(const ora_tree* t, int64_t i, double d1, double d2, int in, double out[7])
 {
     if (t->kind) ora_nfw_terms(d1, d2, t->s[i], t->q, in, out);
@@ -468,7 +473,7 @@ static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5
             particle_term(t, i, te, de, 1.0, acc, adj);
             particle_term(t, i, tpnt, dpnt, -1.0, acc, adj);
             if (psi)
-                *psi += t->m[i] * (ora_unit_psi(d1, d2, t->s[i], t->q, 1) - ora_unit_psi(d1, d2, t->s[i], t->q, 0));
+                *psi += t->m[i] * (psi_of(t, i, d1, d2, 1) - psi_of(t, i, d1, d2, 0));
         }
     }
     const double w1 = X - cl->cx, w2 = Y - cl->cy;
@@ -503,7 +508,7 @@ static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5
             terms_of(t, j, d1, d2, in, tt);
             dterms_of(t, j, d1, d2, in, adj, dt);
             particle_term(t, j, tt, dt, 1.0, acc, adj);
-            if (psi) *psi += t->m[j] * ora_unit_psi(d1, d2, t->s[j], t->q, in);
+            if (psi) *psi += t->m[j] * psi_of(t, j, d1, d2, in);
         }
     } else {
         for (int k = 0; k < cl->nchild; ++k) visit(t, cl->child[k], X, Y, acc, cnt, tp, adj, psi);
@@ -532,7 +537,6 @@ int ora_tree_shoot(const ora_tree* t, const double* rx, const double* ry, int64_
 
 int ora_tree_shoot_psi(const ora_tree* t, const double* rx, const double* ry, int64_t nr, double* psi, int nthreads)
 {
-    if (t->kind) return -1; /* the potential is written for Gaussians and point masses */
     if (nthreads <= 0) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
     for (int64_t r = 0; r < nr; ++r) {

@@ -101,3 +101,48 @@ def test_halo_field_kappa_exact_for_any_theta(ora):
             assert ea < prev
         prev = ea
     assert prev < 1e-6
+
+
+def test_potential_H_is_the_integral_of_g_over_x(ora):
+    """psi of a halo uses H with H' = g(x)/x (alpha = grad psi, Sec. 3.2)."""
+    from scipy.integrate import quad
+
+    for x in (1e-3, 0.05, 0.5, 0.99, 1.0, 1.01, 2.0, 5.0):
+        ref = quad(lambda t: ora.nfw_g(t) / t, 0.7, x, epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+        assert abs((ora.nfw_H(x) - ora.nfw_H(0.7)) - ref) <= 1e-11 * max(1.0, abs(ref)), x
+
+
+@pytest.mark.parametrize("r_over_R", [0.002, 0.1, 0.33, 0.7, 0.99, 1.4])
+def test_potential_gradient_and_laplacian(ora, r_over_R):
+    R, c, phi = 0.3, 3.0, 0.7
+    r = r_over_R * R
+    d1, d2 = r * np.cos(phi), r * np.sin(phi)
+
+    def psi(u, v):
+        return ora.nfw_psi(u, v, R, c, u * u + v * v < R * R)
+
+    # central differences: truncation ~ (h/r)^2 relative, rounding ~ eps |psi| / h
+    h = 1e-4 * r
+    g1 = (psi(d1 + h, d2) - psi(d1 - h, d2)) / (2 * h)
+    g2 = (psi(d1, d2 + h) - psi(d1, d2 - h)) / (2 * h)
+    t = ora.nfw_terms(d1, d2, R, c, r < R)
+    an = np.hypot(t[0], t[1])
+    assert abs(g1 - t[0]) <= 1e-6 * an and abs(g2 - t[1]) <= 1e-6 * an
+    h = 1e-3 * r
+    lap = (psi(d1 + h, d2) + psi(d1 - h, d2) + psi(d1, d2 + h) + psi(d1, d2 - h) - 4 * psi(d1, d2)) / (h * h)
+    # Poisson: laplacian psi = 2 kappa; the 5-point stencil errs by ~ (h/r)^2 / r^2
+    assert abs(lap - 2 * t[2]) <= 1e-4 * 2 * t[2] + 1e-4 / (r * r)
+
+
+def test_potential_continuity_and_tree(ora):
+    R, c = 0.25, 3.0
+    inner = ora.nfw_psi(R * (1 - 1e-13), 0.0, R, c, True)
+    outer = ora.nfw_psi(R * (1 + 1e-13), 0.0, R, c, False)
+    assert abs(inner - outer) <= 1e-12 and abs(outer - np.log(R)) <= 1e-12
+    lens, c = synth.nfw_halo_field(2000, 131)
+    rx, ry = synth.uniform_points(300, 132, -0.9, 0.9)
+    ref = ora.direct_nfw_psi(lens.x, lens.y, lens.m, lens.s, c, rx, ry)
+    T0 = ora.Tree(lens.x, lens.y, lens.m, lens.s, c, 0.0, 8, 4, nfw=True)
+    np.testing.assert_allclose(T0.shoot_psi(rx, ry), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    got = ora.Tree(lens.x, lens.y, lens.m, lens.s, c, 0.3, 8, 8, nfw=True).shoot_psi(rx, ry)
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
