@@ -64,8 +64,10 @@ typedef enum {
  * f = (1 - F)/(x^2 - 1), g = ln(x/2) + F:  alpha = m g(x)/g(c) d/r^2,
  * kappa = m f(x) / (2 r_s^2 g(c)).  A ray exactly at a halo's centre gets
  * nothing from it.  s = 0 is a point mass.  Same big-particle lists (a halo is
- * listed where R > side / 2) and the same walk; the potential and adjoint walks
- * reject such a tree with GLM_ESTATE. */
+ * listed where R > side / 2) and the same walk.  Its potential (glm_shoot_potential)
+ * is psi = m [H(x) - H(c)] / g(c) + m ln R inside R, with H(x) = ln^2(x/2)/2 -
+ * arccosh^2(1/x)/2 (x < 1) or + arccos^2(1/x)/2 (x > 1), and m ln r outside.
+ * The adjoint walk refuses such a tree with GLM_ESTATE. */
 #define GLM_NFW_HALOS 8u
 
 /* Solver parameters (Sec. 3.2 and 3.1). */

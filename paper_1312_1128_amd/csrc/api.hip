@@ -216,7 +216,6 @@ glm_status glm_shoot_potential(const glm_tree* t, const double* rx, const double
     if (nrays == 0) return GLM_OK;
     if (!rx || !ry || !a1 || !a2 || !psi) return fail(GLM_EINVAL, "rx, ry, a1, a2, psi must be device pointers");
     if (flags & ~GLM_RAYS_ORDERED) return fail(GLM_EINVAL, "unknown flag bits");
-    if (t->ts.dev.kind != kKindGauss) return fail(GLM_ESTATE, "the potential walk is for Gaussian particles and point masses");
     const size_t need = ray_layout(nrays).bytes;
     if (!workspace || workspace_bytes < need)
         return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_workspace_bytes(nrays) = " + std::to_string(need));

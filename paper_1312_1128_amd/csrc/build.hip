@@ -826,7 +826,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     ts.dev.kind = kind;
     ts.dev.invC = (float)invC;
     ts.dev.q = q;
-    ts.dev.einU = ein_host(0.5 * q * q);
+    ts.dev.psiK = kind == kKindNfw ? nfw_H(q * q, (q - 1.0) * (q + 1.0)) : ein_host(0.5 * q * q);
     ts.dev.einTerms = ein_terms(0.5 * q * q);
     ts.ccx = ccx;
     ts.ms = ms;

@@ -84,7 +84,7 @@ struct TreeDev {
     float invC;             // 1 / (1 - exp(-q^2/2))
     int32_t einTerms;       // series terms of Ein on [0, q^2/2]
     double q;
-    double einU;            // Ein(q^2/2), for the potential of the truncated Gaussian
+    double psiK;            // potential constant: Ein(q^2/2) (Gaussians) or H(c) (NFW halos)
 };
 
 // ---------------------------------------------------------------------------

@@ -50,10 +50,10 @@ __device__ inline double ein(double u, int terms)
 // Potential of a truncated Gaussian inside its support, per unit mass
 // (alpha = grad psi, Sec. 3.2; equal to the point mass's ln r at the edge):
 //   ln(q s) - (Ein(q^2/2) - Ein(u)) / (2C),  u = r^2 / (2 s^2).
-__device__ inline float gauss_psi(const PRec& pr, double r2, double einU, int terms, float invC)
+__device__ inline float gauss_psi(const PRec& pr, double r2, double psiK, int terms, float invC)
 {
     const double u = r2 * (double)pr.h;
-    return 0.5f * __logf((float)pr.qs2) - (float)((einU - ein(u, terms)) * (0.5 * (double)invC));
+    return 0.5f * __logf((float)pr.qs2) - (float)((psiK - ein(u, terms)) * (0.5 * (double)invC));
 }
 
 // compensated (Kahan) summation step; plain FP32 addition when KAHAN is false
@@ -185,6 +185,36 @@ inline double nfw_g_at(double c)
     return gx2 * (c * c);
 }
 
+// Potential shape of the NFW halo: H with H' = g(x)/x, from x^2 and e = x^2 - 1
+// (FP64).  For x < 1, H = (L^2 - a^2)/2 with L = ln(x/2), a = arccosh(1/x),
+// taken as (L - a)(L + a)/2 with L + a = ln((1 + y)/2) = log1p(-x^2/(2 + 2y)) and
+// L - a = ln x^2 - ln(2 + 2y), y = sqrt(1 - x^2), so that the two large
+// logarithms do not cancel; for x >= 1, H = (L^2 + atan(y)^2)/2, y = sqrt(x^2 - 1).
+__host__ __device__ inline double nfw_H(double x2, double e)
+{
+    if (e < 0.0) {
+        const double y = sqrt(-e), t = 2.0 + 2.0 * y;
+        return 0.5 * (log(x2) - log(t)) * log1p(-x2 / t);
+    }
+    const double L = 0.5 * log1p(e) - 0.693147180559945309417, a = atan(sqrt(e));
+    return 0.5 * (L * L + a * a);
+}
+
+// Mass-weighted potential of one smoothed particle for a lane inside its
+// support (equal to the point mass's m ln r at its edge): the Gaussian's
+// m psi of gauss_psi, or the halo's mC (H(x) - H(c)) + m ln R (0 at the centre).
+template <int KIND>
+__device__ inline float profile_psi(const PRec& pr, double r2, double psiK, int terms, float invC)
+{
+    if constexpr (KIND == kKindNfw) {
+        if (r2 == 0.0) return 0.0f;
+        const double x2 = r2 * ((double)pr.h * (double)pr.h);
+        return (float)((double)pr.mC * (nfw_H(x2, x2 - 1.0) - psiK)) + pr.m * (0.5f * __logf((float)pr.qs2));
+    } else {
+        return pr.m * gauss_psi(pr, r2, psiK, terms, invC);
+    }
+}
+
 // Profile terms of one smoothed particle for a lane inside its support (r^2
 // in FP64 and FP32, ir2 = 1 / r^2): alpha = A d, kappa = K and
 // gamma = -G (cos 2phi, sin 2phi) with G = A - K.
@@ -247,7 +277,7 @@ __device__ inline void add_radial(float coef, float Gam, float f1, float f2, flo
 // terms are formed without FMA contraction, exactly as in point_terms, so a
 // balanced pair cancels bit for bit.
 template <bool AONLY, bool KAHAN, bool PSI = false, int KIND = kKindGauss>
-__device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A, double einU = 0.0,
+__device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A, double psiK = 0.0,
                                      int terms = 1, float invC = 0.0f)
 {
 #pragma clang fp contract(off)
@@ -281,7 +311,7 @@ __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A,
     if constexpr (PSI) {
         // point mass m ln r (0 at r = 0), or the Gaussian inside its support
         const float lnr = r2f > 0.0f ? 0.5f * __logf(r2f) : 0.0f;
-        A.ps += (double)(pr.m * (gauss ? gauss_psi(pr, r2, einU, terms, invC) : lnr));
+        A.ps += (double)(gauss ? profile_psi<KIND>(pr, r2, psiK, terms, invC) : pr.m * lnr);
     }
 }
 
@@ -289,7 +319,7 @@ __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A,
 // inside the particle's support adds Gaussian - point (the tree part counted
 // the particle as a point mass); the point part goes to the FP64 balance.
 template <bool AONLY, bool KAHAN, bool PSI = false, int KIND = kKindGauss>
-__device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A, int& hits, double einU = 0.0,
+__device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A, int& hits, double psiK = 0.0,
                                      int terms = 1, float invC = 0.0f)
 {
     double d1, d2;
@@ -312,7 +342,7 @@ __device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A,
     }
     if constexpr (PSI) {
         const float lnr = r2f > 0.0f ? 0.5f * __logf(r2f) : 0.0f;
-        A.ps += (double)(pr.m * gauss_psi(pr, r2, einU, terms, invC)) - (double)(pr.m * lnr);
+        A.ps += (double)profile_psi<KIND>(pr, r2, psiK, terms, invC) - (double)(pr.m * lnr);
     }
 }
 

@@ -68,7 +68,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                     const int k = __ffsll((unsigned long long)cm) - 1;
                     cm &= cm - 1;
                     const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
-                    if (act) list_particle<AONLY, KAHAN, PSI, KIND>(pr, X, Y, A, n_hit, T.einU, T.einTerms, T.invC);
+                    if (act) list_particle<AONLY, KAHAN, PSI, KIND>(pr, X, Y, A, n_hit, T.psiK, T.einTerms, T.invC);
                 }
             }
         }
@@ -88,7 +88,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                 }
                 for (int j = e.pbeg; j < e.pend; ++j) {
                     const PRec pr = T.prt[j];
-                    if (opn) leaf_particle<AONLY, KAHAN, PSI, KIND>(pr, X, Y, A, T.einU, T.einTerms, T.invC);
+                    if (opn) leaf_particle<AONLY, KAHAN, PSI, KIND>(pr, X, Y, A, T.psiK, T.einTerms, T.invC);
                 }
             }
             cur = cur + 1;
@@ -396,7 +396,12 @@ void launch_potential(const TreeDev& T, const double* rxs, const double* rys, co
                       const WalkOut& out, hipStream_t st)
 {
     const dim3 g((unsigned)walk_grid_blocks((nrays + kWave - 1) / kWave, 1)), b(kBlock);
-    hipLaunchKernelGGL((k_walk<P, true, 0, true>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, 1, nullptr, nullptr);
+    if (T.kind == kKindNfw)
+        hipLaunchKernelGGL((k_walk<P, true, 0, true, kKindNfw>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, 1, nullptr,
+                           nullptr);
+    else
+        hipLaunchKernelGGL((k_walk<P, true, 0, true, kKindGauss>), g, b, 0, st, T, rxs, rys, rperm, nrays, out, 1,
+                           nullptr, nullptr);
 }
 
 template <bool AONLY>

@@ -159,10 +159,36 @@ def test_nfw_batched_and_rejections():
                         order=4)
     with pytest.raises(g.GlamerError):
         g.shoot_batched([ta, tg], [(dev(ra[0]), dev(ra[1])), (dev(rb[0]), dev(rb[1]))])
-    # the potential and adjoint walks are written for Gaussians and point masses
+    # the adjoint walk is written for Gaussians and point masses
     x = dev(ra[0][:64])
-    with pytest.raises(g.GlamerError, match="Gaussian"):
-        g.shoot_potential(ta, x, x)
     ga = torch.ones(64, dtype=torch.float32, device="cuda")
     with pytest.raises(g.GlamerError, match="Gaussian"):
         g.shoot_adjoint(ta, x, x, ga, ga, dm=torch.zeros(lens_a.n, dtype=torch.float64, device="cuda"))
+
+
+def test_nfw_potential_and_time_delay(ora):
+    """psi of a halo field (alpha = grad psi, Sec. 3.2): against the oracle
+    tree's psi on the same decisions and the FP64 direct sum; the time delay
+    |alpha|^2 / 2 - psi from the same walk."""
+    import paper_1312_1128_amd as g
+    import torch
+
+    lens, c = halos_and_stars(3000, 400, 341)
+    rx, ry = synth.ray_grid(67, -0.9, 0.9)
+    rx, ry = special_rays(lens, rx, ry)
+    say(f"[gpu] NFW potential: n={lens.n} rays={rx.size}")
+    for theta, order in ((0.0, 2), (0.4, 8)):
+        tree = halo_build(lens, c, theta, 8, order)
+        out = g.shoot_potential(tree, dev(rx), dev(ry))
+        torch.cuda.synchronize()
+        psi = out["psi"].double().cpu().numpy()
+        ref_t = ora.Tree(lens.x, lens.y, lens.m, lens.s, c, theta, 8, order, nfw=True).shoot_psi(rx, ry)
+        ref_d = ora.direct_nfw_psi(lens.x, lens.y, lens.m, lens.s, c, rx, ry)
+        sc = np.abs(ref_d).max()
+        et, ed = np.abs(psi - ref_t).max() / sc, np.abs(psi - ref_d).max() / sc
+        say(f"  theta={theta}: psi vs oracle tree {et:.2e}, vs direct {ed:.2e} (of max |psi|)")
+        assert et <= 2e-6 and ed <= (2e-6 if theta == 0.0 else 1e-4)
+        a = shoot(tree, rx, ry)[:, :2]
+        td = out["tdelay"].double().cpu().numpy()
+        ref_td = 0.5 * (a[:, 0] ** 2 + a[:, 1] ** 2) - psi
+        np.testing.assert_allclose(td, ref_td, rtol=1e-5, atol=1e-6 * np.abs(ref_td).max())
