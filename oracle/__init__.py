@@ -68,6 +68,9 @@ def _load():
     lib.ora_tree_build_nfw.restype = vp
     lib.ora_tree_shoot_psi.restype = ctypes.c_int
     lib.ora_unit_psi.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int]
+    lib.ora_nfw_df.argtypes = [ctypes.c_double]
+    lib.ora_nfw_df.restype = ctypes.c_double
+    lib.ora_nfw_dterms.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, d]
     lib.ora_nfw_H.argtypes = [ctypes.c_double]
     lib.ora_nfw_H.restype = ctypes.c_double
     lib.ora_nfw_psi.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int]
@@ -181,6 +184,16 @@ def unit_psi(d1: float, d2: float, s: float, q: float, inside: bool) -> float:
 
 def ein(z: float) -> float:
     return _load().ora_ein(z)
+
+
+def nfw_df(x: float) -> float:
+    return _load().ora_nfw_df(x)
+
+
+def nfw_dterms(d1: float, d2: float, R: float, c: float, inside: bool) -> np.ndarray:
+    out = np.zeros(9)
+    _load().ora_nfw_dterms(float(d1), float(d2), float(R), float(c), int(inside), _p(out))
+    return out
 
 
 def nfw_H(x: float) -> float:
@@ -367,5 +380,5 @@ class Tree:
         rc = self._lib.ora_tree_grad_kg(self._h, _p(rx), _p(ry), rx.shape[0], _p(g1), _p(g2), _pn(k), _pn(h1),
                                         _pn(h2), *[_p(o) for o in out])
         if rc != 0:
-            raise ValueError("the kappa and gamma adjoint is written for Gaussians and point masses")
+            raise ValueError("bad arguments")
         return tuple(out)

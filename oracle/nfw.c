@@ -77,19 +77,40 @@ int ora_nfw_inside(double d1, double d2, double R)
     return R > 0.0 && d1 * d1 + d2 * d2 < R * R;
 }
 
-/* per unit mass: out = a1 a2 kappa g1 g2 (0 0); a ray exactly at the centre
- * gets nothing (alpha and gamma vanish by symmetry; kappa diverges there) */
+/* f'(x): (3 x F - 2 x - 1/x) / (x^2 - 1)^2, or near x = 1 from the series of f
+ * in e = x^2 - 1 (f = sum (-e)^k / (2k + 3), so df/dx = 2x sum_{k>=1} k (-1)^k e^(k-1) / (2k + 3)). */
+double ora_nfw_df(double x)
+{
+    const double e = (x - 1.0) * (x + 1.0);
+    if (fabs(e) < 1e-2) {
+        double s = 0.0, p = 1.0; /* p = e^(k-1) */
+        for (int k = 1; k < 14; ++k) {
+            s += ((k & 1) ? -1.0 : 1.0) * (double)k * p / (double)(2 * k + 3);
+            p *= e;
+        }
+        return 2.0 * x * s;
+    }
+    return (3.0 * x * ora_nfw_F(x) - 2.0 * x - 1.0 / x) / (e * e);
+}
+
+/* per unit mass: out = a1 a2 kappa g1 g2, and d(a1, a2)/dR at fixed c; a ray
+ * exactly at the centre gets nothing (alpha and gamma vanish by symmetry;
+ * kappa diverges there).  With G = g(x)/g(c), x = r c / R:
+ * dG/dR = -x g'(x) / (R g(c)) = -x^2 f(x) / (R g(c)). */
 void ora_nfw_terms(double d1, double d2, double R, double c, int inside, double out[7])
 {
     memset(out, 0, 7 * sizeof(double));
     const double r2 = d1 * d1 + d2 * d2;
     if (r2 == 0.0) return;
-    double G = 1.0, K = 0.0;
+    double G = 1.0, K = 0.0, dGR = 0.0;
     if (inside) {
         const double rs = R / c, x = sqrt(r2) / rs, gc = ora_nfw_g(c);
         G = ora_nfw_g(x) / gc;
         K = ora_nfw_f(x) / (2.0 * rs * rs * gc);
+        dGR = -x * x * ora_nfw_f(x) / (R * gc);
     }
+    out[5] = dGR * d1 / r2;
+    out[6] = dGR * d2 / r2;
     const double h = G / r2;
     out[0] = h * d1;
     out[1] = h * d2;
@@ -97,6 +118,43 @@ void ora_nfw_terms(double d1, double d2, double R, double c, int inside, double 
     const double Gam = h - K;
     out[3] = -Gam * (d1 * d1 - d2 * d2) / r2;
     out[4] = -Gam * 2.0 * d1 * d2 / r2;
+}
+
+/* Per unit mass, as ora_unit_dterms for the halo: d(kappa, gamma1, gamma2)
+ * with respect to the offset and to the size R (fixed c).  kappa(r) =
+ * f(x) / (2 r_s^2 g(c)), A = G / r^2, Gam = A - kappa:
+ *   dkappa/dr = f'(x) (c / R) / (2 r_s^2 g(c)),
+ *   dA/dr = x f(x) (c / R) / (g(c) r^2) - 2 A / r,
+ *   dkappa/dR = -(x f'(x) + 2 f(x)) / (2 r_s^2 R g(c)),  dA/dR = (dG/dR) / r^2. */
+void ora_nfw_dterms(double d1, double d2, double R, double c, int inside, double out[9])
+{
+    memset(out, 0, 9 * sizeof(double));
+    const double r2 = d1 * d1 + d2 * d2;
+    if (r2 == 0.0) return;
+    const double r = sqrt(r2), r4 = r2 * r2;
+    double A = 1.0 / r2, K = 0.0, dKr = 0.0, dAr = -2.0 / (r2 * r), dKR = 0.0, dAR = 0.0;
+    if (inside) {
+        const double rs = R / c, x = r / rs, gc = ora_nfw_g(c), f = ora_nfw_f(x), df = ora_nfw_df(x);
+        A = ora_nfw_g(x) / gc / r2;
+        K = f / (2.0 * rs * rs * gc);
+        dKr = df * (c / R) / (2.0 * rs * rs * gc);
+        dAr = x * f * (c / R) / (gc * r2) - 2.0 * A / r;
+        dKR = -(x * df + 2.0 * f) / (2.0 * rs * rs * R * gc);
+        dAR = -x * x * f / (R * gc) / r2;
+    }
+    const double Gam = A - K, dGr = dAr - dKr, dGR = dAR - dKR;
+    const double cc = (d1 * d1 - d2 * d2) / r2, sn = 2.0 * d1 * d2 / r2;
+    const double dc1 = 4.0 * d1 * d2 * d2 / r4, dc2 = -4.0 * d2 * d1 * d1 / r4;
+    const double dsn1 = 2.0 * d2 * (d2 * d2 - d1 * d1) / r4, dsn2 = 2.0 * d1 * (d1 * d1 - d2 * d2) / r4;
+    out[0] = dKr * d1 / r;
+    out[1] = dKr * d2 / r;
+    out[2] = -dGr * (d1 / r) * cc - Gam * dc1;
+    out[3] = -dGr * (d2 / r) * cc - Gam * dc2;
+    out[4] = -dGr * (d1 / r) * sn - Gam * dsn1;
+    out[5] = -dGr * (d2 / r) * sn - Gam * dsn2;
+    out[6] = dKR;
+    out[7] = -dGR * cc;
+    out[8] = -dGR * sn;
 }
 
 int ora_direct_nfw(const double* x, const double* y, const double* m, const double* R, int64_t n, double c,

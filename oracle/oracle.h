@@ -89,6 +89,10 @@ double ora_nfw_f(double x);
 double ora_nfw_g(double x);
 int ora_nfw_inside(double d1, double d2, double R);
 void ora_nfw_terms(double d1, double d2, double R, double c, int inside, double out[7]);
+/* NFW derivatives: f'(x), and per unit mass d(kappa, gamma) by offset and size
+ * (as ora_unit_dterms; ora_nfw_terms gives d alpha / dR in out[5..6]). */
+double ora_nfw_df(double x);
+void ora_nfw_dterms(double d1, double d2, double R, double c, int inside, double out[9]);
 /* NFW potential: H(x) with H' = g(x)/x, psi per unit mass, and the direct sum. */
 double ora_nfw_H(double x);
 double ora_nfw_psi(double d1, double d2, double R, double c, int inside);
@@ -145,8 +149,8 @@ int ora_tree_grad(const ora_tree* t, const double* rx, const double* ry, int64_t
                   const double* ga1, const double* ga2,
                   double* dm, double* dx, double* dy, double* ds);
 /* The same for L = sum_r ga_r . alpha_r + gk_r kappa_r + gg_r . gamma_r
- * (gk, gg1, gg2 nullable).  Gaussian particles and point masses only (-1 for
- * a tree of NFW halos). */
+ * (gk, gg1, gg2 nullable); ds is the derivative by s, or by the size R for a
+ * tree of NFW halos (fixed concentration). */
 int ora_tree_grad_kg(const ora_tree* t, const double* rx, const double* ry, int64_t nr,
                      const double* ga1, const double* ga2, const double* gk, const double* gg1,
                      const double* gg2, double* dm, double* dx, double* dy, double* ds);

@@ -450,8 +450,9 @@ static void particle_term(const ora_tree* t, int64_t i, const double tt[7], cons
 /* kappa and gamma derivatives of particle i (zero unless the adjoint needs them) */
 static void dterms_of(const ora_tree* t, int64_t i, double d1, double d2, int in, const adj_t* adj, double out[9])
 {
-    if (adj && !t->kind) ora_unit_dterms(d1, d2, t->s[i], t->q, in, out);
-    else memset(out, 0, 9 * sizeof(double));
+    if (!adj) memset(out, 0, 9 * sizeof(double));
+    else if (t->kind) ora_nfw_dterms(d1, d2, t->s[i], t->q, in, out);
+    else ora_unit_dterms(d1, d2, t->s[i], t->q, in, out);
 }
 
 static void visit(const ora_tree* t, int64_t c, double X, double Y, double acc[5], int64_t cnt[5],
@@ -617,7 +618,6 @@ int ora_tree_grad_kg(const ora_tree* t, const double* rx, const double* ry, int6
                      const double* ga1, const double* ga2, const double* gk, const double* gg1,
                      const double* gg2, double* dm, double* dx, double* dy, double* ds)
 {
-    if (t->kind && (gk || gg1 || gg2)) return -1;
     const int P = t->p + 1;
     adj_t adj;
     double* ds_local = ds ? ds : (double*)malloc((size_t)t->n * sizeof(double));

@@ -146,3 +146,62 @@ def test_potential_continuity_and_tree(ora):
     np.testing.assert_allclose(T0.shoot_psi(rx, ry), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
     got = ora.Tree(lens.x, lens.y, lens.m, lens.s, c, 0.3, 8, 8, nfw=True).shoot_psi(rx, ry)
     assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def test_derivative_shapes_and_terms(ora):
+    """f'(x) and the per-unit-mass derivatives of alpha, kappa, gamma by the
+    offset and by the size R (the adjoint's terms), against central
+    differences of the pinned shapes and terms."""
+    for x in (0.02, 0.4, 0.93, 0.995, 1.0, 1.004, 1.2, 4.0):
+        h = 1e-6 * x
+        fd = (ora.nfw_f(x + h) - ora.nfw_f(x - h)) / (2 * h)
+        assert abs(ora.nfw_df(x) - fd) <= 1e-6 * abs(fd) + 1e-9, x
+    R, c = 0.3, 3.0
+    for (d1, d2) in [(0.004, -0.002), (0.05, 0.03), (-0.09, 0.1), (0.2, -0.15), (0.29, 0.01), (0.4, 0.2)]:
+        inside = d1 * d1 + d2 * d2 < R * R
+        dt = ora.nfw_dterms(d1, d2, R, c, inside)
+        h = 1e-7
+        fx = (ora.nfw_terms(d1 + h, d2, R, c, inside) - ora.nfw_terms(d1 - h, d2, R, c, inside)) / (2 * h)
+        fy = (ora.nfw_terms(d1, d2 + h, R, c, inside) - ora.nfw_terms(d1, d2 - h, R, c, inside)) / (2 * h)
+        ref = np.array([fx[2], fy[2], fx[3], fy[3], fx[4], fy[4]])
+        np.testing.assert_allclose(dt[:6], ref, rtol=1e-5, atol=1e-7 * np.abs(ref).max())
+        fR = (ora.nfw_terms(d1, d2, R + h, c, inside) - ora.nfw_terms(d1, d2, R - h, c, inside)) / (2 * h)
+        t = ora.nfw_terms(d1, d2, R, c, inside)
+        if inside:
+            np.testing.assert_allclose(dt[6:], fR[2:5], rtol=1e-5, atol=1e-7 * np.abs(fR[2:5]).max())
+            np.testing.assert_allclose(t[5:7], fR[0:2], rtol=1e-5, atol=1e-7 * np.abs(fR[0:2]).max())
+        else:
+            assert np.all(dt[6:] == 0.0) and np.all(t[5:7] == 0.0)
+
+
+def test_halo_tree_gradient_matches_frozen_finite_differences(ora):
+    """L = sum ga . alpha + gk kappa + gg . gamma over a halo field: dL/d(m, x,
+    y, R) of the frozen tree against finite differences."""
+    lens, c = synth.nfw_halo_field(300, 141, rmax=0.3)
+    rx, ry = synth.uniform_points(80, 142, -0.9, 0.9)
+    g0 = synth.rng(143)
+    ga, gk, gg = g0.normal(size=(rx.size, 2)), g0.normal(size=rx.size), g0.normal(size=(rx.size, 2))
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, c, 0.4, 4, 6, nfw=True)
+    _, cnt = T.shoot(rx, ry, counts=True)
+    assert cnt[:, 1].sum() > 0 and cnt[:, 4].sum() > 0
+    dm, dx, dy, ds = T.grad(rx, ry, ga, gk=gk, gg=gg)
+    T.record(rx, ry)
+    base = {"x": lens.x, "y": lens.y, "m": lens.m, "s": lens.s}
+    grads = {"x": dx, "y": dy, "m": dm, "s": ds}
+
+    def loss(B):
+        return float(np.sum(B[:, 0] * ga[:, 0] + B[:, 1] * ga[:, 1] + B[:, 2] * gk + B[:, 3] * gg[:, 0]
+                            + B[:, 4] * gg[:, 1]))
+
+    for i in synth.rng(144).choice(lens.n, 15, replace=False):
+        for name in ["m", "x", "y", "s"]:
+            h, vals = 1e-7, []
+            for sgn in (1, -1):
+                p = {k: v.copy() for k, v in base.items()}
+                p[name][i] += sgn * h
+                T.set_particles(p["x"], p["y"], p["m"], p["s"])
+                vals.append(loss(T.shoot_frozen(rx, ry)))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            gr = grads[name][i]
+            assert abs(fd - gr) <= 1e-5 * max(abs(gr), 1e-3 * np.abs(grads[name]).max()), (name, i, fd, gr)
+    T.set_particles(lens.x, lens.y, lens.m, lens.s)
