@@ -67,7 +67,7 @@ typedef enum {
  * listed where R > side / 2) and the same walk.  Its potential (glm_shoot_potential)
  * is psi = m [H(x) - H(c)] / g(c) + m ln R inside R, with H(x) = ln^2(x/2)/2 -
  * arccosh^2(1/x)/2 (x < 1) or + arccos^2(1/x)/2 (x > 1), and m ln r outside.
- * The adjoint walk refuses such a tree with GLM_ESTATE. */
+ * The adjoint walk gives dL/dR (size, at fixed c) in place of dL/ds. */
 #define GLM_NFW_HALOS 8u
 
 /* Solver parameters (Sec. 3.2 and 3.1). */
@@ -252,8 +252,8 @@ GLM_API glm_status glm_shoot_direct_nfw(const double* x, const double* y, const 
  * Moment contributions are pushed down from boxes to particles through
  * dQ_k/dm_i, dQ_k/dz_i and dz_cm (kappa has no box term; gamma1 - i gamma2 of
  * a box is the derivative of its alpha1 - i alpha2 series).  Uses FP64
- * atomics: results are reproducible to rounding, not bitwise.  Trees of
- * GLM_NFW_HALOS are refused (GLM_ESTATE).
+ * atomics: results are reproducible to rounding, not bitwise.  For a tree of
+ * GLM_NFW_HALOS, ds receives dL/dR (the halo size, concentration fixed).
  *   workspace: at least glm_shoot_workspace_bytes(nrays); the scratch for
  *   box adjoints and per-particle sums is device memory the handle owns.
  */

@@ -60,7 +60,7 @@ __device__ inline void kg_grad(const Cot& cg, float f1, float f2, float ir2, flo
 // Gradient terms of one particle for this lane, per the same cases as the
 // forward's leaf_particle and list_particle.  Returns FP64 (m, x, y, s) contributions in G.
 // mode 0: leaf sum; mode 1: big-particle correction (Gaussian - point).
-template <bool KG>
+template <bool KG, int KIND>
 __device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mode, bool act, const Cot& cg,
                                      float invC, double G[4])
 {
@@ -96,13 +96,53 @@ __device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mod
         G[2] = (double)pm_y;
         return true;
     }
+    const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = 2.0f * f1 * f2 * ir2;
+    if constexpr (KIND == kKindNfw) {
+        // truncated NFW halo per unit mass (invC = 1/g(c), h = c/R): A = h^2 g/x^2 / g(c),
+        // kappa = h^2 f / (2 g(c)); size derivatives of a scale family: d alpha/dR = -(2 kappa/R) d,
+        // d kappa/dR = -2 (kappa + u dkappa/du)/R, d(kappa - A)/dR = -2 u dkappa/du / R
+        const double x2 = r2 * ((double)pr.h * (double)pr.h);
+        float gx2, f, dfde;
+        nfw_shape<float, 12>((float)x2, (float)(x2 - 1.0), 0.25f, &gx2, &f, &dfde);
+        const float hh2 = (invC * pr.h) * pr.h;
+        const float Au = hh2 * gx2;
+        const float Ku = r2 > 0.0 ? 0.5f * hh2 * f : 0.0f;
+        const float Gu = Au - Ku;
+        const float iR = __builtin_amdgcn_rsqf((float)pr.qs2);
+        const float ga1 = -Gu * c2, ga2 = -Gu * s2;
+        float em = Au * gd;
+        float ex = -(g1 * (Ku + ga1) + g2 * ga2) * pr.m;
+        float ey = -(g1 * ga2 + g2 * (Ku - ga1)) * pr.m;
+        float es = -pr.m * 2.0f * Ku * iR * gd;
+        if constexpr (KG) {
+            const float a = (Ku - Au) * ir2;
+            const float dk = r2 > 0.0 ? 0.5f * hh2 * (pr.h * pr.h) * dfde : 0.0f;
+            float km, k1, k2;
+            kg_grad(cg, f1, f2, ir2, Ku, a, dk, &km, &k1, &k2);
+            em += km;
+            ex -= k1 * pr.m;
+            ey -= k2 * pr.m;
+            const float ks = -2.0f * (Ku + r2f * dk) * iR, gs = -2.0f * r2f * dk * iR;
+            es += pr.m * (cg.k * ks + (cg.h1 * c2 + cg.h2 * s2) * gs);
+        }
+        if (mode == 1) {
+            G[0] = (double)em - (double)pm_m;
+            G[1] = (double)ex - (double)pm_x;
+            G[2] = (double)ey - (double)pm_y;
+        } else {
+            G[0] = (double)em;
+            G[1] = (double)ex;
+            G[2] = (double)ey;
+        }
+        G[3] = (double)es;
+        return true;
+    }
     const float u = r2f * pr.h;
     const float e = __expf(-u);
     const float hu = invC * pr.h; // per unit mass m/C/(2 s^2)
     float Au, Gu;
     gauss_terms(u, e, ir2, invC, hu, &Au, &Gu);
     const float Ku = hu * e;
-    const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = 2.0f * f1 * f2 * ir2;
     const float ga1 = -Gu * c2, ga2 = -Gu * s2; // gamma per unit mass
     float em = Au * gd;
     float ex = -(g1 * (Ku + ga1) + g2 * ga2) * pr.m;
@@ -174,7 +214,7 @@ struct CotIn {
     const float *ga1, *ga2, *gk, *gg1, *gg2;
 };
 
-template <int P, bool KG>
+template <int P, bool KG, int KIND>
 __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double* __restrict__ rxs,
                                                         const double* __restrict__ rys,
                                                         const uint32_t* __restrict__ rperm, int64_t nrays,
@@ -243,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                     const int k = __ffsll((unsigned long long)cm) - 1;
                     cm &= cm - 1;
                     const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
-                    const bool hit = particle_grad<KG>(pr, X, Y, 1, act, cg, invC, G);
+                    const bool hit = particle_grad<KG, KIND>(pr, X, Y, 1, act, cg, invC, G);
                     if (__any(hit)) {
                         double S[4];
                         particle_sums(G, true, S);
@@ -345,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 const CellExt e = T.ext[cur];
                 for (int j = e.pbeg; j < e.pend; ++j) {
                     const PRec pr = T.prt[j];
-                    const bool hit = particle_grad<KG>(pr, X, Y, 0, opn, cg, invC, G);
+                    const bool hit = particle_grad<KG, KIND>(pr, X, Y, 0, opn, cg, invC, G);
                     const bool any_s = __any(hit && G[3] != 0.0);
                     double S[4];
                     particle_sums(G, any_s, S);
@@ -462,12 +502,18 @@ glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, 
     double* pg = abar + (size_t)ts.ncells * NA;
     hipLaunchKernelGGL(k_fill_zero, dim3(ceil_div((int64_t)words, kBlock)), dim3(kBlock), 0, st, abar, (int64_t)words);
     const int64_t blocks = walk_grid_blocks((nrays + kWave - 1) / kWave, K);
-    if (ci.gk || ci.gg1 || ci.gg2)
-        hipLaunchKernelGGL((k_adjoint_walk<P, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ts.dev, sr.xs,
-                           sr.ys, sr.perm, nrays, ci, pg, abar, K, split_box);
-    else
-        hipLaunchKernelGGL((k_adjoint_walk<P, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ts.dev, sr.xs,
-                           sr.ys, sr.perm, nrays, ci, pg, abar, K, split_box);
+    const bool kg = ci.gk || ci.gg1 || ci.gg2;
+#define GLM_ADJ(KGV, KD)                                                                                          \
+    hipLaunchKernelGGL((k_adjoint_walk<P, KGV, KD>), dim3((unsigned)blocks), dim3(kBlock), 0, st, ts.dev, sr.xs, \
+                       sr.ys, sr.perm, nrays, ci, pg, abar, K, split_box)
+    if (ts.dev.kind == kKindNfw) {
+        if (kg) GLM_ADJ(true, kKindNfw);
+        else GLM_ADJ(false, kKindNfw);
+    } else {
+        if (kg) GLM_ADJ(true, kKindGauss);
+        else GLM_ADJ(false, kKindGauss);
+    }
+#undef GLM_ADJ
     hipLaunchKernelGGL((k_pushdown<P>), dim3(ceil_div(ts.n, kBlock)), dim3(kBlock), 0, st, ts.dev, ts.ms, abar, pg, dm,
                        dx, dy, ds);
     GLM_HIP(hipGetLastError());

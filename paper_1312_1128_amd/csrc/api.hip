@@ -278,7 +278,6 @@ glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* 
     if (!rx || !ry) return fail(GLM_EINVAL, "rx, ry must be device pointers");
     if (!ga1 && !ga2 && !gk && !gg1 && !gg2) return fail(GLM_EINVAL, "every cotangent is NULL");
     if (flags & ~(GLM_NO_KAHAN | GLM_RAYS_ORDERED | GLM_ALPHA_ONLY)) return fail(GLM_EINVAL, "unknown flag bits");
-    if (t->ts.dev.kind != kKindGauss) return fail(GLM_ESTATE, "the adjoint walk is for Gaussian particles and point masses");
     {
         const size_t need = ray_layout(nrays).bytes;
         if (!workspace || workspace_bytes < need)

@@ -824,7 +824,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     ts.dev.nlisted = -1; // read on demand (sync->nlisted)
     ts.dev.order = p;
     ts.dev.kind = kind;
-    ts.dev.invC = (float)invC;
+    ts.dev.invC = (float)norm; // per-unit-mass normalisation: 1/C, or 1/g(c) for halos
     ts.dev.q = q;
     ts.dev.psiK = kind == kKindNfw ? nfw_H(q * q, (q - 1.0) * (q + 1.0)) : ein_host(0.5 * q * q);
     ts.dev.einTerms = ein_terms(0.5 * q * q);

@@ -81,7 +81,7 @@ struct TreeDev {
     int32_t nlisted;
     int32_t order;
     int32_t kind;           // kKindGauss or kKindNfw
-    float invC;             // 1 / (1 - exp(-q^2/2))
+    float invC;             // mass normalisation: 1 / (1 - exp(-q^2/2)), or 1 / g(c) for NFW halos
     int32_t einTerms;       // series terms of Ein on [0, q^2/2]
     double q;
     double psiK;            // potential constant: Ein(q^2/2) (Gaussians) or H(c) (NFW halos)

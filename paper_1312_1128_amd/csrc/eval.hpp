@@ -152,19 +152,33 @@ __host__ __device__ inline T odd_series(T z)
     return s;
 }
 
+// sum_{k < N} (k + 1) z^k / (2k + 5) by Horner (the series of -df/de)
+template <class T, int N>
+__host__ __device__ inline T dseries(T z)
+{
+    T s = (T)((double)N / (double)(2 * (N - 1) + 5));
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) s = s * z + (T)((double)(k + 1) / (double)(2 * k + 5));
+    return s;
+}
+
+// With dfde: also df/de = f'(x) / (2x) = (3F - 2 - 1/x^2) / (2 e^2), or -sum (k+1)(-e)^k/(2k+5)
+// in the series range (for the adjoint).
 template <class T, int NSER>
-__host__ __device__ inline void nfw_shape(T x2, T e, T eps, T* gx2, T* f)
+__host__ __device__ inline void nfw_shape(T x2, T e, T eps, T* gx2, T* f, T* dfde = nullptr)
 {
     const T ln2 = (T)0.693147180559945309417;
     if (e > -eps && e < eps) {
         const T F = odd_series<T, NSER, 1>(-e);
         *f = odd_series<T, NSER + 1, 3>(-e);
         *gx2 = ((T)0.5 * nfw_log1p(e) - ln2 + F) / x2;
+        if (dfde) *dfde = -dseries<T, NSER + 1>(-e);
     } else if (e > (T)0) {
         const T y = nfw_sqrt(e);
         const T F = nfw_atan(y) / y;
         *f = ((T)1 - F) / e;
         *gx2 = ((T)0.5 * nfw_log1p(e) - ln2 + F) / x2;
+        if (dfde) *dfde = ((T)3 * F - (T)2 - (T)1 / x2) / ((T)2 * e * e);
     } else {
         // x^2 is kept above a tiny floor, so that a ray at the centre gives finite values
         const T tiny = sizeof(T) == 4 ? (T)1e-30 : (T)1e-300;
@@ -174,6 +188,7 @@ __host__ __device__ inline void nfw_shape(T x2, T e, T eps, T* gx2, T* f)
         *f = (F - (T)1) / (-e);
         const T L = ln2 - (T)0.5 * nfw_log(xx);
         *gx2 = (L / opy + nfw_log1p(-xx / ((T)2 * opy)) / xx) / y;
+        if (dfde) *dfde = ((T)3 * F - (T)2 - (T)1 / xx) / ((T)2 * e * e);
     }
 }
 
