@@ -357,10 +357,38 @@ GLM_API glm_status glm_interp_init(const double* cx, const double* cy, int64_t n
  */
 GLM_API glm_status glm_refine_interp_round(double* cx, double* cy, double* side, float* a1, float* a2,
                                            float* kappa, float* g1, float* g2, int64_t ncells, int64_t nrefine,
-                                           int64_t nbase, float tol, int32_t* refined, int32_t* shoot_idx,
-                                           int32_t* shoot_count, int64_t capacity, void* state,
-                                           size_t state_bytes, void* workspace, size_t workspace_bytes,
-                                           void* stream);
+                                           int64_t nbase, float tol, uint32_t flags, int32_t* refined,
+                                           int32_t* shoot_idx, int32_t* shoot_count, int64_t capacity,
+                                           void* state, size_t state_bytes, void* workspace,
+                                           size_t workspace_bytes, void* stream);
+
+/*
+ * Deflection-only magnification matrix (App. A), for walks without kappa and
+ * gamma.  For two neighbours P, Q of a cell c not collinear with its centre
+ * (|det| > 1e-6 |u| |v|), with u = x_P - x_c, v = x_Q - x_c and s, t the
+ * matching source-plane offsets (y = x - alpha), the magnification matrix
+ * A = [[a11, a21], [a12, a22]] (y_1 = a11 x_1 + a21 x_2, y_2 = a12 x_1 + a22 x_2) is
+ *   a11 = (v2 s1 - u2 t1)/det, a21 = (u1 t1 - v1 s1)/det,
+ *   a12 = (v2 s2 - u2 t2)/det, a22 = (u1 t2 - v1 s2)/det,  det = u1 v2 - u2 v1
+ * (FP64).  Neighbours as for glm_refine_interp_round.
+ *
+ * GLM_INTERP_DEFLECTIONS (flags of glm_refine_interp_round): a cell is
+ * uniform if it has at least one such pair and every element of A agrees over
+ * all pairs within tol; its new cells then get alpha = alpha_c + (I - A)(x - x_c)
+ * with A the mean over the pairs, and kappa = 1 - (a11 + a22)/2,
+ * g1 = (a22 - a11)/2, g2 = -(a12 + a21)/2.  kappa, g1, g2 of the cells are
+ * still what ranks them.
+ *
+ * glm_interp_estimate writes those kappa, g1, g2 (from the mean A; 0 without a
+ * pair) for the cells idx[0 .. min(*count, max_count)) -- the cells just walked
+ * without kappa and gamma -- or, with idx NULL, for cells 0 .. max_count - 1
+ * (count NULL reads as max_count).  No host synchronisation.
+ */
+#define GLM_INTERP_DEFLECTIONS 1u
+GLM_API glm_status glm_interp_estimate(const double* cx, const double* cy, const float* a1, const float* a2,
+                                       float* kappa, float* g1, float* g2, const int32_t* idx,
+                                       const int32_t* count, int64_t max_count, int64_t nbase, int64_t capacity,
+                                       const void* state, size_t state_bytes, void* stream);
 
 /* Bytes of device workspace for glm_shoot_indexed of count rays. */
 GLM_API glm_status glm_shoot_indexed_workspace_bytes(int64_t count, size_t* bytes);

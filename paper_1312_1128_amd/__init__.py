@@ -267,5 +267,5 @@ class ShootFn(torch.autograd.Function):
         return None, None, dm, dx, dy, (ds if ctx.has_s else None), None, None
 
 
-from .batch import (RefinementRun, autotune, interp_init, refine_interp_round, refine_round,  # noqa: E402
+from .batch import (RefinementRun, autotune, interp_estimate, interp_init, refine_interp_round, refine_round,  # noqa: E402
                     refine_schedule, shoot_batched, shoot_indexed)

@@ -18,6 +18,7 @@ GLM_ALPHA_ONLY = 1
 GLM_NO_KAHAN = 2
 GLM_RAYS_ORDERED = 4
 GLM_NFW_HALOS = 8
+GLM_INTERP_DEFLECTIONS = 1
 
 # every symbol include/glamer.h declares
 EXPORTED = [
@@ -27,7 +28,7 @@ EXPORTED = [
     "glm_refine_workspace_bytes", "glm_refine_round", "glm_tree_knn", "glm_interp_state_bytes",
     "glm_interp_round_workspace_bytes", "glm_interp_init", "glm_refine_interp_round",
     "glm_shoot_indexed_workspace_bytes", "glm_shoot_indexed", "glm_shoot_potential", "glm_shoot_direct_nfw",
-    "glm_knn_workspace_bytes", "glm_knn",
+    "glm_knn_workspace_bytes", "glm_knn", "glm_interp_estimate",
 ]
 
 
@@ -107,9 +108,11 @@ def load(path: str = LIB_PATH):
     lib.glm_interp_round_workspace_bytes.restype = st
     lib.glm_interp_init.argtypes = [vp, vp, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, vp, sz, vp]
     lib.glm_interp_init.restype = st
-    lib.glm_refine_interp_round.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i64, ctypes.c_float, vp, vp,
-                                            vp, i64, vp, sz, vp, sz, vp]
+    lib.glm_refine_interp_round.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i64, ctypes.c_float, u32, vp,
+                                            vp, vp, i64, vp, sz, vp, sz, vp]
     lib.glm_refine_interp_round.restype = st
+    lib.glm_interp_estimate.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
+    lib.glm_interp_estimate.restype = st
     lib.glm_shoot_indexed_workspace_bytes.argtypes = [i64, P(sz)]
     lib.glm_shoot_indexed_workspace_bytes.restype = st
     lib.glm_shoot_indexed.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, u32, vp, sz, vp]

@@ -10,7 +10,7 @@ import time
 import torch
 
 from . import _capi
-from ._capi import GLM_ALPHA_ONLY, GlmLensRays
+from ._capi import GLM_ALPHA_ONLY, GLM_INTERP_DEFLECTIONS, GlmLensRays
 
 
 def _ptr(t):
@@ -87,10 +87,12 @@ def interp_init(cx, cy, ncells: int, x0: float, y0: float, h0: float, capacity: 
 
 
 def refine_interp_round(cx, cy, side, out, ncells: int, nrefine: int, nbase: int, tol: float, capacity: int, state,
-                        shoot_idx, shoot_count, refined=None, workspace=None):
+                        shoot_idx, shoot_count, refined=None, workspace=None, deflections: bool = False):
     """One refinement round with the interpolation shortcut (Sec. 3.4): new
     cells of uniform cells are filled in `out`, the others are listed in
-    shoot_idx with their number in shoot_count (device)."""
+    shoot_idx with their number in shoot_count (device).  deflections: the
+    uniformity test and the fill use the three-point magnification matrix
+    from deflections (App. A) instead of kappa and gamma."""
     lib = _capi.load()
     if workspace is None:
         workspace = torch.empty(_size(lib.glm_interp_round_workspace_bytes, int(ncells), int(nrefine)),
@@ -98,8 +100,19 @@ def refine_interp_round(cx, cy, side, out, ncells: int, nrefine: int, nbase: int
     v = lambda t: ctypes.c_void_p(_ptr(t))
     _capi.check(lib.glm_refine_interp_round(v(cx), v(cy), v(side), v(out["a1"]), v(out["a2"]), v(out["kappa"]),
                                             v(out["g1"]), v(out["g2"]), int(ncells), int(nrefine), int(nbase),
-                                            float(tol), v(refined), v(shoot_idx), v(shoot_count), int(capacity),
-                                            v(state), state.numel(), v(workspace), workspace.numel(), _stream()))
+                                            float(tol), GLM_INTERP_DEFLECTIONS if deflections else 0, v(refined),
+                                            v(shoot_idx), v(shoot_count), int(capacity), v(state), state.numel(),
+                                            v(workspace), workspace.numel(), _stream()))
+
+
+def interp_estimate(cx, cy, out, nbase: int, capacity: int, state, idx=None, count=None, max_count: int = 0):
+    """kappa, g1, g2 in `out` of the cells idx[:count] (device count; idx None:
+    cells 0 .. max_count - 1) from their three-point magnification matrix (App. A)."""
+    lib = _capi.load()
+    v = lambda t: ctypes.c_void_p(_ptr(t))
+    _capi.check(lib.glm_interp_estimate(v(cx), v(cy), v(out["a1"]), v(out["a2"]), v(out["kappa"]), v(out["g1"]),
+                                        v(out["g2"]), v(idx), v(count), int(max_count), int(nbase), int(capacity),
+                                        v(state), state.numel(), _stream()))
 
 
 def shoot_indexed(tree, cx, cy, idx, count: int, out, workspace=None, alpha_only: bool = False):
@@ -170,13 +183,15 @@ class RefinementRun:
             n += 8 * k
         return n
 
-    def run_interp(self, x0: float, y0: float, h0: float, nbase: int, tol: float = 1e-4):
+    def run_interp(self, x0: float, y0: float, h0: float, nbase: int, tol: float = 1e-4, alpha_only: bool = False):
         """The same schedule with the interpolation shortcut (Sec. 3.4): the
         base cells (an nbase x nbase grid of side h0 from (x0, y0)) are shot,
         then each round fills the new cells of uniform cells by the linear lens
-        equation and walks only the others.  Reads the number of rays to walk
-        once per round (a host synchronisation), so it is not graph-captured.
-        Returns (cells, rays walked)."""
+        equation and walks only the others.  alpha_only: the walks compute
+        deflections only, and the magnification matrix (for the ranking, the
+        uniformity test and the fill) comes from deflections at three points
+        (App. A).  Reads the number of rays to walk once per round (a host
+        synchronisation), so it is not graph-captured.  Returns (cells, rays walked)."""
         lib = _capi.load()
         dev = self.cx.device
         if not hasattr(self, "_interp"):
@@ -193,15 +208,25 @@ class RefinementRun:
         self.cx[: self.n0].copy_(bx)
         self.cy[: self.n0].copy_(by)
         self.side[: self.n0].copy_(bs)
-        self._shoot_range(0, self.n0)
         interp_init(self.cx, self.cy, self.n0, x0, y0, h0, self.cap, it["state"])
+        if alpha_only:
+            shoot_indexed(self.tree, self.cx, self.cy, torch.arange(self.n0, dtype=torch.int32, device=dev), self.n0,
+                          self.out, alpha_only=True)
+            interp_estimate(self.cx, self.cy, self.out, nbase, self.cap, it["state"], max_count=self.n0)
+        else:
+            self._shoot_range(0, self.n0)
         n, walked = self.n0, self.n0
         for k in self.schedule:
             if k > 0:
                 refine_interp_round(self.cx, self.cy, self.side, self.out, n, k, nbase, tol, self.cap, it["state"],
-                                    it["idx"], it["count"], refined=self.refined, workspace=it["ws_round"])
+                                    it["idx"], it["count"], refined=self.refined, workspace=it["ws_round"],
+                                    deflections=alpha_only)
                 cnt = int(it["count"].item())
-                shoot_indexed(self.tree, self.cx, self.cy, it["idx"], cnt, self.out, workspace=it["ws_idx"])
+                shoot_indexed(self.tree, self.cx, self.cy, it["idx"], cnt, self.out, workspace=it["ws_idx"],
+                              alpha_only=alpha_only)
+                if alpha_only:
+                    interp_estimate(self.cx, self.cy, self.out, nbase, self.cap, it["state"], idx=it["idx"],
+                                    count=it["count"], max_count=8 * k)
                 walked += cnt
             n += 8 * k
         return n, walked

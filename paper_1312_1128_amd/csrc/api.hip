@@ -396,10 +396,11 @@ glm_status glm_interp_init(const double* cx, const double* cy, int64_t ncells, d
 
 glm_status glm_refine_interp_round(double* cx, double* cy, double* side, float* a1, float* a2, float* kappa,
                                    float* g1, float* g2, int64_t ncells, int64_t nrefine, int64_t nbase, float tol,
-                                   int32_t* refined, int32_t* shoot_idx, int32_t* shoot_count, int64_t capacity,
-                                   void* state, size_t state_bytes, void* workspace, size_t workspace_bytes,
-                                   void* stream)
+                                   uint32_t flags, int32_t* refined, int32_t* shoot_idx, int32_t* shoot_count,
+                                   int64_t capacity, void* state, size_t state_bytes, void* workspace,
+                                   size_t workspace_bytes, void* stream)
 {
+    if (flags & ~GLM_INTERP_DEFLECTIONS) return fail(GLM_EINVAL, "unknown flag bits");
     if (!cx || !cy || !side || !a1 || !a2 || !kappa || !g1 || !g2 || !shoot_idx || !shoot_count || !state)
         return fail(GLM_EINVAL, "NULL device pointer");
     if (ncells < 1 || nrefine < 0 || nrefine > ncells) return fail(GLM_EINVAL, "need 0 <= nrefine <= ncells");
@@ -412,8 +413,22 @@ glm_status glm_refine_interp_round(double* cx, double* cy, double* side, float* 
     if (!workspace || workspace_bytes < need)
         return fail(GLM_ENOMEM, "workspace smaller than glm_interp_round_workspace_bytes = " + std::to_string(need));
     if (nrefine == 0) return fail(GLM_EINVAL, "nrefine must be >= 1");
-    return interp_round_device(cx, cy, side, a1, a2, kappa, g1, g2, ncells, nrefine, nbase, tol, refined, shoot_idx,
-                               shoot_count, capacity, state, workspace, static_cast<hipStream_t>(stream));
+    return interp_round_device(cx, cy, side, a1, a2, kappa, g1, g2, ncells, nrefine, nbase, tol,
+                               (flags & GLM_INTERP_DEFLECTIONS) != 0, refined, shoot_idx, shoot_count, capacity, state,
+                               workspace, static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_interp_estimate(const double* cx, const double* cy, const float* a1, const float* a2, float* kappa,
+                               float* g1, float* g2, const int32_t* idx, const int32_t* count, int64_t max_count,
+                               int64_t nbase, int64_t capacity, const void* state, size_t state_bytes, void* stream)
+{
+    if (!cx || !cy || !a1 || !a2 || !kappa || !g1 || !g2 || !state) return fail(GLM_EINVAL, "NULL device pointer");
+    if (max_count < 0 || max_count > capacity || capacity > 0x7fffff00) return fail(GLM_EINVAL, "max_count out of range");
+    if (nbase < 1 || nbase > (1 << 28)) return fail(GLM_EINVAL, "nbase out of range");
+    const size_t sneed = interp_layout(capacity).bytes;
+    if (state_bytes < sneed) return fail(GLM_ENOMEM, "state smaller than glm_interp_state_bytes = " + std::to_string(sneed));
+    return interp_estimate_device(cx, cy, a1, a2, kappa, g1, g2, idx, count, max_count, nbase, capacity, state,
+                                  static_cast<hipStream_t>(stream));
 }
 
 glm_status glm_shoot_indexed_workspace_bytes(int64_t count, size_t* bytes)

@@ -51,9 +51,14 @@ size_t interp_round_workspace_bytes(int64_t ncells, int64_t nrefine);
 glm_status interp_init_device(const double* cx, const double* cy, int64_t ncells, double x0, double y0, double h0,
                               int64_t capacity, void* state, hipStream_t st);
 glm_status interp_round_device(double* cx, double* cy, double* side, float* a1, float* a2, float* ka, float* g1,
-                               float* g2, int64_t ncells, int64_t nrefine, int64_t nbase, float tol,
+                               float* g2, int64_t ncells, int64_t nrefine, int64_t nbase, float tol, bool deflections,
                                int32_t* refined, int32_t* shoot_idx, int32_t* shoot_count, int64_t capacity,
                                void* state, void* ws, hipStream_t st);
+// kappa, gamma of cells idx[0 .. min(*count, max_count)) (idx NULL: cells 0 ..
+// max_count; count NULL: max_count) from their three-point magnification matrix.
+glm_status interp_estimate_device(const double* cx, const double* cy, const float* a1, const float* a2, float* ka,
+                                  float* g1, float* g2, const int32_t* idx, const int32_t* count, int64_t max_count,
+                                  int64_t nbase, int64_t capacity, const void* state, hipStream_t st);
 size_t shoot_indexed_workspace_bytes(int64_t count);
 
 // Wavefronts per 64-ray group.  A small launch (few groups) splits the

@@ -221,3 +221,173 @@ def test_interp_invalid_arguments():
         g.interp_init(x, x, 16, 0.0, 0.0, 1.0, 16, st)
     with pytest.raises(g.GlamerError):  # bad base grid
         g.interp_init(x, x, 16, 0.0, 0.0, 0.0, 16, torch.empty(1 << 16, dtype=torch.uint8, device="cuda"))
+
+
+# ------------------------------------------------------------ deflection mode
+
+def mirror_neighbours(S, c, nbase):
+    out = []
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dx == 0 and dy == 0:
+                continue
+            nb = locate(S["table"], S["lev"][c], S["ci"][c] + dx, S["cj"][c] + dy, nbase)
+            if nb < 0 or nb == c:
+                continue
+            out.append(nb)
+    return out
+
+
+def mirror_three_point(S, c, nbase):
+    from oracle import interp
+
+    nb = mirror_neighbours(S, c, nbase)
+    return interp.three_point(S["cx"][c], S["cy"][c], S["a1"][c], S["a2"][c],
+                              [(S["cx"][q], S["cy"][q], S["a1"][q], S["a2"][q]) for q in nb])
+
+
+def mirror_estimates(S, cells, nbase):
+    from oracle import interp
+
+    out = np.zeros((len(cells), 3))
+    for t, c in enumerate(cells):
+        n, mn, mx, sm = mirror_three_point(S, c, nbase)
+        out[t] = interp.kappa_gamma(interp.mean_A(n, sm)) if n > 0 else (0.0, 0.0, 0.0)
+    return out.astype(np.float32).astype(np.float64)
+
+
+def numpy_round_deflections(S, n, k, nbase, tol):
+    """One round of the deflection-only rule (App. A) on the host mirror."""
+    from oracle import interp
+
+    f32 = np.float32
+    h = S["side"][:n].astype(f32)
+    ka, g1, g2 = (S[q][:n].astype(f32) for q in ("kappa", "g1", "g2"))
+    sc = (h * h) * ((ka * ka + g1 * g1) + g2 * g2)
+    key = np.uint32(0xFFFFFFFF) - sc.astype(f32).view(np.uint32)
+    order = np.argsort(key, kind="stable")[:k]
+    tests = [mirror_three_point(S, c, nbase) for c in order]
+    uniform = [interp.uniform(npr, mn, mx, float(f32(tol))) for npr, mn, mx, _ in tests]
+    shoot = []
+    for t, c in enumerate(order):
+        h3 = S["side"][c] / 3.0
+        l, i, j = S["lev"][c] + 1, 3 * S["ci"][c] + 1, 3 * S["cj"][c] + 1
+        A = interp.mean_A(tests[t][0], tests[t][3])
+        m11, m12, m21, m22 = 1.0 - A[0], -A[1], -A[2], 1.0 - A[3]
+        K, G1, G2 = interp.kappa_gamma(A)
+        q = 0
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == 0 and dy == 0:
+                    continue
+                o = n + 8 * t + q
+                S["cx"][o] = S["cx"][c] + float(dx) * h3
+                S["cy"][o] = S["cy"][c] + float(dy) * h3
+                S["side"][o] = h3
+                S["lev"][o], S["ci"][o], S["cj"][o] = l, i + dx, j + dy
+                S["table"][(l, i + dx, j + dy)] = o
+                if uniform[t]:
+                    ux, uy = S["cx"][o] - S["cx"][c], S["cy"][o] - S["cy"][c]
+                    S["a1"][o] = S["a1"][c] + m11 * ux + m12 * uy
+                    S["a2"][o] = S["a2"][c] + m21 * ux + m22 * uy
+                    S["kappa"][o], S["g1"][o], S["g2"][o] = K, G1, G2
+                else:
+                    shoot.append(o)
+                q += 1
+        S["side"][c] = h3
+        S["lev"][c], S["ci"][c], S["cj"][c] = l, i, j
+        S["table"][(l, i, j)] = int(c)
+    return np.array(order), np.array(uniform), np.array(shoot, dtype=np.int64)
+
+
+def test_interp_deflection_mode_matches_rule(ora):
+    """Refinement with deflection-only walks: the base cells and each round's
+    walked cells get kappa, gamma from the three-point magnification matrix
+    (App. A), and the uniformity test compares the pair estimates of A; all
+    against a host restatement of the rule (decisions and walk lists bit for
+    bit, values to FP32 rounding)."""
+    import paper_1312_1128_amd as g
+    import torch
+
+    # five large truncated NFW halos: a deflection field smooth on the cell scale,
+    # where FP32 deflections still resolve A to ~1e-4
+    lens, c = synth.nfw_halo_field(5, 9, rmax=1.5)
+    nbase, patch, (xc, yc), tol = 32, 0.02, (0.3, 0.05), 1e-3
+    x0, y0 = xc - patch / 2, yc - patch / 2
+    h0 = patch / nbase
+    bx, by = synth.ray_grid(nbase, 0.0, patch)
+    bx, by = bx + x0, by + y0
+    sched = g.refine_schedule(bx.size, rounds=3)
+    cap = bx.size + 8 * sum(sched)
+    say(f"[gpu] interpolation, deflection mode: n={lens.n} halos, base={nbase}^2 schedule={sched}")
+    tree = g.Tree().build(dev(lens.x), dev(lens.y), dev(lens.m), dev(lens.s), theta=0.3, q=c, leaf_size=16, order=8,
+                          nfw=True)
+    cx = torch.zeros(cap, dtype=torch.float64, device="cuda")
+    cy, side = torch.zeros_like(cx), torch.zeros_like(cx)
+    n = bx.size
+    cx[:n], cy[:n], side[:n] = dev(bx), dev(by), h0
+    out = {q: torch.zeros(cap, dtype=torch.float32, device="cuda") for q in NAMES}
+    lib = g._capi.load()
+    import ctypes
+
+    sbytes = ctypes.c_size_t()
+    lib.glm_interp_state_bytes(cap, ctypes.byref(sbytes))
+    state = torch.empty(sbytes.value, dtype=torch.uint8, device="cuda")
+    g.interp_init(cx, cy, n, x0, y0, h0, cap, state)
+    g.shoot_indexed(tree, cx, cy, torch.arange(n, dtype=torch.int32, device="cuda"), n, out, alpha_only=True)
+    g.interp_estimate(cx, cy, out, nbase, cap, state, max_count=n)
+    S = {"cx": cx.cpu().numpy().copy(), "cy": cy.cpu().numpy().copy(), "side": side.cpu().numpy().copy()}
+    for q in NAMES:
+        S[q] = out[q].cpu().numpy().astype(np.float64)
+    S["lev"] = np.zeros(cap, dtype=np.int64)
+    S["ci"] = np.zeros(cap, dtype=np.int64)
+    S["cj"] = np.zeros(cap, dtype=np.int64)
+    ii = np.floor((S["cx"][:n] - x0) / h0).astype(np.int64)
+    jj = np.floor((S["cy"][:n] - y0) / h0).astype(np.int64)
+    S["ci"][:n], S["cj"][:n] = ii, jj
+    S["table"] = {(0, int(a), int(b)): c for c, (a, b) in enumerate(zip(ii, jj))}
+    est = mirror_estimates(S, range(n), nbase)
+    got = np.stack([S["kappa"][:n], S["g1"][:n], S["g2"][:n]], axis=1)
+    np.testing.assert_allclose(got, est, rtol=1e-6, atol=1e-6 * np.abs(est).max())
+    idx = torch.zeros(8 * max(sched), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    refined = torch.zeros(max(sched), dtype=torch.int32, device="cuda")
+    filled_all = []
+    for r, k in enumerate(sched):
+        order, uniform, shoot = numpy_round_deflections(S, n, k, nbase, tol)
+        g.refine_interp_round(cx, cy, side, out, n, k, nbase, tol, cap, state, idx, count, refined=refined,
+                              deflections=True)
+        cnt = int(count.item())
+        say(f"  round {r}: refine {k}, uniform {int(uniform.sum())}, walk {cnt}")
+        np.testing.assert_array_equal(refined[:k].cpu().numpy(), order)
+        assert cnt == shoot.size
+        np.testing.assert_array_equal(idx[:cnt].cpu().numpy(), shoot)
+        m = n + 8 * k
+        np.testing.assert_array_equal(cx[:m].cpu().numpy(), S["cx"][:m])
+        filled = np.setdiff1d(np.arange(n, m), shoot)
+        for q in NAMES:
+            if filled.size:
+                gq = out[q][:m].cpu().numpy()[filled].astype(np.float64)
+                np.testing.assert_allclose(gq, S[q][filled], rtol=1e-6, atol=1e-7 * np.abs(S[q][filled]).max())
+        g.shoot_indexed(tree, cx, cy, idx, cnt, out, alpha_only=True)
+        g.interp_estimate(cx, cy, out, nbase, cap, state, idx=idx, count=count, max_count=8 * k)
+        for q in ("a1", "a2"):
+            S[q][shoot] = out[q].cpu().numpy()[shoot].astype(np.float64)
+        S["a1"][filled] = out["a1"].cpu().numpy()[filled].astype(np.float64)
+        S["a2"][filled] = out["a2"].cpu().numpy()[filled].astype(np.float64)
+        est = mirror_estimates(S, shoot, nbase)
+        got = np.stack([out[q].cpu().numpy()[shoot].astype(np.float64) for q in ("kappa", "g1", "g2")], axis=1)
+        np.testing.assert_allclose(got, est, rtol=1e-6, atol=1e-6 * max(np.abs(est).max(), 1e-30))
+        for q in ("kappa", "g1", "g2"):
+            S[q][n:m] = out[q].cpu().numpy()[n:m].astype(np.float64)
+        filled_all.append(filled)
+        n = m
+    filled_all = np.concatenate(filled_all)
+    say(f"  {filled_all.size} of {n - bx.size} new cells interpolated")
+    assert filled_all.size > 0
+    walked = g.shoot(tree, dev(S["cx"][filled_all]), dev(S["cy"][filled_all]), alpha_only=True)
+    a_int = np.stack([out["a1"].cpu().numpy()[filled_all], out["a2"].cpu().numpy()[filled_all]], 1)
+    a_w = np.stack([walked["a1"].cpu().numpy(), walked["a2"].cpu().numpy()], 1).astype(np.float64)
+    err = np.linalg.norm(a_int - a_w, axis=1) / np.linalg.norm(a_w, axis=1)
+    say(f"  interpolated alpha vs walk: max {err.max():.2e} median {np.median(err):.2e}")
+    assert err.max() <= 1e-3
