@@ -407,13 +407,18 @@ __global__ __launch_bounds__(kBlock) void k_list_ranges(int n, const uint32_t* _
 // Reach of each box's big-particle list: the bounding box of its particles'
 // supports, widened by far more than the rounding of any distance test, so
 // that a ray group whose bounding box misses it cannot be inside any of them.
+// One wavefront per box: the lanes stride over the list (coalesced records)
+// and a min/max reduction across the wavefront ends it.
 __global__ __launch_bounds__(kBlock) void k_list_reach(BoxArrays b, int ncells, const PRec* __restrict__ lst,
                                                       double* __restrict__ lreach)
 {
-    const int c = blockIdx.x * kBlock + threadIdx.x;
-    if (c >= ncells) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int c = blockIdx.x * (kBlock / kWave) + (int)(threadIdx.x / kWave);
+    if (c >= ncells) return; // uniform across the wavefront
+    const int lb = b.lbeg[c], le = b.lend[c];
+    if (lb >= le) return; // no list: the walk never reads this box's reach
     double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
-    for (int k = b.lbeg[c]; k < b.lend[c]; ++k) {
+    for (int k = lb + lane; k < le; k += kWave) {
         const PRec pr = lst[k];
         const double r = sqrt(pr.qs2) * (1.0 + 4e-9);
         const double mx = r + 4.5e-16 * fabs(pr.x), my = r + 4.5e-16 * fabs(pr.y);
@@ -422,10 +427,11 @@ __global__ __launch_bounds__(kBlock) void k_list_reach(BoxArrays b, int ncells, 
         y0 = fmin(y0, pr.y - my);
         y1 = fmax(y1, pr.y + my);
     }
-    lreach[4 * (size_t)c + 0] = x0;
-    lreach[4 * (size_t)c + 1] = x1;
-    lreach[4 * (size_t)c + 2] = y0;
-    lreach[4 * (size_t)c + 3] = y1;
+    x0 = wave_min(x0);
+    x1 = wave_max(x1);
+    y0 = wave_min(y0);
+    y1 = wave_max(y1);
+    if (lane < 4) lreach[4 * (size_t)c + lane] = lane == 0 ? x0 : lane == 1 ? x1 : lane == 2 ? y0 : y1;
 }
 
 // ---------------------------------------------------------------- moments
@@ -778,7 +784,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     const int lw = radix_sort_u32(lk0, lv0, lk1, lv1, n, passes, hist, st);
     hipLaunchKernelGGL(k_list_ranges, dim3(gb), dim3(kBlock), 0, st, n, lw ? lk1 : lk0, lw ? lv1 : lv0, unlisted, xs,
                        ys, ms, ss, kind, q, norm, b, lst, sync);
-    hipLaunchKernelGGL(k_list_reach, dim3(gc), dim3(kBlock), 0, st, b, nc, lst, lreach);
+    hipLaunchKernelGGL(k_list_reach, dim3(ceil_div(nc, kBlock / kWave)), dim3(kBlock), 0, st, b, nc, lst, lreach);
     for (int l = kMaxLevel; l >= 0; --l)
         if (lt.cnt[l] > 0) {
             const dim3 g(ceil_div(lt.cnt[l], kBlock)), blk(kBlock);

@@ -3,7 +3,8 @@
 // Sort pass = histogram per 2048-key tile -> one exclusive scan of the
 // digit-major histogram -> scatter, where each tile ranks its keys stably with
 // wave ballots (8 ballots give the lanes holding the same digit) and per-wave
-// digit counts in LDS.  Loads are coalesced; the scatter writes runs per digit.
+// digit counts in LDS, reorders them by digit in LDS and writes each digit's
+// run with consecutive lanes.  Loads and stores are coalesced.
 #include "common.hpp"
 
 namespace glm {
@@ -126,15 +127,32 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const K* keys, int64_t n,
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one tile: the keys are ranked stably per digit (wave ballots and
+// per-wave digit counts in LDS, chunk by chunk), placed in LDS in digit order,
+// then written out slot by slot, so that consecutive lanes write consecutive
+// addresses of the same digit's run.  offs holds the exclusive scan of the
+// digit-major histogram with the total n at offs[256 nb].
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K* kin, const uint32_t* vin, K* kout,
                                                          uint32_t* vout, int64_t n, int shift,
                                                          const int32_t* offs, int nb)
 {
-    __shared__ uint32_t run[256];
+    __shared__ K sk[kTile];
+    __shared__ uint32_t sv[kTile];
+    __shared__ uint32_t lrun[256];  // next free tile slot of digit d
+    __shared__ uint32_t gbase[256]; // global position of slot 0 for digit d's run
     __shared__ uint32_t wcnt[kBlock / kWave][256];
-    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
-    run[t] = (uint32_t)offs[(int64_t)t * nb + blockIdx.x];
+    __shared__ uint32_t lw[kBlock / kWave];
+    const int t = threadIdx.x, w = t / kWave;
+    {
+        const int64_t hi = (int64_t)t * nb + blockIdx.x;
+        const uint32_t g0 = (uint32_t)offs[hi];
+        const uint32_t cnt = (uint32_t)offs[hi + 1] - g0;
+        uint32_t tot;
+        const uint32_t l0 = block_excl_scan(cnt, lw, &tot);
+        lrun[t] = l0;
+        gbase[t] = g0 - l0;
+    }
 #pragma unroll
     for (int k = 0; k < kBlock / kWave; ++k) wcnt[k][t] = 0;
     __syncthreads();
@@ -157,10 +175,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K* kin, const ui
         if (valid && lrank == 0) wcnt[w][d] = (uint32_t)__popcll(same);
         __syncthreads();
         if (valid) {
-            uint32_t pos = run[d] + lrank;
+            uint32_t pos = lrun[d] + lrank;
             for (int k = 0; k < w; ++k) pos += wcnt[k][d];
-            kout[pos] = key;
-            vout[pos] = val;
+            sk[pos] = key;
+            sv[pos] = val;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -169,8 +187,15 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K* kin, const ui
             add += wcnt[k][t];
             wcnt[k][t] = 0;
         }
-        run[t] += add;
+        lrun[t] += add;
         __syncthreads();
+    }
+    const int m = (int)(n - base < (int64_t)kTile ? n - base : (int64_t)kTile);
+    for (int q = t; q < m; q += kBlock) {
+        const K key = sk[q];
+        const uint32_t pos = gbase[(uint32_t)(key >> shift) & 255u] + (uint32_t)q;
+        kout[pos] = key;
+        vout[pos] = sv[q];
     }
 }
 

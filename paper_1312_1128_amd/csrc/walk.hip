@@ -249,6 +249,10 @@ __global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __rest
 
 // ------------------------------------------------------------ ray staging
 
+// blocks of the first pass of the ray bounding box (enough waves in flight to
+// stream the coordinates at full bandwidth)
+constexpr int kRayBboxBlocks = 1024;
+
 __global__ __launch_bounds__(kBlock) void k_ray_bbox(const double* __restrict__ x, const double* __restrict__ y,
                                                     int64_t n, double* __restrict__ part)
 {
@@ -445,7 +449,7 @@ RayLayout ray_layout(int64_t nrays)
     L.xs = a.take(8ull * nrays);
     L.ys = a.take(8ull * nrays);
     L.hist = a.take(4ull * radix_hist_words(nrays));
-    L.part = a.take(sizeof(double) * 4 * 257);
+    L.part = a.take(sizeof(double) * 4 * (kRayBboxBlocks + 1));
     L.sbox = a.take(64);
     L.split = walk_split(nrays);
     L.parts = a.take(sizeof(Partial) * (size_t)split_slots(nrays));
@@ -465,7 +469,7 @@ glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* w
     double* ys = reinterpret_cast<double*>(W + L.ys);
     uint32_t* hist = reinterpret_cast<uint32_t*>(W + L.hist);
     double* part = reinterpret_cast<double*>(W + L.part);
-    const int nbb = 256;
+    const int nbb = kRayBboxBlocks;
     const int g = ceil_div(nrays, kBlock);
     hipLaunchKernelGGL(k_ray_bbox, dim3(nbb), dim3(kBlock), 0, st, rx, ry, nrays, part);
     hipLaunchKernelGGL(k_ray_root, dim3(1), dim3(kBlock), 0, st, part, nbb, part + 4 * nbb);
@@ -689,7 +693,7 @@ glm_status split_box_device(const TreeStorage& ts, const double* rx, const doubl
 {
     char* W = static_cast<char*>(ws);
     double* part = reinterpret_cast<double*>(W + L.part);
-    const int nbb = 256;
+    const int nbb = kRayBboxBlocks;
     if (!have_bbox) {
         hipLaunchKernelGGL(k_ray_bbox, dim3(nbb), dim3(kBlock), 0, st, rx, ry, nrays, part);
         hipLaunchKernelGGL(k_ray_root, dim3(1), dim3(kBlock), 0, st, part, nbb, part + 4 * nbb);
