@@ -53,7 +53,7 @@ typedef enum {
 
 /* flags */
 #define GLM_ALPHA_ONLY 1u   /* skip kappa and gamma (Sec. 3.2: the solver's option) */
-#define GLM_NO_KAHAN 2u     /* plain FP32 accumulation of alpha (debug) */
+#define GLM_FP32_ALPHA 2u   /* alpha terms summed in plain FP32, not FP64 (debug) */
 #define GLM_RAYS_ORDERED 4u /* rays already in a spatially coherent order: skip the ray sort */
 /* build: the particles are truncated NFW halos (Sec. 3.2: analytic halos as
  * particles), not Gaussians.  A halo of mass m, size s = R (its truncation
@@ -195,7 +195,7 @@ GLM_API glm_status glm_shoot_workspace_bytes(int64_t nrays, size_t* bytes);
  *   workspace: device buffer of at least glm_shoot_workspace_bytes(nrays)
  *   (ray sort, and for small ray counts the partial sums of several
  *   wavefronts per ray group, each walking one range of the box array).
- *   flags: GLM_ALPHA_ONLY, GLM_NO_KAHAN, GLM_RAYS_ORDERED (or-ed with the
+ *   flags: GLM_ALPHA_ONLY, GLM_FP32_ALPHA, GLM_RAYS_ORDERED (or-ed with the
  *   tree's).
  * nrays may be 0 (nothing is launched).
  */

@@ -14,11 +14,11 @@ import ctypes
 import torch
 
 from . import _capi
-from ._capi import (GLM_ALPHA_ONLY, GLM_NFW_HALOS, GLM_NO_KAHAN, GLM_RAYS_ORDERED, GlamerError,  # noqa: F401
+from ._capi import (GLM_ALPHA_ONLY, GLM_NFW_HALOS, GLM_FP32_ALPHA, GLM_RAYS_ORDERED, GlamerError,  # noqa: F401
                     GlmParams, GlmTreeInfo)
 
 __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
-           "GLM_NFW_HALOS", "GLM_NO_KAHAN", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
+           "GLM_NFW_HALOS", "GLM_FP32_ALPHA", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
            "refine_schedule", "RefinementRun", "autotune", "smoothing_lengths", "interp_init",
            "refine_interp_round", "shoot_indexed", "shoot_potential", "knn", "knn_workspace_bytes"]
 
@@ -117,14 +117,14 @@ class Tree:
         return out
 
 
-def shoot(tree: Tree, rx, ry, counts: bool = False, alpha_only: bool = False, kahan: bool = True,
+def shoot(tree: Tree, rx, ry, counts: bool = False, alpha_only: bool = False, fp32_alpha: bool = False,
           ordered: bool = False, out=None, workspace=None):
     """Forward walk: returns a dict of float32 tensors a1, a2 (and kappa, g1, g2
     unless alpha_only), plus counts [R, 4] int32 if requested."""
     rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
     R = rx.shape[0]
     dev = rx.device
-    flags = (GLM_ALPHA_ONLY if alpha_only else 0) | (0 if kahan else GLM_NO_KAHAN) | \
+    flags = (GLM_ALPHA_ONLY if alpha_only else 0) | (GLM_FP32_ALPHA if fp32_alpha else 0) | \
             (GLM_RAYS_ORDERED if ordered else 0)
     if out is None:
         names = ["a1", "a2"] if alpha_only else ["a1", "a2", "kappa", "g1", "g2"]

@@ -15,7 +15,7 @@ GLM_ESTATE = -4
 GLM_EDATA = -5
 
 GLM_ALPHA_ONLY = 1
-GLM_NO_KAHAN = 2
+GLM_FP32_ALPHA = 2
 GLM_RAYS_ORDERED = 4
 GLM_NFW_HALOS = 8
 GLM_INTERP_DEFLECTIONS = 1

@@ -52,7 +52,7 @@ static glm_status check_params(const glm_params* p)
     if (!(p->q > 0.0) || !isfinite(p->q)) return fail(GLM_EINVAL, "q must be finite and > 0");
     if (p->leaf_size < 1 || p->leaf_size > 64) return fail(GLM_EINVAL, "leaf_size must be in 1..64");
     if (p->order < 0 || p->order > kMaxOrder) return fail(GLM_EINVAL, "order must be in 0..12");
-    if (p->flags & ~(GLM_ALPHA_ONLY | GLM_NO_KAHAN | GLM_RAYS_ORDERED | GLM_NFW_HALOS))
+    if (p->flags & ~(GLM_ALPHA_ONLY | GLM_FP32_ALPHA | GLM_RAYS_ORDERED | GLM_NFW_HALOS))
         return fail(GLM_EINVAL, "unknown flag bits");
     return GLM_OK;
 }
@@ -193,7 +193,7 @@ glm_status glm_shoot(const glm_tree* t, const double* rx, const double* ry, int6
     if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays must be in 0 .. 2^31 - 256");
     if (nrays == 0) return GLM_OK;
     if (!rx || !ry || !a1 || !a2) return fail(GLM_EINVAL, "rx, ry, a1, a2 must be device pointers");
-    if (flags & ~(GLM_ALPHA_ONLY | GLM_NO_KAHAN | GLM_RAYS_ORDERED)) return fail(GLM_EINVAL, "unknown flag bits");
+    if (flags & ~(GLM_ALPHA_ONLY | GLM_FP32_ALPHA | GLM_RAYS_ORDERED)) return fail(GLM_EINVAL, "unknown flag bits");
     flags |= t->ts.params.flags;
     if (!(flags & GLM_ALPHA_ONLY) && (!kappa || !g1 || !g2))
         return fail(GLM_EINVAL, "kappa, g1, g2 are required unless GLM_ALPHA_ONLY");
@@ -277,7 +277,7 @@ glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* 
     if (nrays == 0) return GLM_OK;
     if (!rx || !ry) return fail(GLM_EINVAL, "rx, ry must be device pointers");
     if (!ga1 && !ga2 && !gk && !gg1 && !gg2) return fail(GLM_EINVAL, "every cotangent is NULL");
-    if (flags & ~(GLM_NO_KAHAN | GLM_RAYS_ORDERED | GLM_ALPHA_ONLY)) return fail(GLM_EINVAL, "unknown flag bits");
+    if (flags & ~(GLM_FP32_ALPHA | GLM_RAYS_ORDERED | GLM_ALPHA_ONLY)) return fail(GLM_EINVAL, "unknown flag bits");
     {
         const size_t need = ray_layout(nrays).bytes;
         if (!workspace || workspace_bytes < need)
@@ -304,7 +304,7 @@ glm_status glm_shoot_batched(const glm_lens_rays* lenses, int nlens, uint32_t fl
                              size_t workspace_bytes, void* stream)
 {
     if (!lenses || nlens < 1 || nlens > 4096) return fail(GLM_EINVAL, "lenses must hold 1..4096 entries");
-    if (flags & ~(GLM_ALPHA_ONLY | GLM_NO_KAHAN)) return fail(GLM_EINVAL, "unknown flag bits");
+    if (flags & ~(GLM_ALPHA_ONLY | GLM_FP32_ALPHA)) return fail(GLM_EINVAL, "unknown flag bits");
     std::vector<int64_t> counts(nlens);
     std::vector<std::pair<double, int>> rank(nlens);
     int order = -1;
@@ -447,7 +447,7 @@ glm_status glm_shoot_indexed(const glm_tree* t, const double* cx, const double* 
     if (count < 0 || count > 0x7fffff00) return fail(GLM_EINVAL, "count out of range");
     if (count == 0) return GLM_OK;
     if (!cx || !cy || !idx || !a1 || !a2) return fail(GLM_EINVAL, "NULL device pointer");
-    if (flags & ~(GLM_ALPHA_ONLY | GLM_NO_KAHAN)) return fail(GLM_EINVAL, "unknown flag bits");
+    if (flags & ~(GLM_ALPHA_ONLY | GLM_FP32_ALPHA)) return fail(GLM_EINVAL, "unknown flag bits");
     flags |= t->ts.params.flags;
     if (!(flags & GLM_ALPHA_ONLY) && (!kappa || !g1 || !g2))
         return fail(GLM_EINVAL, "kappa, g1, g2 are required unless GLM_ALPHA_ONLY");

@@ -1,5 +1,5 @@
 // Plain direct summation over every particle (the theta = 0 limit of the
-// tree, Sec. 5.1), FP32 with compensated alpha or FP64, for truncated
+// tree, Sec. 5.1), FP32 terms summed in FP64 for alpha and shear, or FP64 throughout, for truncated
 // Gaussians or truncated NFW halos (and point masses with either).  One thread per ray;
 // particles stream through LDS in tiles of 256 and every lane reads the same
 // record (LDS broadcast).
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void k_direct32(const double* __restrict__ 
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool valid = r < nr;
     const double X = valid ? rx[r] : 0.0, Y = valid ? ry[r] : 0.0;
-    Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+    Acc A = {};
     for (int base = 0; base < n; base += kBlock) {
         const int j = base + threadIdx.x;
         PRec t;
@@ -52,14 +52,13 @@ __global__ __launch_bounds__(kBlock) void k_direct32(const double* __restrict__ 
         __syncthreads();
     }
     if (!valid) return;
-    a1[r] = A.a1;
-    a2[r] = A.a2;
+    a1[r] = (float)alpha1(A);
+    a2[r] = (float)alpha2(A);
     if (!AONLY) {
         ka[r] = A.k;
         g1[r] = (float)A.g1;
         g2[r] = (float)A.g2;
     }
-    (void)A.b1;
 }
 
 // FP64: the brute-force sum term by term (Sec. 3.1 kernel or the NFW halo of

@@ -8,16 +8,19 @@
 
 namespace glm {
 
-// Per-lane accumulators.  alpha is summed in FP32 with Kahan compensation;
-// the point-mass terms of big-list particles that a ray lies inside (added
-// once with each sign, see leaf_particle) go to an FP64 balance (b1, b2)
-// where they cancel without leaving FP32 rounding of size m / r behind.  The
-// shear, a sum of large terms of both signs that nearly cancel near a mass
-// concentration, takes its FP32 terms into FP64 accumulators (the balanced
-// point terms included); kappa, a sum of positive terms, stays FP32.
+// Per-lane accumulators.  Deflection and shear are sums of large terms of
+// both signs that nearly cancel near a mass concentration: their FP32 terms
+// are added into FP64 accumulators (an FP64 add costs what an FP32 add costs
+// on this chip, and is cheaper than compensated FP32 summation).  The
+// point-mass terms of big-list particles that a ray lies inside (added once
+// with each sign, see leaf_particle) thus cancel there without leaving FP32
+// rounding of size m / r behind.  kappa, a sum of positive terms, stays FP32.
+// The debug mode without FP64 alpha sums the alpha terms in plain FP32 (p1,
+// p2) and keeps only the balanced point terms in a1, a2.
 struct Acc {
-    float a1, c1, a2, c2, k;
-    double g1, g2, b1, b2;
+    double a1, a2;
+    float p1, p2, k;
+    double g1, g2;
     double ps; // lensing potential (FP64 sum of FP32 terms), when asked for
 };
 
@@ -56,19 +59,22 @@ __device__ inline float gauss_psi(const PRec& pr, double r2, double psiK, int te
     return 0.5f * __logf((float)pr.qs2) - (float)((psiK - ein(u, terms)) * (0.5 * (double)invC));
 }
 
-// compensated (Kahan) summation step; plain FP32 addition when KAHAN is false
-template <bool KAHAN>
-__device__ inline void kadd(float& s, float& c, float v)
+// alpha += (v1, v2): in FP64, or in plain FP32 when F64A is false (debug)
+template <bool F64A>
+__device__ inline void add_alpha(Acc& A, float v1, float v2)
 {
-    if constexpr (KAHAN) {
-        const float y = v - c;
-        const float t = s + y;
-        c = (t - s) - y;
-        s = t;
+    if constexpr (F64A) {
+        A.a1 += (double)v1;
+        A.a2 += (double)v2;
     } else {
-        s += v;
+        A.p1 += v1;
+        A.p2 += v2;
     }
 }
+
+// The alpha of one ray from its accumulators
+__device__ inline double alpha1(const Acc& A) { return A.a1 + (double)A.p1; }
+__device__ inline double alpha2(const Acc& A) { return A.a2 + (double)A.p2; }
 
 // FP64 offset and its squared length, rounded exactly as written (the inside
 // and opening decisions must not depend on FMA contraction).
@@ -269,11 +275,10 @@ __device__ inline void point_terms(float m, float f1, float f2, float ir2, float
 
 // Accumulate alpha += coef * (f1, f2) and gamma -= Gam * (cos 2phi, sin 2phi)
 // (with ir2 = 1 / r^2: cos 2phi = (f1^2 - f2^2) ir2, sin 2phi = 2 f1 f2 ir2).
-template <bool AONLY, bool KAHAN>
+template <bool AONLY, bool F64A>
 __device__ inline void add_radial(float coef, float Gam, float f1, float f2, float ir2, Acc& A)
 {
-    kadd<KAHAN>(A.a1, A.c1, coef * f1);
-    kadd<KAHAN>(A.a2, A.c2, coef * f2);
+    add_alpha<F64A>(A, coef * f1, coef * f2);
     if (!AONLY) {
         const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = 2.0f * f1 * f2 * ir2;
         A.g1 -= (double)(Gam * c2);
@@ -284,14 +289,14 @@ __device__ inline void add_radial(float coef, float Gam, float f1, float f2, flo
 // One particle of a leaf for this lane (a direct-sum term).
 //  - listed particle: a point mass (its box's moments and leaf treat it as
 //    one).  A lane inside its support also gets Gaussian - point from the
-//    list of the box that holds it, so that lane's point part goes to the
-//    FP64 balance, where it cancels exactly.
+//    list of the box that holds it; the two point parts meet in the FP64
+//    alpha and shear sums, where they cancel exactly.
 //  - unlisted particle: the truncated Gaussian of Sec. 3.1 inside the
 //    support, a point mass outside.
 // All cases share one select-based path (no divergent branches).  The point
 // terms are formed without FMA contraction, exactly as in point_terms, so a
 // balanced pair cancels bit for bit.
-template <bool AONLY, bool KAHAN, bool PSI = false, int KIND = kKindGauss>
+template <bool AONLY, bool F64A, bool PSI = false, int KIND = kKindGauss>
 __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A, double psiK = 0.0,
                                      int terms = 1, float invC = 0.0f)
 {
@@ -314,10 +319,13 @@ __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A,
         if (!AONLY) A.k += gauss ? Kg : 0.0f;
     }
     const float v1 = coef * f1, v2 = coef * f2;
-    kadd<KAHAN>(A.a1, A.c1, balance ? 0.0f : v1);
-    kadd<KAHAN>(A.a2, A.c2, balance ? 0.0f : v2);
-    A.b1 += (double)(balance ? v1 : 0.0f);
-    A.b2 += (double)(balance ? v2 : 0.0f);
+    if constexpr (F64A) {
+        add_alpha<true>(A, v1, v2);
+    } else {
+        add_alpha<false>(A, balance ? 0.0f : v1, balance ? 0.0f : v2);
+        A.a1 += (double)(balance ? v1 : 0.0f);
+        A.a2 += (double)(balance ? v2 : 0.0f);
+    }
     if (!AONLY) {
         const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = (2.0f * f1 * f2) * ir2;
         A.g1 -= (double)(Gam * c2);
@@ -332,8 +340,8 @@ __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A,
 
 // One entry of the big-particle list of a visited box (Sec. 3.2): a lane
 // inside the particle's support adds Gaussian - point (the tree part counted
-// the particle as a point mass); the point part goes to the FP64 balance.
-template <bool AONLY, bool KAHAN, bool PSI = false, int KIND = kKindGauss>
+// the particle as a point mass); the point part is taken off in FP64.
+template <bool AONLY, bool F64A, bool PSI = false, int KIND = kKindGauss>
 __device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A, int& hits, double psiK = 0.0,
                                      int terms = 1, float invC = 0.0f)
 {
@@ -346,10 +354,10 @@ __device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A,
     point_terms(pr.m, f1, f2, ir2, P);
     float Ag, Gg, Kg;
     profile_terms<KIND>(pr, r2, r2f, ir2, &Ag, &Gg, &Kg);
-    add_radial<AONLY, KAHAN>(Ag, Gg, f1, f2, ir2, A);
+    add_radial<AONLY, F64A>(Ag, Gg, f1, f2, ir2, A);
     hits++;
-    A.b1 -= (double)P[0];
-    A.b2 -= (double)P[1];
+    A.a1 -= (double)P[0];
+    A.a2 -= (double)P[1];
     if (!AONLY) {
         A.k += Kg;
         A.g1 -= (double)P[2];
@@ -364,7 +372,7 @@ __device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A,
 // Multipole expansion of an accepted box about its centre of mass (Sec. 3.2):
 //   alpha1 - i alpha2 = M v P(t),  gamma1 - i gamma2 = -M v^2 (P(t) + t P'(t)),
 // v = 1/w, t = r_cm v, P(t) = 1 + sum_{k>=2} Qn_k t^k, Qn_k = Q_k / (M r_cm^k).
-template <int P, bool AONLY, bool KAHAN, bool PSI = false>
+template <int P, bool AONLY, bool F64A, bool PSI = false>
 __device__ inline void eval_box(const float* __restrict__ mo, double w1, double w2, Acc& A)
 {
     const float M = mo[0], rcm = mo[1];
@@ -400,8 +408,7 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
     }
     // alpha1 - i alpha2 = M v b
     const float F1 = M * fmaf(v1, b1, -v2 * b2), F2 = M * fmaf(v1, b2, v2 * b1);
-    kadd<KAHAN>(A.a1, A.c1, F1);
-    kadd<KAHAN>(A.a2, A.c2, -F2);
+    add_alpha<F64A>(A, F1, -F2);
     if constexpr (!AONLY) {
         // gamma1 - i gamma2 = -M v^2 (b + t c)
         const float S1 = fmaf(t1, c1, fmaf(-t2, c2, b1)), S2 = fmaf(t1, c2, fmaf(t2, c1, b2));

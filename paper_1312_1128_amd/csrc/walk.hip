@@ -12,7 +12,7 @@
 // big-particle lists are first filtered lane-parallel against the group's
 // bounding box.  Evaluation is FP32: the multipole series is a Horner scheme
 // in t = r_cm / w on moments normalised by M r_cm^k, alpha is accumulated with
-// compensated (Kahan) summation.
+// FP64 accumulation of the FP32 terms.
 #include <math.h>
 
 #include <algorithm>
@@ -27,11 +27,11 @@ namespace {
 
 // The traversal of one 64-ray group (see the file comment).  Every lane of
 // the wave must call it; `valid` lanes carry a ray.
-// MODE: 0 = Kahan-compensated alpha (the product walk), 1 = the same plus
-// per-ray interaction counts, 2 = plain FP32 accumulation.
+// MODE: 0 = alpha summed in FP64 (the product walk), 1 = the same plus
+// per-ray interaction counts, 2 = plain FP32 sum of the alpha terms (debug).
 template <int MODE>
 struct WalkMode {
-    static constexpr bool kahan = MODE != 2;
+    static constexpr bool f64a = MODE != 2;
     static constexpr bool stats = MODE == 1;
 };
 
@@ -39,7 +39,7 @@ template <int P, bool AONLY, int MODE, bool PSI = false, int KIND = kKindGauss>
 __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool valid, int lane, Acc& A, int cnt[4],
                                   int c0, int c1)
 {
-    constexpr bool KAHAN = WalkMode<MODE>::kahan;
+    constexpr bool F64A = WalkMode<MODE>::f64a;
     constexpr bool STATS = WalkMode<MODE>::stats;
     const double gx0 = wave_min(valid ? X : INFINITY), gx1 = wave_max(valid ? X : -INFINITY);
     const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
@@ -68,7 +68,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                     const int k = __ffsll((unsigned long long)cm) - 1;
                     cm &= cm - 1;
                     const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
-                    if (act) list_particle<AONLY, KAHAN, PSI, KIND>(pr, X, Y, A, n_hit, T.psiK, T.einTerms, T.invC);
+                    if (act) list_particle<AONLY, F64A, PSI, KIND>(pr, X, Y, A, n_hit, T.psiK, T.einTerms, T.invC);
                 }
             }
         }
@@ -78,7 +78,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
         const bool opn = act && !acc;
         if constexpr (STATS) n_acc += acc;
         if (__any(acc)) {
-            if (acc) eval_box<P, AONLY, KAHAN, PSI>(T.mom + (size_t)cur * mom_stride(P), w1, w2, A);
+            if (acc) eval_box<P, AONLY, F64A, PSI>(T.mom + (size_t)cur * mom_stride(P), w1, w2, A);
         }
         if (h.info & kInfoLeaf) {
             if (__any(opn)) {
@@ -88,7 +88,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                 }
                 for (int j = e.pbeg; j < e.pend; ++j) {
                     const PRec pr = T.prt[j];
-                    if (opn) leaf_particle<AONLY, KAHAN, PSI, KIND>(pr, X, Y, A, T.psiK, T.einTerms, T.invC);
+                    if (opn) leaf_particle<AONLY, F64A, PSI, KIND>(pr, X, Y, A, T.psiK, T.einTerms, T.invC);
                 }
             }
             cur = cur + 1;
@@ -108,8 +108,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
 template <bool AONLY, bool STATS, bool PSI = false>
 __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, const WalkOut& out)
 {
-    // fold the FP64 balance of the big-particle point terms into the result
-    const double a1 = ((double)A.a1 - (double)A.c1) + A.b1, a2 = ((double)A.a2 - (double)A.c2) + A.b2;
+    const double a1 = alpha1(A), a2 = alpha2(A);
     out.a1[o] = (float)a1;
     out.a2[o] = (float)a2;
     if constexpr (PSI) {
@@ -159,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __rest
         c0 = 0;
         c1 = nc;
     }
-    Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    Acc A = {};
     int cnt[4];
     walk_group<P, AONLY, MODE, PSI, KIND>(T, X, Y, valid, lane, A, cnt, c0, c1);
     if (!valid) return;
@@ -168,16 +167,12 @@ __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __rest
         return;
     }
     Partial q;
-    q.a1 = A.a1;
-    q.c1 = A.c1;
-    q.a2 = A.a2;
-    q.c2 = A.c2;
+    q.a1 = alpha1(A);
+    q.a2 = alpha2(A);
     q.k = A.k;
     q.pad = 0.0f;
     q.g1 = A.g1;
     q.g2 = A.g2;
-    q.b1 = A.b1;
-    q.b2 = A.b2;
     for (int i = 0; i < 4; ++i) q.cnt[i] = WalkMode<MODE>::stats ? cnt[i] : 0;
     parts[(int64_t)k * nrays + r] = q;
 }
@@ -194,8 +189,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_merge(const Partial* __restrict
     int c[4] = {0, 0, 0, 0};
     for (int k = 0; k < K; ++k) {
         const Partial& q = parts[(int64_t)k * nrays + r];
-        a1 += ((double)q.a1 - (double)q.c1) + q.b1;
-        a2 += ((double)q.a2 - (double)q.c2) + q.b2;
+        a1 += q.a1;
+        a2 += q.a2;
         ka += q.k;
         g1 += q.g1;
         g2 += q.g2;
@@ -240,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __rest
         const bool valid = rl < L.nrays;
         const int64_t gi = L.ray_off + (valid ? rl : 0);
         const double X = valid ? xs[gi] : 0.0, Y = valid ? ys[gi] : 0.0;
-        Acc A = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        Acc A = {};
         int cnt[4];
         walk_group<P, AONLY, MODE, false, KIND>(L.tree, X, Y, valid, lane, A, cnt, 0, L.tree.ncells);
         if (valid) write_out<AONLY, false>(A, cnt, (int64_t)perm[gi] - L.ray_off, L.out);
@@ -603,17 +598,17 @@ BatchLayout batch_layout(int nlens, int64_t total)
 
 template <int P, bool AONLY>
 void launch_batched(const BatchLens* table, int nlens, const int64_t* gpre, int* counter, const double* xs,
-                    const double* ys, const uint32_t* perm, int64_t items, int kahan, int kind, hipStream_t st)
+                    const double* ys, const uint32_t* perm, int64_t items, int f64a, int kind, hipStream_t st)
 {
     const int blocks = (int)std::min<int64_t>((items + 3) / 4, 256 * 8);
 #define GLM_WALK(MD, KD)                                                                                    \
     hipLaunchKernelGGL((k_walk_batched<P, AONLY, MD, KD>), dim3(blocks), dim3(kBlock), 0, st, table, nlens, gpre, \
                        counter, xs, ys, perm)
     if (kind == kKindNfw) {
-        if (kahan) GLM_WALK(0, kKindNfw);
+        if (f64a) GLM_WALK(0, kKindNfw);
         else GLM_WALK(2, kKindNfw);
     } else {
-        if (kahan) GLM_WALK(0, kKindGauss);
+        if (f64a) GLM_WALK(0, kKindGauss);
         else GLM_WALK(2, kKindGauss);
     }
 #undef GLM_WALK
@@ -669,14 +664,14 @@ glm_status shoot_batched_device(const BatchLens* host_table, int nlens, int orde
     const uint64_t* ks = w ? k1 : k0;
     const uint32_t* perm = w ? v1 : v0;
     hipLaunchKernelGGL(k_batch_gather, dim3(g), dim3(kBlock), 0, st, dtab, droff, ks, perm, total, xs, ys);
-    const int kahan = (flags & GLM_NO_KAHAN) ? 0 : 1;
+    const int f64a = (flags & GLM_FP32_ALPHA) ? 0 : 1;
     const int kind = host_table[0].tree.kind; // every lens of a batch has the same particle kind
 #define GLM_CASE(PP)                                                                                     \
     case PP:                                                                                             \
         if (flags & GLM_ALPHA_ONLY)                                                                      \
-            launch_batched<PP, true>(dtab, nlens, dgpre, counter, xs, ys, perm, items, kahan, kind, st); \
+            launch_batched<PP, true>(dtab, nlens, dgpre, counter, xs, ys, perm, items, f64a, kind, st); \
         else                                                                                             \
-            launch_batched<PP, false>(dtab, nlens, dgpre, counter, xs, ys, perm, items, kahan, kind, st);\
+            launch_batched<PP, false>(dtab, nlens, dgpre, counter, xs, ys, perm, items, f64a, kind, st);\
         break;
     switch (order) {
         GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
@@ -727,8 +722,8 @@ glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* r
         glm_status rc = split_box_device(ts, rx, ry, nrays, ws, L, !(flags & GLM_RAYS_ORDERED), &split_box, st);
         if (rc != GLM_OK) return rc;
     }
-    // counts requested: Kahan walk with counters; else plain or Kahan walk
-    const int mode = counts ? 1 : ((flags & GLM_NO_KAHAN) ? 2 : 0);
+    // counts requested: the product walk with counters; else the product or the plain-FP32 walk
+    const int mode = counts ? 1 : ((flags & GLM_FP32_ALPHA) ? 2 : 0);
     if (flags & GLM_ALPHA_ONLY)
         dispatch_walk<true>(ts.params.order, ts.dev, sr.xs, sr.ys, sr.perm, nrays,
                             WalkOut{a1, a2, nullptr, nullptr, nullptr, counts}, mode, K, parts, split_box, st);

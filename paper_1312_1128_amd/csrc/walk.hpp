@@ -93,8 +93,8 @@ inline int64_t split_slots(int64_t nrays)
 
 // Partial sums of one ray over one range of boxes (merged by k_walk_merge).
 struct alignas(16) Partial {
-    float a1, c1, a2, c2, k, pad;
-    double g1, g2, b1, b2;
+    double a1, a2, g1, g2;
+    float k, pad;
     int32_t cnt[4];
 };
 

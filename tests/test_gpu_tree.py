@@ -214,7 +214,7 @@ def test_determinism_and_flags(ora):
     # rays passed as they are (no ray sort): other groups, same per-ray decisions and arithmetic
     od = shoot(tree, rx, ry, ordered=True)
     np.testing.assert_array_equal(od, a)
-    nk = shoot(tree, rx, ry, kahan=False)  # plain FP32 summation of alpha: ~sqrt(terms) eps
+    nk = shoot(tree, rx, ry, fp32_alpha=True)  # plain FP32 summation of alpha: ~sqrt(terms) eps
     ea = np.linalg.norm(nk[:, :2] - a[:, :2], axis=1) / np.linalg.norm(a[:, :2], axis=1)
     assert ea.max() < 1e-5
 

@@ -14,6 +14,8 @@ mathematics fix independently of the oracle's own formulas.
   sign of the spin-2 shear.
 * Many particles in a uniform disk reproduce the analytic deflection of a
   uniform disk (Sec. 5.3: particle approximations of analytic profiles).
+* n point masses on a circle: the closed form of the sum over the ring, and
+  the exact multipole series of the same ring as one tree box.
 """
 import math
 
@@ -204,3 +206,50 @@ def test_uniform_disk_from_particles(ora):
 def test_kernel_norm(ora):
     assert abs(ora.kernel_norm(3.0) - (1 - math.exp(-4.5))) < 1e-15
     assert abs(ora.kernel_norm(1e-4) - (0.5e-8 - 0.125e-16)) < 1e-24
+
+
+def test_point_mass_ring_closed_form(ora):
+    """n equal point masses on a circle, z_j = b w^j (w = e^(2 pi i / n)): the
+    sum over the ring has the closed form sum_j 1/(z - z_j) = n z^(n-1) / (z^n - b^n),
+    so alpha1 - i alpha2 = m n z^(n-1) / (z^n - b^n) and, as its derivative,
+    gamma1 - i gamma2 = -m n z^(n-2) (z^n + (n-1) b^n) / (z^n - b^n)^2 (the
+    point lens of Sec. 3.5 superposed), inside and outside the ring."""
+    n, m, a, phi0 = 7, 0.3, 0.4, 0.37
+    b = a * np.exp(1j * phi0)
+    zj = b * np.exp(2j * math.pi * np.arange(n) / n)
+    g = synth.rng(131)
+    r = np.concatenate([g.uniform(0.02, 0.3, 200), g.uniform(0.5, 3.0, 200)])
+    ph = g.uniform(0, 2 * math.pi, 400)
+    z = r * np.exp(1j * ph)
+    assert np.min(np.abs(z[:, None] - zj[None])) > 0.05
+    out = ora.direct(zj.real, zj.imag, np.full(n, m), np.zeros(n), 3.0, z.real, z.imag)
+    F = m * n * z ** (n - 1) / (z ** n - b ** n)
+    G = -m * n * z ** (n - 2) * (z ** n + (n - 1) * b ** n) / (z ** n - b ** n) ** 2
+    scale = np.abs(F) + m / np.min(np.abs(z[:, None] - zj[None]), axis=1)
+    assert np.all(np.abs((out[:, 0] - 1j * out[:, 1]) - F) <= 1e-13 * scale)
+    gscale = np.abs(G) + m / np.min(np.abs(z[:, None] - zj[None]), axis=1) ** 2
+    assert np.all(np.abs((out[:, 3] - 1j * out[:, 4]) - G) <= 1e-13 * gscale)
+    assert np.all(out[:, 2] == 0.0)
+
+
+def test_point_mass_ring_multipoles(ora):
+    """The same ring as one accepted tree box: its moments about the centre are
+    Q_k = n m b^k when n divides k and 0 otherwise, so the expansion to order p
+    is exactly m n / z (1 + (b/z)^n [p >= n]) for alpha1 - i alpha2 and
+    -m n / z^2 (1 + (n+1) (b/z)^n [p >= n]) for gamma1 - i gamma2 (Sec. 3.2,
+    multipole expansion of a box)."""
+    n, m, a, phi0 = 7, 0.3, 0.4, 0.37
+    b = a * np.exp(1j * phi0)
+    zj = b * np.exp(2j * math.pi * np.arange(n) / n)
+    g = synth.rng(132)
+    z = g.uniform(4.0, 8.0, 64) * np.exp(1j * g.uniform(0, 2 * math.pi, 64))
+    for p in [0, 2, 6, 7, 9, 12]:
+        T = ora.Tree(zj.real, zj.imag, np.full(n, m), np.zeros(n), 3.0, 0.9, n, p)
+        assert T.ncells == 1
+        B, cnt = T.shoot(z.real, z.imag, counts=True)
+        assert np.all(cnt[:, 1] == 1)
+        t = (b / z) ** n if p >= n else 0.0
+        F = m * n / z * (1 + t)
+        G = -m * n / z ** 2 * (1 + (n + 1) * t)
+        assert np.all(np.abs((B[:, 0] - 1j * B[:, 1]) - F) <= 1e-14 * np.abs(F)), p
+        assert np.all(np.abs((B[:, 3] - 1j * B[:, 4]) - G) <= 1e-14 * np.abs(G)), p
