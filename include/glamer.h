@@ -189,9 +189,9 @@ GLM_API glm_status glm_shoot_workspace_bytes(int64_t nrays, size_t* bytes);
  * kappa, g1, g2 may be NULL when the tree was built with GLM_ALPHA_ONLY or
  * `flags` carries it.  counts (device int32, 4 per ray, nullable) receives per
  * ray: boxes visited (opening tests), boxes accepted, leaf particles summed,
- * list particles the ray falls inside.  The walk is FP32 with compensated
- * summation of alpha; ray-particle and ray-box offsets and every accept/inside
- * decision are taken in FP64.
+ * list particles the ray falls inside.  The walk evaluates its terms in FP32
+ * and sums alpha and gamma in FP64; ray-particle and ray-box offsets and every
+ * accept/inside decision are taken in FP64.
  *   workspace: device buffer of at least glm_shoot_workspace_bytes(nrays)
  *   (ray sort, and for small ray counts the partial sums of several
  *   wavefronts per ray group, each walking one range of the box array).
@@ -223,7 +223,7 @@ GLM_API glm_status glm_shoot_potential(const glm_tree* t, const double* rx, cons
 /*
  * Plain direct sum over all n particles (theta = 0 equivalent; Sec. 5.1), for
  * rays (device FP64).  fp64 != 0: outputs are device double arrays; else
- * float arrays with FP32 evaluation and compensated accumulation.
+ * float arrays with FP32 evaluation and FP64 sums of alpha and gamma.
  * out5: device pointers a1, a2, kappa, g1, g2 (kappa/g1/g2 nullable).
  * s may be NULL (point masses).
  */
@@ -235,8 +235,8 @@ GLM_API glm_status glm_shoot_direct(const double* x, const double* y, const doub
  * Plain direct sum over n truncated NFW halos (the profile of GLM_NFW_HALOS;
  * Sec. 3.2 and the halo tests of Sec. 5.1): R = sizes (device FP64, >= 0,
  * 0 = point mass), c = concentration > 0, other arguments as glm_shoot_direct.
- * fp64 != 0 evaluates the profile in FP64; else FP32 terms with compensated
- * alpha, as the tree walk does.
+ * fp64 != 0 evaluates the profile in FP64; else FP32 terms summed in FP64,
+ * as the tree walk does.
  */
 GLM_API glm_status glm_shoot_direct_nfw(const double* x, const double* y, const double* m, const double* R,
                                 int64_t n, double c, const double* rx, const double* ry,
