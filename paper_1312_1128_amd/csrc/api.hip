@@ -50,7 +50,7 @@ static glm_status check_params(const glm_params* p)
     if (!p) return fail(GLM_EINVAL, "params is NULL");
     if (!(p->theta >= 0.0 && p->theta < 1.0)) return fail(GLM_EINVAL, "theta must be in [0, 1)");
     if (!(p->q > 0.0) || !isfinite(p->q)) return fail(GLM_EINVAL, "q must be finite and > 0");
-    if (p->leaf_size < 1 || p->leaf_size > 64) return fail(GLM_EINVAL, "leaf_size must be in 1..64");
+    if (p->leaf_size < 1 || p->leaf_size > kMaxLeafSize) return fail(GLM_EINVAL, "leaf_size must be in 1..64");
     if (p->order < 0 || p->order > kMaxOrder) return fail(GLM_EINVAL, "order must be in 0..12");
     if (p->flags & ~(GLM_ALPHA_ONLY | GLM_FP32_ALPHA | GLM_RAYS_ORDERED | GLM_NFW_HALOS))
         return fail(GLM_EINVAL, "unknown flag bits");

@@ -207,36 +207,56 @@ __global__ __launch_bounds__(kBlock) void k_gather(const uint32_t* __restrict__ 
 // Per Morton position i: number of boxes whose range starts at i.  A box at
 // level l >= 1 exists iff its parent holds more than L particles (every
 // ancestor then does too); the boxes starting at i form a chain from the
-// shallowest new level down to the first leaf.
+// shallowest new level down to the first leaf.  With ls(j) = level_start(j)
+// (the shallowest level at which the box of particle j differs from that of
+// particle j - 1; positions 0 and n count as level 0), the box (i, l) ends
+// at the first j > i with ls(j) <= l, so:
+//  - (i, l) is a leaf iff some j in (i, i + L] has ls(j) <= l (or l is the
+//    deepest level);
+//  - the parent of (i, ls(i)) holds at most L particles only if it starts in
+//    [i - L, i) and ends in (i, i + L].
+// A window of L positions on either side of i decides both; the block keeps
+// ls over its window in LDS.
 __global__ __launch_bounds__(kBlock) void k_topo_count(const uint64_t* __restrict__ K, int n, int L,
                                                       int32_t* __restrict__ cnt, int8_t* __restrict__ lstart,
                                                       BuildSync* __restrict__ sync)
 {
     __shared__ int32_t hist[kMaxLevel + 1];
+    __shared__ int8_t lsw[kBlock + 2 * kMaxLeafSize + 1]; // ls(j) for j in [base - L, base + kBlock + L]
     if (threadIdx.x <= kMaxLevel) hist[threadIdx.x] = 0;
+    const int base = blockIdx.x * kBlock, w0 = base - L, wn = kBlock + 2 * L + 1;
+    for (int t = threadIdx.x; t < wn; t += kBlock) {
+        const int j = w0 + t;
+        lsw[t] = (int8_t)((j <= 0 || j >= n) ? 0 : level_start(K, j));
+    }
     __syncthreads();
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = base + threadIdx.x;
     if (i < n) {
-        const int ls = level_start(K, i);
+        const int ls = lsw[i - w0];
         lstart[i] = (int8_t)ls;
         int c = 0;
         if (ls <= kMaxLevel) {
-            int hi = n;
             bool exists = true;
             if (ls > 0) {
-                const uint64_t P = prefix_at(K[i], ls - 1);
-                const int lo = lower_prefix(K, 0, i, P, ls - 1);
-                hi = upper_prefix(K, i, n, P, ls - 1);
-                exists = (hi - lo) > L;
+                int lo = -1, hi = -1; // the parent's range, if it lies within the window
+                for (int j = i - 1; j >= i - L && j >= 0; --j)
+                    if (lsw[j - w0] <= ls - 1) {
+                        lo = j;
+                        break;
+                    }
+                for (int j = i + 1; j <= i + L && j <= n; ++j)
+                    if (lsw[j - w0] <= ls - 1) {
+                        hi = j;
+                        break;
+                    }
+                exists = lo < 0 || hi < 0 || hi - lo > L;
             }
             if (exists) {
-                for (int l = ls;; ++l) {
-                    const int end = l == 0 ? n : upper_prefix(K, i, hi, prefix_at(K[i], l), l);
-                    ++c;
-                    atomicAdd(&hist[l], 1);
-                    if (end - i <= L || l == kMaxLevel) break;
-                    hi = end;
-                }
+                int mL = kMaxLevel + 1;
+                for (int j = i + 1; j <= i + L && j <= n; ++j) mL = min(mL, (int)lsw[j - w0]);
+                const int last = min(max(ls, mL), kMaxLevel); // level of the chain's leaf
+                c = last - ls + 1;
+                for (int l = ls; l <= last; ++l) atomicAdd(&hist[l], 1);
             }
         }
         cnt[i] = c;
@@ -250,7 +270,11 @@ __global__ void k_sync_counts(const int32_t* __restrict__ cs, int n, BuildSync* 
     if (threadIdx.x == 0 && blockIdx.x == 0) sync->ncells = cs[n];
 }
 
-__global__ __launch_bounds__(kBlock) void k_topo_emit(const uint64_t* __restrict__ K, int n, int L,
+// One thread per box: the particle whose chain holds box idx is the i with
+// cs[i] <= idx < cs[i + 1] (cs = exclusive scan of the per-particle counts);
+// the box's level is ls(i) + (idx - cs[i]) and its end a binary search over
+// the sorted keys.
+__global__ __launch_bounds__(kBlock) void k_topo_emit(const uint64_t* __restrict__ K, int n, int ncells,
                                                      const int32_t* __restrict__ cs, const int8_t* __restrict__ lstart,
                                                      BoxArrays b, BuildSync* __restrict__ sync, LevelTable lt,
                                                      int32_t* __restrict__ levidx)
@@ -263,46 +287,47 @@ __global__ __launch_bounds__(kBlock) void k_topo_emit(const uint64_t* __restrict
         s_maxl = 0;
     }
     __syncthreads();
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    int c0 = 0, c = 0, ls = 0, hi0 = n;
-    if (i < n) {
-        c0 = cs[i];
-        c = cs[i + 1] - c0;
-        ls = lstart[i];
-        if (c > 0 && ls > 0) hi0 = upper_prefix(K, i, n, prefix_at(K[i], ls - 1), ls - 1);
+    const int idx = blockIdx.x * kBlock + threadIdx.x;
+    int i = 0, l = 0;
+    bool leaf = false;
+    if (idx < ncells) {
+        int lo = 0, hi = n; // largest i in [0, n) with cs[i] <= idx
+        while (hi - lo > 1) {
+            const int mid = lo + ((hi - lo) >> 1);
+            if (cs[mid] <= idx) lo = mid;
+            else hi = mid;
+        }
+        i = lo;
+        const int k = idx - cs[i];
+        l = lstart[i] + k;
+        leaf = idx == cs[i + 1] - 1;
+        atomicAdd(&lcnt[l], 1);
     }
-    for (int k = 0; k < c; ++k) atomicAdd(&lcnt[ls + k], 1);
     __syncthreads();
     if (threadIdx.x <= kMaxLevel) {
         lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&sync->levfill[threadIdx.x], lcnt[threadIdx.x]) : 0;
         lcnt[threadIdx.x] = 0;
     }
     __syncthreads();
-    if (c > 0) {
-        const uint32_t qx = compact_bits(K[i]), qy = compact_bits(K[i] >> 1);
-        int hi = hi0;
-        for (int k = 0; k < c; ++k) {
-            const int l = ls + k;
-            const int end = l == 0 ? n : upper_prefix(K, i, hi, prefix_at(K[i], l), l);
-            const int idx = c0 + k;
-            const bool leaf = (k == c - 1);
-            b.beg[idx] = i;
-            b.end[idx] = end;
-            b.level[idx] = l;
-            b.next[idx] = cs[end];
-            b.leaf[idx] = leaf ? 1 : 0;
-            b.ix[idx] = l == 0 ? 0u : (uint32_t)((uint64_t)qx >> (32 - l));
-            b.iy[idx] = l == 0 ? 0u : (uint32_t)((uint64_t)qy >> (32 - l));
-            b.lbeg[idx] = 0;
-            b.lend[idx] = 0;
-            const int slot = lbase[l] + atomicAdd(&lcnt[l], 1);
-            if (slot < lt.cnt[l]) levidx[lt.off[l] + slot] = idx;
-            else atomicOr(&sync->internal, 4);
-            hi = end;
-            if (leaf) {
-                atomicAdd(&s_leaves, 1);
-                atomicMax(&s_maxl, l);
-            }
+    if (idx < ncells) {
+        const uint64_t Ki = K[i];
+        const int end = l == 0 ? n : upper_prefix(K, i, n, prefix_at(Ki, l), l);
+        const uint32_t qx = compact_bits(Ki), qy = compact_bits(Ki >> 1);
+        b.beg[idx] = i;
+        b.end[idx] = end;
+        b.level[idx] = l;
+        b.next[idx] = cs[end];
+        b.leaf[idx] = leaf ? 1 : 0;
+        b.ix[idx] = l == 0 ? 0u : (uint32_t)((uint64_t)qx >> (32 - l));
+        b.iy[idx] = l == 0 ? 0u : (uint32_t)((uint64_t)qy >> (32 - l));
+        b.lbeg[idx] = 0;
+        b.lend[idx] = 0;
+        const int slot = lbase[l] + atomicAdd(&lcnt[l], 1);
+        if (slot < lt.cnt[l]) levidx[lt.off[l] + slot] = idx;
+        else atomicOr(&sync->internal, 4);
+        if (leaf) {
+            atomicAdd(&s_leaves, 1);
+            atomicMax(&s_maxl, l);
         }
     }
     __syncthreads();
@@ -477,11 +502,26 @@ __global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restr
     for (int k = 0; k < P1; ++k) Qr[k] = Qi[k] = 0.0;
     double M = 0.0, cx, cy;
     if (b.leaf[c]) {
+        // a leaf's particles (at most 64) in groups of four, so that their
+        // loads are in flight together; the sums keep particle order
+        const int j0 = b.beg[c], j1 = b.end[c];
         double sx = 0.0, sy = 0.0;
-        for (int j = b.beg[c]; j < b.end[c]; ++j) {
-            M += ms[j];
-            sx += ms[j] * xs[j];
-            sy += ms[j] * ys[j];
+        for (int j = j0; j < j1; j += 4) {
+            double mm[4], xx[4], yy[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jj = j + u < j1 ? j + u : j0;
+                mm[u] = ms[jj];
+                xx[u] = xs[jj];
+                yy[u] = ys[jj];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j + u < j1) {
+                    M += mm[u];
+                    sx += mm[u] * xx[u];
+                    sy += mm[u] * yy[u];
+                }
         }
         if (M > 0.0) {
             cx = sx / M;
@@ -492,25 +532,53 @@ __global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restr
             cx = 0.5 * (bx0 + bx1);
             cy = 0.5 * (by0 + by1);
         }
-        for (int j = b.beg[c]; j < b.end[c]; ++j) {
-            const double dr = xs[j] - cx, di = ys[j] - cy;
-            double pr = ms[j], pi = 0.0;
+        for (int j = j0; j < j1; j += 4) {
+            double mm[4], xx[4], yy[4];
 #pragma unroll
-            for (int k = 0; k < P1; ++k) {
-                Qr[k] += pr;
-                Qi[k] += pi;
-                const double t = pr * dr - pi * di;
-                pi = pr * di + pi * dr;
-                pr = t;
+            for (int u = 0; u < 4; ++u) {
+                const int jj = j + u < j1 ? j + u : j0;
+                mm[u] = ms[jj];
+                xx[u] = xs[jj];
+                yy[u] = ys[jj];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (j + u >= j1) break;
+                const double dr = xx[u] - cx, di = yy[u] - cy;
+                double pr = mm[u], pi = 0.0;
+#pragma unroll
+                for (int k = 0; k < P1; ++k) {
+                    Qr[k] += pr;
+                    Qi[k] += pi;
+                    const double t = pr * dr - pi * di;
+                    pi = pr * di + pi * dr;
+                    pr = t;
+                }
             }
         }
     } else {
-        double sx = 0.0, sy = 0.0;
-        for (int ch = c + 1; ch < b.next[c]; ch = b.next[ch] > ch ? b.next[ch] : ch + 1) {
-            M += cM[ch];
-            sx += cM[ch] * ccx[ch];
-            sy += cM[ch] * ccy[ch];
+        // the children (at most four, one level down) in preorder; their
+        // records are loaded together once the chain of indices is known
+        int chs[4];
+        int nch = 0;
+        const int cend = b.next[c];
+        for (int ch = c + 1; ch < cend && nch < 4; ch = b.next[ch] > ch ? b.next[ch] : ch + 1) chs[nch++] = ch;
+        double cm[4], cxs[4], cys[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int ch = u < nch ? chs[u] : c;
+            cm[u] = cM[ch];
+            cxs[u] = ccx[ch];
+            cys[u] = ccy[ch];
         }
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u < nch) {
+                M += cm[u];
+                sx += cm[u] * cxs[u];
+                sy += cm[u] * cys[u];
+            }
         if (M > 0.0) {
             cx = sx / M;
             cy = sy / M;
@@ -520,8 +588,8 @@ __global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restr
             cx = 0.5 * (bx0 + bx1);
             cy = 0.5 * (by0 + by1);
         }
-        for (int ch = c + 1; ch < b.next[c]; ch = b.next[ch] > ch ? b.next[ch] : ch + 1) {
-            const double tr = ccx[ch] - cx, ti = ccy[ch] - cy;
+        for (int u = 0; u < nch; ++u) {
+            const double tr = cxs[u] - cx, ti = cys[u] - cy;
             double tpr[P1], tpi[P1];
             tpr[0] = 1.0;
             tpi[0] = 0.0;
@@ -530,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restr
                 tpr[k] = tpr[k - 1] * tr - tpi[k - 1] * ti;
                 tpi[k] = tpr[k - 1] * ti + tpi[k - 1] * tr;
             }
-            const double* q = cQ + (size_t)ch * P1 * 2;
+            const double* q = cQ + (size_t)chs[u] * P1 * 2;
             double qr[P1], qi[P1];
 #pragma unroll
             for (int k = 0; k < P1; ++k) {
@@ -762,7 +830,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     }
 
     const int gc = ceil_div(nc, kBlock);
-    hipLaunchKernelGGL(k_topo_emit, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart, b, sync, lt, levidx);
+    hipLaunchKernelGGL(k_topo_emit, dim3(gc), dim3(kBlock), 0, st, K, n, nc, cnt, lstart, b, sync, lt, levidx);
     GLM_HIP(hipMemsetAsync(leaf_of, 0xff, 4ull * n, st)); // -1: no leaf (an internal error if it stays)
     hipLaunchKernelGGL(k_leaf_of, dim3(gc), dim3(kBlock), 0, st, b, nc, leaf_of);
     // list keys: box index, or all-ones on the sorted bits for unlisted particles

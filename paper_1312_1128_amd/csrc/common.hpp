@@ -16,6 +16,7 @@ constexpr int kWave = 64;     // CDNA wavefront
 constexpr int kBlock = 256;   // 4 waves per workgroup
 constexpr int kMaxOrder = 12;
 constexpr int kMaxLevel = 32; // 32-bit quantised coordinates per axis
+constexpr int kMaxLeafSize = 64; // largest accepted leaf size L
 
 // ---------------------------------------------------------------------------
 // Walk-side records.  Box and particle records are read with wave-uniform
