@@ -184,29 +184,83 @@ __device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mod
     return true;
 }
 
-// Sums of one particle's per-lane gradient terms (m, x, y, s) over the
-// wavefront; every lane gets the totals.
-__device__ inline void particle_sums(const double G[4], bool any_s, double S[4])
+// Position of the c-th set bit (from 0) of m, for c < popcount(m).
+__device__ inline int nth_set_bit(uint64_t m, int c)
 {
-    S[0] = G[0];
-    S[1] = G[1];
-    S[2] = G[2];
-    S[3] = G[3];
-    if (any_s) {
-        wave_sum_n<4>(S);
-    } else {
-        wave_sum_n<3>(S);
-        S[3] = 0.0;
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w > 0; w >>= 1) {
+        const int low = __popcll(m & ((1ull << w) - 1));
+        if (c >= low) {
+            c -= low;
+            m >>= w;
+            pos += w;
+        }
     }
+    return pos;
 }
 
-// The particle's four interleaved FP64 accumulators (m, x, y, s) sit at
-// pg + 4 * (Morton position); lanes 0..3 add one each, so the wave issues a
-// single atomic instruction that touches one cache line.
-__device__ inline void add_particle(const double S[4], uint32_t meta, double* __restrict__ pg, int lane)
+// Gradient terms of the particles selected by `sel` (bit k: record rec[k])
+// for the rays of the wavefront whose bit is set in `rays`, summed over those
+// rays into the particles' four FP64 accumulators (m, x, y, s) at
+// pg + 4 * (Morton position).  Lanes hold (particle, ray group) pairs rather
+// than rays: a pass takes up to 32 particles, splits the 64 rays into
+// G = 64 / count groups, and each lane sums its particle's terms over its
+// group's rays one after another (the rays' data arrive by lane shuffles);
+// the G partial sums then meet in the lanes of group 0, which add them with
+// one atomic instruction per accumulator.  This replaces a wavefront sum per
+// particle and ray set with a few shuffles per (particle, ray) pair.
+template <bool KG, int KIND>
+__device__ inline void particles_grad(const PRec* __restrict__ rec, uint64_t sel, int mode, uint64_t rays, double X,
+                                      double Y, const Cot& cg, float invC, double* __restrict__ pg, int lane)
 {
-    const double mine = lane == 0 ? S[0] : lane == 1 ? S[1] : lane == 2 ? S[2] : S[3];
-    if (lane < 4) unsafeAtomicAdd(pg + 4 * (size_t)(meta & 0x7fffffffu) + lane, mine);
+    while (sel) {
+        const int total = __popcll(sel);
+        const int C = total < 32 ? total : 32; // particles in this pass
+        const int G = kWave / C;               // ray groups (>= 2)
+        const int its = (kWave + G - 1) / G;   // rays per group
+        const int c = lane % C, g = lane / C;
+        const PRec pr = rec[nth_set_bit(sel, c)];
+        double A[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < its; ++t) {
+            const int r = g * its + t;
+            const bool act = g < G && r < kWave && ((rays >> (r & (kWave - 1))) & 1ull);
+            if (!__any(act)) continue;
+            const int rs = act ? r : 0;
+            Cot cr;
+            cr.g1 = __shfl(cg.g1, rs, kWave);
+            cr.g2 = __shfl(cg.g2, rs, kWave);
+            if constexpr (KG) {
+                cr.k = __shfl(cg.k, rs, kWave);
+                cr.h1 = __shfl(cg.h1, rs, kWave);
+                cr.h2 = __shfl(cg.h2, rs, kWave);
+            } else {
+                cr.k = cr.h1 = cr.h2 = 0.0f;
+            }
+            const double Xr = __shfl(X, rs, kWave), Yr = __shfl(Y, rs, kWave);
+            double Gt[4];
+            particle_grad<KG, KIND>(pr, Xr, Yr, mode, act, cr, invC, Gt);
+            A[0] += Gt[0];
+            A[1] += Gt[1];
+            A[2] += Gt[2];
+            A[3] += Gt[3];
+        }
+        for (int gg = 1; gg < G; ++gg) {
+            const int src = c + gg * C;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const double v = __shfl(A[w], src, kWave);
+                if (g == 0) A[w] += v;
+            }
+        }
+        if (g == 0) {
+            double* dst = pg + 4 * (size_t)(pr.meta & 0x7fffffffu);
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (A[w] != 0.0) unsafeAtomicAdd(dst + w, A[w]);
+        }
+        for (int q = 0; q < C; ++q) sel &= sel - 1; // drop this pass's particles
+    }
 }
 
 // Cotangent arrays of the rays (input order); any may be NULL (zero).
@@ -262,7 +316,6 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
     int skip = valid ? 0 : 0x7fffffff;
     if (c0 > 0) skip = ancestor_skip(T, X, Y, c0, skip);
     int cur = c0;
-    double G[4];
     while (cur < c1) {
         cur = __builtin_amdgcn_readfirstlane(cur);
         const CellHdr h = T.hdr[cur];
@@ -278,18 +331,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                     const double dyb = fmax(fmax(gy0 - pr.y, pr.y - gy1), 0.0);
                     cand = dxb * dxb + dyb * dyb < pr.qs2 * (1.0 + 1e-9);
                 }
-                uint64_t cm = __ballot(cand);
-                while (cm) {
-                    const int k = __ffsll((unsigned long long)cm) - 1;
-                    cm &= cm - 1;
-                    const PRec pr = T.lst[__builtin_amdgcn_readfirstlane(base + k)];
-                    const bool hit = particle_grad<KG, KIND>(pr, X, Y, 1, act, cg, invC, G);
-                    if (__any(hit)) {
-                        double S[4];
-                        particle_sums(G, true, S);
-                        add_particle(S, pr.meta, pg, lane);
-                    }
-                }
+                const uint64_t cm = __ballot(cand);
+                if (cm) particles_grad<KG, KIND>(T.lst + base, cm, 1, __ballot(act), X, Y, cg, invC, pg, lane);
             }
         }
         double w1, w2;
@@ -383,13 +426,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
         if (h.info & kInfoLeaf) {
             if (__any(opn)) {
                 const CellExt e = T.ext[cur];
-                for (int j = e.pbeg; j < e.pend; ++j) {
-                    const PRec pr = T.prt[j];
-                    const bool hit = particle_grad<KG, KIND>(pr, X, Y, 0, opn, cg, invC, G);
-                    const bool any_s = __any(hit && G[3] != 0.0);
-                    double S[4];
-                    particle_sums(G, any_s, S);
-                    add_particle(S, pr.meta, pg, lane);
+                const uint64_t rays = __ballot(opn);
+                for (int j = e.pbeg; j < e.pend; j += kWave) { // a leaf at the depth cap may exceed 64
+                    const int np = e.pend - j < kWave ? e.pend - j : kWave;
+                    const uint64_t sel = np == kWave ? ~0ull : ((1ull << np) - 1);
+                    particles_grad<KG, KIND>(T.prt + j, sel, 0, rays, X, Y, cg, invC, pg, lane);
                 }
             }
             cur = cur + 1;
