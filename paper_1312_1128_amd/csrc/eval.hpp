@@ -294,8 +294,10 @@ __device__ inline void add_radial(float coef, float Gam, float f1, float f2, flo
 //  - unlisted particle: the truncated Gaussian of Sec. 3.1 inside the
 //    support, a point mass outside.
 // All cases share one select-based path (no divergent branches).  The point
-// terms are formed without FMA contraction, exactly as in point_terms, so a
-// balanced pair cancels bit for bit.
+// terms' shear is formed without FMA contraction, exactly as in point_terms,
+// so a balanced pair cancels bit for bit there; alpha is coef * d with the
+// FP64 offset d, and a balanced pair meets the list's (A - pm) d in the FP64
+// sums (cancelling to FP64 rounding of the point term).
 template <bool AONLY, bool F64A, bool PSI = false, int KIND = kKindGauss>
 __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A, double psiK = 0.0,
                                      int terms = 1, float invC = 0.0f)
@@ -318,10 +320,14 @@ __device__ inline void leaf_particle(const PRec& pr, double X, double Y, Acc& A,
         Gam = gauss ? Gg : pm;
         if (!AONLY) A.k += gauss ? Kg : 0.0f;
     }
-    const float v1 = coef * f1, v2 = coef * f2;
     if constexpr (F64A) {
-        add_alpha<true>(A, v1, v2);
+        // alpha = coef d with the FP64 offset; a balanced point term (coef = pm)
+        // meets the list's (A - pm) d in the same FP64 sums
+        const double cd = (double)coef;
+        A.a1 = fma(cd, d1, A.a1);
+        A.a2 = fma(cd, d2, A.a2);
     } else {
+        const float v1 = coef * f1, v2 = coef * f2;
         add_alpha<false>(A, balance ? 0.0f : v1, balance ? 0.0f : v2);
         A.a1 += (double)(balance ? v1 : 0.0f);
         A.a2 += (double)(balance ? v2 : 0.0f);
@@ -354,10 +360,22 @@ __device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A,
     point_terms(pr.m, f1, f2, ir2, P);
     float Ag, Gg, Kg;
     profile_terms<KIND>(pr, r2, r2f, ir2, &Ag, &Gg, &Kg);
-    add_radial<AONLY, F64A>(Ag, Gg, f1, f2, ir2, A);
+    if constexpr (F64A) {
+        // (A - pm) d in FP64: the leaf sums this lane's point term as pm d
+        const double diff = (double)Ag - (double)(pr.m * ir2);
+        A.a1 = fma(diff, d1, A.a1);
+        A.a2 = fma(diff, d2, A.a2);
+        if (!AONLY) {
+            const float c2 = (f1 * f1 - f2 * f2) * ir2, s2 = 2.0f * f1 * f2 * ir2;
+            A.g1 -= (double)(Gg * c2);
+            A.g2 -= (double)(Gg * s2);
+        }
+    } else {
+        add_radial<AONLY, F64A>(Ag, Gg, f1, f2, ir2, A);
+        A.a1 -= (double)P[0];
+        A.a2 -= (double)P[1];
+    }
     hits++;
-    A.a1 -= (double)P[0];
-    A.a2 -= (double)P[1];
     if (!AONLY) {
         A.k += Kg;
         A.g1 -= (double)P[2];

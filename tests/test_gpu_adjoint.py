@@ -36,10 +36,15 @@ def mixed_lens(n, seed):
     return lens
 
 
-@pytest.mark.parametrize("case", ["mixed_3k", "nfw_20k", "point_masses_2k"])
+@pytest.mark.parametrize("case", ["mixed_3k", "nfw_20k", "point_masses_2k", "clump_100"])
 def test_adjoint_matches_oracle_tree(ora, case):
     if case == "mixed_3k":
         lens, theta, leaf, order = mixed_lens(3000, 301), 0.5, 4, 4
+    elif case == "clump_100":
+        # 100 coincident particles: one leaf at the depth cap holding more than
+        # a wavefront's worth of particles
+        lens, theta, leaf, order = mixed_lens(1000, 311), 0.5, 8, 4
+        lens.x[:100], lens.y[:100] = lens.x[0], lens.y[0]
     elif case == "nfw_20k":
         lens, theta, leaf, order = synth.nfw_halo(20000, 303), 0.3, 8, 8
     else:
