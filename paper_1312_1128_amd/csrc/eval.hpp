@@ -50,13 +50,31 @@ __device__ inline double ein(double u, int terms)
     return s * u;
 }
 
+// The same series in FP32 where a tree needs at most 34 FP64 terms (u below
+// about 4.75, q up to 3): 24 terms leave a tail below 2e-9, the coefficients
+// are instruction constants, and the rounding of the alternating sum (about
+// 1e-6 absolute at the top of the range) is far below what an FP32 potential
+// term resolves.
+constexpr int kEin32Terms = 24;
+__device__ inline float ein32(float u)
+{
+    constexpr EinTable t = make_ein_table();
+    float s = (float)t.c[kEin32Terms - 1];
+#pragma unroll
+    for (int k = kEin32Terms - 2; k >= 0; --k) s = fmaf(s, u, (float)t.c[k]);
+    return s * u;
+}
+
 // Potential of a truncated Gaussian inside its support, per unit mass
 // (alpha = grad psi, Sec. 3.2; equal to the point mass's ln r at the edge):
 //   ln(q s) - (Ein(q^2/2) - Ein(u)) / (2C),  u = r^2 / (2 s^2).
+// Ein(q^2/2) (psiK) is the host's FP64 value; Ein(u) is FP32 up to q = 3
+// (terms <= 34 marks that range), FP64 beyond.
 __device__ inline float gauss_psi(const PRec& pr, double r2, double psiK, int terms, float invC)
 {
     const double u = r2 * (double)pr.h;
-    return 0.5f * __logf((float)pr.qs2) - (float)((psiK - ein(u, terms)) * (0.5 * (double)invC));
+    const double e = terms <= 34 ? (double)ein32((float)u) : ein(u, terms);
+    return 0.5f * __logf((float)pr.qs2) - (float)((psiK - e) * (0.5 * (double)invC));
 }
 
 // alpha += (v1, v2): in FP64, or in plain FP32 when F64A is false (debug)
@@ -459,8 +477,10 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
 // lie inside a particle of box c's big-particle list (see the list reach).
 __device__ inline bool list_reaches(const TreeDev& T, int c, double gx0, double gx1, double gy0, double gy1)
 {
+    // the four bounds load together and the tests combine without branches
     const double* lr = T.lreach + 4 * (size_t)c;
-    return !(gx1 < lr[0] || gx0 > lr[1] || gy1 < lr[2] || gy0 > lr[3]);
+    const double r0 = lr[0], r1 = lr[1], r2 = lr[2], r3 = lr[3];
+    return (gx1 >= r0) & (gx0 <= r1) & (gy1 >= r2) & (gy0 <= r3);
 }
 
 // The walk of a preorder range [c0, c1) of boxes: every ancestor of a box in
