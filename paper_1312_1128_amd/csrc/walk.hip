@@ -312,9 +312,9 @@ __global__ __launch_bounds__(kBlock) void k_ray_root(const double* __restrict__ 
     if (threadIdx.x < 4) bb[threadIdx.x] = red[threadIdx.x][0];
 }
 
-// 16-bit-per-axis Morton keys of the rays in their bounding square
+// Morton keys of the rays in their bounding square, `bits` (<= 16) per axis
 __global__ __launch_bounds__(kBlock) void k_ray_keys(const double* __restrict__ x, const double* __restrict__ y,
-                                                    int64_t n, const double* __restrict__ bb,
+                                                    int64_t n, const double* __restrict__ bb, int bits,
                                                     uint32_t* __restrict__ key, uint32_t* __restrict__ val)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -322,9 +322,10 @@ __global__ __launch_bounds__(kBlock) void k_ray_keys(const double* __restrict__ 
     const double bx0 = bb[0], by0 = bb[2];
     double ext = fmax(bb[1] - bx0, bb[3] - by0);
     if (!(ext > 0.0)) ext = 1.0;
-    const double sc = 65535.0 / ext;
-    const uint32_t qx = (uint32_t)fmin(fmax((x[i] - bx0) * sc, 0.0), 65535.0);
-    const uint32_t qy = (uint32_t)fmin(fmax((y[i] - by0) * sc, 0.0), 65535.0);
+    const double top = (double)((1u << bits) - 1u);
+    const double sc = top / ext;
+    const uint32_t qx = (uint32_t)fmin(fmax((x[i] - bx0) * sc, 0.0), top);
+    const uint32_t qy = (uint32_t)fmin(fmax((y[i] - by0) * sc, 0.0), top);
     key[i] = spread16(qx) | (spread16(qy) << 1);
     val[i] = (uint32_t)i;
 }
@@ -468,8 +469,12 @@ glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* w
     const int g = ceil_div(nrays, kBlock);
     hipLaunchKernelGGL(k_ray_bbox, dim3(nbb), dim3(kBlock), 0, st, rx, ry, nrays, part);
     hipLaunchKernelGGL(k_ray_root, dim3(1), dim3(kBlock), 0, st, part, nbb, part + 4 * nbb);
-    hipLaunchKernelGGL(k_ray_keys, dim3(g), dim3(kBlock), 0, st, rx, ry, nrays, part + 4 * nbb, k0, v0);
-    const int w = radix_sort_u32(k0, v0, k1, v1, nrays, 4, hist, st);
+    // the key only forms the 64-ray groups (per-ray results do not depend on
+    // them): about four cells per ray suffice, 8 to 16 bits per axis
+    int bits = 8;
+    while (bits < 16 && (1ll << (2 * bits)) < 4 * nrays) ++bits;
+    hipLaunchKernelGGL(k_ray_keys, dim3(g), dim3(kBlock), 0, st, rx, ry, nrays, part + 4 * nbb, bits, k0, v0);
+    const int w = radix_sort_u32(k0, v0, k1, v1, nrays, (2 * bits + 7) / 8, hist, st);
     const uint32_t* perm = w ? v1 : v0;
     hipLaunchKernelGGL(k_ray_gather, dim3(g), dim3(kBlock), 0, st, perm, rx, ry, nrays, xs, ys);
     GLM_HIP(hipGetLastError());
