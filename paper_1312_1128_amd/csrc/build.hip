@@ -175,31 +175,40 @@ __device__ inline uint32_t quantise(double v, double v0, double scale)
     return (uint32_t)floor(t);
 }
 
+// One particle's inputs side by side, so that the gather after the sort
+// reads one 32-byte record per particle instead of four scattered words.
+struct alignas(32) Particle4 {
+    double x, y, m, s;
+};
+
 __global__ __launch_bounds__(kBlock) void k_morton(const double* __restrict__ x, const double* __restrict__ y,
+                                                  const double* __restrict__ m, const double* __restrict__ s,
                                                   int64_t n, const BuildSync* __restrict__ sync,
-                                                  uint64_t* __restrict__ key, uint32_t* __restrict__ val)
+                                                  uint64_t* __restrict__ key, uint32_t* __restrict__ val,
+                                                  Particle4* __restrict__ packed)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const uint32_t qx = quantise(x[i], sync->x0, sync->scale);
-    const uint32_t qy = quantise(y[i], sync->y0, sync->scale);
+    const double xi = x[i], yi = y[i];
+    const uint32_t qx = quantise(xi, sync->x0, sync->scale);
+    const uint32_t qy = quantise(yi, sync->y0, sync->scale);
     key[i] = spread_bits(qx) | (spread_bits(qy) << 1);
     val[i] = (uint32_t)i;
+    packed[i] = Particle4{xi, yi, m[i], s ? s[i] : 0.0};
 }
 
-__global__ __launch_bounds__(kBlock) void k_gather(const uint32_t* __restrict__ perm, const double* __restrict__ x,
-                                                  const double* __restrict__ y, const double* __restrict__ m,
-                                                  const double* __restrict__ s, int64_t n, double* __restrict__ xs,
-                                                  double* __restrict__ ys, double* __restrict__ ms,
-                                                  double* __restrict__ ss)
+__global__ __launch_bounds__(kBlock) void k_gather(const uint32_t* __restrict__ perm,
+                                                  const Particle4* __restrict__ packed, int64_t n,
+                                                  double* __restrict__ xs, double* __restrict__ ys,
+                                                  double* __restrict__ ms, double* __restrict__ ss)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= n) return;
-    const uint32_t i = perm[k];
-    xs[k] = x[i];
-    ys[k] = y[i];
-    ms[k] = m[i];
-    ss[k] = s ? s[i] : 0.0;
+    const Particle4 p = packed[perm[k]];
+    xs[k] = p.x;
+    ys[k] = p.y;
+    ms[k] = p.m;
+    ss[k] = p.s;
 }
 
 // --------------------------------------------------------------- topology
@@ -766,12 +775,15 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     const int gb = ceil_div(n, kBlock);
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kBlock), 0, st, x, y, m, s, (int64_t)n, part);
     hipLaunchKernelGGL(k_root, dim3(1), dim3(kBlock), 0, st, part, nbb, sync);
-    hipLaunchKernelGGL(k_morton, dim3(gb), dim3(kBlock), 0, st, x, y, (int64_t)n, sync, k0, v0);
+    // the particle records' space holds the packed inputs until the records are made
+    static_assert(sizeof(PRec) >= sizeof(Particle4), "packed inputs must fit the record array");
+    Particle4* packed = reinterpret_cast<Particle4*>(prt);
+    hipLaunchKernelGGL(k_morton, dim3(gb), dim3(kBlock), 0, st, x, y, m, s, (int64_t)n, sync, k0, v0, packed);
     const int where = radix_sort_u64(k0, v0, k1, v1, n, 8, hist, st);
     uint64_t* K = where ? k1 : k0;
     uint32_t* pv = where ? v1 : v0;
     GLM_HIP(hipMemcpyAsync(perm, pv, 4ull * n, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_gather, dim3(gb), dim3(kBlock), 0, st, perm, x, y, m, s, (int64_t)n, xs, ys, ms, ss);
+    hipLaunchKernelGGL(k_gather, dim3(gb), dim3(kBlock), 0, st, perm, packed, (int64_t)n, xs, ys, ms, ss);
     hipLaunchKernelGGL(k_topo_count, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart, sync);
     exclusive_scan_i32(cnt, cnt, n, scr, st);
     hipLaunchKernelGGL(k_sync_counts, dim3(1), dim3(1), 0, st, cnt, n, sync);

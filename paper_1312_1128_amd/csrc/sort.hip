@@ -1,10 +1,11 @@
 // Stable LSD radix sort (8-bit digits) and exclusive scan for gfx950.
 //
-// Sort pass = histogram per 2048-key tile -> one exclusive scan of the
-// digit-major histogram -> scatter, where each tile ranks its keys stably with
-// wave ballots (8 ballots give the lanes holding the same digit) and per-wave
-// digit counts in LDS, reorders them by digit in LDS and writes each digit's
-// run with consecutive lanes.  Loads and stores are coalesced.
+// Sort pass = histogram per 2048-key tile (plus per-digit totals) -> per
+// digit, an exclusive scan of its counts over the tiles -> scatter, where each
+// tile takes its digit bases from the scanned totals, ranks its keys stably
+// with wave ballots (8 ballots give the lanes holding the same digit) and
+// per-wave digit counts in LDS, reorders them by digit in LDS and writes each
+// digit's run with consecutive lanes.  Loads and stores are coalesced.
 #include "common.hpp"
 
 namespace glm {
@@ -110,9 +111,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t* in, int32_
     }
 }
 
+// Digit counts of one tile into hist[d * nb + tile]; the tile's counts are
+// also added to the pass's digit totals (zeroed before the pass).
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const K* keys, int64_t n, int shift, uint32_t* hist,
-                                                      int nb)
+                                                      int nb, uint32_t* dtot)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
@@ -124,18 +127,52 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const K* keys, int64_t n,
         if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    const uint32_t c = h[threadIdx.x];
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = c;
+    if (c) atomicAdd(&dtot[threadIdx.x], c);
+}
+
+// One block per digit d: exclusive scan of hist[d * nb .. d * nb + nb) over
+// the tiles into pre[].  Also clears the next pass's digit totals.
+__global__ __launch_bounds__(kBlock) void k_radix_rowscan(const uint32_t* __restrict__ hist, int nb,
+                                                         uint32_t* __restrict__ pre, uint32_t* __restrict__ dnext)
+{
+    __shared__ uint32_t lw[kBlock / kWave];
+    const int d = blockIdx.x, t = threadIdx.x;
+    const int per = (nb + kBlock - 1) / kBlock;
+    const int64_t row = (int64_t)d * nb;
+    const int b0 = t * per;
+    uint32_t sum = 0;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nb) sum += hist[row + b0 + k];
+    uint32_t tot;
+    uint32_t run = block_excl_scan(sum, lw, &tot);
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nb) {
+            const uint32_t c = hist[row + b0 + k];
+            pre[row + b0 + k] = run;
+            run += c;
+        }
+    if (t == 0 && dnext) dnext[d] = 0;
+}
+
+__global__ void k_radix_zero(uint32_t* __restrict__ v, int n)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) v[i] = 0;
 }
 
 // Scatter of one tile: the keys are ranked stably per digit (wave ballots and
 // per-wave digit counts in LDS, chunk by chunk), placed in LDS in digit order,
 // then written out slot by slot, so that consecutive lanes write consecutive
-// addresses of the same digit's run.  offs holds the exclusive scan of the
-// digit-major histogram with the total n at offs[256 nb].
+// addresses of the same digit's run.  The tile's run of digit d starts at
+// (keys of digits below d) + pre[d * nb + tile] and holds hist[d * nb + tile] keys.
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K* kin, const uint32_t* vin, K* kout,
                                                          uint32_t* vout, int64_t n, int shift,
-                                                         const int32_t* offs, int nb)
+                                                         const uint32_t* __restrict__ hist,
+                                                         const uint32_t* __restrict__ pre,
+                                                         const uint32_t* __restrict__ dtot, int nb)
 {
     __shared__ K sk[kTile];
     __shared__ uint32_t sv[kTile];
@@ -146,9 +183,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K* kin, const ui
     const int t = threadIdx.x, w = t / kWave;
     {
         const int64_t hi = (int64_t)t * nb + blockIdx.x;
-        const uint32_t g0 = (uint32_t)offs[hi];
-        const uint32_t cnt = (uint32_t)offs[hi + 1] - g0;
         uint32_t tot;
+        const uint32_t dbase = block_excl_scan(dtot[t], lw, &tot); // keys of the digits below t
+        const uint32_t g0 = dbase + pre[hi];
+        const uint32_t cnt = hist[hi];
         const uint32_t l0 = block_excl_scan(cnt, lw, &tot);
         lrun[t] = l0;
         gbase[t] = g0 - l0;
@@ -206,18 +244,21 @@ int radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n, int pas
     if (n <= 1 || passes <= 0) return 0;
     const int nb = ceil_div(n, kTile);
     const int64_t hn = (int64_t)256 * nb;
-    int32_t* offs = reinterpret_cast<int32_t*>(hist);
-    int32_t* scr = offs + hn + 1;
+    uint32_t* pre = hist + hn;
+    uint32_t* dtot = pre + hn; // two sets of 256 digit totals, used by alternate passes
+    hipLaunchKernelGGL(k_radix_zero, dim3(1), dim3(kBlock), 0, s, dtot, 256);
     K* ki = k0;
     uint32_t* vi = v0;
     K* ko = k1;
     uint32_t* vo = v1;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(kBlock), 0, s, ki, n, shift, hist, nb);
-        exclusive_scan_i32(offs, offs, hn, scr, s);
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, n, shift,
-                           offs, nb);
+        uint32_t* dcur = dtot + 256 * (p & 1);
+        uint32_t* dnext = p + 1 < passes ? dtot + 256 * ((p + 1) & 1) : nullptr;
+        hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(kBlock), 0, s, ki, n, shift, hist, nb, dcur);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kBlock), 0, s, hist, nb, pre, dnext);
+        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, n, shift, hist,
+                           pre, dcur, nb);
         K* tk = ki; ki = ko; ko = tk;
         uint32_t* tv = vi; vi = vo; vo = tv;
     }
@@ -240,7 +281,7 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* scr
 size_t radix_hist_words(int64_t n)
 {
     const int64_t hn = (int64_t)256 * ceil_div(n > 0 ? n : 1, kTile);
-    return (size_t)hn + 1 + scan_scratch_words(hn);
+    return 2 * (size_t)hn + 512; // counts, their per-digit prefixes, two sets of digit totals
 }
 
 int radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t n, int passes,
