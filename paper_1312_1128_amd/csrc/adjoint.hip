@@ -263,6 +263,45 @@ __device__ inline void particles_grad(const PRec* __restrict__ rec, uint64_t sel
     }
 }
 
+// Orders this wavefront's LDS accesses around a hand-over between its lanes
+// (LDS operations of one wavefront complete in program order).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Totals over the wavefront of NA per-lane words, returned in lane k for word
+// k < NA.  The lanes store their words in the wavefront's LDS slice (NA * 64
+// floats); lane (k, g) = (l % NA, l / NA) then sums word k over the g-th of
+// G = 64 / NA slices of lanes, and the G partial sums meet by lane shuffles.
+// This replaces NA six-step wavefront sums.
+template <int NA>
+__device__ inline float word_totals(const float* a, float* red, int lane)
+{
+    constexpr int G = kWave / NA;            // lane slices (>= 2 for NA <= 32)
+    constexpr int SL = (kWave + G - 1) / G;  // lanes per slice
+    static_assert(G >= 2, "at most 32 words");
+#pragma unroll
+    for (int k = 0; k < NA; ++k) red[lane * NA + k] = a[k];
+    wave_lds_sync();
+    const int k = lane % NA, g = lane / NA;
+    float sum = 0.0f;
+    if (g < G) {
+#pragma unroll
+        for (int i = 0; i < SL; ++i) {
+            const int j = g * SL + i;
+            if (j < kWave) sum += red[j * NA + k];
+        }
+    }
+    wave_lds_sync(); // the slice is written again for the next box
+    float tot = sum; // every shuffle reads the slices' own sums, not updated ones
+#pragma unroll
+    for (int gg = 1; gg < G; ++gg) tot += __shfl(sum, k + gg * NA, kWave);
+    return tot;
+}
+
 // Cotangent arrays of the rays (input order); any may be NULL (zero).
 struct CotIn {
     const float *ga1, *ga2, *gk, *gg1, *gg2;
@@ -276,10 +315,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                                                         int K, const int* __restrict__ split_box)
 {
     constexpr int NA = 2 * (P + 1) + 2; // (Re, Im) of Abar_0..Abar_P, Bbar
+    __shared__ float red_all[(kBlock / kWave) * kWave * NA]; // per wavefront: the box words of its 64 lanes
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t groups = (nrays + kWave - 1) / kWave;
     // wave-uniform work item (kept in SGPRs): box range kr, ray group grp
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    float* red = red_all + (size_t)w * kWave * NA;
     int kr;
     int64_t grp;
     if (!walk_task(blockIdx.x, w, groups, K, &kr, &grp)) return;
@@ -416,11 +457,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                     a[NA - 1] -= h1 * U2 + h2 * U1;
                 }
             }
-            wave_sum_n<NA>(a);
             // lane k adds total k: one atomic instruction over NA adjacent words
-            float mine = 0.0f;
-#pragma unroll
-            for (int k = 0; k < NA; ++k) mine = lane == k ? a[k] : mine;
+            const float mine = word_totals<NA>(a, red, lane);
             if (lane < NA) unsafeAtomicAdd(abar + (size_t)cur * NA + lane, (double)mine);
         }
         if (h.info & kInfoLeaf) {
