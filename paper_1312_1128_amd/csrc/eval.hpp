@@ -569,81 +569,4 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
-// Full-wavefront sums with DPP lane moves (each step one VALU op, no LDS
-// crossbar): pairs and quads (quad_perm), 8 and 16 lanes (half-row and row
-// mirrors), then rows via row_bcast15 / row_bcast31.  Lane 63 ends with the
-// total, returned to every lane through readlane.  Fixed order, so the result
-// is deterministic.  Must be called with every lane of the wavefront active.
-template <int CTRL, int ROWS>
-__device__ inline int dpp_i(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
-}
-
-template <int CTRL, int ROWS>
-__device__ inline float dpp_step(float v)
-{
-    return v + __builtin_bit_cast(float, dpp_i<CTRL, ROWS>(__builtin_bit_cast(int, v)));
-}
-
-template <int CTRL, int ROWS>
-__device__ inline double dpp_step(double v)
-{
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = dpp_i<CTRL, ROWS>((int)(b & 0xffffffffll));
-    const int hi = dpp_i<CTRL, ROWS>((int)(b >> 32));
-    const long long m = ((long long)(unsigned)lo) | ((long long)hi << 32);
-    return v + __builtin_bit_cast(double, m);
-}
-
-template <class T>
-__device__ inline T wave_sum(T v)
-{
-    v = dpp_step<0xB1, 0xF>(v);  // quad_perm [1,0,3,2]
-    v = dpp_step<0x4E, 0xF>(v);  // quad_perm [2,3,0,1]
-    v = dpp_step<0x141, 0xF>(v); // row_half_mirror
-    v = dpp_step<0x140, 0xF>(v); // row_mirror
-    v = dpp_step<0x142, 0xA>(v); // row_bcast15 into rows 1, 3
-    v = dpp_step<0x143, 0xC>(v); // row_bcast31 into rows 2, 3
-    if constexpr (sizeof(T) == 4) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
-    } else {
-        const long long b = __builtin_bit_cast(long long, v);
-        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
-        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-        return __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
-    }
-}
-
-// N independent wavefront sums, interleaved step by step (each DPP step runs
-// over all N values, so no step waits on the lane move just before it);
-// every lane gets the N totals.  Same order of additions as wave_sum.
-template <int N, class T>
-__device__ inline void wave_sum_n(T* v)
-{
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = dpp_step<0xB1, 0xF>(v[k]);
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = dpp_step<0x4E, 0xF>(v[k]);
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = dpp_step<0x141, 0xF>(v[k]);
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = dpp_step<0x140, 0xF>(v[k]);
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = dpp_step<0x142, 0xA>(v[k]);
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = dpp_step<0x143, 0xC>(v[k]);
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        if constexpr (sizeof(T) == 4) {
-            v[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[k]), 63));
-        } else {
-            const long long b = __builtin_bit_cast(long long, v[k]);
-            const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
-            const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-            v[k] = __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
-        }
-    }
-}
-
 } // namespace glm
