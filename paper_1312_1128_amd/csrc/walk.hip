@@ -543,7 +543,7 @@ __device__ inline int find_lens(const int64_t* __restrict__ roff, int nlens, int
 // key = lens rank << 32 | 16-bit-per-axis Morton code in the lens's ray box
 __global__ __launch_bounds__(kBlock) void k_batch_keys(const BatchLens* __restrict__ lenses, int nlens,
                                                       const int64_t* __restrict__ roff, const double* __restrict__ bb,
-                                                      int64_t total, uint64_t* __restrict__ key,
+                                                      int64_t total, int bits, uint64_t* __restrict__ key,
                                                       uint32_t* __restrict__ val)
 {
     const int64_t gi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -553,22 +553,23 @@ __global__ __launch_bounds__(kBlock) void k_batch_keys(const BatchLens* __restri
     const double bx0 = bb[4 * l], by0 = bb[4 * l + 2];
     double ext = fmax(bb[4 * l + 1] - bx0, bb[4 * l + 3] - by0);
     if (!(ext > 0.0)) ext = 1.0;
-    const double sc = 65535.0 / ext;
-    const uint32_t qx = (uint32_t)fmin(fmax((lenses[l].rx[i] - bx0) * sc, 0.0), 65535.0);
-    const uint32_t qy = (uint32_t)fmin(fmax((lenses[l].ry[i] - by0) * sc, 0.0), 65535.0);
-    key[gi] = ((uint64_t)l << 32) | (uint64_t)(spread16(qx) | (spread16(qy) << 1));
+    const double top = (double)((1u << bits) - 1u);
+    const double sc = top / ext;
+    const uint32_t qx = (uint32_t)fmin(fmax((lenses[l].rx[i] - bx0) * sc, 0.0), top);
+    const uint32_t qy = (uint32_t)fmin(fmax((lenses[l].ry[i] - by0) * sc, 0.0), top);
+    key[gi] = ((uint64_t)l << (2 * bits)) | (uint64_t)(spread16(qx) | (spread16(qy) << 1));
     val[gi] = (uint32_t)gi;
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch_gather(const BatchLens* __restrict__ lenses,
                                                         const int64_t* __restrict__ roff,
                                                         const uint64_t* __restrict__ key,
-                                                        const uint32_t* __restrict__ val, int64_t total,
+                                                        const uint32_t* __restrict__ val, int64_t total, int bits,
                                                         double* __restrict__ xs, double* __restrict__ ys)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= total) return;
-    const int l = (int)(key[k] >> 32);
+    const int l = (int)(key[k] >> (2 * bits));
     const int64_t i = (int64_t)val[k] - roff[l];
     xs[k] = lenses[l].rx[i];
     ys[k] = lenses[l].ry[i];
@@ -661,14 +662,19 @@ glm_status shoot_batched_device(const BatchLens* host_table, int nlens, int orde
     hipLaunchKernelGGL(k_batch_bbox, dim3(nlens, kBboxSplit), dim3(kBlock), 0, st, dtab, bbpart);
     hipLaunchKernelGGL(k_batch_bbox_final, dim3(ceil_div(4 * nlens, 64)), dim3(64), 0, st, bbpart, nlens, bb);
     const int g = ceil_div(total, kBlock);
-    hipLaunchKernelGGL(k_batch_keys, dim3(g), dim3(kBlock), 0, st, dtab, nlens, droff, bb, total, k0, v0);
+    // per lens, about four Morton cells per ray (the largest lens sets the width)
+    int64_t most = 0;
+    for (int l = 0; l < nlens; ++l) most = std::max(most, host_table[l].nrays);
+    int bits = 8;
+    while (bits < 16 && (1ll << (2 * bits)) < 4 * most) ++bits;
+    hipLaunchKernelGGL(k_batch_keys, dim3(g), dim3(kBlock), 0, st, dtab, nlens, droff, bb, total, bits, k0, v0);
     int lens_bits = 0;
     while ((1 << lens_bits) < nlens) ++lens_bits;
-    const int passes = 4 + (lens_bits + 7) / 8;
+    const int passes = (2 * bits + lens_bits + 7) / 8;
     const int w = radix_sort_u64(k0, v0, k1, v1, total, passes, hist, st);
     const uint64_t* ks = w ? k1 : k0;
     const uint32_t* perm = w ? v1 : v0;
-    hipLaunchKernelGGL(k_batch_gather, dim3(g), dim3(kBlock), 0, st, dtab, droff, ks, perm, total, xs, ys);
+    hipLaunchKernelGGL(k_batch_gather, dim3(g), dim3(kBlock), 0, st, dtab, droff, ks, perm, total, bits, xs, ys);
     const int f64a = (flags & GLM_FP32_ALPHA) ? 0 : 1;
     const int kind = host_table[0].tree.kind; // every lens of a batch has the same particle kind
 #define GLM_CASE(PP)                                                                                     \

@@ -111,7 +111,7 @@ struct StagedRays {
     const uint32_t* perm; // sorted -> input position, or null when unsorted
 };
 
-// Morton-sort the rays (16 bits per axis in their bounding square) so that
+// Morton-sort the rays (8 to 16 bits per axis in their bounding square) so that
 // each 64-ray group is spatially compact.
 glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* ws, const RayLayout& L,
                       StagedRays* out, hipStream_t st);
