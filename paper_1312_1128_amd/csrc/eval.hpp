@@ -159,12 +159,16 @@ __device__ inline void gauss_terms(float u, float e, float ir2, float mC, float 
 // ---------------------------------------------------------------------------
 __host__ __device__ inline float nfw_log1p(float v) { return log1pf(v); }
 __host__ __device__ inline double nfw_log1p(double v) { return log1p(v); }
-__host__ __device__ inline float nfw_log(float v) { return logf(v); }
+__device__ inline float nfw_log(float v) { return __logf(v); } // v <= 0.75: no cancellation near 1
 __host__ __device__ inline double nfw_log(double v) { return log(v); }
 __host__ __device__ inline float nfw_atan(float v) { return atanf(v); }
 __host__ __device__ inline double nfw_atan(double v) { return atan(v); }
-__host__ __device__ inline float nfw_sqrt(float v) { return sqrtf(v); }
+// FP32 (the walk's shapes): hardware square root and reciprocal (about 1 ulp
+// each), well inside the 1e-6 the FP32 shapes are held to; FP64 stays exact.
+__device__ inline float nfw_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __host__ __device__ inline double nfw_sqrt(double v) { return sqrt(v); }
+__device__ inline float nfw_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__host__ __device__ inline double nfw_div(double a, double b) { return a / b; }
 
 // sum_{k < N} z^k / (2k + OFF) by Horner
 template <class T, int N, int OFF>
@@ -195,24 +199,24 @@ __host__ __device__ inline void nfw_shape(T x2, T e, T eps, T* gx2, T* f, T* dfd
     if (e > -eps && e < eps) {
         const T F = odd_series<T, NSER, 1>(-e);
         *f = odd_series<T, NSER + 1, 3>(-e);
-        *gx2 = ((T)0.5 * nfw_log1p(e) - ln2 + F) / x2;
+        *gx2 = nfw_div((T)0.5 * nfw_log1p(e) - ln2 + F, x2);
         if (dfde) *dfde = -dseries<T, NSER + 1>(-e);
     } else if (e > (T)0) {
         const T y = nfw_sqrt(e);
-        const T F = nfw_atan(y) / y;
-        *f = ((T)1 - F) / e;
-        *gx2 = ((T)0.5 * nfw_log1p(e) - ln2 + F) / x2;
-        if (dfde) *dfde = ((T)3 * F - (T)2 - (T)1 / x2) / ((T)2 * e * e);
+        const T F = nfw_div(nfw_atan(y), y);
+        *f = nfw_div((T)1 - F, e);
+        *gx2 = nfw_div((T)0.5 * nfw_log1p(e) - ln2 + F, x2);
+        if (dfde) *dfde = nfw_div((T)3 * F - (T)2 - nfw_div((T)1, x2), (T)2 * e * e);
     } else {
         // x^2 is kept above a tiny floor, so that a ray at the centre gives finite values
         const T tiny = sizeof(T) == 4 ? (T)1e-30 : (T)1e-300;
         const T xx = x2 > tiny ? x2 : tiny;
         const T y = nfw_sqrt(-e), opy = (T)1 + y;
-        const T F = (T)0.5 * nfw_log1p((T)2 * y * opy / xx) / y;
-        *f = (F - (T)1) / (-e);
+        const T F = nfw_div((T)0.5 * nfw_log1p(nfw_div((T)2 * y * opy, xx)), y);
+        *f = nfw_div(F - (T)1, -e);
         const T L = ln2 - (T)0.5 * nfw_log(xx);
-        *gx2 = (L / opy + nfw_log1p(-xx / ((T)2 * opy)) / xx) / y;
-        if (dfde) *dfde = ((T)3 * F - (T)2 - (T)1 / xx) / ((T)2 * e * e);
+        *gx2 = nfw_div(nfw_div(L, opy) + nfw_div(nfw_log1p(nfw_div(-xx, (T)2 * opy)), xx), y);
+        if (dfde) *dfde = nfw_div((T)3 * F - (T)2 - nfw_div((T)1, xx), (T)2 * e * e);
     }
 }
 
