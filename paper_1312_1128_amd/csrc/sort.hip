@@ -1,8 +1,8 @@
 // Stable LSD radix sort (8-bit digits) and exclusive scan for gfx950.
 //
-// Sort pass = histogram per 2048-key tile (plus per-digit totals) -> per
-// digit, an exclusive scan of its counts over the tiles -> scatter, where each
-// tile takes its digit bases from the scanned totals, ranks its keys stably
+// Sort pass = histogram per 2048-key tile -> per digit, an exclusive scan of
+// its counts over the tiles (and the digit's total) -> scatter, where each
+// tile takes its digit bases from the digit totals, ranks its keys stably
 // with wave ballots (8 ballots give the lanes holding the same digit) and
 // per-wave digit counts in LDS, reorders them by digit in LDS and writes each
 // digit's run with consecutive lanes.  Loads and stores are coalesced.
@@ -111,11 +111,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t* in, int32_
     }
 }
 
-// Digit counts of one tile into hist[d * nb + tile]; the tile's counts are
-// also added to the pass's digit totals (zeroed before the pass).
+// Digit counts of one tile into hist[d * nb + tile].
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const K* keys, int64_t n, int shift, uint32_t* hist,
-                                                      int nb, uint32_t* dtot)
+                                                      int nb)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
@@ -127,15 +126,13 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const K* keys, int64_t n,
         if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    const uint32_t c = h[threadIdx.x];
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = c;
-    if (c) atomicAdd(&dtot[threadIdx.x], c);
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
 // One block per digit d: exclusive scan of hist[d * nb .. d * nb + nb) over
-// the tiles into pre[].  Also clears the next pass's digit totals.
+// the tiles into pre[], and the digit's total into dtot[d].
 __global__ __launch_bounds__(kBlock) void k_radix_rowscan(const uint32_t* __restrict__ hist, int nb,
-                                                         uint32_t* __restrict__ pre, uint32_t* __restrict__ dnext)
+                                                         uint32_t* __restrict__ pre, uint32_t* __restrict__ dtot)
 {
     __shared__ uint32_t lw[kBlock / kWave];
     const int d = blockIdx.x, t = threadIdx.x;
@@ -153,13 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_rowscan(const uint32_t* __rest
             pre[row + b0 + k] = run;
             run += c;
         }
-    if (t == 0 && dnext) dnext[d] = 0;
-}
-
-__global__ void k_radix_zero(uint32_t* __restrict__ v, int n)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) v[i] = 0;
+    if (t == 0) dtot[d] = tot;
 }
 
 // Scatter of one tile: the keys are ranked stably per digit (wave ballots and
@@ -245,20 +236,17 @@ int radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n, int pas
     const int nb = ceil_div(n, kTile);
     const int64_t hn = (int64_t)256 * nb;
     uint32_t* pre = hist + hn;
-    uint32_t* dtot = pre + hn; // two sets of 256 digit totals, used by alternate passes
-    hipLaunchKernelGGL(k_radix_zero, dim3(1), dim3(kBlock), 0, s, dtot, 256);
+    uint32_t* dtot = pre + hn; // 256 digit totals
     K* ki = k0;
     uint32_t* vi = v0;
     K* ko = k1;
     uint32_t* vo = v1;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        uint32_t* dcur = dtot + 256 * (p & 1);
-        uint32_t* dnext = p + 1 < passes ? dtot + 256 * ((p + 1) & 1) : nullptr;
-        hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(kBlock), 0, s, ki, n, shift, hist, nb, dcur);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kBlock), 0, s, hist, nb, pre, dnext);
+        hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(kBlock), 0, s, ki, n, shift, hist, nb);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kBlock), 0, s, hist, nb, pre, dtot);
         hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, n, shift, hist,
-                           pre, dcur, nb);
+                           pre, dtot, nb);
         K* tk = ki; ki = ko; ko = tk;
         uint32_t* tv = vi; vi = vo; vo = tv;
     }
@@ -281,7 +269,7 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* scr
 size_t radix_hist_words(int64_t n)
 {
     const int64_t hn = (int64_t)256 * ceil_div(n > 0 ? n : 1, kTile);
-    return 2 * (size_t)hn + 512; // counts, their per-digit prefixes, two sets of digit totals
+    return 2 * (size_t)hn + 256; // counts, their per-digit prefixes, digit totals
 }
 
 int radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t n, int passes,
