@@ -495,16 +495,11 @@ __device__ inline void box_bounds(const BoxArrays& b, int c, const BuildSync* sy
 // translated, Q_k = sum_children sum_j C(k, j) Q_j(child) t^(k-j) with
 // t = z_child - z_cm (exact re-expansion of sum m (z - z_cm)^k).
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restrict__ levidx, int count, BoxArrays b,
-                                                         const double* __restrict__ xs, const double* __restrict__ ys,
-                                                         const double* __restrict__ ms,
-                                                         const BuildSync* __restrict__ sync, double* __restrict__ cM,
-                                                         double* __restrict__ ccx, double* __restrict__ ccy,
-                                                         double* __restrict__ cQ)
+__device__ inline void moments_box(int c, const BoxArrays& b, const double* __restrict__ xs,
+                                   const double* __restrict__ ys, const double* __restrict__ ms,
+                                   const BuildSync* __restrict__ sync, double* __restrict__ cM,
+                                   double* __restrict__ ccx, double* __restrict__ ccy, double* __restrict__ cQ)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= count) return;
-    const int c = levidx[t];
     constexpr int P1 = P + 1; // Q_0 .. Q_P
     double Qr[P1], Qi[P1];
 #pragma unroll
@@ -636,6 +631,37 @@ __global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restr
     for (int k = 0; k < P1; ++k) {
         q[2 * k] = Qr[k];
         q[2 * k + 1] = Qi[k];
+    }
+}
+
+// One level of boxes, one thread per box.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restrict__ levidx, int count, BoxArrays b,
+                                                         const double* __restrict__ xs, const double* __restrict__ ys,
+                                                         const double* __restrict__ ms,
+                                                         const BuildSync* __restrict__ sync, double* __restrict__ cM,
+                                                         double* __restrict__ ccx, double* __restrict__ ccy,
+                                                         double* __restrict__ cQ)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= count) return;
+    moments_box<P>(levidx[t], b, xs, ys, ms, sync, cM, ccx, ccy, cQ);
+}
+
+// Levels ltop .. 0 (each with at most kBlock boxes) in one block, deepest
+// first; the barrier between levels makes a level's results visible to its
+// parents' threads.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_moments_top(const int32_t* __restrict__ levidx, LevelTable lt, int ltop,
+                                                       BoxArrays b, const double* __restrict__ xs,
+                                                       const double* __restrict__ ys, const double* __restrict__ ms,
+                                                       const BuildSync* __restrict__ sync, double* __restrict__ cM,
+                                                       double* __restrict__ ccx, double* __restrict__ ccy,
+                                                       double* __restrict__ cQ)
+{
+    for (int l = ltop; l >= 0; --l) {
+        if ((int)threadIdx.x < lt.cnt[l]) moments_box<P>(levidx[lt.off[l] + threadIdx.x], b, xs, ys, ms, sync, cM, ccx, ccy, cQ);
+        __syncthreads();
     }
 }
 
@@ -865,7 +891,11 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     hipLaunchKernelGGL(k_list_ranges, dim3(gb), dim3(kBlock), 0, st, n, lw ? lk1 : lk0, lw ? lv1 : lv0, unlisted, xs,
                        ys, ms, ss, kind, q, norm, b, lst, sync);
     hipLaunchKernelGGL(k_list_reach, dim3(ceil_div(nc, kBlock / kWave)), dim3(kBlock), 0, st, b, nc, lst, lreach);
-    for (int l = kMaxLevel; l >= 0; --l)
+    // the top levels, as long as each holds at most kBlock boxes, go to one
+    // block; the deeper ones get a launch per level, deepest first
+    int ltop = -1;
+    while (ltop < kMaxLevel && lt.cnt[ltop + 1] <= kBlock) ++ltop;
+    for (int l = kMaxLevel; l > ltop; --l)
         if (lt.cnt[l] > 0) {
             const dim3 g(ceil_div(lt.cnt[l], kBlock)), blk(kBlock);
 #define GLM_CASE(PP)                                                                                          \
@@ -880,6 +910,19 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
             }
 #undef GLM_CASE
         }
+    if (ltop >= 0) {
+#define GLM_CASE(PP)                                                                                            \
+    case PP:                                                                                                    \
+        hipLaunchKernelGGL((k_moments_top<PP>), dim3(1), dim3(kBlock), 0, st, levidx, lt, ltop, b, xs, ys, ms, sync, \
+                           cM, ccx, ccy, cQ);                                                                   \
+        break;
+        switch (p) {
+            GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
+            GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
+            default: break;
+        }
+#undef GLM_CASE
+    }
     hipLaunchKernelGGL(k_finalize, dim3(gc), dim3(kBlock), 0, st, nc, p, prm.theta, b, sync, cM, ccx, ccy, cQ, hdr, ext,
                        mom);
     GLM_HIP(hipGetLastError());
