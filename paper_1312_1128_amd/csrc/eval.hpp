@@ -538,14 +538,30 @@ __device__ inline void split_range(int k, int K, int B, int NB, int nc, int* c0,
 
 // Work of one wavefront in a walk launch over `groups` ray groups, each walked
 // by K wavefronts (one per box range).  Workgroups are dispatched round-robin
-// over the 8 XCDs: each XCD takes a contiguous chunk of ray groups (its L2 then
-// holds the boxes of neighbouring rays), and inside an XCD the waves run
-// range-major, so that the first range of every group is dispatched first.
+// over the 8 XCDs; inside an XCD the waves run range-major, so that the first
+// range of every group is dispatched first.
 constexpr int kXcds = 8;
+
+// Groups go to the XCDs in chunks of C consecutive groups (C = groups / 512,
+// 1 to 128), round robin, so that every XCD gets a share of each part of the
+// image, whose cost per ray varies a lot across it (one contiguous eighth per
+// XCD left the XCDs holding the dense centre running 12% longer), while
+// neighbouring groups stay together on one XCD for its L2.
+__host__ __device__ inline int64_t walk_chunk(int64_t groups)
+{
+    const int64_t c = groups / (64 * kXcds);
+    return c < 1 ? 1 : (c > 128 ? 128 : c);
+}
+__host__ __device__ inline int64_t walk_slots(int64_t groups) // group slots per XCD
+{
+    const int64_t c = walk_chunk(groups);
+    const int64_t chunks = (groups + c - 1) / c;
+    return (chunks + kXcds - 1) / kXcds * c;
+}
 
 __host__ __device__ inline int64_t walk_grid_blocks(int64_t groups, int K)
 {
-    const int64_t gx = (groups + kXcds - 1) / kXcds;
+    const int64_t gx = walk_slots(groups);
     return kXcds * ((K * gx + kBlock / kWave - 1) / (kBlock / kWave));
 }
 
@@ -553,10 +569,11 @@ __host__ __device__ inline int64_t walk_grid_blocks(int64_t groups, int K)
 // false for the waves of the padded grid that have no work.
 __device__ inline bool walk_task(int b, int w, int64_t groups, int K, int* k, int64_t* group)
 {
-    const int64_t gx = (groups + kXcds - 1) / kXcds;
+    const int64_t gx = walk_slots(groups), c = walk_chunk(groups);
     const int64_t wj = (int64_t)(b / kXcds) * (kBlock / kWave) + w;
     *k = (int)(wj / gx);
-    *group = (int64_t)(b % kXcds) * gx + wj % gx;
+    const int64_t slot = wj % gx;
+    *group = ((slot / c) * kXcds + b % kXcds) * c + slot % c;
     return *k < K && *group < groups;
 }
 
