@@ -346,11 +346,27 @@ __global__ __launch_bounds__(kBlock) void k_topo_emit(const uint64_t* __restrict
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_leaf_of(BoxArrays b, int ncells, int32_t* __restrict__ leaf_of)
+// Each particle's leaf, and each internal box's children (preorder: c + 1,
+// then each child's next, up to the box's own next; -1 past the last child).
+__global__ __launch_bounds__(kBlock) void k_leaf_of(BoxArrays b, int ncells, int32_t* __restrict__ leaf_of,
+                                                    int32_t* __restrict__ kids)
 {
     const int c = blockIdx.x * kBlock + threadIdx.x;
-    if (c >= ncells || !b.leaf[c]) return;
-    for (int j = b.beg[c]; j < b.end[c]; ++j) leaf_of[j] = c;
+    if (c >= ncells) return;
+    if (b.leaf[c]) {
+        for (int j = b.beg[c]; j < b.end[c]; ++j) leaf_of[j] = c;
+        return;
+    }
+    const int cend = b.next[c];
+    int ch = c + 1;
+    for (int u = 0; u < 4; ++u) {
+        const bool has = ch < cend;
+        kids[4 * (size_t)c + u] = has ? ch : -1;
+        if (has) {
+            const int nx = b.next[ch];
+            ch = nx > ch ? nx : ch + 1;
+        }
+    }
 }
 
 // Big-particle lists (Sec. 3.2): a smoothed particle of support radius
@@ -490,177 +506,194 @@ __device__ inline void box_bounds(const BoxArrays& b, int c, const BuildSync* sy
     *by1 = sync->y0 + ((double)b.iy[c] + 1.0) * side;
 }
 
-// One level of the bottom-up pass.  Leaves: moments from their particles.
-// Internal boxes: centre of mass of the children, then the children's moments
-// translated, Q_k = sum_children sum_j C(k, j) Q_j(child) t^(k-j) with
-// t = z_child - z_cm (exact re-expansion of sum m (z - z_cm)^k).
-template <int P>
-__device__ inline void moments_box(int c, const BoxArrays& b, const double* __restrict__ xs,
-                                   const double* __restrict__ ys, const double* __restrict__ ms,
-                                   const BuildSync* __restrict__ sync, double* __restrict__ cM,
-                                   double* __restrict__ ccx, double* __restrict__ ccy, double* __restrict__ cQ)
+// Sum of v over an aligned group of G lanes (G a power of two, at most the
+// wavefront) by butterfly exchanges; a + b == b + a in IEEE arithmetic, so
+// every lane of the group ends with the same bits.
+template <int G>
+__device__ inline double group_sum(double v)
 {
-    constexpr int P1 = P + 1; // Q_0 .. Q_P
-    double Qr[P1], Qi[P1];
 #pragma unroll
-    for (int k = 0; k < P1; ++k) Qr[k] = Qi[k] = 0.0;
-    double M = 0.0, cx, cy;
-    if (b.leaf[c]) {
-        // a leaf's particles (at most 64) in groups of four, so that their
-        // loads are in flight together; the sums keep particle order
-        const int j0 = b.beg[c], j1 = b.end[c];
-        double sx = 0.0, sy = 0.0;
-        for (int j = j0; j < j1; j += 4) {
-            double mm[4], xx[4], yy[4];
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+// Store the moments Q_0 .. Q_P of box c (identical in every lane of a group of
+// G lanes): lane u writes the words u, u + G, ... of the box's record.
+template <int P, int G>
+__device__ inline void store_moments(int c, int u, const double* Qr, const double* Qi, double* __restrict__ cQ)
+{
+    double* q = cQ + (size_t)c * (P + 1) * 2;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int jj = j + u < j1 ? j + u : j0;
-                mm[u] = ms[jj];
-                xx[u] = xs[jj];
-                yy[u] = ys[jj];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (j + u < j1) {
-                    M += mm[u];
-                    sx += mm[u] * xx[u];
-                    sy += mm[u] * yy[u];
-                }
-        }
-        if (M > 0.0) {
-            cx = sx / M;
-            cy = sy / M;
-        } else {
-            double bx0, bx1, by0, by1;
-            box_bounds(b, c, sync, &bx0, &bx1, &by0, &by1);
-            cx = 0.5 * (bx0 + bx1);
-            cy = 0.5 * (by0 + by1);
-        }
-        for (int j = j0; j < j1; j += 4) {
-            double mm[4], xx[4], yy[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int jj = j + u < j1 ? j + u : j0;
-                mm[u] = ms[jj];
-                xx[u] = xs[jj];
-                yy[u] = ys[jj];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (j + u >= j1) break;
-                const double dr = xx[u] - cx, di = yy[u] - cy;
-                double pr = mm[u], pi = 0.0;
-#pragma unroll
-                for (int k = 0; k < P1; ++k) {
-                    Qr[k] += pr;
-                    Qi[k] += pi;
-                    const double t = pr * dr - pi * di;
-                    pi = pr * di + pi * dr;
-                    pr = t;
-                }
-            }
-        }
-    } else {
-        // the children (at most four, one level down) in preorder; their
-        // records are loaded together once the chain of indices is known
-        int chs[4];
-        int nch = 0;
-        const int cend = b.next[c];
-        for (int ch = c + 1; ch < cend && nch < 4; ch = b.next[ch] > ch ? b.next[ch] : ch + 1) chs[nch++] = ch;
-        double cm[4], cxs[4], cys[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int ch = u < nch ? chs[u] : c;
-            cm[u] = cM[ch];
-            cxs[u] = ccx[ch];
-            cys[u] = ccy[ch];
-        }
-        double sx = 0.0, sy = 0.0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (u < nch) {
-                M += cm[u];
-                sx += cm[u] * cxs[u];
-                sy += cm[u] * cys[u];
-            }
-        if (M > 0.0) {
-            cx = sx / M;
-            cy = sy / M;
-        } else {
-            double bx0, bx1, by0, by1;
-            box_bounds(b, c, sync, &bx0, &bx1, &by0, &by1);
-            cx = 0.5 * (bx0 + bx1);
-            cy = 0.5 * (by0 + by1);
-        }
-        for (int u = 0; u < nch; ++u) {
-            const double tr = cxs[u] - cx, ti = cys[u] - cy;
-            double tpr[P1], tpi[P1];
-            tpr[0] = 1.0;
-            tpi[0] = 0.0;
-#pragma unroll
-            for (int k = 1; k < P1; ++k) {
-                tpr[k] = tpr[k - 1] * tr - tpi[k - 1] * ti;
-                tpi[k] = tpr[k - 1] * ti + tpi[k - 1] * tr;
-            }
-            const double* q = cQ + (size_t)chs[u] * P1 * 2;
-            double qr[P1], qi[P1];
-#pragma unroll
-            for (int k = 0; k < P1; ++k) {
-                qr[k] = q[2 * k];
-                qi[k] = q[2 * k + 1];
-            }
-#pragma unroll
-            for (int k = 0; k < P1; ++k) {
-                double sr = 0.0, si = 0.0;
-#pragma unroll
-                for (int j = 0; j <= k; ++j) {
-                    const double br = binomial(k, j) * qr[j], bi = binomial(k, j) * qi[j];
-                    sr += br * tpr[k - j] - bi * tpi[k - j];
-                    si += br * tpi[k - j] + bi * tpr[k - j];
-                }
-                Qr[k] += sr;
-                Qi[k] += si;
-            }
-        }
-    }
-    cM[c] = M;
-    ccx[c] = cx;
-    ccy[c] = cy;
-    double* q = cQ + (size_t)c * P1 * 2;
-#pragma unroll
-    for (int k = 0; k < P1; ++k) {
-        q[2 * k] = Qr[k];
-        q[2 * k + 1] = Qi[k];
+    for (int k = 0; k <= P; ++k) {
+        if ((2 * k) % G == u) q[2 * k] = Qr[k];
+        if ((2 * k + 1) % G == u) q[2 * k + 1] = Qi[k];
     }
 }
 
-// One level of boxes, one thread per box.
+// Leaf moments (Sec. 3.2) about the leaf's centre of mass, Q_k = sum m (z - z_cm)^k,
+// for every leaf at once (they depend on no other box): kLeafLanes lanes per
+// box, lane u summing the leaf's particles u, u + kLeafLanes, ...; the lanes'
+// partial sums meet by butterfly exchanges.
+constexpr int kLeafLanes = 16;
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_moments_leaves(int ncells, BoxArrays b, const double* __restrict__ xs,
+                                                          const double* __restrict__ ys, const double* __restrict__ ms,
+                                                          const BuildSync* __restrict__ sync, double* __restrict__ cM,
+                                                          double* __restrict__ ccx, double* __restrict__ ccy,
+                                                          double* __restrict__ cQ)
+{
+    constexpr int P1 = P + 1;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int c = (int)(gid / kLeafLanes), u = (int)(gid % kLeafLanes);
+    // a group's lanes share c, so whole groups leave together
+    if (c >= ncells || !b.leaf[c]) return;
+    const int j0 = b.beg[c], j1 = b.end[c];
+    double M = 0.0, sx = 0.0, sy = 0.0;
+    for (int j = j0 + u; j < j1; j += kLeafLanes) {
+        const double mm = ms[j];
+        M += mm;
+        sx += mm * xs[j];
+        sy += mm * ys[j];
+    }
+    M = group_sum<kLeafLanes>(M);
+    sx = group_sum<kLeafLanes>(sx);
+    sy = group_sum<kLeafLanes>(sy);
+    double cx, cy;
+    if (M > 0.0) {
+        cx = sx / M;
+        cy = sy / M;
+    } else {
+        double bx0, bx1, by0, by1;
+        box_bounds(b, c, sync, &bx0, &bx1, &by0, &by1);
+        cx = 0.5 * (bx0 + bx1);
+        cy = 0.5 * (by0 + by1);
+    }
+    double Qr[P1], Qi[P1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) Qr[k] = Qi[k] = 0.0;
+    for (int j = j0 + u; j < j1; j += kLeafLanes) {
+        const double dr = xs[j] - cx, di = ys[j] - cy;
+        double pr = ms[j], pi = 0.0;
+#pragma unroll
+        for (int k = 0; k < P1; ++k) {
+            Qr[k] += pr;
+            Qi[k] += pi;
+            const double t = pr * dr - pi * di;
+            pi = pr * di + pi * dr;
+            pr = t;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+        Qr[k] = group_sum<kLeafLanes>(Qr[k]);
+        Qi[k] = group_sum<kLeafLanes>(Qi[k]);
+    }
+    if (u == 0) {
+        cM[c] = M;
+        ccx[c] = cx;
+        ccy[c] = cy;
+    }
+    store_moments<P, kLeafLanes>(c, u, Qr, Qi, cQ);
+}
+
+// An internal box c from its (at most four) children, lane u of an aligned
+// group of four holding child u: the centre of mass of the children, then each
+// child's moments translated, Q_k = sum_children sum_j C(k, j) Q_j(child) t^(k-j)
+// with t = z_child - z_cm (the exact re-expansion of sum m (z - z_cm)^k).  All
+// four lanes load their child's records together.
+template <int P>
+__device__ inline void moments_internal(int c, int u, const BoxArrays& b, const int32_t* __restrict__ kids,
+                                        const BuildSync* __restrict__ sync, double* __restrict__ cM,
+                                        double* __restrict__ ccx, double* __restrict__ ccy, double* __restrict__ cQ)
+{
+    constexpr int P1 = P + 1;
+    const int ch = kids[4 * (size_t)c + u];
+    const bool has = ch >= 0;
+    const int cc = has ? ch : c; // an in-bounds index for the loads of an absent child
+    double qr[P1], qi[P1];
+    const double* q = cQ + (size_t)cc * P1 * 2;
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+        qr[k] = q[2 * k];
+        qi[k] = q[2 * k + 1];
+    }
+    const double m = has ? cM[cc] : 0.0, x = ccx[cc], y = ccy[cc];
+    const double M = group_sum<4>(m), sx = group_sum<4>(has ? m * x : 0.0), sy = group_sum<4>(has ? m * y : 0.0);
+    double cx, cy;
+    if (M > 0.0) {
+        cx = sx / M;
+        cy = sy / M;
+    } else {
+        double bx0, bx1, by0, by1;
+        box_bounds(b, c, sync, &bx0, &bx1, &by0, &by1);
+        cx = 0.5 * (bx0 + bx1);
+        cy = 0.5 * (by0 + by1);
+    }
+    const double tr = x - cx, ti = y - cy;
+    double tpr[P1], tpi[P1];
+    tpr[0] = 1.0;
+    tpi[0] = 0.0;
+#pragma unroll
+    for (int k = 1; k < P1; ++k) {
+        tpr[k] = tpr[k - 1] * tr - tpi[k - 1] * ti;
+        tpi[k] = tpr[k - 1] * ti + tpi[k - 1] * tr;
+    }
+    double Qr[P1], Qi[P1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int j = 0; j <= k; ++j) {
+            const double br = binomial(k, j) * qr[j], bi = binomial(k, j) * qi[j];
+            sr += br * tpr[k - j] - bi * tpi[k - j];
+            si += br * tpi[k - j] + bi * tpr[k - j];
+        }
+        Qr[k] = group_sum<4>(has ? sr : 0.0);
+        Qi[k] = group_sum<4>(has ? si : 0.0);
+    }
+    if (u == 0) {
+        cM[c] = M;
+        ccx[c] = cx;
+        ccy[c] = cy;
+    }
+    store_moments<P, 4>(c, u, Qr, Qi, cQ);
+}
+
+// The internal boxes of one level, four lanes per box (its leaves are done).
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_moments_level(const int32_t* __restrict__ levidx, int count, BoxArrays b,
-                                                         const double* __restrict__ xs, const double* __restrict__ ys,
-                                                         const double* __restrict__ ms,
+                                                         const int32_t* __restrict__ kids,
                                                          const BuildSync* __restrict__ sync, double* __restrict__ cM,
                                                          double* __restrict__ ccx, double* __restrict__ ccy,
                                                          double* __restrict__ cQ)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int t = (int)(gid >> 2), u = (int)(gid & 3);
     if (t >= count) return;
-    moments_box<P>(levidx[t], b, xs, ys, ms, sync, cM, ccx, ccy, cQ);
+    const int c = levidx[t];
+    if (b.leaf[c]) return;
+    moments_internal<P>(c, u, b, kids, sync, cM, ccx, ccy, cQ);
 }
 
-// Levels ltop .. 0 (each with at most kBlock boxes) in one block, deepest
-// first; the barrier between levels makes a level's results visible to its
-// parents' threads.
+// Levels ltop .. 0 (each with at most kBlock boxes) in one block of
+// kTopThreads = 4 kBlock lanes, deepest first; the barrier between levels
+// makes a level's results visible to its parents' lanes.
+constexpr int kTopThreads = 4 * kBlock;
+
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_moments_top(const int32_t* __restrict__ levidx, LevelTable lt, int ltop,
-                                                       BoxArrays b, const double* __restrict__ xs,
-                                                       const double* __restrict__ ys, const double* __restrict__ ms,
-                                                       const BuildSync* __restrict__ sync, double* __restrict__ cM,
-                                                       double* __restrict__ ccx, double* __restrict__ ccy,
-                                                       double* __restrict__ cQ)
+__global__ __launch_bounds__(kTopThreads) void k_moments_top(const int32_t* __restrict__ levidx, LevelTable lt, int ltop,
+                                                            BoxArrays b, const int32_t* __restrict__ kids,
+                                                            const BuildSync* __restrict__ sync, double* __restrict__ cM,
+                                                            double* __restrict__ ccx, double* __restrict__ ccy,
+                                                            double* __restrict__ cQ)
 {
+    const int t = (int)threadIdx.x >> 2, u = (int)threadIdx.x & 3;
     for (int l = ltop; l >= 0; --l) {
-        if ((int)threadIdx.x < lt.cnt[l]) moments_box<P>(levidx[lt.off[l] + threadIdx.x], b, xs, ys, ms, sync, cM, ccx, ccy, cQ);
+        if (t < lt.cnt[l]) {
+            const int c = levidx[lt.off[l] + t];
+            if (!b.leaf[c]) moments_internal<P>(c, u, b, kids, sync, cM, ccx, ccy, cQ);
+        }
         __syncthreads();
     }
 }
@@ -833,6 +866,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     const size_t o_ext = ca.take(sizeof(CellExt) * (size_t)nc);
     const size_t o_mom = ca.take(4ull * stride * nc);
     const size_t o_levidx = ca.take(4ull * nc);
+    const size_t o_kids = ca.take(16ull * nc);
     const size_t o_lreach = ca.take(32ull * nc);
     rc = ts.cbuf.ensure(ca.size);
     if (rc != GLM_OK) return rc;
@@ -855,6 +889,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     CellExt* ext = reinterpret_cast<CellExt*>(C0 + o_ext);
     float* mom = reinterpret_cast<float*>(C0 + o_mom);
     int32_t* levidx = reinterpret_cast<int32_t*>(C0 + o_levidx);
+    int32_t* kids = reinterpret_cast<int32_t*>(C0 + o_kids);
     double* lreach = reinterpret_cast<double*>(C0 + o_lreach);
     LevelTable lt;
     {
@@ -870,7 +905,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     const int gc = ceil_div(nc, kBlock);
     hipLaunchKernelGGL(k_topo_emit, dim3(gc), dim3(kBlock), 0, st, K, n, nc, cnt, lstart, b, sync, lt, levidx);
     GLM_HIP(hipMemsetAsync(leaf_of, 0xff, 4ull * n, st)); // -1: no leaf (an internal error if it stays)
-    hipLaunchKernelGGL(k_leaf_of, dim3(gc), dim3(kBlock), 0, st, b, nc, leaf_of);
+    hipLaunchKernelGGL(k_leaf_of, dim3(gc), dim3(kBlock), 0, st, b, nc, leaf_of, kids);
     // list keys: box index, or all-ones on the sorted bits for unlisted particles
     int passes = 1;
     while (passes < 4 && ((uint64_t)nc >= (1ull << (8 * passes)) - 1)) ++passes;
@@ -891,17 +926,31 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     hipLaunchKernelGGL(k_list_ranges, dim3(gb), dim3(kBlock), 0, st, n, lw ? lk1 : lk0, lw ? lv1 : lv0, unlisted, xs,
                        ys, ms, ss, kind, q, norm, b, lst, sync);
     hipLaunchKernelGGL(k_list_reach, dim3(ceil_div(nc, kBlock / kWave)), dim3(kBlock), 0, st, b, nc, lst, lreach);
-    // the top levels, as long as each holds at most kBlock boxes, go to one
-    // block; the deeper ones get a launch per level, deepest first
+    // every leaf at once; then the internal boxes: the top levels, as long as
+    // each holds at most kBlock boxes, in one block, the deeper ones in a
+    // launch per level, deepest first
+    {
+        const dim3 g((unsigned)ceil_div((int64_t)nc * kLeafLanes, (int64_t)kBlock)), blk(kBlock);
+#define GLM_CASE(PP)                                                                                                \
+    case PP:                                                                                                        \
+        hipLaunchKernelGGL((k_moments_leaves<PP>), g, blk, 0, st, nc, b, xs, ys, ms, sync, cM, ccx, ccy, cQ); \
+        break;
+        switch (p) {
+            GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
+            GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)
+            default: break;
+        }
+#undef GLM_CASE
+    }
     int ltop = -1;
     while (ltop < kMaxLevel && lt.cnt[ltop + 1] <= kBlock) ++ltop;
     for (int l = kMaxLevel; l > ltop; --l)
         if (lt.cnt[l] > 0) {
-            const dim3 g(ceil_div(lt.cnt[l], kBlock)), blk(kBlock);
+            const dim3 g((unsigned)ceil_div(4 * (int64_t)lt.cnt[l], (int64_t)kBlock)), blk(kBlock);
 #define GLM_CASE(PP)                                                                                          \
     case PP:                                                                                                  \
-        hipLaunchKernelGGL((k_moments_level<PP>), g, blk, 0, st, levidx + lt.off[l], lt.cnt[l], b, xs, ys, ms, \
-                           sync, cM, ccx, ccy, cQ);                                                           \
+        hipLaunchKernelGGL((k_moments_level<PP>), g, blk, 0, st, levidx + lt.off[l], lt.cnt[l], b, kids, sync, \
+                           cM, ccx, ccy, cQ);                                                                 \
         break;
             switch (p) {
                 GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
@@ -913,7 +962,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     if (ltop >= 0) {
 #define GLM_CASE(PP)                                                                                            \
     case PP:                                                                                                    \
-        hipLaunchKernelGGL((k_moments_top<PP>), dim3(1), dim3(kBlock), 0, st, levidx, lt, ltop, b, xs, ys, ms, sync, \
+        hipLaunchKernelGGL((k_moments_top<PP>), dim3(1), dim3(kTopThreads), 0, st, levidx, lt, ltop, b, kids, sync, \
                            cM, ccx, ccy, cQ);                                                                   \
         break;
         switch (p) {
