@@ -402,8 +402,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                     p1 = n1;
                     p2 = n2;
                 }
-                // S = P(t) + t P'(t) = sum (k+1) Qn_k t^k  (Qn_0 = 1, Qn_1 = 0)
-                float b1 = 1.0f, b2 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+                // M S = M (P(t) + t P'(t)) = sum (k+1) M Qn_k t^k  (Qn_0 = 1, Qn_1 = 0;
+                // the record holds M Qn_k)
+                float b1 = M, b2 = 0.0f, c1 = 0.0f, c2 = 0.0f;
                 if constexpr (P >= 2) {
                     b1 = mo[2 + 2 * (P - 2)];
                     b2 = mo[3 + 2 * (P - 2)];
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                     c2 = b2;
 #pragma unroll
                     for (int k = P - 1; k >= 0; --k) {
-                        const float q1 = k >= 2 ? mo[2 + 2 * (k - 2)] : (k == 0 ? 1.0f : 0.0f);
+                        const float q1 = k >= 2 ? mo[2 + 2 * (k - 2)] : (k == 0 ? M : 0.0f);
                         const float q2 = k >= 2 ? mo[3 + 2 * (k - 2)] : 0.0f;
                         const float m1 = fmaf(b1, t1, fmaf(-b2, t2, q1)), m2 = fmaf(b1, t2, fmaf(b2, t1, q2));
                         b1 = m1;
@@ -425,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 }
                 const float S1 = fmaf(t1, c1, fmaf(-t2, c2, b1)), S2 = fmaf(t1, c2, fmaf(t2, c1, b2));
                 const float w21 = fmaf(v1, v1, -v2 * v2), w22 = 2.0f * v1 * v2;
-                const float V1 = M * fmaf(w21, S1, -w22 * S2), V2 = M * fmaf(w21, S2, w22 * S1);
+                const float V1 = fmaf(w21, S1, -w22 * S2), V2 = fmaf(w21, S2, w22 * S1);
                 a[NA - 2] = g1 * V1 - g2 * V2;
                 a[NA - 1] = g1 * V2 + g2 * V1;
                 if constexpr (KG) {
@@ -440,19 +441,19 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                         q1 = n1;
                         q2 = n2;
                     }
-                    // T(t) = sum_k (k+1)(k+2) Qn_k t^k by Horner (Qn_0 = 1, Qn_1 = 0)
+                    // M T(t) = sum_k (k+1)(k+2) M Qn_k t^k by Horner (Qn_0 = 1, Qn_1 = 0)
                     float T1 = 0.0f, T2 = 0.0f;
 #pragma unroll
                     for (int k = P; k >= 0; --k) {
                         const float cf = (float)((k + 1) * (k + 2));
-                        const float q1k = k >= 2 ? cf * mo[2 + 2 * (k - 2)] : (k == 0 ? cf : 0.0f);
+                        const float q1k = k >= 2 ? cf * mo[2 + 2 * (k - 2)] : (k == 0 ? cf * M : 0.0f);
                         const float q2k = k >= 2 ? cf * mo[3 + 2 * (k - 2)] : 0.0f;
                         const float n1 = fmaf(T1, t1, fmaf(-T2, t2, q1k)), n2 = fmaf(T1, t2, fmaf(T2, t1, q2k));
                         T1 = n1;
                         T2 = n2;
                     }
                     const float w31 = fmaf(w21, v1, -w22 * v2), w32 = fmaf(w21, v2, w22 * v1); // v^3
-                    const float U1 = M * fmaf(w31, T1, -w32 * T2), U2 = M * fmaf(w31, T2, w32 * T1);
+                    const float U1 = fmaf(w31, T1, -w32 * T2), U2 = fmaf(w31, T2, w32 * T1);
                     a[NA - 2] -= h1 * U1 - h2 * U2;
                     a[NA - 1] -= h1 * U2 + h2 * U1;
                 }

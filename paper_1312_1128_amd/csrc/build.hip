@@ -737,8 +737,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int ncells, int p, double t
     const double rcm = sqrt(dmax2);
     mo[0] = (float)M;
     mo[1] = (float)rcm;
+    // M Qn_k = Q_k / r_cm^k (Qn_k = Q_k / (M r_cm^k)): the walk's series then
+    // carries the box mass in its coefficients
     const double* q = cQ + (size_t)c * (p + 1) * 2;
-    double scale = (M > 0.0) ? 1.0 / M : 0.0;
+    double scale = 1.0;
     const double irc = 1.0 / rcm;
     scale *= irc; // k = 1
     for (int k = 2; k <= p; ++k) {

@@ -410,8 +410,9 @@ __device__ inline void list_particle(const PRec& pr, double X, double Y, Acc& A,
 }
 
 // Multipole expansion of an accepted box about its centre of mass (Sec. 3.2):
-//   alpha1 - i alpha2 = M v P(t),  gamma1 - i gamma2 = -M v^2 (P(t) + t P'(t)),
-// v = 1/w, t = r_cm v, P(t) = 1 + sum_{k>=2} Qn_k t^k, Qn_k = Q_k / (M r_cm^k).
+//   alpha1 - i alpha2 = v B(t),  gamma1 - i gamma2 = -v^2 (B(t) + t B'(t)),
+// v = 1/w, t = r_cm v, B(t) = M P(t) = M + sum_{k>=2} (M Qn_k) t^k with
+// Qn_k = Q_k / (M r_cm^k); the record holds M, r_cm and M Qn_k = Q_k / r_cm^k.
 template <int P, bool AONLY, bool F64A, bool PSI = false>
 __device__ inline void eval_box(const float* __restrict__ mo, double w1, double w2, Acc& A)
 {
@@ -420,9 +421,9 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
     const float inv = __builtin_amdgcn_rcpf(fmaf(f1, f1, f2 * f2));
     const float v1 = f1 * inv, v2 = -f2 * inv;
     const float t1 = rcm * v1, t2 = rcm * v2;
-    // Horner in t for b = P(t) and c = P'(t): c <- c t + b, b <- b t + Qn_k,
+    // Horner in t for b = B(t) and c = B'(t): c <- c t + b, b <- b t + M Qn_k,
     // each complex multiply-add as two FMAs per component
-    float b1 = 1.0f, b2 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    float b1 = M, b2 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     if constexpr (P >= 2) {
         b1 = mo[2 + 2 * (P - 2)];
         b2 = mo[3 + 2 * (P - 2)];
@@ -430,7 +431,7 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
         c2 = b2;
 #pragma unroll
         for (int k = P - 1; k >= 0; --k) {
-            const float q1 = k >= 2 ? mo[2 + 2 * (k - 2)] : (k == 0 ? 1.0f : 0.0f);
+            const float q1 = k >= 2 ? mo[2 + 2 * (k - 2)] : (k == 0 ? M : 0.0f);
             const float q2 = k >= 2 ? mo[3 + 2 * (k - 2)] : 0.0f;
             const float n1 = fmaf(b1, t1, fmaf(-b2, t2, q1));
             const float n2 = fmaf(b1, t2, fmaf(b2, t1, q2));
@@ -446,19 +447,19 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
             }
         }
     }
-    // alpha1 - i alpha2 = M v b
-    const float F1 = M * fmaf(v1, b1, -v2 * b2), F2 = M * fmaf(v1, b2, v2 * b1);
+    // alpha1 - i alpha2 = v b
+    const float F1 = fmaf(v1, b1, -v2 * b2), F2 = fmaf(v1, b2, v2 * b1);
     add_alpha<F64A>(A, F1, -F2);
     if constexpr (!AONLY) {
-        // gamma1 - i gamma2 = -M v^2 (b + t c)
+        // gamma1 - i gamma2 = -v^2 (b + t c)
         const float S1 = fmaf(t1, c1, fmaf(-t2, c2, b1)), S2 = fmaf(t1, c2, fmaf(t2, c1, b2));
         const float w21 = fmaf(v1, v1, -v2 * v2), w22 = 2.0f * v1 * v2;
-        const float G1 = M * fmaf(w21, S1, -w22 * S2), G2 = M * fmaf(w21, S2, w22 * S1);
+        const float G1 = fmaf(w21, S1, -w22 * S2), G2 = fmaf(w21, S2, w22 * S1);
         A.g1 -= (double)G1;
         A.g2 += (double)G2;
     }
     if constexpr (PSI) {
-        // psi = Re[Q_0 ln w - sum_k Q_k / (k w^k)] = M (ln|w| - Re sum_{k>=2} (Qn_k / k) t^k)
+        // psi = Re[Q_0 ln w - sum_k Q_k / (k w^k)] = M ln|w| - Re sum_{k>=2} (M Qn_k / k) t^k
         float re = 0.0f;
         if constexpr (P >= 2) {
             float s1 = 0.0f, s2 = 0.0f;
@@ -473,7 +474,7 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
             const float u1 = fmaf(t1, t1, -t2 * t2), u2 = 2.0f * t1 * t2; // t^2
             re = fmaf(s1, u1, -s2 * u2);
         }
-        A.ps += (double)(M * (0.5f * __logf(fmaf(f1, f1, f2 * f2)) - re));
+        A.ps += (double)(fmaf(0.5f * M, __logf(fmaf(f1, f1, f2 * f2)), -re));
     }
 }
 
