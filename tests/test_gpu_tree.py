@@ -86,6 +86,28 @@ def test_tree_and_walk_match_oracle_tree(ora, case):
     assert np.all(np.linalg.norm(got[:, 3:] - ref[:, 3:], axis=1) <= 1e-4 * gn + 1e-6 * np.median(gn))
 
 
+def test_massless_boxes_match_oracle_tree(ora):
+    """Every particle in one quadrant of the image massless, so that whole boxes
+    have M = 0 and take their geometric centre as expansion centre (the rule
+    both sides follow); topology, moments, counts and values as above."""
+    lens = mixed_lens(4000, 23)
+    lens.m[(lens.x < np.median(lens.x)) & (lens.y < np.median(lens.y))] = 0.0
+    say(f"[gpu] massless quadrant: n={lens.n}, {int((lens.m == 0).sum())} massless")
+    T, tree = compare_topology(ora, lens, 0.5, 4, 6)
+    assert (T.export()["M"] == 0).sum() > 10
+    rx, ry = synth.ray_grid(50)
+    ref, rcnt = T.shoot(rx, ry, counts=True)
+    got, gcnt = shoot(tree, rx, ry, counts=True)
+    np.testing.assert_array_equal(gcnt, rcnt[:, [0, 1, 2, 4]])
+    an = np.linalg.norm(ref[:, :2], axis=1)
+    assert np.all(np.linalg.norm(got[:, :2] - ref[:, :2], axis=1) <= 1e-4 * an + 1e-6 * an.max())
+    assert np.all(got[ref[:, 2] == 0, 2] == 0.0)
+    kn = np.abs(ref[:, 2])
+    assert np.all(np.abs(got[:, 2] - ref[:, 2]) <= 1e-4 * kn + 1e-6 * kn.max())
+    gn = np.linalg.norm(ref[:, 3:], axis=1)
+    assert np.all(np.linalg.norm(got[:, 3:] - ref[:, 3:], axis=1) <= 1e-4 * gn + 1e-6 * gn.max())
+
+
 def test_theta_zero_walk_is_direct_sum(ora):
     lens = mixed_lens(4000, 23)
     say("[gpu] theta=0 walk vs oracle A")
