@@ -172,6 +172,17 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K* kin, const ui
     __shared__ uint32_t wcnt[kBlock / kWave][256];
     __shared__ uint32_t lw[kBlock / kWave];
     const int t = threadIdx.x, w = t / kWave;
+    // the thread's keys and values of the whole tile are loaded up front, so
+    // their latency overlaps the digit bases' loads and is paid once per tile
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    K keys[kItems];
+    uint32_t vals[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t i = base + (int64_t)j * kBlock + t;
+        keys[j] = i < n ? kin[i] : (K)0;
+        vals[j] = i < n ? vin[i] : 0u;
+    }
     {
         const int64_t hi = (int64_t)t * nb + blockIdx.x;
         uint32_t tot;
@@ -185,13 +196,13 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K* kin, const ui
 #pragma unroll
     for (int k = 0; k < kBlock / kWave; ++k) wcnt[k][t] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile;
     const uint64_t lt = __lanemask_lt();
+#pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t i = base + (int64_t)j * kBlock + t;
         const bool valid = i < n;
-        const K key = valid ? kin[i] : (K)0;
-        const uint32_t val = valid ? vin[i] : 0u;
+        const K key = keys[j];
+        const uint32_t val = vals[j];
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
         uint64_t same = __ballot(valid);
 #pragma unroll
