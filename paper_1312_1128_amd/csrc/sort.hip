@@ -120,11 +120,16 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const K* keys, int64_t n,
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
+    // all of the thread's keys in flight together, then the counts
+    K k[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+        k[j] = i < n ? keys[i] : (K)0;
     }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j)
+        if (base + (int64_t)j * kBlock + threadIdx.x < n) atomicAdd(&h[(uint32_t)(k[j] >> shift) & 255u], 1u);
     __syncthreads();
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
