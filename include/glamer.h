@@ -80,9 +80,9 @@ typedef struct {
     uint32_t flags;    /* GLM_* flags */
 } glm_params;
 
-/* Opaque tree handle: host struct plus library-owned device storage for the
- * sorted particles, boxes, moments and lists.  Rebuilding reuses the storage
- * when it is large enough. */
+/* Opaque tree handle: a host struct that points into the caller's tree
+ * workspace (see glm_build_tree), which holds every device array of the
+ * built tree.  The library never allocates or frees device memory for it. */
 typedef struct glm_tree glm_tree;
 
 typedef struct {
@@ -95,14 +95,30 @@ typedef struct {
     int32_t check_flags; /* 0 when the build's internal consistency checks passed */
     int32_t reserved;
     double root_x0, root_y0, root_side; /* root square */
-    size_t device_bytes; /* device memory held by the handle */
+    size_t device_bytes; /* bytes of the caller's tree workspace the built tree occupies */
 } glm_tree_info;
 
 /* Create an empty handle.  *out receives it.  Host allocation only. */
 GLM_API glm_status glm_tree_create(glm_tree** out);
 
-/* Release the handle and its device storage.  Synchronises the device. NULL is ignored. */
+/* Release the host handle.  The tree workspace stays the caller's; nothing
+ * is synchronised or freed on the device.  NULL is ignored. */
 GLM_API void glm_tree_destroy(glm_tree* t);
+
+/*
+ * Upper bound of the device workspace glm_build_tree needs for n particles
+ * with these parameters (host arithmetic only, no device call).  The bound
+ * counts the particle arrays (Morton sort, sorted copies, walk records, list
+ * entries: about 150 bytes per particle) and the box arrays for the largest
+ * box count such a tree can have: every leaf holds at least one particle and
+ * every internal box more than leaf_size, so a level holds at most
+ * min(4^l, n / (leaf_size + 1)) internal boxes, and a tree of I internal
+ * boxes at most 4 I + 1 boxes (Sec. 3.2: boxes split into four until they
+ * hold at most the leaf size).  Real trees need far less (the 1e6-particle
+ * NFW halo at leaf size 16 holds 181k boxes of the 2.4M the bound allows):
+ * glm_tree_required_bytes gives the exact figure after a build.
+ */
+GLM_API glm_status glm_tree_workspace_bytes(int64_t n, const glm_params* params, size_t* bytes);
 
 /*
  * Build the tree of n particles (Sec. 3.2): the root square covers the
@@ -119,12 +135,28 @@ GLM_API void glm_tree_destroy(glm_tree* t);
  *             all point masses
  *   n       : 1 .. 2^31 - 1
  *
+ *   workspace, workspace_bytes: caller-owned device memory that receives
+ *             every array of the tree; it must stay allocated and unmodified
+ *             while the handle is used (walks, adjoints, exports) and may be
+ *             reused by the next build on this or another handle.
+ *             glm_tree_workspace_bytes(n, params) always suffices.  A smaller
+ *             one is accepted: the build fails with GLM_ENOMEM if it cannot
+ *             hold the particle arrays (before anything is launched) or,
+ *             after the box count is known, the box arrays; then
+ *             glm_tree_required_bytes gives the exact size this input needs.
+ *
  * Synchronises `stream` once (to size the box arrays); the inputs may be
  * reused or freed after return.  GLM_EDATA if any value is NaN/Inf or a mass
  * or smoothing length is negative.
  */
 GLM_API glm_status glm_build_tree(glm_tree* t, const double* x, const double* y, const double* m,
-                          const double* s, int64_t n, const glm_params* params, void* stream);
+                          const double* s, int64_t n, const glm_params* params, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* Exact workspace bytes the last glm_build_tree on this handle needed (also
+ * when it failed with GLM_ENOMEM for lack of space).  GLM_ESTATE before any
+ * build got that far. */
+GLM_API glm_status glm_tree_required_bytes(const glm_tree* t, size_t* bytes);
 
 /* Host copy of the tree summary. */
 GLM_API glm_status glm_tree_get_info(const glm_tree* t, glm_tree_info* out);
@@ -254,9 +286,13 @@ GLM_API glm_status glm_shoot_direct_nfw(const double* x, const double* y, const 
  * a box is the derivative of its alpha1 - i alpha2 series).  Uses FP64
  * atomics: results are reproducible to rounding, not bitwise.  For a tree of
  * GLM_NFW_HALOS, ds receives dL/dR (the halo size, concentration fixed).
- *   workspace: at least glm_shoot_workspace_bytes(nrays); the scratch for
- *   box adjoints and per-particle sums is device memory the handle owns.
+ *   workspace: at least glm_adjoint_workspace_bytes(t, nrays) bytes: the ray
+ *   staging of glm_shoot, then FP64 scratch for the box adjoints (2 (order +
+ *   1) + 2 words per box) and the per-particle direct-term sums (4 words per
+ *   particle).  The tree itself is only read, so adjoints on one tree may run
+ *   concurrently on separate streams with separate workspaces.
  */
+GLM_API glm_status glm_adjoint_workspace_bytes(const glm_tree* t, int64_t nrays, size_t* bytes);
 GLM_API glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* ry,
                              int64_t nrays, const float* ga1, const float* ga2, const float* gk,
                              const float* gg1, const float* gg2, double* dm, double* dx, double* dy,

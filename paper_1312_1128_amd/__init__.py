@@ -19,8 +19,9 @@ from ._capi import (GLM_ALPHA_ONLY, GLM_NFW_HALOS, GLM_FP32_ALPHA, GLM_RAYS_ORDE
 
 __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
            "GLM_NFW_HALOS", "GLM_FP32_ALPHA", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
-           "refine_schedule", "RefinementRun", "autotune", "smoothing_lengths", "interp_init",
-           "refine_interp_round", "shoot_indexed", "shoot_potential", "knn", "knn_workspace_bytes"]
+           "refine_schedule", "RefinementRun", "autotune", "autotune_batch", "smoothing_lengths", "interp_init",
+           "refine_interp_round", "shoot_indexed", "shoot_potential", "knn", "knn_workspace_bytes",
+           "tree_workspace_bytes", "adjoint_workspace_bytes"]
 
 
 def _ptr(t):
@@ -46,6 +47,19 @@ def workspace_bytes(nrays: int) -> int:
     return int(b.value)
 
 
+def tree_workspace_bytes(n: int, params) -> int:
+    """Upper bound of the tree workspace for n particles (params: GlmParams)."""
+    b = ctypes.c_size_t(0)
+    _capi.check(_capi.load().glm_tree_workspace_bytes(int(n), ctypes.byref(params), ctypes.byref(b)))
+    return int(b.value)
+
+
+def adjoint_workspace_bytes(tree, nrays: int) -> int:
+    b = ctypes.c_size_t(0)
+    _capi.check(_capi.load().glm_adjoint_workspace_bytes(tree.handle, int(nrays), ctypes.byref(b)))
+    return int(b.value)
+
+
 class Tree:
     """Handle of a tree built on the GPU (glm_tree)."""
 
@@ -56,6 +70,7 @@ class Tree:
         self._h = h
         self.params = None
         self.n = 0
+        self.workspace = None  # uint8 CUDA tensor holding the tree's device arrays
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -67,8 +82,11 @@ class Tree:
     def handle(self):
         return self._h
 
-    def build(self, x, y, m, s=None, theta=0.3, q=3.0, leaf_size=8, order=8, flags=0, nfw: bool = False):
-        """nfw: the particles are truncated NFW halos of sizes s and concentration q."""
+    def build(self, x, y, m, s=None, theta=0.3, q=3.0, leaf_size=8, order=8, flags=0, nfw: bool = False,
+              workspace=None):
+        """nfw: the particles are truncated NFW halos of sizes s and concentration q.
+        workspace: uint8 CUDA tensor for the tree's device arrays; by default the
+        handle keeps one of glm_tree_workspace_bytes (reused while large enough)."""
         if nfw:
             flags |= GLM_NFW_HALOS
         x, y, m = _f64(x, "x"), _f64(y, "y"), _f64(m, "m")
@@ -77,11 +95,24 @@ class Tree:
         if y.shape[0] != n or m.shape[0] != n or (s is not None and s.shape[0] != n):
             raise ValueError("x, y, m, s must have the same length")
         p = GlmParams(float(theta), float(q), int(leaf_size), int(order), int(flags))
+        if workspace is None:
+            need = tree_workspace_bytes(n, p)
+            workspace = self.workspace
+            if workspace is None or workspace.numel() < need or workspace.device != x.device:
+                self.workspace = None
+                workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+        self.workspace = workspace
         _capi.check(self._lib.glm_build_tree(self._h, _ptr(x), _ptr(y), _ptr(m), _ptr(s), n,
-                                             ctypes.byref(p), _stream()))
+                                             ctypes.byref(p), _ptr(workspace), workspace.numel(), _stream()))
         self.params = p
         self.n = n
         return self
+
+    def required_bytes(self) -> int:
+        """Exact workspace bytes the last build needed."""
+        b = ctypes.c_size_t(0)
+        _capi.check(self._lib.glm_tree_required_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
 
     def info(self) -> dict:
         inf = GlmTreeInfo()
@@ -232,7 +263,7 @@ def shoot_adjoint(tree: Tree, rx, ry, ga1, ga2, dm=None, dx=None, dy=None, ds=No
     dy = torch.zeros(n, dtype=torch.float64, device=dev) if dy is None else dy
     ds = torch.zeros(n, dtype=torch.float64, device=dev) if ds is None else ds
     if workspace is None:
-        workspace = torch.empty(max(workspace_bytes(R), 1), dtype=torch.uint8, device=dev)
+        workspace = torch.empty(max(adjoint_workspace_bytes(tree, R), 1), dtype=torch.uint8, device=dev)
     ws_bytes = workspace.numel()
     flags = GLM_RAYS_ORDERED if ordered else 0
     lib = _capi.load()
@@ -267,5 +298,5 @@ class ShootFn(torch.autograd.Function):
         return None, None, dm, dx, dy, (ds if ctx.has_s else None), None, None
 
 
-from .batch import (RefinementRun, autotune, interp_estimate, interp_init, refine_interp_round, refine_round,  # noqa: E402
+from .batch import (RefinementRun, autotune, autotune_batch, interp_estimate, interp_init, refine_interp_round, refine_round,  # noqa: E402
                     refine_schedule, shoot_batched, shoot_indexed)

@@ -28,7 +28,8 @@ EXPORTED = [
     "glm_refine_workspace_bytes", "glm_refine_round", "glm_tree_knn", "glm_interp_state_bytes",
     "glm_interp_round_workspace_bytes", "glm_interp_init", "glm_refine_interp_round",
     "glm_shoot_indexed_workspace_bytes", "glm_shoot_indexed", "glm_shoot_potential", "glm_shoot_direct_nfw",
-    "glm_knn_workspace_bytes", "glm_knn", "glm_interp_estimate",
+    "glm_knn_workspace_bytes", "glm_knn", "glm_interp_estimate", "glm_tree_workspace_bytes",
+    "glm_tree_required_bytes", "glm_adjoint_workspace_bytes",
 ]
 
 
@@ -77,8 +78,14 @@ def load(path: str = LIB_PATH):
     lib.glm_tree_create.restype = st
     lib.glm_tree_destroy.argtypes = [vp]
     lib.glm_tree_destroy.restype = None
-    lib.glm_build_tree.argtypes = [vp, vp, vp, vp, vp, i64, P(GlmParams), vp]
+    lib.glm_build_tree.argtypes = [vp, vp, vp, vp, vp, i64, P(GlmParams), vp, ctypes.c_size_t, vp]
     lib.glm_build_tree.restype = st
+    lib.glm_tree_workspace_bytes.argtypes = [i64, P(GlmParams), P(ctypes.c_size_t)]
+    lib.glm_tree_workspace_bytes.restype = st
+    lib.glm_tree_required_bytes.argtypes = [vp, P(ctypes.c_size_t)]
+    lib.glm_tree_required_bytes.restype = st
+    lib.glm_adjoint_workspace_bytes.argtypes = [vp, i64, P(ctypes.c_size_t)]
+    lib.glm_adjoint_workspace_bytes.restype = st
     lib.glm_tree_get_info.argtypes = [vp, P(GlmTreeInfo)]
     lib.glm_tree_get_info.restype = st
     lib.glm_tree_export.argtypes = [vp] + [vp] * 17

@@ -250,35 +250,70 @@ class RefinementRun:
         return g
 
 
-def autotune(x, y, m, s, rx, ry, q: float = 3.0, tol: float = 1e-4, thetas=(0.2, 0.3, 0.4, 0.5),
-             orders=(4, 6, 8, 10), leaves=(4, 8, 16), sample: int = 512, reps: int = 3, seed: int = 0):
-    """Pick (theta, order, leaf size) for one lens: the fastest build + walk
-    whose max fractional error of alpha, kappa and gamma on a seeded ray sample
-    stays below `tol` against the library's FP64 direct sum on the GPU.  The
-    walk group is one wavefront (64 rays) by construction.  Returns (best, table)."""
-    from . import Tree, shoot, shoot_direct, workspace_bytes
-
+def validation_rays(x, y, s, rx, ry, sample: int = 16384, dense: int = 4096, seed: int = 0):
+    """Indices of the rays an autotuned configuration must pass on: `sample`
+    seeded random rays plus the `dense` rays nearest the densest point (the
+    particle with the smallest smoothing length, or the centre of mass of
+    equal point masses), where the walk opens the most boxes and the shear is
+    the smallest difference of large terms.  All rays if there are fewer."""
     R = rx.numel()
+    if sample + dense >= R:
+        return torch.arange(R, device=rx.device)
     gen = torch.Generator(device="cpu").manual_seed(seed)
-    idx = torch.randperm(R, generator=gen)[: min(sample, R)].to(rx.device)
-    sx, sy = rx[idx].contiguous(), ry[idx].contiguous()
-    ref = shoot_direct(x, y, m, s, q, sx, sy, fp64=True)
+    pick = torch.randperm(R, generator=gen)[:sample].to(rx.device)
+    if s is not None and bool((s > 0).any()):
+        sp = torch.where(s > 0, s, torch.full_like(s, float("inf")))
+        j = int(torch.argmin(sp))
+        cx, cy = x[j], y[j]
+    else:
+        cx, cy = x.mean(), y.mean()
+    near = torch.argsort((rx - cx) ** 2 + (ry - cy) ** 2)[:dense]
+    return torch.unique(torch.cat([pick, near]))
+
+
+def _errors(o, ref):
     ra = torch.stack([ref["a1"], ref["a2"]], 1)
     rg = torch.stack([ref["g1"], ref["g2"]], 1)
     rk = ref["kappa"]
+    ea = ((torch.stack([o["a1"], o["a2"]], 1).double() - ra).norm(dim=1) / ra.norm(dim=1)).max().item()
+    eg = ((torch.stack([o["g1"], o["g2"]], 1).double() - rg).norm(dim=1) / rg.norm(dim=1)).max().item()
+    nz = rk != 0
+    ek = ((o["kappa"].double() - rk).abs()[nz] / rk.abs()[nz]).max().item() if bool(nz.any()) else 0.0
+    # kappa must vanish exactly where no particle holds the ray
+    if bool((~nz).any()) and bool((o["kappa"][~nz] != 0).any()):
+        ek = float("inf")
+    return ea, ek, eg
+
+
+def autotune(x, y, m, s, rx, ry, q: float = 3.0, tol: float = 1e-4, thetas=(0.2, 0.3, 0.4, 0.5),
+             orders=(4, 6, 8, 10, 12), leaves=(8, 16, 24), sample: int = 16384, dense: int = 4096, reps: int = 3,
+             seed: int = 0, nfw: bool = False):
+    """Pick (theta, order, leaf size) for one lens: the fastest build + walk of
+    all rays rx, ry whose max fractional errors of alpha, kappa and gamma stay
+    within `tol` against the library's FP64 direct sum on the validation rays
+    (validation_rays: `sample` random rays plus the `dense` nearest the densest
+    point; every ray when sample + dense covers them).  For each (leaf size,
+    theta) only the smallest passing order is timed (a larger order costs more
+    and is no more needed).  The walk group is one wavefront (64 rays) by
+    construction.  Returns (best, table); best is None when nothing passes,
+    table has a row per evaluated (theta, order, leaf size) with its errors,
+    whether it passed, and its time (NaN unless timed)."""
+    from . import Tree, shoot, shoot_direct, workspace_bytes
+
+    R = rx.numel()
+    idx = validation_rays(x, y, s, rx, ry, sample, dense, seed)
+    sx, sy = rx[idx].contiguous(), ry[idx].contiguous()
+    ref = shoot_direct(x, y, m, s, q, sx, sy, fp64=True, nfw=nfw)
     ws = torch.empty(workspace_bytes(R), dtype=torch.uint8, device=rx.device)
     out = {k: torch.empty(R, dtype=torch.float32, device=rx.device) for k in ["a1", "a2", "kappa", "g1", "g2"]}
     table = []
     best = None
+    tree = Tree()
     for L in leaves:
         for th in thetas:
-            for p in orders:
-                tree = Tree().build(x, y, m, s, theta=th, q=q, leaf_size=L, order=p)
-                o = shoot(tree, sx, sy)
-                ea = ((torch.stack([o["a1"], o["a2"]], 1).double() - ra).norm(dim=1) / ra.norm(dim=1)).max().item()
-                eg = ((torch.stack([o["g1"], o["g2"]], 1).double() - rg).norm(dim=1) / rg.norm(dim=1)).max().item()
-                nz = rk != 0
-                ek = ((o["kappa"].double() - rk).abs()[nz] / rk.abs()[nz]).max().item() if bool(nz.any()) else 0.0
+            for p in sorted(orders):
+                tree.build(x, y, m, s, theta=th, q=q, leaf_size=L, order=p, nfw=nfw)
+                ea, ek, eg = _errors(shoot(tree, sx, sy), ref)
                 ok = max(ea, eg, ek) <= tol
                 ms = float("nan")
                 if ok:
@@ -286,12 +321,39 @@ def autotune(x, y, m, s, rx, ry, q: float = 3.0, tol: float = 1e-4, thetas=(0.2,
                     ts = []
                     for _ in range(reps):
                         t0 = time.perf_counter()
-                        tree.build(x, y, m, s, theta=th, q=q, leaf_size=L, order=p)
+                        tree.build(x, y, m, s, theta=th, q=q, leaf_size=L, order=p, nfw=nfw)
                         shoot(tree, rx, ry, out=out, workspace=ws)
                         torch.cuda.synchronize()
                         ts.append(time.perf_counter() - t0)
                     ms = 1e3 * sorted(ts)[len(ts) // 2]
                     if best is None or ms < best["ms"]:
-                        best = dict(theta=th, order=p, leaf_size=L, ms=ms, err=max(ea, eg, ek))
-                table.append(dict(theta=th, order=p, leaf_size=L, err_alpha=ea, err_kappa=ek, err_gamma=eg, ok=ok, ms=ms))
+                        best = dict(theta=th, order=p, leaf_size=L, ms=ms, err=max(ea, eg, ek),
+                                    err_alpha=ea, err_kappa=ek, err_gamma=eg, rays_checked=int(idx.numel()))
+                table.append(dict(theta=th, order=p, leaf_size=L, err_alpha=ea, err_kappa=ek, err_gamma=eg, ok=ok,
+                                  ms=ms))
+                if ok:
+                    break  # larger orders at this (leaf size, theta) only cost more
     return best, table
+
+
+def autotune_batch(lenses, q: float = 3.0, tol: float = 1e-4, thetas=(0.2, 0.3, 0.4), orders=(6, 8, 10, 12),
+                   leaves=(8, 16, 24), sample: int = 16384, dense: int = 4096, reps: int = 3, seed: int = 0):
+    """Tune a batch of lenses for one persistent launch: every tree of a batch
+    has the same order, while theta and the leaf size may differ per lens.
+    lenses: list of (x, y, m, s, rx, ry) CUDA float64 tensors.  Each lens is
+    tuned by `autotune` over the orders; the common order is the one with the
+    smallest summed time of the lenses' fastest passing (theta, leaf size) at
+    that order.  Returns (order, [per-lens dict(theta, leaf_size, ms, err...)])
+    or (None, []) when no order passes on every lens."""
+    per_order = {p: [] for p in orders}
+    for li, (x, y, m, s, rx, ry) in enumerate(lenses):
+        _, table = autotune(x, y, m, s, rx, ry, q=q, tol=tol, thetas=thetas, orders=orders, leaves=leaves,
+                            sample=sample, dense=dense, reps=reps, seed=seed + li)
+        for p in orders:
+            rows = [t for t in table if t["ok"] and t["order"] == p]
+            per_order[p].append(min(rows, key=lambda t: t["ms"]) if rows else None)
+    feasible = {p: sum(r["ms"] for r in rows) for p, rows in per_order.items() if all(r is not None for r in rows)}
+    if not feasible:
+        return None, []
+    p = min(feasible, key=feasible.get)
+    return p, per_order[p]

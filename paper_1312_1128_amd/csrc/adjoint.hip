@@ -569,16 +569,20 @@ __global__ void k_fill_zero(double* p, int64_t n)
     if (i < n) p[i] = 0.0;
 }
 
+// FP64 scratch words: box adjoints (NA per box), then 4 direct-term gradients per particle.
+size_t adjoint_scratch_words(const TreeStorage& ts)
+{
+    const int NA = 2 * (ts.params.order + 1) + 2;
+    return (size_t)ts.ncells * NA + 4 * (size_t)ts.n;
+}
+
 template <int P>
-glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, const CotIn& ci, double* dm,
-                          double* dx, double* dy, double* ds, int K, const int* split_box, hipStream_t st)
+glm_status launch_adjoint(const TreeStorage& ts, const StagedRays& sr, int64_t nrays, const CotIn& ci, double* dm,
+                          double* dx, double* dy, double* ds, int K, const int* split_box, double* abar,
+                          hipStream_t st)
 {
     constexpr int NA = 2 * (P + 1) + 2;
-    // scratch: box adjoints (NA per box), then 4 direct-term gradients per particle
-    const size_t words = (size_t)ts.ncells * NA + 4 * (size_t)ts.n;
-    glm_status rc = ts.abuf.ensure(words * sizeof(double));
-    if (rc != GLM_OK) return rc;
-    double* abar = ts.abuf.as<double>();
+    const size_t words = adjoint_scratch_words(ts);
     double* pg = abar + (size_t)ts.ncells * NA;
     hipLaunchKernelGGL(k_fill_zero, dim3(ceil_div((int64_t)words, kBlock)), dim3(kBlock), 0, st, abar, (int64_t)words);
     const int64_t blocks = walk_grid_blocks((nrays + kWave - 1) / kWave, K);
@@ -602,7 +606,12 @@ glm_status launch_adjoint(TreeStorage& ts, const StagedRays& sr, int64_t nrays, 
 
 } // namespace
 
-glm_status adjoint_device(TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, const float* ga1,
+size_t adjoint_workspace_bytes(const TreeStorage& ts, int64_t nrays)
+{
+    return ray_layout(nrays).bytes + sizeof(double) * adjoint_scratch_words(ts);
+}
+
+glm_status adjoint_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, const float* ga1,
                           const float* ga2, const float* gk, const float* gg1, const float* gg2, double* dm,
                           double* dx, double* dy, double* ds, uint32_t flags, void* ws, hipStream_t st)
 {
@@ -621,8 +630,11 @@ glm_status adjoint_device(TreeStorage& ts, const double* rx, const double* ry, i
         glm_status rc = split_box_device(ts, rx, ry, nrays, ws, L, !(flags & GLM_RAYS_ORDERED), &split_box, st);
         if (rc != GLM_OK) return rc;
     }
-#define GLM_CASE(PP) \
-    case PP: return launch_adjoint<PP>(ts, sr, nrays, CotIn{ga1, ga2, gk, gg1, gg2}, dm, dx, dy, ds, K, split_box, st);
+    double* abar = reinterpret_cast<double*>(static_cast<char*>(ws) + L.bytes);
+#define GLM_CASE(PP)                                                                                              \
+    case PP:                                                                                                      \
+        return launch_adjoint<PP>(ts, sr, nrays, CotIn{ga1, ga2, gk, gg1, gg2}, dm, dx, dy, ds, K, split_box, abar, \
+                                  st);
     switch (ts.params.order) {
         GLM_CASE(0) GLM_CASE(1) GLM_CASE(2) GLM_CASE(3) GLM_CASE(4) GLM_CASE(5) GLM_CASE(6)
         GLM_CASE(7) GLM_CASE(8) GLM_CASE(9) GLM_CASE(10) GLM_CASE(11) GLM_CASE(12)

@@ -23,28 +23,6 @@ glm_status fail(glm_status st, const std::string& msg)
     return st;
 }
 
-glm_status DevBuf::ensure(size_t want)
-{
-    if (want <= bytes && p) return GLM_OK;
-    release();
-    hipError_t e = hipMalloc(&p, want > 0 ? want : 256);
-    if (e != hipSuccess) {
-        p = nullptr;
-        bytes = 0;
-        return fail(GLM_ENOMEM, std::string("device allocation of ") + std::to_string(want) +
-                                    " bytes failed: " + hipGetErrorString(e));
-    }
-    bytes = want;
-    return GLM_OK;
-}
-
-void DevBuf::release()
-{
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-}
-
 static glm_status check_params(const glm_params* p)
 {
     if (!p) return fail(GLM_EINVAL, "params is NULL");
@@ -79,26 +57,39 @@ glm_status glm_tree_create(glm_tree** out)
     return GLM_OK;
 }
 
-void glm_tree_destroy(glm_tree* t)
+void glm_tree_destroy(glm_tree* t) { delete t; }
+
+glm_status glm_tree_workspace_bytes(int64_t n, const glm_params* params, size_t* bytes)
 {
-    if (!t) return;
-    (void)hipDeviceSynchronize();
-    t->ts.pbuf.release();
-    t->ts.cbuf.release();
-    t->ts.abuf.release();
-    delete t;
+    if (!bytes) return fail(GLM_EINVAL, "bytes is NULL");
+    glm_status rc = check_params(params);
+    if (rc != GLM_OK) return rc;
+    if (n < 1 || n > 0x7ffffff0) return fail(GLM_EINVAL, "n must be in 1 .. 2^31 - 16");
+    *bytes = tree_particle_bytes(n) + tree_box_bytes(max_boxes(n, params->leaf_size), params->order);
+    return GLM_OK;
 }
 
 glm_status glm_build_tree(glm_tree* t, const double* x, const double* y, const double* m, const double* s, int64_t n,
-                          const glm_params* params, void* stream)
+                          const glm_params* params, void* workspace, size_t workspace_bytes, void* stream)
 {
     if (!t) return fail(GLM_EINVAL, "tree handle is NULL");
     glm_status rc = check_params(params);
     if (rc != GLM_OK) return rc;
     if (!x || !y || !m) return fail(GLM_EINVAL, "x, y and m must be device pointers");
     if (n < 1 || n > 0x7ffffff0) return fail(GLM_EINVAL, "n must be in 1 .. 2^31 - 16");
+    if (!workspace) return fail(GLM_EINVAL, "workspace must be a device pointer");
     t->ts.built = false;
+    t->ts.ws = static_cast<char*>(workspace);
+    t->ts.ws_bytes = workspace_bytes;
     return build_tree_device(t->ts, x, y, m, s, n, *params, static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_tree_required_bytes(const glm_tree* t, size_t* bytes)
+{
+    if (!t || !bytes) return fail(GLM_EINVAL, "NULL argument");
+    if (t->ts.need == 0) return fail(GLM_ESTATE, "no build has been attempted on this handle");
+    *bytes = t->ts.need;
+    return GLM_OK;
 }
 
 glm_status glm_tree_get_info(const glm_tree* t, glm_tree_info* out)
@@ -119,7 +110,7 @@ glm_status glm_tree_get_info(const glm_tree* t, glm_tree_info* out)
     out->root_x0 = t->ts.x0;
     out->root_y0 = t->ts.y0;
     out->root_side = t->ts.side;
-    out->device_bytes = t->ts.pbuf.bytes + t->ts.cbuf.bytes + t->ts.abuf.bytes;
+    out->device_bytes = t->ts.need;
     return GLM_OK;
 }
 
@@ -266,6 +257,15 @@ glm_status glm_shoot_direct_nfw(const double* x, const double* y, const double* 
     return direct_device(x, y, m, R, n, c, kKindNfw, rx, ry, nrays, fp64, out5, static_cast<hipStream_t>(stream));
 }
 
+glm_status glm_adjoint_workspace_bytes(const glm_tree* t, int64_t nrays, size_t* bytes)
+{
+    if (!t || !bytes) return fail(GLM_EINVAL, "NULL argument");
+    if (!t->ts.built) return fail(GLM_ESTATE, "tree not built");
+    if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays out of range");
+    *bytes = adjoint_workspace_bytes(t->ts, nrays);
+    return GLM_OK;
+}
+
 glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* ry, int64_t nrays, const float* ga1,
                              const float* ga2, const float* gk, const float* gg1, const float* gg2, double* dm,
                              double* dx, double* dy, double* ds, uint32_t flags, void* workspace,
@@ -279,12 +279,13 @@ glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* 
     if (!ga1 && !ga2 && !gk && !gg1 && !gg2) return fail(GLM_EINVAL, "every cotangent is NULL");
     if (flags & ~(GLM_FP32_ALPHA | GLM_RAYS_ORDERED | GLM_ALPHA_ONLY)) return fail(GLM_EINVAL, "unknown flag bits");
     {
-        const size_t need = ray_layout(nrays).bytes;
+        const size_t need = adjoint_workspace_bytes(t->ts, nrays);
         if (!workspace || workspace_bytes < need)
-            return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_workspace_bytes(nrays) = " + std::to_string(need));
+            return fail(GLM_ENOMEM, "workspace smaller than glm_adjoint_workspace_bytes(tree, nrays) = " +
+                                        std::to_string(need));
     }
-    return adjoint_device(const_cast<glm_tree*>(t)->ts, rx, ry, nrays, ga1, ga2, gk, gg1, gg2, dm, dx, dy, ds, flags,
-                          workspace, static_cast<hipStream_t>(stream));
+    return adjoint_device(t->ts, rx, ry, nrays, ga1, ga2, gk, gg1, gg2, dm, dx, dy, ds, flags, workspace,
+                          static_cast<hipStream_t>(stream));
 }
 
 glm_status glm_shoot_batched_workspace_bytes(const int64_t* nrays, int nlens, size_t* bytes)

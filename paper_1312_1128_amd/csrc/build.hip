@@ -780,6 +780,86 @@ static int32_t ein_terms(double U)
     return 100;
 }
 
+// Offsets of the per-particle part of a tree's workspace.
+struct ParticleLayout {
+    size_t sync, part, k0, k1, v0, v1, perm, hist, xs, ys, ms, ss, cnt, scr, ls, leafof, prt, lst, size;
+};
+
+constexpr int kBboxBlocks = 256;
+
+static ParticleLayout particle_layout(int64_t n)
+{
+    ParticleLayout o;
+    Arena pa;
+    o.sync = pa.take(sizeof(BuildSync));
+    o.part = pa.take(sizeof(double) * 5 * kBboxBlocks);
+    o.k0 = pa.take(8ull * n);
+    o.k1 = pa.take(8ull * n);
+    o.v0 = pa.take(4ull * n);
+    o.v1 = pa.take(4ull * n);
+    o.perm = pa.take(4ull * n);
+    o.hist = pa.take(4ull * radix_hist_words(n));
+    o.xs = pa.take(8ull * n);
+    o.ys = pa.take(8ull * n);
+    o.ms = pa.take(8ull * n);
+    o.ss = pa.take(8ull * n);
+    o.cnt = pa.take(4ull * (n + 1));
+    o.scr = pa.take(4ull * scan_scratch_words(n + 1));
+    o.ls = pa.take((size_t)n);
+    o.leafof = pa.take(4ull * n);
+    o.prt = pa.take(sizeof(PRec) * (size_t)n);
+    o.lst = pa.take(sizeof(PRec) * (size_t)n);
+    o.size = pa.size;
+    return o;
+}
+
+// Offsets of the per-box part (after the per-particle part).
+struct BoxLayout {
+    size_t beg, end, lev, next, leaf, ix, iy, lbeg, lend, M, cx, cy, Q, hdr, ext, mom, levidx, kids, lreach, size;
+};
+
+static BoxLayout box_layout(int64_t nc, int p)
+{
+    BoxLayout o;
+    Arena ca;
+    o.beg = ca.take(4ull * nc);
+    o.end = ca.take(4ull * nc);
+    o.lev = ca.take(4ull * nc);
+    o.next = ca.take(4ull * nc);
+    o.leaf = ca.take(4ull * nc);
+    o.ix = ca.take(4ull * nc);
+    o.iy = ca.take(4ull * nc);
+    o.lbeg = ca.take(4ull * nc);
+    o.lend = ca.take(4ull * nc);
+    o.M = ca.take(8ull * nc);
+    o.cx = ca.take(8ull * nc);
+    o.cy = ca.take(8ull * nc);
+    o.Q = ca.take(16ull * (p + 1) * nc);
+    o.hdr = ca.take(sizeof(CellHdr) * (size_t)nc);
+    o.ext = ca.take(sizeof(CellExt) * (size_t)nc);
+    o.mom = ca.take(4ull * mom_stride(p) * nc);
+    o.levidx = ca.take(4ull * nc);
+    o.kids = ca.take(16ull * nc);
+    o.lreach = ca.take(32ull * nc);
+    o.size = ca.size;
+    return o;
+}
+
+int64_t max_boxes(int64_t n, int L)
+{
+    const int64_t per_level = n / (L + 1);
+    int64_t internal = 0, pow4 = 1;
+    for (int l = 0; l < kMaxLevel; ++l) {
+        internal += pow4 < per_level ? pow4 : per_level;
+        if (pow4 < per_level) pow4 *= 4;
+    }
+    const int64_t a = n + internal, b = 4 * internal + 1;
+    return a < b ? a : b;
+}
+
+size_t tree_particle_bytes(int64_t n) { return particle_layout(n).size; }
+size_t tree_box_bytes(int64_t ncells, int order) { return box_layout(ncells, order).size; }
+
 glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, const double* m, const double* s,
                              int64_t n64, const glm_params& prm, hipStream_t st)
 {
@@ -793,44 +873,32 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     const double supp = kind == kKindNfw ? 1.0 : q;
     const double norm = kind == kKindNfw ? 1.0 / nfw_g_at(q) : invC;
 
-    // ---- per-particle arena
-    Arena pa;
-    const int nbb = 256;
-    const size_t o_sync = pa.take(sizeof(BuildSync));
-    const size_t o_part = pa.take(sizeof(double) * 5 * nbb);
-    const size_t o_k0 = pa.take(8ull * n), o_k1 = pa.take(8ull * n);
-    const size_t o_v0 = pa.take(4ull * n), o_v1 = pa.take(4ull * n);
-    const size_t o_perm = pa.take(4ull * n);
-    const size_t o_hist = pa.take(4ull * radix_hist_words(n));
-    const size_t o_xs = pa.take(8ull * n), o_ys = pa.take(8ull * n), o_ms = pa.take(8ull * n),
-                 o_ss = pa.take(8ull * n);
-    const size_t o_cnt = pa.take(4ull * (n + 1));
-    const size_t o_scr = pa.take(4ull * scan_scratch_words(n + 1));
-    const size_t o_ls = pa.take((size_t)n);
-    const size_t o_leafof = pa.take(4ull * n);
-    const size_t o_prt = pa.take(sizeof(PRec) * (size_t)n);
-    const size_t o_lst = pa.take(sizeof(PRec) * (size_t)n);
-    glm_status rc = ts.pbuf.ensure(pa.size);
-    if (rc != GLM_OK) return rc;
-    char* P0 = ts.pbuf.as<char>();
-    BuildSync* sync = reinterpret_cast<BuildSync*>(P0 + o_sync);
-    double* part = reinterpret_cast<double*>(P0 + o_part);
-    uint64_t* k0 = reinterpret_cast<uint64_t*>(P0 + o_k0);
-    uint64_t* k1 = reinterpret_cast<uint64_t*>(P0 + o_k1);
-    uint32_t* v0 = reinterpret_cast<uint32_t*>(P0 + o_v0);
-    uint32_t* v1 = reinterpret_cast<uint32_t*>(P0 + o_v1);
-    uint32_t* perm = reinterpret_cast<uint32_t*>(P0 + o_perm);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(P0 + o_hist);
-    double* xs = reinterpret_cast<double*>(P0 + o_xs);
-    double* ys = reinterpret_cast<double*>(P0 + o_ys);
-    double* ms = reinterpret_cast<double*>(P0 + o_ms);
-    double* ss = reinterpret_cast<double*>(P0 + o_ss);
-    int32_t* cnt = reinterpret_cast<int32_t*>(P0 + o_cnt);
-    int32_t* scr = reinterpret_cast<int32_t*>(P0 + o_scr);
-    int8_t* lstart = reinterpret_cast<int8_t*>(P0 + o_ls);
-    int32_t* leaf_of = reinterpret_cast<int32_t*>(P0 + o_leafof);
-    PRec* prt = reinterpret_cast<PRec*>(P0 + o_prt);
-    PRec* lst = reinterpret_cast<PRec*>(P0 + o_lst);
+    // ---- per-particle part of the workspace
+    const ParticleLayout pl = particle_layout(n);
+    const int nbb = kBboxBlocks;
+    ts.need = pl.size;
+    if (pl.size > ts.ws_bytes)
+        return fail(GLM_ENOMEM, "build_tree: workspace of " + std::to_string(ts.ws_bytes) +
+                                    " bytes is smaller than the particle part (" + std::to_string(pl.size) + ")");
+    char* P0 = ts.ws;
+    BuildSync* sync = reinterpret_cast<BuildSync*>(P0 + pl.sync);
+    double* part = reinterpret_cast<double*>(P0 + pl.part);
+    uint64_t* k0 = reinterpret_cast<uint64_t*>(P0 + pl.k0);
+    uint64_t* k1 = reinterpret_cast<uint64_t*>(P0 + pl.k1);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(P0 + pl.v0);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(P0 + pl.v1);
+    uint32_t* perm = reinterpret_cast<uint32_t*>(P0 + pl.perm);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(P0 + pl.hist);
+    double* xs = reinterpret_cast<double*>(P0 + pl.xs);
+    double* ys = reinterpret_cast<double*>(P0 + pl.ys);
+    double* ms = reinterpret_cast<double*>(P0 + pl.ms);
+    double* ss = reinterpret_cast<double*>(P0 + pl.ss);
+    int32_t* cnt = reinterpret_cast<int32_t*>(P0 + pl.cnt);
+    int32_t* scr = reinterpret_cast<int32_t*>(P0 + pl.scr);
+    int8_t* lstart = reinterpret_cast<int8_t*>(P0 + pl.ls);
+    int32_t* leaf_of = reinterpret_cast<int32_t*>(P0 + pl.leafof);
+    PRec* prt = reinterpret_cast<PRec*>(P0 + pl.prt);
+    PRec* lst = reinterpret_cast<PRec*>(P0 + pl.lst);
 
     GLM_HIP(hipMemsetAsync(sync, 0, sizeof(BuildSync), st));
     const int gb = ceil_div(n, kBlock);
@@ -856,43 +924,33 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     if (hs.bad) return fail(GLM_EDATA, "build_tree: NaN/Inf value or negative mass/smoothing length");
     const int nc = hs.ncells;
 
-    // ---- per-box arena
-    Arena ca;
-    const int P = p + 1, stride = mom_stride(p);
-    const size_t o_beg = ca.take(4ull * nc), o_end = ca.take(4ull * nc), o_lev = ca.take(4ull * nc),
-                 o_next = ca.take(4ull * nc), o_leaf = ca.take(4ull * nc), o_ix = ca.take(4ull * nc),
-                 o_iy = ca.take(4ull * nc), o_lbeg = ca.take(4ull * nc), o_lend = ca.take(4ull * nc);
-    const size_t o_M = ca.take(8ull * nc), o_cx = ca.take(8ull * nc), o_cy = ca.take(8ull * nc);
-    const size_t o_Q = ca.take(16ull * P * nc);
-    const size_t o_hdr = ca.take(sizeof(CellHdr) * (size_t)nc);
-    const size_t o_ext = ca.take(sizeof(CellExt) * (size_t)nc);
-    const size_t o_mom = ca.take(4ull * stride * nc);
-    const size_t o_levidx = ca.take(4ull * nc);
-    const size_t o_kids = ca.take(16ull * nc);
-    const size_t o_lreach = ca.take(32ull * nc);
-    rc = ts.cbuf.ensure(ca.size);
-    if (rc != GLM_OK) return rc;
-    char* C0 = ts.cbuf.as<char>();
+    // ---- per-box part of the workspace, after the per-particle part
+    const BoxLayout bl = box_layout(nc, p);
+    ts.need = pl.size + bl.size;
+    if (ts.need > ts.ws_bytes)
+        return fail(GLM_ENOMEM, "build_tree: " + std::to_string(nc) + " boxes need a workspace of " +
+                                    std::to_string(ts.need) + " bytes, got " + std::to_string(ts.ws_bytes));
+    char* C0 = ts.ws + pl.size;
     BoxArrays b;
-    b.beg = reinterpret_cast<int32_t*>(C0 + o_beg);
-    b.end = reinterpret_cast<int32_t*>(C0 + o_end);
-    b.level = reinterpret_cast<int32_t*>(C0 + o_lev);
-    b.next = reinterpret_cast<int32_t*>(C0 + o_next);
-    b.leaf = reinterpret_cast<int32_t*>(C0 + o_leaf);
-    b.ix = reinterpret_cast<uint32_t*>(C0 + o_ix);
-    b.iy = reinterpret_cast<uint32_t*>(C0 + o_iy);
-    b.lbeg = reinterpret_cast<int32_t*>(C0 + o_lbeg);
-    b.lend = reinterpret_cast<int32_t*>(C0 + o_lend);
-    double* cM = reinterpret_cast<double*>(C0 + o_M);
-    double* ccx = reinterpret_cast<double*>(C0 + o_cx);
-    double* ccy = reinterpret_cast<double*>(C0 + o_cy);
-    double* cQ = reinterpret_cast<double*>(C0 + o_Q);
-    CellHdr* hdr = reinterpret_cast<CellHdr*>(C0 + o_hdr);
-    CellExt* ext = reinterpret_cast<CellExt*>(C0 + o_ext);
-    float* mom = reinterpret_cast<float*>(C0 + o_mom);
-    int32_t* levidx = reinterpret_cast<int32_t*>(C0 + o_levidx);
-    int32_t* kids = reinterpret_cast<int32_t*>(C0 + o_kids);
-    double* lreach = reinterpret_cast<double*>(C0 + o_lreach);
+    b.beg = reinterpret_cast<int32_t*>(C0 + bl.beg);
+    b.end = reinterpret_cast<int32_t*>(C0 + bl.end);
+    b.level = reinterpret_cast<int32_t*>(C0 + bl.lev);
+    b.next = reinterpret_cast<int32_t*>(C0 + bl.next);
+    b.leaf = reinterpret_cast<int32_t*>(C0 + bl.leaf);
+    b.ix = reinterpret_cast<uint32_t*>(C0 + bl.ix);
+    b.iy = reinterpret_cast<uint32_t*>(C0 + bl.iy);
+    b.lbeg = reinterpret_cast<int32_t*>(C0 + bl.lbeg);
+    b.lend = reinterpret_cast<int32_t*>(C0 + bl.lend);
+    double* cM = reinterpret_cast<double*>(C0 + bl.M);
+    double* ccx = reinterpret_cast<double*>(C0 + bl.cx);
+    double* ccy = reinterpret_cast<double*>(C0 + bl.cy);
+    double* cQ = reinterpret_cast<double*>(C0 + bl.Q);
+    CellHdr* hdr = reinterpret_cast<CellHdr*>(C0 + bl.hdr);
+    CellExt* ext = reinterpret_cast<CellExt*>(C0 + bl.ext);
+    float* mom = reinterpret_cast<float*>(C0 + bl.mom);
+    int32_t* levidx = reinterpret_cast<int32_t*>(C0 + bl.levidx);
+    int32_t* kids = reinterpret_cast<int32_t*>(C0 + bl.kids);
+    double* lreach = reinterpret_cast<double*>(C0 + bl.lreach);
     LevelTable lt;
     {
         int off = 0;

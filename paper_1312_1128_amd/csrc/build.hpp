@@ -42,10 +42,13 @@ struct Arena {
     }
 };
 
+// Every device array of a tree lives in the caller's workspace: the
+// per-particle part first (its size follows from n), then the per-box part
+// (its size from the box count, known after the topology pass).
 struct TreeStorage {
-    DevBuf pbuf;  // per-particle data (sorted particles, records, lists, scratch)
-    DevBuf cbuf;  // per-box data
-    DevBuf abuf;  // adjoint scratch (box adjoints)
+    char* ws = nullptr;      // caller's workspace (device), borrowed
+    size_t ws_bytes = 0;
+    size_t need = 0;         // bytes the last build needed (also after a refusal for space)
     bool built = false;
     int32_t n = 0, ncells = 0;
     glm_params params{};
@@ -59,6 +62,17 @@ struct TreeStorage {
     TreeDev dev{};
 };
 
+// Largest number of boxes a tree of n particles and leaf size L can have:
+// leaves are disjoint and non-empty (at most n); an internal box holds more
+// than L particles, so a level has at most min(4^l, n / (L + 1)) of them
+// (levels 0..31); and a tree with I internal boxes has at most 4 I + 1.
+int64_t max_boxes(int64_t n, int L);
+// Bytes of the per-particle part and of the per-box part of a tree.
+size_t tree_particle_bytes(int64_t n);
+size_t tree_box_bytes(int64_t ncells, int order);
+
+// Build into ts.ws (ws_bytes >= tree_particle_bytes(n)); GLM_ENOMEM when the
+// boxes do not fit after it (ts.need then holds the bytes required).
 glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, const double* m, const double* s,
                              int64_t n, const glm_params& prm, hipStream_t st);
 

@@ -103,15 +103,6 @@ glm_status fail(glm_status st, const std::string& msg);
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-// Device buffer owned by the library (grow-only).
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    glm_status ensure(size_t want);
-    void release();
-    template <class T> T* as() const { return static_cast<T*>(p); }
-};
-
 // ---------------------------------------------------------------------------
 // radix sort and scans (sort.hip)
 // ---------------------------------------------------------------------------

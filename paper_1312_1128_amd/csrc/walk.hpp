@@ -140,7 +140,10 @@ glm_status direct_device(const double* x, const double* y, const double* m, cons
                          hipStream_t st);
 
 // Cotangents: ga1, ga2 = dL/dalpha, gk = dL/dkappa, gg1, gg2 = dL/dgamma (each nullable: zero).
-glm_status adjoint_device(TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, const float* ga1,
+// The workspace holds the ray staging, then the box adjoints and the
+// per-particle direct-term sums.
+size_t adjoint_workspace_bytes(const TreeStorage& ts, int64_t nrays);
+glm_status adjoint_device(const TreeStorage& ts, const double* rx, const double* ry, int64_t nrays, const float* ga1,
                           const float* ga2, const float* gk, const float* gg1, const float* gg2, double* dm,
                           double* dx, double* dy, double* ds, uint32_t flags, void* ws, hipStream_t st);
 

@@ -54,13 +54,18 @@ def test_host_validation(lib):
                                          (0.3, float("inf"), 8, 2, 0), (0.3, 3.0, 0, 2, 0), (0.3, 3.0, 65, 2, 0),
                                          (0.3, 3.0, 8, 13, 0), (0.3, 3.0, 8, -1, 0), (0.3, 3.0, 8, 2, 64)]:
         p = _capi.GlmParams(theta, q, leaf, order, flags)
-        rc = lib.glm_build_tree(h, buf, buf, buf, None, 4, ctypes.byref(p), None)
+        rc = lib.glm_build_tree(h, buf, buf, buf, None, 4, ctypes.byref(p), buf, 1 << 30, None)
         assert rc == _capi.GLM_EINVAL, (theta, q, leaf, order, flags)
         assert lib.glm_last_error()
     p = _capi.GlmParams(0.3, 3.0, 8, 2, 0)
-    assert lib.glm_build_tree(h, None, buf, buf, None, 4, ctypes.byref(p), None) == _capi.GLM_EINVAL
-    assert lib.glm_build_tree(h, buf, buf, buf, None, 0, ctypes.byref(p), None) == _capi.GLM_EINVAL
-    assert lib.glm_build_tree(None, buf, buf, buf, None, 4, ctypes.byref(p), None) == _capi.GLM_EINVAL
+    ws = 1 << 30
+    assert lib.glm_build_tree(h, None, buf, buf, None, 4, ctypes.byref(p), buf, ws, None) == _capi.GLM_EINVAL
+    assert lib.glm_build_tree(h, buf, buf, buf, None, 0, ctypes.byref(p), buf, ws, None) == _capi.GLM_EINVAL
+    assert lib.glm_build_tree(None, buf, buf, buf, None, 4, ctypes.byref(p), buf, ws, None) == _capi.GLM_EINVAL
+    assert lib.glm_build_tree(h, buf, buf, buf, None, 4, ctypes.byref(p), None, ws, None) == _capi.GLM_EINVAL
+    # a workspace too small for the particle arrays is refused before any launch
+    assert lib.glm_build_tree(h, buf, buf, buf, None, 4, ctypes.byref(p), buf, 64, None) == _capi.GLM_ENOMEM
+    assert b"workspace" in lib.glm_last_error()
     # an unbuilt tree cannot be walked
     rc = lib.glm_shoot(h, buf, buf, 4, buf, buf, buf, buf, buf, None, 0, None, 0, None)
     assert rc == _capi.GLM_ESTATE
@@ -70,6 +75,8 @@ def test_host_validation(lib):
     assert lib.glm_tree_get_info(h, ctypes.byref(info)) == _capi.GLM_ESTATE
     assert lib.glm_tree_knn(h, 32, buf, None) == _capi.GLM_ESTATE
     assert lib.glm_tree_knn(None, 32, buf, None) == _capi.GLM_EINVAL
+    b = ctypes.c_size_t()
+    assert lib.glm_adjoint_workspace_bytes(h, 16, ctypes.byref(b)) == _capi.GLM_ESTATE
     # workspace size is a host-side function of the ray count
     b = ctypes.c_size_t()
     assert lib.glm_shoot_workspace_bytes(1 << 20, ctypes.byref(b)) == 0 and b.value > (1 << 20) * 32
@@ -77,6 +84,34 @@ def test_host_validation(lib):
     arr = (ctypes.c_void_p * 5)()
     assert lib.glm_shoot_direct(buf, buf, buf, None, 4, 3.0, buf, buf, 4, 0, arr, None) == _capi.GLM_EINVAL
     lib.glm_tree_destroy(None)
+    lib.glm_tree_destroy(h)
+
+
+def test_tree_workspace_bound(lib):
+    """The tree workspace bound is host arithmetic: it grows with n, shrinks
+    with the leaf size, grows with the order, and is refused for bad input."""
+    from paper_1312_1128_amd import _capi
+
+    def bound(n, leaf=8, order=8):
+        b = ctypes.c_size_t()
+        p = _capi.GlmParams(0.3, 3.0, leaf, order, 0)
+        assert lib.glm_tree_workspace_bytes(n, ctypes.byref(p), ctypes.byref(b)) == 0
+        return b.value
+
+    sizes = [bound(n) for n in (1, 9, 100, 10_000, 1_000_000)]
+    assert all(a < b for a, b in zip(sizes, sizes[1:]))
+    assert bound(10_000, leaf=16) < bound(10_000, leaf=8) < bound(10_000, leaf=1)
+    assert bound(10_000, order=2) < bound(10_000, order=12)
+    # at least the per-particle arrays (keys, sorted copies, records, list entries)
+    assert bound(1_000_000) > 1_000_000 * 140
+    b = ctypes.c_size_t()
+    p = _capi.GlmParams(0.3, 3.0, 8, 8, 0)
+    assert lib.glm_tree_workspace_bytes(0, ctypes.byref(p), ctypes.byref(b)) == _capi.GLM_EINVAL
+    bad = _capi.GlmParams(0.3, 3.0, 0, 8, 0)
+    assert lib.glm_tree_workspace_bytes(10, ctypes.byref(bad), ctypes.byref(b)) == _capi.GLM_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.glm_tree_create(ctypes.byref(h)) == 0
+    assert lib.glm_tree_required_bytes(h, ctypes.byref(b)) == _capi.GLM_ESTATE
     lib.glm_tree_destroy(h)
 
 

@@ -72,13 +72,15 @@ def test_adjoint_fitting_workload_vs_bruteforce(ora):
     a_true = ora.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx, ry)[:, :2]
     noise = synth.rng(synth.BASE_SEED + 8).normal(0.0, 1e-4, size=(rx.size, 2))
     bx, by = rx - a_true[:, 0] + noise[:, 0], ry - a_true[:, 1] + noise[:, 1]
+    # the cotangents come from the oracle tree's forward (an FP32 input to both sides)
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.3, 8, 8)
+    AB = T.shoot(rx, ry)
+    ga = np.stack([-2 * (rx - AB[:, 0] - bx), -2 * (ry - AB[:, 1] - by)], axis=1)
+    ga = ga.astype(np.float32).astype(np.float64)
     tree = build(lens, 0.3, 8, 8)
     A = shoot(tree, rx, ry)
-    ga = np.stack([-2 * (rx - A[:, 0] - bx), -2 * (ry - A[:, 1] - by)], axis=1)
-    ga = ga.astype(np.float32).astype(np.float64)
     dm, dx, dy, ds = gpu_grad(tree, rx, ry, ga)
     # the same tree in FP64 (decisions identical to the GPU walk)
-    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.3, 8, 8)
     rm, rxg, ryg, rs = T.grad(rx, ry, ga)
     compare("tree dL/dm", dm, rm, 1e-4, 2e-6)
     compare("tree dL/dx", dx, rxg, 1e-4, 2e-6)
@@ -93,6 +95,73 @@ def test_adjoint_fitting_workload_vs_bruteforce(ora):
     # Euler: alpha is homogeneous of degree 1 in the masses
     L1 = np.sum(ga[:, 0] * A[:, 0] + ga[:, 1] * A[:, 1])
     assert abs(np.sum(lens.m * dm) - L1) <= 1e-4 * np.sum(np.abs(lens.m * dm))
+
+
+def test_adjoint_headline_1e6_vs_oracle_tree(ora):
+    """The adjoint at the headline size: 1e6 smoothed NFW particles, theta =
+    0.3, p = 8, leaf size 16, on 4,096 seeded rays of the 2048^2 grid plus the
+    512 nearest the halo centre, with the fitting loss L = sum |x - alpha -
+    beta*|^2 (beta* = x - alpha_true + N(0, 1e-4), alpha_true from the FP64
+    brute force), against the oracle tree's frozen-walk gradient."""
+    lens, gx, gy = synth.workload_nfw()
+    central = np.argsort(gx * gx + gy * gy, kind="stable")[:512]
+    idx = np.union1d(synth.sample_rays(gx, gy, 4096, synth.BASE_SEED + 12), central)
+    rx, ry = gx[idx], gy[idx]
+    say(f"[gpu] adjoint at 1e6 particles: {rx.size} rays")
+    a_true = ora.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx, ry)[:, :2]
+    noise = synth.rng(synth.BASE_SEED + 13).normal(0.0, 1e-4, size=(rx.size, 2))
+    bx, by = rx - a_true[:, 0] + noise[:, 0], ry - a_true[:, 1] + noise[:, 1]
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.3, 16, 8)
+    AB = T.shoot(rx, ry)
+    ga = np.stack([-2 * (rx - AB[:, 0] - bx), -2 * (ry - AB[:, 1] - by)], axis=1)
+    ga = ga.astype(np.float32).astype(np.float64)
+    tree = build(lens, 0.3, 16, 8)
+    dm, dx, dy, ds = gpu_grad(tree, rx, ry, ga)
+    rm, rxg, ryg, rs = T.grad(rx, ry, ga)
+    compare("dL/dm", dm, rm, 1e-4, 2e-6)
+    compare("dL/dx", dx, rxg, 1e-4, 2e-6)
+    compare("dL/dy", dy, ryg, 1e-4, 2e-6)
+    compare("dL/ds", ds, rs, 1e-4, 2e-6)
+    # Euler: sum_i m_i dL/dm_i = sum_r ga . alpha_r (alpha is linear in the masses)
+    A = shoot(tree, rx, ry)
+    L1 = np.sum(ga[:, 0] * A[:, 0] + ga[:, 1] * A[:, 1])
+    assert abs(np.sum(lens.m * dm) - L1) <= 1e-5 * np.sum(np.abs(lens.m * dm))
+
+
+def test_adjoint_workspace_and_concurrent_streams(ora):
+    """The adjoint only reads the tree: two adjoints of one tree on two streams
+    with their own workspaces give the sequential result (to the rounding of
+    the FP64 atomics); a workspace below glm_adjoint_workspace_bytes is refused."""
+    import paper_1312_1128_amd as g
+    import torch
+
+    lens = synth.nfw_halo(30000, 341)
+    rx, ry = synth.uniform_points(20000, 343)
+    say("[gpu] adjoint workspaces on two streams")
+    tree = build(lens, 0.3, 8, 6)
+    gen = synth.rng(345)
+    cots = [torch.from_numpy(gen.normal(size=rx.size).astype(np.float32)).cuda() for _ in range(4)]
+    X, Y = dev(rx), dev(ry)
+    seq = [g.shoot_adjoint(tree, X, Y, cots[2 * j], cots[2 * j + 1]) for j in range(2)]
+    torch.cuda.synchronize()
+    need = g.adjoint_workspace_bytes(tree, rx.size)
+    assert need > g.workspace_bytes(rx.size)
+    with pytest.raises(g.GlamerError) as e:
+        g.shoot_adjoint(tree, X, Y, cots[0], cots[1],
+                        workspace=torch.empty(need - 8, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == -2
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    wss = [torch.empty(need, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    outs = []
+    torch.cuda.synchronize()
+    for j, st in enumerate(streams):
+        with torch.cuda.stream(st):
+            outs.append(g.shoot_adjoint(tree, X, Y, cots[2 * j], cots[2 * j + 1], workspace=wss[j]))
+    torch.cuda.synchronize()
+    for j in range(2):
+        for a, b in zip(outs[j], seq[j]):
+            a, b = a.cpu().numpy(), b.cpu().numpy()
+            np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12 * np.abs(b).max())
 
 
 def test_adjoint_identities_and_autograd(ora):

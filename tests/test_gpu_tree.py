@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import build, dev, rel_err, say, shoot, stats
+from gpu_helpers import assert_matches_oracle_tree, build, dev, rel_err, say, shoot, stats
 
 pytestmark = pytest.mark.gpu
 
@@ -75,15 +75,13 @@ def test_tree_and_walk_match_oracle_tree(ora, case):
     ea, ek, eg = rel_err(got, ref)
     stats("alpha vs oracle tree", ea)
     stats("gamma vs oracle tree", eg)
-    assert np.quantile(ea, 0.999) < 1e-5 and ea.max() < 1e-4
+    # measured worst: alpha 5.4e-6 per ray (p99.9 1.3e-6), kappa 1.1e-6
+    assert np.quantile(ea, 0.999) < 5e-6 and ea.max() < 2e-5
     if lens.s.max() > 0:
         ok = np.abs(ref[:, 2]) > 0
         stats("kappa vs oracle tree", ek[ok])
-        assert np.all(ek[ok] < 1e-4)
-    else:
-        assert np.all(got[:, 2] == 0.0)
-    gn = np.linalg.norm(ref[:, 3:], axis=1)
-    assert np.all(np.linalg.norm(got[:, 3:] - ref[:, 3:], axis=1) <= 1e-4 * gn + 1e-6 * np.median(gn))
+        assert np.all(ek[ok] < 5e-6)
+    assert_matches_oracle_tree(got, ref)
 
 
 def test_massless_boxes_match_oracle_tree(ora):
@@ -99,13 +97,7 @@ def test_massless_boxes_match_oracle_tree(ora):
     ref, rcnt = T.shoot(rx, ry, counts=True)
     got, gcnt = shoot(tree, rx, ry, counts=True)
     np.testing.assert_array_equal(gcnt, rcnt[:, [0, 1, 2, 4]])
-    an = np.linalg.norm(ref[:, :2], axis=1)
-    assert np.all(np.linalg.norm(got[:, :2] - ref[:, :2], axis=1) <= 1e-4 * an + 1e-6 * an.max())
-    assert np.all(got[ref[:, 2] == 0, 2] == 0.0)
-    kn = np.abs(ref[:, 2])
-    assert np.all(np.abs(got[:, 2] - ref[:, 2]) <= 1e-4 * kn + 1e-6 * kn.max())
-    gn = np.linalg.norm(ref[:, 3:], axis=1)
-    assert np.all(np.linalg.norm(got[:, 3:] - ref[:, 3:], axis=1) <= 1e-4 * gn + 1e-6 * gn.max())
+    assert_matches_oracle_tree(got, ref)
 
 
 def test_theta_zero_walk_is_direct_sum(ora):
@@ -143,6 +135,7 @@ def test_headline_nfw_1e6_vs_bruteforce(ora):
     stats("gamma vs brute force", eg)
     say(f"  mean counts per ray (visited, accepted, leaf, list hits): {cnt.mean(0)}")
     assert ea.max() <= 1e-4 and ek.max() <= 1e-4 and eg.max() <= 1e-4
+    assert np.all(got[idx][ref[:, 2] == 0, 2] == 0.0)
     # the same sampled rays through the oracle tree: identical decisions
     T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.3, 16, 8)
     refB, rc = T.shoot(rx[idx], ry[idx], counts=True)
@@ -196,9 +189,8 @@ def test_parameter_extremes(ora, leaf, order):
     np.testing.assert_array_equal(gcnt, rcnt[:, [0, 1, 2, 4]])
     ea, ek, eg = rel_err(got, ref)
     stats("alpha vs oracle tree", ea)
-    assert np.quantile(ea, 0.999) < 1e-5 and ea.max() < 1e-4
-    ok = np.abs(ref[:, 2]) > 0
-    assert np.all(ek[ok] < 1e-4)
+    assert np.quantile(ea, 0.999) < 5e-6 and ea.max() < 2e-5
+    assert_matches_oracle_tree(got, ref)
 
 
 def test_point_masses_without_smoothing_array(ora):
@@ -284,3 +276,54 @@ def test_bad_inputs_are_rejected():
     with pytest.raises(g.GlamerError) as e:
         g.shoot(t, dev(np.zeros(3)), dev(np.zeros(3)))
     assert e.value.status == -4
+
+
+def test_caller_workspace_contract(ora):
+    """The tree lives in the caller's workspace: the bound of
+    glm_tree_workspace_bytes holds on a worst case of depth-capped clusters; a
+    workspace too small for the boxes is refused after the box count is known
+    (with the exact size reported); a build into exactly that size equals one
+    into the bound; two trees in two workspaces do not disturb each other."""
+    import paper_1312_1128_amd as g
+    import torch
+
+    say("[gpu] caller workspace contract")
+    # clusters of L + 1 coincident particles: each one a chain of boxes down to the depth cap
+    L = 4
+    gen = synth.rng(61)
+    centres = gen.uniform(-0.5, 0.5, (200, 2))
+    pos = np.repeat(centres, L + 1, axis=0)
+    lens = synth.Lens(pos[:, 0].copy(), pos[:, 1].copy(), np.full(pos.shape[0], 1e-3), np.zeros(pos.shape[0]))
+    p = g.GlmParams(0.5, 3.0, L, 4, 0)
+    bound = g.tree_workspace_bytes(lens.n, p)
+    tree = g.Tree().build(dev(lens.x), dev(lens.y), dev(lens.m), None, theta=0.5, leaf_size=L, order=4)
+    need = tree.required_bytes()
+    inf = tree.info()
+    say(f"  {lens.n} particles: {inf['ncells']} boxes, need {need} of the bound {bound} bytes")
+    assert inf["check_flags"] == 0 and inf["max_level"] == 32 and need <= bound and inf["device_bytes"] == need
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, 3.0, 0.5, L, 4)
+    assert inf["ncells"] == T.ncells
+    rx, ry = synth.uniform_points(500, 62)
+    ref = shoot(tree, rx, ry)
+    # too small for the boxes: refused after the count, exact need reported
+    small = torch.empty(need - 4096, dtype=torch.uint8, device="cuda")
+    t2 = g.Tree()
+    with pytest.raises(g.GlamerError) as e:
+        t2.build(dev(lens.x), dev(lens.y), dev(lens.m), None, theta=0.5, leaf_size=L, order=4, workspace=small)
+    assert e.value.status == -2
+    assert t2.required_bytes() == need
+    with pytest.raises(g.GlamerError) as e:
+        g.shoot(t2, dev(rx), dev(ry))
+    assert e.value.status == -4
+    exact = torch.empty(need, dtype=torch.uint8, device="cuda")
+    t2.build(dev(lens.x), dev(lens.y), dev(lens.m), None, theta=0.5, leaf_size=L, order=4, workspace=exact)
+    np.testing.assert_array_equal(shoot(t2, rx, ry), ref)
+    # a second tree in its own workspace; rebuilding it leaves the first intact
+    other = synth.nfw_halo(5000, 63)
+    t3 = build(other, 0.3, 8, 6)
+    a3 = shoot(t3, rx, ry)
+    t3.build(dev(other.x[::-1].copy()), dev(other.y[::-1].copy()), dev(other.m), dev(other.s[::-1].copy()),
+             theta=0.3, q=other.q, leaf_size=8, order=6)
+    np.testing.assert_array_equal(shoot(t2, rx, ry), ref)
+    np.testing.assert_array_equal(shoot(tree, rx, ry), ref)
+    np.testing.assert_allclose(shoot(t3, rx, ry), a3, rtol=1e-6, atol=1e-7 * np.abs(a3).max())
