@@ -1,6 +1,6 @@
 """Batched walks, device refinement rounds (and their HIP-graph replay) and the
-autotuner, against per-lens walks, a plain numpy restatement of the
-refinement rule, and the FP64 oracle."""
+autotuner, against per-lens walks, the oracle's statement of the refinement
+rule (oracle/refine.py), and the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -46,29 +46,6 @@ def test_batched_equals_per_lens_and_oracle(ora):
         np.testing.assert_array_equal(o["a1"].cpu().numpy(), oa["a1"].cpu().numpy())
 
 
-def numpy_refine(cx, cy, side, kap, g1, g2, n, k):
-    """The refinement rule restated in numpy (float32 score, stable ranking)."""
-    h = side[:n].astype(np.float32)
-    sc = (h * h) * ((kap[:n] * kap[:n] + g1[:n] * g1[:n]) + g2[:n] * g2[:n])
-    key = np.uint32(0xFFFFFFFF) - sc.astype(np.float32).view(np.uint32)
-    order = np.argsort(key, kind="stable")[:k]
-    cx, cy, side = cx.copy(), cy.copy(), side.copy()
-    for t, c in enumerate(order):
-        h3 = side[c] / 3.0
-        j = 0
-        for dy in (-1, 0, 1):
-            for dx in (-1, 0, 1):
-                if dx == 0 and dy == 0:
-                    continue
-                o = n + 8 * t + j
-                cx[o] = cx[c] + float(dx) * h3
-                cy[o] = cy[c] + float(dy) * h3
-                side[o] = h3
-                j += 1
-        side[c] = h3
-    return order, cx, cy, side
-
-
 def test_refine_round_matches_rule():
     import paper_1312_1128_amd as g
     import torch
@@ -94,7 +71,10 @@ def test_refine_round_matches_rule():
     refined = torch.zeros(k, dtype=torch.int32, device="cuda")
     g.refine_round(tx, ty, ts, f(kap), f(g1), f(g2), n, k, refined=refined)
     torch.cuda.synchronize()
-    order, ex, ey, es = numpy_refine(cx, cy, side, kap, g1, g2, n, k)
+    from oracle import refine
+
+    ex, ey, es = cx.copy(), cy.copy(), side.copy()
+    order = refine.refine_round(ex, ey, es, kap, g1, g2, n, k)
     np.testing.assert_array_equal(refined.cpu().numpy(), order)
     np.testing.assert_array_equal(tx.cpu().numpy(), ex)
     np.testing.assert_array_equal(ty.cpu().numpy(), ey)
@@ -147,15 +127,33 @@ def test_refinement_rounds_graph_replay_and_oracle(ora):
         torch.cuda.synchronize()
 
 
-def test_autotune_picks_a_passing_configuration():
+def test_autotune_picks_a_passing_configuration(ora):
+    """The tuner accepts a configuration on 16,384 random rays plus the 4,096
+    nearest the densest point; the choice must then hold on held-out rays
+    against the CPU brute force, and be the fastest accepted row."""
     import paper_1312_1128_amd as g
 
     lens = synth.nfw_halo(50_000, 441)
     rx, ry = synth.ray_grid(256)
     say("[gpu] autotune")
-    best, table = g.autotune(dev(lens.x), dev(lens.y), dev(lens.m), dev(lens.s), dev(rx), dev(ry),
-                             thetas=(0.3, 0.5), orders=(4, 8), leaves=(8,), sample=256, reps=2)
-    assert best is not None and best["err"] <= 1e-4
-    assert any(not t["ok"] for t in table) or all(t["ok"] for t in table)
+    X, Y, M, S, RX, RY = (dev(a) for a in (lens.x, lens.y, lens.m, lens.s, rx, ry))
+    best, table = g.autotune(X, Y, M, S, RX, RY, thetas=(0.3, 0.5), orders=(4, 6, 8, 10), leaves=(8, 16), reps=2)
+    assert best is not None and best["err"] <= 1e-4 and best["rays_checked"] >= 16384
+    # held out: rays not in the tuner's validation set, against the FP64 brute force
+    val = set(g.batch.validation_rays(X, Y, S, RX, RY).cpu().numpy().tolist())
+    rest = np.array(sorted(set(range(rx.size)) - val))
+    hold = rest[synth.sample_rays(rest, None, 4096, 443)]
+    tree = build(lens, best["theta"], best["leaf_size"], best["order"])
+    got = shoot(tree, rx[hold], ry[hold])
+    ref = ora.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx[hold], ry[hold])
+    ea, ek, eg = rel_err(got, ref)
+    ok = ref[:, 2] != 0
+    say(f"  chosen {best['theta']}, {best['order']}, {best['leaf_size']}: held-out max e_alpha {ea.max():.2e} "
+        f"e_kappa {ek[ok].max():.2e} e_gamma {eg.max():.2e}")
+    assert ea.max() <= 1e-4 and eg.max() <= 1e-4 and np.all(ek[ok] <= 1e-4)
+    # every accepted row met the tolerance, every refused one missed it
+    for t in table:
+        err = max(t["err_alpha"], t["err_kappa"], t["err_gamma"])
+        assert t["ok"] == (err <= 1e-4), t
     passing = [t for t in table if t["ok"]]
     assert best["ms"] == min(t["ms"] for t in passing)

@@ -7,6 +7,11 @@ from gpu_helpers import dev, rel_err, say, stats
 
 pytestmark = pytest.mark.gpu
 
+# FP32 terms summed in FP64, against the FP64 brute force: largest measured per-ray
+# errors alpha 2.8e-7, kappa 9.6e-7, gamma 1.9e-5 (a ray of the 1k point-mass field
+# where the shear is a small difference of large terms); the bounds are ~3x those
+FP32_MAX = {"alpha": 1e-6, "kappa": 3e-6, "gamma": 6e-5}
+
 
 def run_direct(lens, rx, ry, fp64):
     import paper_1312_1128_amd as g
@@ -41,4 +46,11 @@ def test_direct_matches_oracle(ora, which):
     ea, ek, eg = rel_err(d32, ref)
     stats("fp32 alpha", ea)
     stats("fp32 gamma", eg)
-    assert np.quantile(ea, 0.999) < 1e-5
+    zero = ref[:, 2] == 0
+    assert np.all(d32[zero, 2] == 0.0)  # no particle holds the ray: kappa exactly 0
+    if (~zero).any():
+        stats("fp32 kappa", ek[~zero])
+    # each FP32 term is within a few ulp, so per ray the error is a few 1e-7 of
+    # the sum of the terms' magnitudes, which exceeds |gamma| where terms cancel
+    assert ea.max() <= FP32_MAX["alpha"] and eg.max() <= FP32_MAX["gamma"]
+    assert np.all(ek[~zero] <= FP32_MAX["kappa"])

@@ -50,7 +50,7 @@ def test_microlensing_refinement_graph_full_size(ora):
     got_all = np.stack([run.out[k][:n].double().cpu().numpy() for k in ["a1", "a2", "kappa", "g1", "g2"]], axis=1)
     a = 0
     for r, size in enumerate(run.sizes):
-        idx = a + synth.sample_rays(np.zeros(size), None, 32, 470 + r)
+        idx = a + synth.sample_rays(np.zeros(size), None, 512, 470 + r)
         ref = ora.direct(lens.x, lens.y, lens.m, lens.s, lens.q, px[idx], py[idx])
         ea, ek, eg = errors(got_all[idx], ref)
         say(f"  round {r} ({size} rays): max e_alpha {ea.max():.2e} e_kappa {ek.max():.2e} e_gamma {eg.max():.2e}")
@@ -59,14 +59,21 @@ def test_microlensing_refinement_graph_full_size(ora):
 
 
 def test_batched_64_lenses_full_size(ora):
+    """The 64 lenses autotuned as the benchmark does (one order for the batch,
+    theta and leaf size per lens, each accepted on 16,384 random rays plus the
+    4,096 nearest its densest point), then walked in one persistent launch."""
     import paper_1312_1128_amd as g
     import torch
 
     lenses = synth.workload_batched_lenses(64)
     say(f"[gpu] full-size batch: {sum(l.n for l, _, _ in lenses)} particles, "
         f"{sum(rx.size for _, rx, _ in lenses)} rays")
-    trees = [g.Tree().build(d(l.x), d(l.y), d(l.m), d(l.s), theta=THETA, q=l.q, leaf_size=LEAF, order=ORDER)
-             for l, _, _ in lenses]
+    dl = [(d(l.x), d(l.y), d(l.m), d(l.s), d(rx), d(ry)) for l, rx, ry in lenses]
+    order, picks = g.autotune_batch(dl, q=lenses[0][0].q)
+    assert order is not None
+    say(f"  tuned order {order}; (theta, leaf) per lens: {[(p['theta'], p['leaf_size']) for p in picks]}")
+    trees = [g.Tree().build(x, y, m, s, theta=p["theta"], q=l.q, leaf_size=p["leaf_size"], order=order)
+             for (x, y, m, s, _, _), p, (l, _, _) in zip(dl, picks, lenses)]
     rays = [(d(rx), d(ry)) for _, rx, ry in lenses]
     outs = [{k: torch.empty(r[0].numel(), dtype=torch.float32, device="cuda") for k in ["a1", "a2", "kappa", "g1", "g2"]}
             for r in rays]
@@ -75,7 +82,7 @@ def test_batched_64_lenses_full_size(ora):
     torch.cuda.synchronize()
     errs = []
     for i, ((l, rx, ry), o) in enumerate(zip(lenses, outs)):
-        idx = synth.sample_rays(rx, ry, 8, 500 + i)
+        idx = synth.sample_rays(rx, ry, 128, 500 + i)
         got = np.stack([o[k][idx].double().cpu().numpy() for k in ["a1", "a2", "kappa", "g1", "g2"]], axis=1)
         ref = ora.direct(l.x, l.y, l.m, l.s, l.q, rx[idx], ry[idx])
         errs.append(np.stack(errors(got, ref), axis=1))

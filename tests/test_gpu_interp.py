@@ -1,8 +1,8 @@
-"""Interpolation shortcut of refinement (Sec. 3.4) on the device, against a
-plain numpy restatement of the rule (decisions, neighbours, shoot lists
-bit for bit; filled values to FP32 rounding), and against the tree walk at
-the interpolated points (the paper finds interpolation and direct shooting
-agree to a part in 1e4 for the deflection)."""
+"""Interpolation shortcut of refinement (Sec. 3.4) on the device, against the
+oracle's statement of the rule (oracle/refine.py: decisions, neighbours,
+shoot lists bit for bit; filled values to FP32 rounding), and against the tree
+walk at the interpolated points (the paper finds interpolation and direct
+shooting agree to a part in 1e4 for the deflection)."""
 import numpy as np
 import pytest
 
@@ -12,72 +12,6 @@ from gpu_helpers import build, dev, say
 pytestmark = pytest.mark.gpu
 
 NAMES = ["a1", "a2", "kappa", "g1", "g2"]
-
-
-def locate(table, level, i, j, nbase):
-    """The cell at (level, i, j), else the nearest coarser cell covering it."""
-    for l in range(level, -1, -1):
-        span = 3 ** l
-        if i < 0 or j < 0 or i >= nbase * span or j >= nbase * span:
-            return -1
-        c = table.get((l, i, j), -1)
-        if c >= 0:
-            return c
-        i //= 3
-        j //= 3
-    return -1
-
-
-def numpy_round(S, n, k, nbase, tol):
-    """One round of the rule on host copies S (cx, cy, side, outputs, lev, ci,
-    cj, table).  Returns the shoot list."""
-    f32 = np.float32
-    h = S["side"][:n].astype(f32)
-    ka, g1, g2 = (S[q][:n].astype(f32) for q in ("kappa", "g1", "g2"))
-    sc = (h * h) * ((ka * ka + g1 * g1) + g2 * g2)
-    key = np.uint32(0xFFFFFFFF) - sc.astype(f32).view(np.uint32)
-    order = np.argsort(key, kind="stable")[:k]
-    uniform = []
-    for c in order:
-        found, ok = 0, True
-        for dy in (-1, 0, 1):
-            for dx in (-1, 0, 1):
-                if dx == 0 and dy == 0:
-                    continue
-                nb = locate(S["table"], S["lev"][c], S["ci"][c] + dx, S["cj"][c] + dy, nbase)
-                if nb < 0 or nb == c:
-                    continue
-                found += 1
-                ok = ok and all(abs(f32(S[q][nb]) - f32(S[q][c])) <= f32(tol) for q in ("kappa", "g1", "g2"))
-        uniform.append(ok and found > 0)
-    shoot = []
-    for t, c in enumerate(order):
-        h3 = S["side"][c] / 3.0
-        l, i, j = S["lev"][c] + 1, 3 * S["ci"][c] + 1, 3 * S["cj"][c] + 1
-        A1, A2, K, G1, G2 = (float(S[q][c]) for q in NAMES)
-        q = 0
-        for dy in (-1, 0, 1):
-            for dx in (-1, 0, 1):
-                if dx == 0 and dy == 0:
-                    continue
-                o = n + 8 * t + q
-                S["cx"][o] = S["cx"][c] + float(dx) * h3
-                S["cy"][o] = S["cy"][c] + float(dy) * h3
-                S["side"][o] = h3
-                S["lev"][o], S["ci"][o], S["cj"][o] = l, i + dx, j + dy
-                S["table"][(l, i + dx, j + dy)] = o
-                if uniform[t]:
-                    ux, uy = S["cx"][o] - S["cx"][c], S["cy"][o] - S["cy"][c]
-                    S["a1"][o] = A1 + (K + G1) * ux + G2 * uy
-                    S["a2"][o] = A2 + G2 * ux + (K - G1) * uy
-                    S["kappa"][o], S["g1"][o], S["g2"][o] = K, G1, G2
-                else:
-                    shoot.append(o)
-                q += 1
-        S["side"][c] = h3
-        S["lev"][c], S["ci"][c], S["cj"][c] = l, i, j
-        S["table"][(l, i, j)] = int(c)
-    return np.array(order), np.array(uniform), np.array(shoot, dtype=np.int64)
 
 
 def micro_lens(nhalo, nstars, seed):
@@ -132,20 +66,15 @@ def test_interp_rounds_match_rule_and_walk(ora, case):
     idx = torch.zeros(8 * max(sched), dtype=torch.int32, device="cuda")
     count = torch.zeros(1, dtype=torch.int32, device="cuda")
     refined = torch.zeros(max(sched), dtype=torch.int32, device="cuda")
-    # host mirror of the state
-    S = {"cx": cx.cpu().numpy().copy(), "cy": cy.cpu().numpy().copy(), "side": side.cpu().numpy().copy()}
+    # the oracle's copy of the grid, fed the device's walked values
+    from oracle import refine
+
+    G = refine.NestedGrid(bx, by, x0, y0, h0, nbase, cap)
     for q in NAMES:
-        S[q] = out[q].cpu().numpy().astype(np.float64)
-    S["lev"] = np.zeros(cap, dtype=np.int64)
-    S["ci"] = np.zeros(cap, dtype=np.int64)
-    S["cj"] = np.zeros(cap, dtype=np.int64)
-    ii = np.floor((S["cx"][:n] - x0) / h0).astype(np.int64)
-    jj = np.floor((S["cy"][:n] - y0) / h0).astype(np.int64)
-    S["ci"][:n], S["cj"][:n] = ii, jj
-    S["table"] = {(0, int(a), int(b)): c for c, (a, b) in enumerate(zip(ii, jj))}
+        G.out[q][:n] = out[q][:n].cpu().numpy().astype(np.float64)
     interpolated = []
     for r, k in enumerate(sched):
-        order, uniform, shoot = numpy_round(S, n, k, nbase, 1e-4)
+        order, uniform, shoot = G.interp_round(k, 1e-4)
         g.refine_interp_round(cx, cy, side, out, n, k, nbase, 1e-4, cap, state, idx, count, refined=refined)
         cnt = int(count.item())
         say(f"  round {r}: refine {k}, uniform {int(uniform.sum())}, walk {cnt}")
@@ -153,18 +82,18 @@ def test_interp_rounds_match_rule_and_walk(ora, case):
         assert cnt == shoot.size
         np.testing.assert_array_equal(idx[:cnt].cpu().numpy(), shoot)
         m = n + 8 * k
-        np.testing.assert_array_equal(cx[:m].cpu().numpy(), S["cx"][:m])
-        np.testing.assert_array_equal(cy[:m].cpu().numpy(), S["cy"][:m])
-        np.testing.assert_array_equal(side[:m].cpu().numpy(), S["side"][:m])
+        np.testing.assert_array_equal(cx[:m].cpu().numpy(), G.cx[:m])
+        np.testing.assert_array_equal(cy[:m].cpu().numpy(), G.cy[:m])
+        np.testing.assert_array_equal(side[:m].cpu().numpy(), G.side[:m])
         filled = np.setdiff1d(np.arange(n, m), shoot)
         for q in NAMES:
             if filled.size == 0:
                 break
             got = out[q][:m].cpu().numpy()[filled].astype(np.float64)
-            np.testing.assert_allclose(got, S[q][filled], rtol=1e-6, atol=1e-7 * np.abs(S[q][filled]).max())
+            np.testing.assert_allclose(got, G.out[q][filled], rtol=1e-6, atol=1e-7 * np.abs(G.out[q][filled]).max())
         g.shoot_indexed(tree, cx, cy, idx, cnt, out)
-        for q in NAMES:  # the device values (walked, and filled up to rounding) carry over to the mirror
-            S[q][n:m] = out[q][n:m].cpu().numpy().astype(np.float64)
+        for q in NAMES:  # the device values (walked, and filled up to rounding) carry over to the oracle's grid
+            G.out[q][n:m] = out[q][n:m].cpu().numpy().astype(np.float64)
         interpolated.append(filled)
         n = m
     interpolated = np.concatenate(interpolated)
@@ -174,7 +103,7 @@ def test_interp_rounds_match_rule_and_walk(ora, case):
     if interpolated.size == 0:
         return
     # interpolated cells against walking the same points
-    walked = g.shoot(tree, dev(S["cx"][interpolated]), dev(S["cy"][interpolated]))
+    walked = g.shoot(tree, dev(G.cx[interpolated]), dev(G.cy[interpolated]))
     a_int = np.stack([out["a1"].cpu().numpy()[interpolated], out["a2"].cpu().numpy()[interpolated]], 1)
     a_w = np.stack([walked["a1"].cpu().numpy(), walked["a2"].cpu().numpy()], 1).astype(np.float64)
     err = np.linalg.norm(a_int - a_w, axis=1) / np.linalg.norm(a_w, axis=1)
@@ -182,6 +111,13 @@ def test_interp_rounds_match_rule_and_walk(ora, case):
     assert err.max() <= 1e-4
     dk = np.abs(out["kappa"].cpu().numpy()[interpolated] - walked["kappa"].cpu().numpy())
     say(f"  kappa vs walk max {dk.max():.2e}")
+    # and against the FP64 brute force at a sample of the interpolated points
+    pick = interpolated[synth.sample_rays(interpolated, None, 256, 509)]
+    ref = ora.direct(lens.x, lens.y, lens.m, lens.s, lens.q, G.cx[pick], G.cy[pick])
+    a_i = np.stack([out["a1"].cpu().numpy()[pick], out["a2"].cpu().numpy()[pick]], 1).astype(np.float64)
+    eb = np.linalg.norm(a_i - ref[:, :2], axis=1) / np.linalg.norm(ref[:, :2], axis=1)
+    say(f"  interpolated alpha vs brute force ({pick.size} rays): max {eb.max():.2e}")
+    assert eb.max() <= 1e-4
 
 
 def test_interp_tol_zero_walks_everything():
@@ -225,87 +161,14 @@ def test_interp_invalid_arguments():
 
 # ------------------------------------------------------------ deflection mode
 
-def mirror_neighbours(S, c, nbase):
-    out = []
-    for dy in (-1, 0, 1):
-        for dx in (-1, 0, 1):
-            if dx == 0 and dy == 0:
-                continue
-            nb = locate(S["table"], S["lev"][c], S["ci"][c] + dx, S["cj"][c] + dy, nbase)
-            if nb < 0 or nb == c:
-                continue
-            out.append(nb)
-    return out
-
-
-def mirror_three_point(S, c, nbase):
-    from oracle import interp
-
-    nb = mirror_neighbours(S, c, nbase)
-    return interp.three_point(S["cx"][c], S["cy"][c], S["a1"][c], S["a2"][c],
-                              [(S["cx"][q], S["cy"][q], S["a1"][q], S["a2"][q]) for q in nb])
-
-
-def mirror_estimates(S, cells, nbase):
-    from oracle import interp
-
-    out = np.zeros((len(cells), 3))
-    for t, c in enumerate(cells):
-        n, mn, mx, sm = mirror_three_point(S, c, nbase)
-        out[t] = interp.kappa_gamma(interp.mean_A(n, sm)) if n > 0 else (0.0, 0.0, 0.0)
-    return out.astype(np.float32).astype(np.float64)
-
-
-def numpy_round_deflections(S, n, k, nbase, tol):
-    """One round of the deflection-only rule (App. A) on the host mirror."""
-    from oracle import interp
-
-    f32 = np.float32
-    h = S["side"][:n].astype(f32)
-    ka, g1, g2 = (S[q][:n].astype(f32) for q in ("kappa", "g1", "g2"))
-    sc = (h * h) * ((ka * ka + g1 * g1) + g2 * g2)
-    key = np.uint32(0xFFFFFFFF) - sc.astype(f32).view(np.uint32)
-    order = np.argsort(key, kind="stable")[:k]
-    tests = [mirror_three_point(S, c, nbase) for c in order]
-    uniform = [interp.uniform(npr, mn, mx, float(f32(tol))) for npr, mn, mx, _ in tests]
-    shoot = []
-    for t, c in enumerate(order):
-        h3 = S["side"][c] / 3.0
-        l, i, j = S["lev"][c] + 1, 3 * S["ci"][c] + 1, 3 * S["cj"][c] + 1
-        A = interp.mean_A(tests[t][0], tests[t][3])
-        m11, m12, m21, m22 = 1.0 - A[0], -A[1], -A[2], 1.0 - A[3]
-        K, G1, G2 = interp.kappa_gamma(A)
-        q = 0
-        for dy in (-1, 0, 1):
-            for dx in (-1, 0, 1):
-                if dx == 0 and dy == 0:
-                    continue
-                o = n + 8 * t + q
-                S["cx"][o] = S["cx"][c] + float(dx) * h3
-                S["cy"][o] = S["cy"][c] + float(dy) * h3
-                S["side"][o] = h3
-                S["lev"][o], S["ci"][o], S["cj"][o] = l, i + dx, j + dy
-                S["table"][(l, i + dx, j + dy)] = o
-                if uniform[t]:
-                    ux, uy = S["cx"][o] - S["cx"][c], S["cy"][o] - S["cy"][c]
-                    S["a1"][o] = S["a1"][c] + m11 * ux + m12 * uy
-                    S["a2"][o] = S["a2"][c] + m21 * ux + m22 * uy
-                    S["kappa"][o], S["g1"][o], S["g2"][o] = K, G1, G2
-                else:
-                    shoot.append(o)
-                q += 1
-        S["side"][c] = h3
-        S["lev"][c], S["ci"][c], S["cj"][c] = l, i, j
-        S["table"][(l, i, j)] = int(c)
-    return np.array(order), np.array(uniform), np.array(shoot, dtype=np.int64)
-
-
 def test_interp_deflection_mode_matches_rule(ora):
     """Refinement with deflection-only walks: the base cells and each round's
     walked cells get kappa, gamma from the three-point magnification matrix
     (App. A), and the uniformity test compares the pair estimates of A; all
-    against a host restatement of the rule (decisions and walk lists bit for
-    bit, values to FP32 rounding)."""
+    against the oracle's statement of the rule (decisions and walk lists bit
+    for bit, values to FP32 rounding)."""
+    from oracle import refine
+
     import paper_1312_1128_amd as g
     import torch
 
@@ -336,25 +199,18 @@ def test_interp_deflection_mode_matches_rule(ora):
     g.interp_init(cx, cy, n, x0, y0, h0, cap, state)
     g.shoot_indexed(tree, cx, cy, torch.arange(n, dtype=torch.int32, device="cuda"), n, out, alpha_only=True)
     g.interp_estimate(cx, cy, out, nbase, cap, state, max_count=n)
-    S = {"cx": cx.cpu().numpy().copy(), "cy": cy.cpu().numpy().copy(), "side": side.cpu().numpy().copy()}
+    G = refine.NestedGrid(bx, by, x0, y0, h0, nbase, cap)
     for q in NAMES:
-        S[q] = out[q].cpu().numpy().astype(np.float64)
-    S["lev"] = np.zeros(cap, dtype=np.int64)
-    S["ci"] = np.zeros(cap, dtype=np.int64)
-    S["cj"] = np.zeros(cap, dtype=np.int64)
-    ii = np.floor((S["cx"][:n] - x0) / h0).astype(np.int64)
-    jj = np.floor((S["cy"][:n] - y0) / h0).astype(np.int64)
-    S["ci"][:n], S["cj"][:n] = ii, jj
-    S["table"] = {(0, int(a), int(b)): c for c, (a, b) in enumerate(zip(ii, jj))}
-    est = mirror_estimates(S, range(n), nbase)
-    got = np.stack([S["kappa"][:n], S["g1"][:n], S["g2"][:n]], axis=1)
+        G.out[q][:n] = out[q][:n].cpu().numpy().astype(np.float64)
+    est = G.estimate_kg(range(n)).astype(np.float32).astype(np.float64)
+    got = np.stack([G.out["kappa"][:n], G.out["g1"][:n], G.out["g2"][:n]], axis=1)
     np.testing.assert_allclose(got, est, rtol=1e-6, atol=1e-6 * np.abs(est).max())
     idx = torch.zeros(8 * max(sched), dtype=torch.int32, device="cuda")
     count = torch.zeros(1, dtype=torch.int32, device="cuda")
     refined = torch.zeros(max(sched), dtype=torch.int32, device="cuda")
     filled_all = []
     for r, k in enumerate(sched):
-        order, uniform, shoot = numpy_round_deflections(S, n, k, nbase, tol)
+        order, uniform, shoot = G.interp_round(k, tol, deflections=True)
         g.refine_interp_round(cx, cy, side, out, n, k, nbase, tol, cap, state, idx, count, refined=refined,
                               deflections=True)
         cnt = int(count.item())
@@ -363,31 +219,37 @@ def test_interp_deflection_mode_matches_rule(ora):
         assert cnt == shoot.size
         np.testing.assert_array_equal(idx[:cnt].cpu().numpy(), shoot)
         m = n + 8 * k
-        np.testing.assert_array_equal(cx[:m].cpu().numpy(), S["cx"][:m])
+        np.testing.assert_array_equal(cx[:m].cpu().numpy(), G.cx[:m])
         filled = np.setdiff1d(np.arange(n, m), shoot)
         for q in NAMES:
             if filled.size:
                 gq = out[q][:m].cpu().numpy()[filled].astype(np.float64)
-                np.testing.assert_allclose(gq, S[q][filled], rtol=1e-6, atol=1e-7 * np.abs(S[q][filled]).max())
+                np.testing.assert_allclose(gq, G.out[q][filled], rtol=1e-6,
+                                           atol=1e-7 * np.abs(G.out[q][filled]).max())
         g.shoot_indexed(tree, cx, cy, idx, cnt, out, alpha_only=True)
         g.interp_estimate(cx, cy, out, nbase, cap, state, idx=idx, count=count, max_count=8 * k)
         for q in ("a1", "a2"):
-            S[q][shoot] = out[q].cpu().numpy()[shoot].astype(np.float64)
-        S["a1"][filled] = out["a1"].cpu().numpy()[filled].astype(np.float64)
-        S["a2"][filled] = out["a2"].cpu().numpy()[filled].astype(np.float64)
-        est = mirror_estimates(S, shoot, nbase)
+            G.out[q][shoot] = out[q].cpu().numpy()[shoot].astype(np.float64)
+            G.out[q][filled] = out[q].cpu().numpy()[filled].astype(np.float64)
+        est = G.estimate_kg(shoot).astype(np.float32).astype(np.float64)
         got = np.stack([out[q].cpu().numpy()[shoot].astype(np.float64) for q in ("kappa", "g1", "g2")], axis=1)
         np.testing.assert_allclose(got, est, rtol=1e-6, atol=1e-6 * max(np.abs(est).max(), 1e-30))
         for q in ("kappa", "g1", "g2"):
-            S[q][n:m] = out[q].cpu().numpy()[n:m].astype(np.float64)
+            G.out[q][n:m] = out[q].cpu().numpy()[n:m].astype(np.float64)
         filled_all.append(filled)
         n = m
     filled_all = np.concatenate(filled_all)
     say(f"  {filled_all.size} of {n - bx.size} new cells interpolated")
     assert filled_all.size > 0
-    walked = g.shoot(tree, dev(S["cx"][filled_all]), dev(S["cy"][filled_all]), alpha_only=True)
+    walked = g.shoot(tree, dev(G.cx[filled_all]), dev(G.cy[filled_all]), alpha_only=True)
     a_int = np.stack([out["a1"].cpu().numpy()[filled_all], out["a2"].cpu().numpy()[filled_all]], 1)
     a_w = np.stack([walked["a1"].cpu().numpy(), walked["a2"].cpu().numpy()], 1).astype(np.float64)
     err = np.linalg.norm(a_int - a_w, axis=1) / np.linalg.norm(a_w, axis=1)
     say(f"  interpolated alpha vs walk: max {err.max():.2e} median {np.median(err):.2e}")
     assert err.max() <= 1e-3
+    pick = filled_all[synth.sample_rays(filled_all, None, 256, 519)]
+    ref = ora.direct_nfw(lens.x, lens.y, lens.m, lens.s, c, G.cx[pick], G.cy[pick])
+    a_i = np.stack([out["a1"].cpu().numpy()[pick], out["a2"].cpu().numpy()[pick]], 1).astype(np.float64)
+    eb = np.linalg.norm(a_i - ref[:, :2], axis=1) / np.linalg.norm(ref[:, :2], axis=1)
+    say(f"  interpolated alpha vs brute force ({pick.size} rays): max {eb.max():.2e}")
+    assert eb.max() <= 1e-3

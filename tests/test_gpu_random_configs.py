@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import build, dev, say, shoot
+from gpu_helpers import assert_matches_oracle_tree, build, dev, say, shoot
 
 pytestmark = pytest.mark.gpu
 
@@ -66,15 +66,7 @@ def test_random_configuration_matches_oracle_tree(ora, seed):
     T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, theta, leaf, order, nfw=nfw)
     ref, rcnt = T.shoot(rx, ry, counts=True)
     np.testing.assert_array_equal(gcnt, rcnt[:, [0, 1, 2, 4]])
-    a_err = np.linalg.norm(got[:, :2] - ref[:, :2], axis=1)
-    a_ref = np.linalg.norm(ref[:, :2], axis=1)
-    assert np.all(a_err <= 1e-4 * a_ref + 1e-6 * a_ref.max())
-    k_ref = np.abs(ref[:, 2])
-    assert np.all(got[ref[:, 2] == 0, 2] == 0.0)
-    assert np.all(np.abs(got[:, 2] - ref[:, 2]) <= 1e-4 * k_ref + 1e-6 * k_ref.max())
-    g_err = np.linalg.norm(got[:, 3:] - ref[:, 3:], axis=1)
-    g_ref = np.linalg.norm(ref[:, 3:], axis=1)
-    assert np.all(g_err <= 1e-4 * g_ref + 1e-6 * g_ref.max())
+    assert_matches_oracle_tree(got, ref)
     # potential
     import paper_1312_1128_amd as g
     import torch
