@@ -236,6 +236,25 @@ GLM_API glm_status glm_shoot(const glm_tree* t, const double* rx, const double* 
                      uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): glm_shoot
+ * with no workspace argument.  The same walk and the same results as
+ * glm_shoot; its ray workspace is a static device array of 128 MiB that the
+ * library holds on every GPU it runs on until the process ends, so the call
+ * allocates nothing.  All calls on one GPU share that array (each call's
+ * contents are left behind and overwritten by the next): calls that overlap
+ * on one GPU -- on different streams or from different threads -- race, and
+ * must be ordered by the caller.
+ *   nrays: 0 .. GLM_NOALLOC_MAX_RAYS, else GLM_EINVAL with nothing launched;
+ *   stream: must belong to the current device (GLM_EINVAL otherwise);
+ *   other arguments as glm_shoot.
+ */
+#define GLM_NOALLOC_MAX_RAYS 1048576
+GLM_API glm_status glm_shoot_noalloc(const glm_tree* t, const double* rx, const double* ry, int64_t nrays,
+                                     float* a1, float* a2, float* kappa, float* g1, float* g2, int32_t* counts,
+                                     uint32_t flags, void* stream);
+
+/*
  * Deflection and lensing potential (Sec. 3.2: alpha = grad psi; the time
  * delay of a single plane is |alpha|^2 / 2 - psi), in one tree walk with the
  * decisions of glm_shoot.  A point mass contributes m ln r (0 for a ray

@@ -21,7 +21,7 @@ __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerE
            "GLM_NFW_HALOS", "GLM_FP32_ALPHA", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
            "refine_schedule", "RefinementRun", "autotune", "autotune_batch", "smoothing_lengths", "interp_init",
            "refine_interp_round", "shoot_indexed", "shoot_potential", "knn", "knn_workspace_bytes",
-           "tree_workspace_bytes", "adjoint_workspace_bytes"]
+           "tree_workspace_bytes", "adjoint_workspace_bytes", "shoot_noalloc"]
 
 
 def _ptr(t):
@@ -170,6 +170,20 @@ def shoot(tree: Tree, rx, ry, counts: bool = False, alpha_only: bool = False, fp
                               _ptr(workspace), ws_bytes, _stream()))
     if counts:
         out["counts"] = cnt
+    return out
+
+
+def shoot_noalloc(tree: Tree, rx, ry, out, counts=None, alpha_only: bool = False, ordered: bool = False):
+    """glm_shoot_noalloc: the forward walk with the library's static ray
+    workspace (no device allocation in the call; at most GLM_NOALLOC_MAX_RAYS
+    rays).  out: dict of float32 tensors a1, a2 (kappa, g1, g2 unless
+    alpha_only); counts: int32 [R, 4] tensor or None."""
+    rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
+    flags = (GLM_ALPHA_ONLY if alpha_only else 0) | (GLM_RAYS_ORDERED if ordered else 0)
+    lib = _capi.load()
+    _capi.check(lib.glm_shoot_noalloc(tree.handle, _ptr(rx), _ptr(ry), rx.shape[0], _ptr(out["a1"]),
+                                      _ptr(out["a2"]), _ptr(out.get("kappa")), _ptr(out.get("g1")),
+                                      _ptr(out.get("g2")), _ptr(counts), flags, _stream()))
     return out
 
 

@@ -29,8 +29,10 @@ EXPORTED = [
     "glm_interp_round_workspace_bytes", "glm_interp_init", "glm_refine_interp_round",
     "glm_shoot_indexed_workspace_bytes", "glm_shoot_indexed", "glm_shoot_potential", "glm_shoot_direct_nfw",
     "glm_knn_workspace_bytes", "glm_knn", "glm_interp_estimate", "glm_tree_workspace_bytes",
-    "glm_tree_required_bytes", "glm_adjoint_workspace_bytes",
+    "glm_tree_required_bytes", "glm_adjoint_workspace_bytes", "glm_shoot_noalloc",
 ]
+
+GLM_NOALLOC_MAX_RAYS = 1048576
 
 
 class GlmParams(ctypes.Structure):
@@ -94,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.glm_shoot_workspace_bytes.restype = st
     lib.glm_shoot.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp]
     lib.glm_shoot.restype = st
+    lib.glm_shoot_noalloc.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, u32, vp]
+    lib.glm_shoot_noalloc.restype = st
     lib.glm_shoot_direct.argtypes = [vp, vp, vp, vp, i64, ctypes.c_double, vp, vp, i64, i32, P(vp), vp]
     lib.glm_shoot_direct.restype = st
     lib.glm_shoot_direct_nfw.argtypes = [vp, vp, vp, vp, i64, ctypes.c_double, vp, vp, i64, i32, P(vp), vp]

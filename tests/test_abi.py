@@ -115,6 +115,18 @@ def test_tree_workspace_bound(lib):
     lib.glm_tree_destroy(h)
 
 
+def test_noalloc_scratch_holds_the_largest_ray_set(lib):
+    """glm_shoot_noalloc's static ray workspace (128 MiB) holds the workspace
+    glm_shoot needs for GLM_NOALLOC_MAX_RAYS rays."""
+    from paper_1312_1128_amd import _capi
+
+    b = ctypes.c_size_t()
+    assert lib.glm_shoot_workspace_bytes(_capi.GLM_NOALLOC_MAX_RAYS, ctypes.byref(b)) == 0
+    assert b.value <= 128 << 20
+    text = open(os.path.join(ROOT, "include", "glamer.h")).read()
+    assert f"#define GLM_NOALLOC_MAX_RAYS {_capi.GLM_NOALLOC_MAX_RAYS}" in text
+
+
 def test_binding_fails_loudly_without_library(tmp_path):
     from paper_1312_1128_amd import _capi
 
