@@ -51,6 +51,9 @@ typedef enum {
     GLM_EDATA = -5   /* input values rejected (NaN/Inf, negative mass or smoothing) */
 } glm_status;
 
+/* int32 counts per ray written by glm_shoot and glm_shoot_noalloc */
+#define GLM_COUNTS 8
+
 /* flags */
 #define GLM_ALPHA_ONLY 1u   /* skip kappa and gamma (Sec. 3.2: the solver's option) */
 #define GLM_FP32_ALPHA 2u   /* alpha terms summed in plain FP32, not FP64 (debug) */
@@ -219,9 +222,16 @@ GLM_API glm_status glm_shoot_workspace_bytes(int64_t nrays, size_t* bytes);
  * Forward tree walk (Sec. 3.2) for nrays rays at (rx[i], ry[i]) (device FP64).
  * Outputs (device FP32, length nrays, input order): a1, a2, kappa, g1, g2.
  * kappa, g1, g2 may be NULL when the tree was built with GLM_ALPHA_ONLY or
- * `flags` carries it.  counts (device int32, 4 per ray, nullable) receives per
- * ray: boxes visited (opening tests), boxes accepted, leaf particles summed,
- * list particles the ray falls inside.  The walk evaluates its terms in FP32
+ * `flags` carries it.  counts (device int32, GLM_COUNTS = 8 per ray, nullable)
+ * receives per ray: boxes visited (opening tests), boxes accepted, leaf
+ * particles summed, list particles the ray falls inside; then four counts of
+ * the wavefront that walked the ray's 64-ray group (summed over the box
+ * ranges of a split walk): big-particle list entries tested against the
+ * group's bounding box (the list search), boxes some ray of the group
+ * accepted, leaf particles evaluated, list candidates evaluated.  The per-ray
+ * counts over the wavefront counts give each phase's lane use.  A box's list
+ * is tested 64 entries at a time, and not at all when the bounding box of its
+ * particles' supports misses the group.  The walk evaluates its terms in FP32
  * and sums alpha and gamma in FP64; ray-particle and ray-box offsets and every
  * accept/inside decision are taken in FP64.
  *   workspace: device buffer of at least glm_shoot_workspace_bytes(nrays)

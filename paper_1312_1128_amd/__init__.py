@@ -151,7 +151,9 @@ class Tree:
 def shoot(tree: Tree, rx, ry, counts: bool = False, alpha_only: bool = False, fp32_alpha: bool = False,
           ordered: bool = False, out=None, workspace=None):
     """Forward walk: returns a dict of float32 tensors a1, a2 (and kappa, g1, g2
-    unless alpha_only), plus counts [R, 4] int32 if requested."""
+    unless alpha_only), plus counts [R, 8] int32 if requested: per ray boxes
+    visited, accepted, leaf particles, list hits; per wavefront list entries
+    tested, boxes accepted, leaf particles and list candidates evaluated."""
     rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
     R = rx.shape[0]
     dev = rx.device
@@ -160,7 +162,7 @@ def shoot(tree: Tree, rx, ry, counts: bool = False, alpha_only: bool = False, fp
     if out is None:
         names = ["a1", "a2"] if alpha_only else ["a1", "a2", "kappa", "g1", "g2"]
         out = {k: torch.empty(R, dtype=torch.float32, device=dev) for k in names}
-    cnt = torch.empty((R, 4), dtype=torch.int32, device=dev) if counts else None
+    cnt = torch.empty((R, _capi.GLM_COUNTS), dtype=torch.int32, device=dev) if counts else None
     if workspace is None:
         workspace = torch.empty(max(workspace_bytes(R), 1), dtype=torch.uint8, device=dev)
     ws_bytes = workspace.numel() if workspace is not None else 0
@@ -177,7 +179,7 @@ def shoot_noalloc(tree: Tree, rx, ry, out, counts=None, alpha_only: bool = False
     """glm_shoot_noalloc: the forward walk with the library's static ray
     workspace (no device allocation in the call; at most GLM_NOALLOC_MAX_RAYS
     rays).  out: dict of float32 tensors a1, a2 (kappa, g1, g2 unless
-    alpha_only); counts: int32 [R, 4] tensor or None."""
+    alpha_only); counts: int32 [R, 8] tensor or None."""
     rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
     flags = (GLM_ALPHA_ONLY if alpha_only else 0) | (GLM_RAYS_ORDERED if ordered else 0)
     lib = _capi.load()

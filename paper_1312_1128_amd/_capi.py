@@ -33,6 +33,7 @@ EXPORTED = [
 ]
 
 GLM_NOALLOC_MAX_RAYS = 1048576
+GLM_COUNTS = 8  # int32 counts per ray (glm_shoot)
 
 
 class GlmParams(ctypes.Structure):

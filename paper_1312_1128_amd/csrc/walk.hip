@@ -36,14 +36,14 @@ struct WalkMode {
 };
 
 template <int P, bool AONLY, int MODE, bool PSI = false, int KIND = kKindGauss>
-__device__ inline void walk_group(const TreeDev& T, double X, double Y, bool valid, int lane, Acc& A, int cnt[4],
+__device__ inline void walk_group(const TreeDev& T, double X, double Y, bool valid, int lane, Acc& A, int cnt[kCounts],
                                   int c0, int c1)
 {
     constexpr bool F64A = WalkMode<MODE>::f64a;
     constexpr bool STATS = WalkMode<MODE>::stats;
     const double gx0 = wave_min(valid ? X : INFINITY), gx1 = wave_max(valid ? X : -INFINITY);
     const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
-    int n_vis = 0, n_acc = 0, n_dir = 0, n_hit = 0;
+    int n_vis = 0, n_acc = 0, n_dir = 0, n_hit = 0, n_scan = 0, w_acc = 0, w_dir = 0, w_cand = 0;
     int skip = valid ? 0 : 0x7fffffff;
     if (c0 > 0) skip = ancestor_skip(T, X, Y, c0, skip);
     int cur = c0;
@@ -55,6 +55,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
         if ((h.info & kInfoList) && list_reaches(T, cur, gx0, gx1, gy0, gy1)) {
             const CellExt e = T.ext[cur];
             for (int base = e.lbeg; base < e.lend; base += kWave) {
+                if constexpr (STATS) n_scan += (base + kWave < e.lend ? kWave : e.lend - base);
                 const int j = base + lane;
                 bool cand = false;
                 if (j < e.lend) {
@@ -64,6 +65,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                     cand = dx * dx + dy * dy < pr.qs2 * (1.0 + 1e-9);
                 }
                 uint64_t cm = __ballot(cand);
+                if constexpr (STATS) w_cand += __popcll(cm);
                 while (cm) {
                     const int k = __ffsll((unsigned long long)cm) - 1;
                     cm &= cm - 1;
@@ -78,6 +80,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
         const bool opn = act && !acc;
         if constexpr (STATS) n_acc += acc;
         if (__any(acc)) {
+            if constexpr (STATS) ++w_acc;
             if (acc) eval_box<P, AONLY, F64A, PSI>(T.mom + (size_t)cur * mom_stride(P), w1, w2, A);
         }
         if (h.info & kInfoLeaf) {
@@ -85,6 +88,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
                 const CellExt e = T.ext[cur];
                 if constexpr (STATS) {
                     if (opn) n_dir += e.pend - e.pbeg;
+                    w_dir += e.pend - e.pbeg;
                 }
                 for (int j = e.pbeg; j < e.pend; ++j) {
                     const PRec pr = T.prt[j];
@@ -103,10 +107,14 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
     cnt[1] = n_acc;
     cnt[2] = n_dir;
     cnt[3] = n_hit;
+    cnt[4] = n_scan;
+    cnt[5] = w_acc;
+    cnt[6] = w_dir;
+    cnt[7] = w_cand;
 }
 
 template <bool AONLY, bool STATS, bool PSI = false>
-__device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, const WalkOut& out)
+__device__ inline void write_out(const Acc& A, const int cnt[kCounts], int64_t o, const WalkOut& out)
 {
     const double a1 = alpha1(A), a2 = alpha2(A);
     out.a1[o] = (float)a1;
@@ -120,12 +128,8 @@ __device__ inline void write_out(const Acc& A, const int cnt[4], int64_t o, cons
         if (out.g1) out.g1[o] = (float)A.g1;
         if (out.g2) out.g2[o] = (float)A.g2;
     }
-    if (STATS && out.counts) {
-        out.counts[4 * o + 0] = cnt[0];
-        out.counts[4 * o + 1] = cnt[1];
-        out.counts[4 * o + 2] = cnt[2];
-        out.counts[4 * o + 3] = cnt[3];
-    }
+    if (STATS && out.counts)
+        for (int i = 0; i < kCounts; ++i) out.counts[kCounts * o + i] = cnt[i];
 }
 
 template <int P, bool AONLY, int MODE, bool PSI = false, int KIND = kKindGauss>
@@ -159,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __rest
         c1 = nc;
     }
     Acc A = {};
-    int cnt[4];
+    int cnt[kCounts];
     walk_group<P, AONLY, MODE, PSI, KIND>(T, X, Y, valid, lane, A, cnt, c0, c1);
     if (!valid) return;
     if (K == 1) {
@@ -170,10 +174,9 @@ __global__ __launch_bounds__(kBlock) void k_walk(TreeDev T, const double* __rest
     q.a1 = alpha1(A);
     q.a2 = alpha2(A);
     q.k = A.k;
-    q.pad = 0.0f;
     q.g1 = A.g1;
     q.g2 = A.g2;
-    for (int i = 0; i < 4; ++i) q.cnt[i] = WalkMode<MODE>::stats ? cnt[i] : 0;
+    for (int i = 0; i < kCounts; ++i) q.cnt[i] = WalkMode<MODE>::stats ? cnt[i] : 0;
     parts[(int64_t)k * nrays + r] = q;
 }
 
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_merge(const Partial* __restrict
     if (r >= nrays) return;
     double a1 = 0.0, a2 = 0.0, g1 = 0.0, g2 = 0.0;
     float ka = 0.0f;
-    int c[4] = {0, 0, 0, 0};
+    int c[kCounts] = {};
     for (int k = 0; k < K; ++k) {
         const Partial& q = parts[(int64_t)k * nrays + r];
         a1 += q.a1;
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_merge(const Partial* __restrict
         ka += q.k;
         g1 += q.g1;
         g2 += q.g2;
-        for (int i = 0; i < 4; ++i) c[i] += q.cnt[i];
+        for (int i = 0; i < kCounts; ++i) c[i] += q.cnt[i];
     }
     const int64_t o = rperm ? (int64_t)rperm[r] : r;
     out.a1[o] = (float)a1;
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_merge(const Partial* __restrict
         if (out.g2) out.g2[o] = (float)g2;
     }
     if (out.counts)
-        for (int i = 0; i < 4; ++i) out.counts[4 * o + i] = c[i];
+        for (int i = 0; i < kCounts; ++i) out.counts[kCounts * o + i] = c[i];
 }
 
 // Persistent walk over many lenses: every wavefront takes (lens, 64-ray group)
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_batched(const BatchLens* __rest
         const int64_t gi = L.ray_off + (valid ? rl : 0);
         const double X = valid ? xs[gi] : 0.0, Y = valid ? ys[gi] : 0.0;
         Acc A = {};
-        int cnt[4];
+        int cnt[kCounts];
         walk_group<P, AONLY, MODE, false, KIND>(L.tree, X, Y, valid, lane, A, cnt, 0, L.tree.ncells);
         if (valid) write_out<AONLY, false>(A, cnt, (int64_t)perm[gi] - L.ray_off, L.out);
     }

@@ -91,12 +91,23 @@ inline int64_t split_slots(int64_t nrays)
     return 64 * (kMaxSplit * groups < cap ? kMaxSplit * groups : cap);
 }
 
-// Partial sums of one ray over one range of boxes (merged by k_walk_merge).
-struct alignas(16) Partial {
+// Per-ray counts of a walk: boxes visited (opening tests), boxes accepted,
+// leaf particles summed, list particles the ray falls inside; then counts of
+// its wavefront (the same for the 64 rays of a group): list entries tested
+// against the ray group (the search overhead), boxes some lane accepted, leaf
+// particles evaluated, list candidates evaluated.  The per-lane counts over the
+// wavefront's give the lane use of each phase.
+constexpr int kCounts = 8;
+
+// Partial sums of one ray over one range of boxes (merged by k_walk_merge);
+// 72 bytes, so that the largest partial-sum region (20480 groups x 64 rays)
+// stays at 94 MB.
+struct alignas(8) Partial {
     double a1, a2, g1, g2;
-    float k, pad;
-    int32_t cnt[4];
+    float k;
+    int32_t cnt[kCounts];
 };
+static_assert(sizeof(Partial) == 72, "partial-sum record size");
 
 // Byte offsets of the ray workspace pieces.
 struct RayLayout {

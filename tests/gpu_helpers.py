@@ -22,16 +22,20 @@ def build(lens, theta, leaf, order, flags=0):
                           leaf_size=leaf, order=order, flags=flags)
 
 
-def shoot(tree, rx, ry, counts=False, **kw):
+def shoot(tree, rx, ry, counts=False, all_counts=False, **kw):
+    """The walk's outputs as an [R, 5] array; with counts, also the per-ray
+    decision counts [R, 4] (boxes visited, accepted, leaf particles, list hits),
+    or all eight counts with all_counts."""
     import paper_1312_1128_amd as g
     import torch
 
-    out = g.shoot(tree, dev(rx), dev(ry), counts=counts, **kw)
+    out = g.shoot(tree, dev(rx), dev(ry), counts=counts or all_counts, **kw)
     torch.cuda.synchronize()
     names = [k for k in ["a1", "a2", "kappa", "g1", "g2"] if k in out]
     res = np.stack([out[k].double().cpu().numpy() for k in names], axis=1)
-    if counts:
-        return res, out["counts"].cpu().numpy()
+    if counts or all_counts:
+        c = out["counts"].cpu().numpy()
+        return res, (c if all_counts else c[:, :4])
     return res
 
 

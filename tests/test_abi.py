@@ -125,6 +125,7 @@ def test_noalloc_scratch_holds_the_largest_ray_set(lib):
     assert b.value <= 128 << 20
     text = open(os.path.join(ROOT, "include", "glamer.h")).read()
     assert f"#define GLM_NOALLOC_MAX_RAYS {_capi.GLM_NOALLOC_MAX_RAYS}" in text
+    assert f"#define GLM_COUNTS {_capi.GLM_COUNTS}" in text
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -327,3 +327,42 @@ def test_caller_workspace_contract(ora):
     np.testing.assert_array_equal(shoot(t2, rx, ry), ref)
     np.testing.assert_array_equal(shoot(tree, rx, ry), ref)
     np.testing.assert_allclose(shoot(t3, rx, ry), a3, rtol=1e-6, atol=1e-7 * np.abs(a3).max())
+
+
+def test_wavefront_counts_and_list_search(ora):
+    """The four wavefront counts (list entries tested, boxes accepted, leaf
+    particles and list candidates evaluated) are shared by the 64 rays of a
+    group and bound the per-ray counts: every list hit was a tested entry and
+    an evaluated candidate, every accepted box and leaf particle of a ray was
+    evaluated by its wavefront.  On the 1e6-particle halo the lists whose
+    support bounds miss the group are skipped whole, so far fewer entries are
+    tested than a per-ray scan of every visited box's list (oracle B's count)."""
+    lens, gx, gy = synth.workload_nfw()
+    say("[gpu] wavefront counts and list search")
+    tree = build(lens, 0.3, 16, 8)
+    # a 256 x 256 block of the grid near the centre, listed in 8 x 8 tiles (one group per tile)
+    n = 2048
+    i0 = n // 2 - 128
+    ti, tj = np.meshgrid(np.arange(32), np.arange(32), indexing="ij")
+    ii, jj = np.meshgrid(np.arange(8), np.arange(8), indexing="ij")
+    gi = (i0 + 8 * ti.reshape(-1, 1) + ii.reshape(1, -1)).ravel()
+    gj = (i0 + 8 * tj.reshape(-1, 1) + jj.reshape(1, -1)).ravel()
+    rx = -0.5 + (gi + 0.5) / n
+    ry = -0.5 + (gj + 0.5) / n
+    _, c = shoot(tree, rx, ry, all_counts=True, ordered=True)
+    grp = c.reshape(-1, 64, 8)
+    for k in range(4, 8):
+        assert np.all(grp[:, :, k] == grp[:, :1, k]), k  # one value per group
+    assert np.all(c[:, 4] >= c[:, 3]) and np.all(c[:, 7] >= grp[:, :, 3].max(1).repeat(64))
+    assert np.all(c[:, 5] >= grp[:, :, 1].max(1).repeat(64))
+    assert np.all(c[:, 6] >= grp[:, :, 2].max(1).repeat(64))
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.3, 16, 8)
+    _, rc = T.shoot(rx, ry, counts=True)
+    np.testing.assert_array_equal(c[:, :4], rc[:, [0, 1, 2, 4]])
+    lane_use = [c[:, 1].sum() / (64 * grp[:, 0, 5].sum()), c[:, 2].sum() / (64 * grp[:, 0, 6].sum()),
+                c[:, 3].sum() / (64 * grp[:, 0, 7].sum())]
+    say(f"  per ray: list entries tested {c[:, 4].mean():.0f} (a per-ray scan of every visited list: "
+        f"{rc[:, 3].mean():.0f}), hits {c[:, 3].mean():.0f}; lane use accepted {lane_use[0]:.2f} leaf "
+        f"{lane_use[1]:.2f} list {lane_use[2]:.2f}")
+    assert c[:, 4].mean() < 0.5 * rc[:, 3].mean()
+    assert all(0.3 < u <= 1.0 for u in lane_use)

@@ -26,7 +26,7 @@ def test_noalloc_matches_shoot_on_shrinking_calls():
         say(f"[gpu] noalloc walk, {nr} rays")
         rx, ry = dev(big_x[:nr]), dev(big_y[:nr])
         out = {k: torch.full((nr,), float("nan"), dtype=torch.float32, device="cuda") for k in NAMES}
-        cnt = torch.full((nr, 4), -1, dtype=torch.int32, device="cuda")
+        cnt = torch.full((nr, _capi.GLM_COUNTS), -1, dtype=torch.int32, device="cuda")
         g.shoot_noalloc(tree, rx, ry, out, counts=cnt)
         ref = g.shoot(tree, rx, ry, counts=True)
         torch.cuda.synchronize()
