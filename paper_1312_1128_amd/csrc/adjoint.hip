@@ -10,7 +10,10 @@
 //   dL/ds_i = ga . d alpha_i / d s_i = -m (ga . d) e^-u / (s^3 C) inside.
 // An accepted box contributes F = alpha1 - i alpha2 = sum_k Q_k w^-(k+1), so
 // with g_hat = ga1 + i ga2 the walk accumulates per box
-//   Abar_k r_cm^k = sum_r g_hat v t^k   (v = 1/w, t = r_cm v)
+//   Abar_k r_cm^k = sum_r g_hat v t^k   (v = 1/w, t = r_cm v), k = 0 .. P + 1,
+// and the centre-of-mass adjoint sum_r g_hat dF/dz_cm = sum_{k <= P} (k + 1) Q_k Abar_{k+1}
+// follows from them in the push-down.  With kappa and gamma cotangents the
+// walk keeps Abar_0 .. Abar_P and accumulates that adjoint directly:
 //   Bbar          = sum_r g_hat M v^2 (P(t) + t P'(t))     (= g_hat dF/dz_cm)
 // A gamma cotangent adds, with gg_hat = gg1 + i gg2 (gamma1 - i gamma2 = F'(w)),
 //   Abar_k r_cm^k -= (k + 1) gg_hat v^2 t^k,   Bbar -= gg_hat F''(w) = gg_hat M v^3 T(t),
@@ -200,46 +203,93 @@ __device__ inline int nth_set_bit(uint64_t m, int c)
     return pos;
 }
 
+// Orders this wavefront's LDS accesses around a hand-over between its lanes
+// (LDS operations of one wavefront complete in program order).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The rays of a wavefront that take part in a particle pass, packed in the
+// wavefront's LDS slice: ray slot s (s < popcount(rays)) is the s-th set bit.
+struct RayTable {
+    double* x;
+    double* y;
+    float2* g;   // alpha cotangent
+    float* k;    // kappa cotangent
+    float2* h;   // gamma cotangent
+};
+
+__device__ inline RayTable ray_table(float* lds)
+{
+    RayTable t;
+    t.x = reinterpret_cast<double*>(lds);
+    t.y = t.x + kWave;
+    t.g = reinterpret_cast<float2*>(t.y + kWave);
+    t.k = reinterpret_cast<float*>(t.g + kWave);
+    t.h = reinterpret_cast<float2*>(t.k + kWave);
+    return t;
+}
+constexpr int kRayTableFloats = 2 * 2 * kWave + 2 * kWave + kWave + 2 * kWave; // 2304 bytes
+
 // Gradient terms of the particles selected by `sel` (bit k: record rec[k])
 // for the rays of the wavefront whose bit is set in `rays`, summed over those
 // rays into the particles' four FP64 accumulators (m, x, y, s) at
-// pg + 4 * (Morton position).  Lanes hold (particle, ray group) pairs rather
-// than rays: a pass takes up to 32 particles, splits the 64 rays into
-// G = 64 / count groups, and each lane sums its particle's terms over its
-// group's rays one after another (the rays' data arrive by lane shuffles);
-// the G partial sums then meet in the lanes of group 0, which add them with
-// one atomic instruction per accumulator.  This replaces a wavefront sum per
-// particle and ray set with a few shuffles per (particle, ray) pair.
+// pg + 4 * (Morton position).  Lanes hold (particle, ray slot) pairs rather
+// than rays: the taking-part rays are first packed into the wavefront's LDS
+// slice (their positions and cotangents), then a pass takes up to 32
+// particles, splits the lanes into G = 64 / count groups, and each lane sums
+// its particle's terms over the ray slots g, g + G, ... of the packed table
+// (so no pass is spent on rays that do not take part); the G partial sums
+// then meet in the lanes of group 0, which add them with one atomic
+// instruction per accumulator.
 template <bool KG, int KIND>
 __device__ inline void particles_grad(const PRec* __restrict__ rec, uint64_t sel, int mode, uint64_t rays, double X,
-                                      double Y, const Cot& cg, float invC, double* __restrict__ pg, int lane)
+                                      double Y, const Cot& cg, float invC, double* __restrict__ pg, int lane,
+                                      float* lds)
 {
+    const RayTable tab = ray_table(lds);
+    const int nr = __popcll(rays);
+    if ((rays >> lane) & 1ull) {
+        const int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(rays >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)rays, 0u));
+        tab.x[slot] = X;
+        tab.y[slot] = Y;
+        tab.g[slot] = make_float2(cg.g1, cg.g2);
+        if constexpr (KG) {
+            tab.k[slot] = cg.k;
+            tab.h[slot] = make_float2(cg.h1, cg.h2);
+        }
+    }
+    wave_lds_sync();
     while (sel) {
         const int total = __popcll(sel);
         const int C = total < 32 ? total : 32; // particles in this pass
         const int G = kWave / C;               // ray groups (>= 2)
-        const int its = (kWave + G - 1) / G;   // rays per group
+        const int its = (nr + G - 1) / G;      // ray slots per group
         const int c = lane % C, g = lane / C;
         const PRec pr = rec[nth_set_bit(sel, c)];
         double A[4] = {0.0, 0.0, 0.0, 0.0};
         for (int t = 0; t < its; ++t) {
-            const int r = g * its + t;
-            const bool act = g < G && r < kWave && ((rays >> (r & (kWave - 1))) & 1ull);
-            if (!__any(act)) continue;
-            const int rs = act ? r : 0;
+            const int s = g + G * t;
+            const bool act = g < G && s < nr;
+            const int ss = act ? s : 0;
             Cot cr;
-            cr.g1 = __shfl(cg.g1, rs, kWave);
-            cr.g2 = __shfl(cg.g2, rs, kWave);
+            const float2 gg = tab.g[ss];
+            cr.g1 = gg.x;
+            cr.g2 = gg.y;
             if constexpr (KG) {
-                cr.k = __shfl(cg.k, rs, kWave);
-                cr.h1 = __shfl(cg.h1, rs, kWave);
-                cr.h2 = __shfl(cg.h2, rs, kWave);
+                cr.k = tab.k[ss];
+                const float2 hh = tab.h[ss];
+                cr.h1 = hh.x;
+                cr.h2 = hh.y;
             } else {
                 cr.k = cr.h1 = cr.h2 = 0.0f;
             }
-            const double Xr = __shfl(X, rs, kWave), Yr = __shfl(Y, rs, kWave);
             double Gt[4];
-            particle_grad<KG, KIND>(pr, Xr, Yr, mode, act, cr, invC, Gt);
+            particle_grad<KG, KIND>(pr, tab.x[ss], tab.y[ss], mode, act, cr, invC, Gt);
             A[0] += Gt[0];
             A[1] += Gt[1];
             A[2] += Gt[2];
@@ -261,15 +311,7 @@ __device__ inline void particles_grad(const PRec* __restrict__ rec, uint64_t sel
         }
         for (int q = 0; q < C; ++q) sel &= sel - 1; // drop this pass's particles
     }
-}
-
-// Orders this wavefront's LDS accesses around a hand-over between its lanes
-// (LDS operations of one wavefront complete in program order).
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync(); // the slice is written again by the next user
 }
 
 // Totals over the wavefront of NA per-lane words, returned in lane k for word
@@ -314,13 +356,16 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                                                         CotIn ci, double* __restrict__ pg, double* __restrict__ abar,
                                                         int K, const int* __restrict__ split_box)
 {
-    constexpr int NA = 2 * (P + 1) + 2; // (Re, Im) of Abar_0..Abar_P, Bbar
-    __shared__ float red_all[(kBlock / kWave) * kWave * NA]; // per wavefront: the box words of its 64 lanes
+    // (Re, Im) of Abar_0 .. Abar_{P+1}, or with KG of Abar_0 .. Abar_P and Bbar
+    constexpr int NA = 2 * (P + 1) + 2;
+    // per wavefront: the box words of its 64 lanes, or the packed ray table of a particle pass
+    constexpr int kSlice = kWave * NA > kRayTableFloats ? kWave * NA : kRayTableFloats;
+    __shared__ __align__(16) float red_all[(kBlock / kWave) * kSlice];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t groups = (nrays + kWave - 1) / kWave;
     // wave-uniform work item (kept in SGPRs): box range kr, ray group grp
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    float* red = red_all + (size_t)w * kWave * NA;
+    float* red = red_all + (size_t)w * kSlice;
     int kr;
     int64_t grp;
     if (!walk_task(blockIdx.x, w, groups, K, &kr, &grp)) return;
@@ -373,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                     cand = dxb * dxb + dyb * dyb < pr.qs2 * (1.0 + 1e-9);
                 }
                 const uint64_t cm = __ballot(cand);
-                if (cm) particles_grad<KG, KIND>(T.lst + base, cm, 1, __ballot(act), X, Y, cg, invC, pg, lane);
+                if (cm) particles_grad<KG, KIND>(T.lst + base, cm, 1, __ballot(act), X, Y, cg, invC, pg, lane, red);
             }
         }
         double w1, w2;
@@ -385,7 +430,27 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
             float a[NA];
 #pragma unroll
             for (int k = 0; k < NA; ++k) a[k] = 0.0f;
-            if (acc) {
+            if constexpr (!KG) {
+                // alpha cotangents only: the words are g_hat v t^k for k = 0 .. P + 1; the
+                // centre-of-mass adjoint sum_k (k + 1) Q_k Abar_{k+1} is formed from them
+                // in the push-down
+                if (acc) {
+                    const float rcm = T.mom[(size_t)cur * mom_stride(P) + 1];
+                    const float f1 = (float)w1, f2 = (float)w2;
+                    const float inv = __builtin_amdgcn_rcpf(f1 * f1 + f2 * f2);
+                    const float v1 = f1 * inv, v2 = -f2 * inv;
+                    const float t1 = rcm * v1, t2 = rcm * v2;
+                    float p1 = fmaf(g1, v1, -g2 * v2), p2 = fmaf(g1, v2, g2 * v1);
+#pragma unroll
+                    for (int k = 0; k <= P + 1; ++k) {
+                        a[2 * k] = p1;
+                        a[2 * k + 1] = p2;
+                        const float n1 = fmaf(p1, t1, -p2 * t2), n2 = fmaf(p1, t2, p2 * t1);
+                        p1 = n1;
+                        p2 = n2;
+                    }
+                }
+            } else if (acc) {
                 const float* mo = T.mom + (size_t)cur * mom_stride(P);
                 const float M = mo[0], rcm = mo[1];
                 const float f1 = (float)w1, f2 = (float)w2;
@@ -429,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 const float V1 = fmaf(w21, S1, -w22 * S2), V2 = fmaf(w21, S2, w22 * S1);
                 a[NA - 2] = g1 * V1 - g2 * V2;
                 a[NA - 1] = g1 * V2 + g2 * V1;
-                if constexpr (KG) {
+                {
                     // gamma: Abar_k r_cm^k -= (k+1) gg v^2 t^k, Bbar -= gg M v^3 T(t)
                     const float h1 = cg.h1, h2 = cg.h2;
                     float q1 = fmaf(h1, w21, -h2 * w22), q2 = fmaf(h1, w22, h2 * w21); // gg v^2
@@ -469,7 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 for (int j = e.pbeg; j < e.pend; j += kWave) { // a leaf at the depth cap may exceed 64
                     const int np = e.pend - j < kWave ? e.pend - j : kWave;
                     const uint64_t sel = np == kWave ? ~0ull : ((1ull << np) - 1);
-                    particles_grad<KG, KIND>(T.prt + j, sel, 0, rays, X, Y, cg, invC, pg, lane);
+                    particles_grad<KG, KIND>(T.prt + j, sel, 0, rays, X, Y, cg, invC, pg, lane, red);
                 }
             }
             cur = cur + 1;
@@ -483,8 +548,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
 }
 
 // Box adjoints -> particles.  One thread per particle walks its ancestors,
-// then adds the direct-term gradients the walk gathered.
-template <int P>
+// then adds the direct-term gradients the walk gathered.  Without kappa and
+// gamma cotangents (KG false) a box holds Abar_0 .. Abar_{P+1} (scaled by
+// r_cm^k) and its centre-of-mass adjoint is Bbar = sum_{k <= P} (k + 1) Q_k Abar_{k+1}
+// (dF/dz_cm = sum (k + 1) Q_k w^-(k+2)), formed here in FP64; with them the
+// walk accumulated Bbar itself in the last two words.
+template <int P, bool KG>
 __global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __restrict__ ms,
                                                     const double* __restrict__ abar, const double* __restrict__ pg,
                                                     double* __restrict__ dm, double* __restrict__ dx,
@@ -509,6 +578,22 @@ __global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __
             const double rcm = (double)T.mom[(size_t)c * mom_stride(P) + 1];
             const double* Q = T.cq + (size_t)c * (P + 1) * 2;
             const double dr = pr.x - h.cx, di = pr.y - h.cy;
+            double Br, Bi;
+            if constexpr (KG) {
+                Br = ab[NA - 2];
+                Bi = ab[NA - 1];
+            } else {
+                Br = Bi = 0.0;
+                double irk = 1.0 / rcm; // r_cm^-(k+1)
+                const double irc = irk;
+                for (int kk = 0; kk <= P; ++kk) {
+                    const double Ar = ab[2 * (kk + 1)] * irk, Ai = ab[2 * (kk + 1) + 1] * irk;
+                    const double qr = Q[2 * kk], qi = Q[2 * kk + 1];
+                    Br += (kk + 1) * (qr * Ar - qi * Ai);
+                    Bi += (kk + 1) * (qr * Ai + qi * Ar);
+                    irk *= irc;
+                }
+            }
             // sm = sum_k Abar_k dQ_k/dm + Bbar d/M ; sz = sum_k Abar_k dQ_k/dz + Bbar m/M
             double smr = 0.0, smi = 0.0, szr = 0.0, szi = 0.0;
             double dkr = 1.0, dki = 0.0, dkm1r = 0.0, dkm1i = 0.0; // d^k, d^(k-1)
@@ -538,7 +623,6 @@ __global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __
                 irk *= irc;
             }
             if (M > 0.0) {
-                const double Br = ab[NA - 2], Bi = ab[NA - 1];
                 smr += (Br * dr - Bi * di) / M;
                 smi += (Br * di + Bi * dr) / M;
                 szr += Br * mi / M;
@@ -598,8 +682,12 @@ glm_status launch_adjoint(const TreeStorage& ts, const StagedRays& sr, int64_t n
         else GLM_ADJ(false, kKindGauss);
     }
 #undef GLM_ADJ
-    hipLaunchKernelGGL((k_pushdown<P>), dim3(ceil_div(ts.n, kBlock)), dim3(kBlock), 0, st, ts.dev, ts.ms, abar, pg, dm,
-                       dx, dy, ds);
+    if (kg)
+        hipLaunchKernelGGL((k_pushdown<P, true>), dim3(ceil_div(ts.n, kBlock)), dim3(kBlock), 0, st, ts.dev, ts.ms, abar,
+                           pg, dm, dx, dy, ds);
+    else
+        hipLaunchKernelGGL((k_pushdown<P, false>), dim3(ceil_div(ts.n, kBlock)), dim3(kBlock), 0, st, ts.dev, ts.ms,
+                           abar, pg, dm, dx, dy, ds);
     GLM_HIP(hipGetLastError());
     return GLM_OK;
 }
