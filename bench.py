@@ -16,8 +16,11 @@ Printed as one JSON line, with:
   roofline     -- the walk kernel alone, timed with HIP events on the stream it
                   runs on; algorithmic FLOPs from its own per-ray interaction
                   counts times fixed per-interaction weights;
+  fwd_adjoint  -- the same particles and grid with the fitting loss: build +
+                  alpha walk + adjoint walk, and the adjoint call's roofline;
   cpu_baseline -- the FP64 brute-force oracle on a bounded ray sample on the
-                  host cores (also yields the sample's error vs FP64);
+                  host cores, on all threads and on one (also yields the
+                  sample's error vs FP64), and the FP64 reference tree;
   extras       -- build time, walk-only rate, plain GPU direct sum rates, and
                   the fitting (forward + adjoint), refinement and 64-lens
                   workloads (--no-extras leaves these out).
@@ -51,6 +54,15 @@ def flops_per_ray(counts: np.ndarray, p: int) -> np.ndarray:
     return 5.0 * counts[:, 0] + (20.0 + 16.0 * p) * counts[:, 1] + 22.0 * counts[:, 2] + 60.0 * counts[:, 3]
 
 
+# algorithmic FLOPs per interaction of the adjoint walk (FMA = 2): opening
+# test; accepted box at order p (1/w and t = r_cm / w: 7, g v: 6, g v t^k for
+# k <= p + 1: 6 (p + 1), one add per box-adjoint word per ray for the sum over
+# the rays: 2 p + 4); leaf particle (point-mass gradient of alpha and its four
+# FP64 sums); big-particle correction (profile minus point gradient)
+def adjoint_flops_per_ray(counts: np.ndarray, p: int) -> np.ndarray:
+    return 5.0 * counts[:, 0] + (23.0 + 8.0 * p) * counts[:, 1] + 38.0 * counts[:, 2] + 90.0 * counts[:, 3]
+
+
 WALK_SOURCES = ["walk.hip", "walk.hpp", "eval.hpp", "common.hpp"]
 HBM_PROFILE = os.path.join(ROOT, "profiles", "k_walk_nfw1e6_grid2048_hbm.txt")
 
@@ -80,8 +92,42 @@ def measured_traffic():
         return None
 
 
+SQ_PROFILE = os.path.join(ROOT, "profiles", "k_walk_nfw1e6_grid2048_sq.txt")
+
+
+def issued_valu(flop: float) -> dict:
+    """Issued VALU lane-operations per walk launch (wavefront instructions x 64,
+    masked lanes included) from the committed counter summary, and the
+    algorithmic FLOPs over them (an FMA counts 2 FLOPs and one lane-operation);
+    empty when there is no summary for the current walk sources."""
+    try:
+        with open(SQ_PROFILE) as fh:
+            kv = dict(l.split(":", 1) for l in fh.read().splitlines() if ":" in l and not l.startswith(" "))
+    except OSError:
+        return {}
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("walk_sources_sha256") != walk_sources_sha256():
+        return {}
+    try:
+        ops = 64.0 * float(kv["valu_insts_per_launch"])
+    except (KeyError, ValueError):
+        return {}
+    return {"issued_valu_lane_ops_per_launch": ops, "algorithmic_flop_over_issued_lane_ops": flop / ops}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_threads() -> int:
@@ -165,8 +211,83 @@ def main():
     cnt = g.shoot(tree, rx, ry, counts=True, ordered=True)["counts"].cpu().numpy().astype(np.float64)
     flop = float(flops_per_ray(cnt, ORDER).sum())
     achieved = flop / (walk_ms * 1e-3) / 1e12
+    # rays in tile order: each wavefront walks 64 consecutive rays, which carry its counts
+    lane_use = {"accepted_boxes": float(cnt[:, 1].sum() / cnt[:, 5].sum()),
+                "leaf_particles": float(cnt[:, 2].sum() / cnt[:, 6].sum()),
+                "list_candidates": float(cnt[:, 3].sum() / cnt[:, 7].sum())}
+    scan_flop = 5.0 * float(cnt[:, 4].sum())  # list-entry distance checks: search overhead, not algorithmic
+    log(f"lane use: {lane_use}; list entries tested per ray {cnt[:, 4].mean():.0f} "
+        f"(search overhead {scan_flop:.3e} FLOP per launch)")
     log(f"walk: {walk_ms:.3f} ms, {flop:.3e} algorithmic FLOP -> {achieved:.2f} TFLOP/s "
         f"({achieved / PEAK_FP32_TFLOPS:.3f} of FP32 peak); counts/ray {cnt.mean(0)}")
+
+    # the tree's error over every ray of the grid, against the library's FP64
+    # direct sum (itself held to 1e-10 of the CPU oracle by the tests)
+    g.shoot(tree, rx, ry, out=out, workspace=ws)
+    full = g.shoot_direct(x, y, m, s, lens.q, rx, ry, fp64=True)
+    ref_a = torch.stack([full["a1"], full["a2"]], 1)
+    ref_g = torch.stack([full["g1"], full["g2"]], 1)
+    e_a = (torch.stack([out["a1"], out["a2"]], 1).double() - ref_a).norm(dim=1) / ref_a.norm(dim=1)
+    e_g = (torch.stack([out["g1"], out["g2"]], 1).double() - ref_g).norm(dim=1) / ref_g.norm(dim=1)
+    e_k = (out["kappa"].double() - full["kappa"]).abs() / full["kappa"].abs()
+    full_err = {"rays": R, "alpha_max": float(e_a.max()), "kappa_max": float(e_k.max()),
+                "gamma_max": float(e_g.max()), "alpha_median": float(e_a.median()),
+                "gamma_median": float(e_g.median())}
+    del ref_a, ref_g, e_a, e_g, e_k
+    log(f"tree vs GPU FP64 direct over all {R} rays: max rel err alpha {full_err['alpha_max']:.2e} "
+        f"kappa {full_err['kappa_max']:.2e} gamma {full_err['gamma_max']:.2e}")
+
+    # forward + adjoint at the headline size: the fitting loss L = sum |x - alpha - beta*|^2
+    # over the 2048^2 grid, beta* = x - alpha_true + N(0, 1e-4) per component (alpha_true:
+    # the FP64 direct sum above); step = build + alpha walk + dL/dalpha + adjoint walk
+    # (dL/d(m, x, y, s) of the 1e6 particles, FP64)
+    noise = synth.rng(synth.BASE_SEED + 14).normal(0.0, 1e-4, size=(2, R))
+    bx = rx - full["a1"] + torch.from_numpy(noise[0]).to(dev)
+    by = ry - full["a2"] + torch.from_numpy(noise[1]).to(dev)
+    del full, noise
+    outa = {k: torch.empty(R, dtype=torch.float32, device=dev) for k in ["a1", "a2"]}
+    grads = [torch.zeros(lens.n, dtype=torch.float64, device=dev) for _ in range(4)]
+    ws_adj = torch.empty(g.adjoint_workspace_bytes(tree, R), dtype=torch.uint8, device=dev)
+
+    def step_fa():
+        tree.build(x, y, m, s, theta=THETA, q=lens.q, leaf_size=LEAF, order=ORDER)
+        g.shoot(tree, rx, ry, out=outa, workspace=ws, alpha_only=True)
+        ga1 = (-2.0 * (rx - outa["a1"] - bx)).float()
+        ga2 = (-2.0 * (ry - outa["a2"] - by)).float()
+        for t_ in grads:
+            t_.zero_()
+        g.shoot_adjoint(tree, rx, ry, ga1, ga2, *grads, workspace=ws_adj)
+        return ga1, ga2
+
+    for _ in range(args.warmup):
+        step_fa()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        ga1, ga2 = step_fa()
+    torch.cuda.synchronize()
+    fa_ms = 1e3 * (time.perf_counter() - t) / args.steps
+    # the adjoint call alone on ordered rays (box-adjoint clear + adjoint walk + push-down)
+    nrep = 5
+    ev0.record(stream)
+    for _ in range(nrep):
+        g.shoot_adjoint(tree, rx, ry, ga1, ga2, *grads, workspace=ws_adj, ordered=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    adj_ms = ev0.elapsed_time(ev1) / nrep
+    adj_flop = float(adjoint_flops_per_ray(cnt, ORDER).sum())
+    adj_tf = adj_flop / (adj_ms * 1e-3) / 1e12
+    log(f"fwd+adjoint (1e6 particles, {R} rays): {fa_ms:.3f} ms -> {R / (fa_ms * 1e-3):.4e} rays/s; adjoint call "
+        f"{adj_ms:.3f} ms, {adj_flop:.3e} algorithmic FLOP -> {adj_tf:.2f} TFLOP/s ({adj_tf / PEAK_FP32_TFLOPS:.3f})")
+    fwd_adjoint = {"value": R / (fa_ms * 1e-3), "unit": "rays/s", "ms_per_step": fa_ms,
+                   "workload": "nfw_1e6_particles_grid2048, L = sum |x - alpha - beta*|^2, "
+                               "beta* = x - alpha_true + N(0, 1e-4)",
+                   "step": "build_tree + shoot (alpha) + dL/dalpha + shoot_adjoint -> dL/d(m, x, y, s)",
+                   "roofline": {"bound": "alu", "kernel": "glm_shoot_adjoint (k_fill_zero + k_adjoint_walk + "
+                                                          "k_pushdown)",
+                                "achieved": adj_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                "frac": adj_tf / PEAK_FP32_TFLOPS, "kernel_ms": adj_ms, "flop_per_launch": adj_flop}}
+    del grads, ws_adj, outa, bx, by, ga1, ga2
 
     extras = {}
     if not args.no_extras:
@@ -181,22 +302,6 @@ def main():
             torch.cuda.synchronize()
             res[fp64] = nd / (time.perf_counter() - t)
         log(f"direct sum: fp32 {res[False]:.3e} rays/s, fp64 {res[True]:.3e} rays/s")
-
-        # the tree's error over every ray of the grid, against the library's FP64
-        # direct sum (itself held to 1e-10 of the CPU oracle by the tests)
-        g.shoot(tree, rx, ry, out=out, workspace=ws)
-        full = g.shoot_direct(x, y, m, s, lens.q, rx, ry, fp64=True)
-        ref_a = torch.stack([full["a1"], full["a2"]], 1)
-        ref_g = torch.stack([full["g1"], full["g2"]], 1)
-        e_a = (torch.stack([out["a1"], out["a2"]], 1).double() - ref_a).norm(dim=1) / ref_a.norm(dim=1)
-        e_g = (torch.stack([out["g1"], out["g2"]], 1).double() - ref_g).norm(dim=1) / ref_g.norm(dim=1)
-        e_k = (out["kappa"].double() - full["kappa"]).abs() / full["kappa"].abs()
-        full_err = {"rays": R, "alpha_max": float(e_a.max()), "kappa_max": float(e_k.max()),
-                    "gamma_max": float(e_g.max()), "alpha_median": float(e_a.median()),
-                    "gamma_median": float(e_g.median())}
-        del full, ref_a, ref_g, e_a, e_g, e_k
-        log(f"tree vs GPU FP64 direct over all {R} rays: max rel err alpha {full_err['alpha_max']:.2e} "
-            f"kappa {full_err['kappa_max']:.2e} gamma {full_err['gamma_max']:.2e}")
 
         # deflection + potential + time delay of the headline grid in one walk
         pot = g.shoot_potential(tree, rx, ry, ordered=True, workspace=ws)
@@ -252,9 +357,9 @@ def main():
         r5x, r5y = synth.uniform_points(100_000, synth.BASE_SEED + 6)
         x5, y5, m5, s5, rx5, ry5 = (d(a) for a in (lens5.x, lens5.y, lens5.m, lens5.s, r5x, r5y))
         bx5 = rx5 - 0.1 * rx5  # fixed target source positions (only the data flow matters for timing)
-        by5 = ry5 - 0.1 * ry5
-        tree5 = g.Tree()
-        ws5 = torch.empty(g.workspace_bytes(rx5.numel()), dtype=torch.uint8, device=dev)
+        by5 = ry5 - 0.1 * ry5  # (the 1e6 step above uses the fitting recipe's beta*)
+        tree5 = g.Tree().build(x5, y5, m5, s5, theta=THETA, q=lens5.q, leaf_size=LEAF, order=ORDER)
+        ws5 = torch.empty(g.adjoint_workspace_bytes(tree5, rx5.numel()), dtype=torch.uint8, device=dev)
         out5 = {k: torch.empty(rx5.numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2"]}
         grads5 = [torch.zeros(lens5.n, dtype=torch.float64, device=dev) for _ in range(4)]
 
@@ -275,8 +380,8 @@ def main():
         for _ in range(n5):
             step5()
         torch.cuda.synchronize()
-        fa_ms = 1e3 * (time.perf_counter() - t) / n5
-        log(f"fwd+adjoint (1e5 particles, 1e5 rays): {fa_ms:.3f} ms -> {rx5.numel() / (fa_ms * 1e-3):.4e} rays/s")
+        fa5_ms = 1e3 * (time.perf_counter() - t) / n5
+        log(f"fwd+adjoint (1e5 particles, 1e5 rays): {fa5_ms:.3f} ms -> {rx5.numel() / (fa5_ms * 1e-3):.4e} rays/s")
 
         # the same with kappa and gamma in the loss: L += sum (kappa - 1/2)^2 + |gamma|^2
         out5k = {k: torch.empty(rx5.numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2", "kappa", "g1", "g2"]}
@@ -349,13 +454,17 @@ def main():
         log(f"refinement of a smooth patch ({n6} cells): plain {1e3 * plain6:.2f} ms, with interpolation "
             f"{1e3 * interp6:.2f} ms, walking {walked6} rays")
 
-        # 64 independent lenses in one persistent launch
+        # 64 independent lenses in one persistent launch, autotuned: one order for the
+        # batch, theta and leaf size per lens, each accepted on 16,384 random rays plus
+        # the 4,096 nearest its densest point against the FP64 direct sum
         lenses4 = synth.workload_batched_lenses(64)
-        trees4, rays4 = [], []
-        for l4, r4x, r4y in lenses4:
-            trees4.append(g.Tree().build(d(l4.x), d(l4.y), d(l4.m), d(l4.s), theta=THETA, q=l4.q, leaf_size=LEAF,
-                                         order=ORDER))
-            rays4.append((d(r4x), d(r4y)))
+        dl4 = [(d(l4.x), d(l4.y), d(l4.m), d(l4.s), d(r4x), d(r4y)) for l4, r4x, r4y in lenses4]
+        t = time.perf_counter()
+        order4, picks4 = g.autotune_batch(dl4, q=lenses4[0][0].q)
+        tune4_s = time.perf_counter() - t
+        trees4 = [g.Tree().build(x4, y4, m4, s4, theta=p4["theta"], q=l4.q, leaf_size=p4["leaf_size"], order=order4)
+                  for (x4, y4, m4, s4, _, _), p4, (l4, _, _) in zip(dl4, picks4, lenses4)]
+        rays4 = [(r4x, r4y) for (_, _, _, _, r4x, r4y) in dl4]
         R4 = sum(r[0].numel() for r in rays4)
         outs4 = [{k: torch.empty(r[0].numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2", "kappa", "g1", "g2"]}
                  for r in rays4]
@@ -374,9 +483,28 @@ def main():
                 g.shoot(tr, r4x, r4y, out=o4, workspace=ws4b)
         torch.cuda.synchronize()
         l4 = (time.perf_counter() - t) / 3
-        log(f"64 lenses ({R4} rays): one persistent launch {1e3 * b4:.2f} ms ({R4 / b4:.4e} rays/s), "
-            f"per-lens launches {1e3 * l4:.2f} ms")
-        del trees4, rays4, outs4, ws4, ws4b
+        # every lens's error over all its rays against the FP64 direct sum
+        g.shoot_batched(trees4, rays4, outs=outs4, workspace=ws4)
+        lens4_err = []
+        for (x4, y4, m4, s4, r4x, r4y), o4, l4_ in zip(dl4, outs4, lenses4):
+            f4 = g.shoot_direct(x4, y4, m4, s4, l4_[0].q, r4x, r4y, fp64=True)
+            ra = torch.stack([f4["a1"], f4["a2"]], 1)
+            rg = torch.stack([f4["g1"], f4["g2"]], 1)
+            e_a = float(((torch.stack([o4["a1"], o4["a2"]], 1).double() - ra).norm(dim=1) / ra.norm(dim=1)).max())
+            e_g = float(((torch.stack([o4["g1"], o4["g2"]], 1).double() - rg).norm(dim=1) / rg.norm(dim=1)).max())
+            nz = f4["kappa"] != 0
+            e_k = float(((o4["kappa"].double() - f4["kappa"]).abs()[nz] / f4["kappa"][nz]).max()) if bool(nz.any()) \
+                else 0.0
+            lens4_err.append(max(e_a, e_k, e_g))
+        log(f"64 lenses ({R4} rays), autotuned in {tune4_s:.1f} s: order {order4}, (theta, leaf) "
+            f"{sorted(set((p4['theta'], p4['leaf_size']) for p4 in picks4))}; one persistent launch {1e3 * b4:.2f} ms "
+            f"({R4 / b4:.4e} rays/s), per-lens launches {1e3 * l4:.2f} ms; worst lens error over all its rays "
+            f"{max(lens4_err):.2e}")
+        batched4 = {"lenses": len(lenses4), "rays": R4, "ms": 1e3 * b4, "rays_per_s": R4 / b4,
+                    "per_lens_launches_ms": 1e3 * l4, "order": order4, "tune_s": tune4_s,
+                    "theta_leaf_per_lens": [(p4["theta"], p4["leaf_size"]) for p4 in picks4],
+                    "max_err_per_lens_vs_gpu_fp64_direct_all_rays": lens4_err}
+        del trees4, rays4, outs4, ws4, ws4b, dl4
 
         # truncated NFW halos as particles: the halo convergence test's field (1e4 halos
         # in the unit disk, sizes U(0, 0.3), dN/dm ~ m^-2 on [1e-3, 1], c = 3) under a
@@ -429,19 +557,22 @@ def main():
                    "gamma_rays_above_1e-4": int((e_g > 1e-4).sum()),
                    "gamma_worst_ray_abs_over_median_abs": float(gnorm[worst] / gnorm.median()),
                    "kappa_zero_outside_exact": bool((out["kappa"][~inside] == 0).all())}
-        del fullh, ref_a, ref_g, e_a, e_g, e_k, gnorm
-        log(f"NFW halo field (1e4 halos, 2048^2 rays): build + shoot {nfw_ms:.2f} ms -> {R / (nfw_ms * 1e-3):.4e} "
-            f"rays/s (walk {nfw_walk_ms:.2f} ms); direct fp32 {resh[False]:.3e}, fp64 {resh[True]:.3e} rays/s; "
-            f"vs GPU FP64 direct: alpha max {nfw_err['alpha_max']:.2e} kappa max {nfw_err['kappa_max']:.2e} "
-            f"gamma max {nfw_err['gamma_max']:.2e} (p99.9 {nfw_err['gamma_p999']:.2e}, "
-            f"{nfw_err['gamma_rays_above_1e-4']} rays above 1e-4); counts/ray {cnth.mean(0)}")
+        # the bar's definition: rays whose reference is under 1e-3 of the median are measured against the median
+        ebar = g.batch._errors(out, fullh)
+        nfw_err["max_err_bar_definition"] = max(ebar)
+        gbar = g.batch._rel_errors((torch.stack([out["g1"], out["g2"]], 1).double() - ref_g).norm(dim=1),
+                                   ref_g.norm(dim=1))
+        nfw_err["gamma_rays_above_1e-4_bar_definition"] = int((gbar > 1e-4).sum())
+        nfw_err["passes_1e-4_bar_definition"] = max(ebar) <= 1e-4
+        del fullh, ref_a, ref_g, e_a, e_g, e_k, gnorm, gbar
+        log(f"NFW halo field under the bar's definition: max error {max(ebar):.2e}, "
+            f"{nfw_err['gamma_rays_above_1e-4_bar_definition']} rays with gamma above 1e-4")
         extras = {"direct_fp32_rays_per_s": res[False], "direct_fp64_rays_per_s": res[True],
-                  "full_grid_err_vs_gpu_fp64_direct": full_err,
                   "potential_walk_ms": pot_ms, "potential_walk_rays_per_s": R / (pot_ms * 1e-3),
                   "knn_smoothing_1e6_ms": knn_ms, "knn_max_rel_diff_vs_host_kdtree": knn_diff,
                   "knn_from_positions_ms": knn_pos,
-                  "fwd_adjoint_rays_per_s": rx5.numel() / (fa_ms * 1e-3), "fwd_adjoint_ms": fa_ms,
-                  "fwd_adjoint_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2",
+                  "fwd_adjoint_1e5_rays_per_s": rx5.numel() / (fa5_ms * 1e-3), "fwd_adjoint_1e5_ms": fa5_ms,
+                  "fwd_adjoint_1e5_workload": "nfw_1e5_particles_1e5_uniform_rays, L = sum |x - alpha - beta*|^2",
                   "fwd_adjoint_kappa_gamma_ms": fak_ms,
                   "fwd_adjoint_kappa_gamma_rays_per_s": rx5.numel() / (fak_ms * 1e-3),
                   "refinement_rays": n3, "refinement_graph_ms": 1e3 * graph3_s, "refinement_eager_ms": 1e3 * eager3,
@@ -451,10 +582,13 @@ def main():
                   "interp_refinement_plain_ms": 1e3 * plain6, "interp_refinement_ms": 1e3 * interp6,
                   "interp_refinement_workload": "nfw_1e6 + stars tree, smooth 0.0002 patch at (0.3, 0.05), "
                                                 "256^2 base, 6 rounds, tol 1e-4",
-                  "batched_lenses": len(lenses4), "batched_rays": R4, "batched_ms": 1e3 * b4,
-                  "batched_rays_per_s": R4 / b4, "per_lens_launches_ms": 1e3 * l4,
+                  "batched_64_lenses": batched4,
                   "nfw_halos": {"workload": "1e4 truncated NFW halos (unit disk, sizes U(0, 0.3), dN/dm ~ m^-2 "
                                             "on [1e-3, 1], c = 3), 2048^2 grid over [-1, 1]^2",
+                                "note": "this field fails the 1e-4 bar on the shear of the rays where |gamma| is "
+                                        "under about a percent of the median (the FP32 halo terms leave ~1e-7 of "
+                                        "the summed term magnitudes; theta 0.2-0.3 with order 8-12 all fail); "
+                                        "see err_vs_gpu_fp64_direct",
                                 "step_ms": nfw_ms, "rays_per_s": R / (nfw_ms * 1e-3), "walk_ms": nfw_walk_ms,
                                 "direct_fp32_rays_per_s": resh[False], "direct_fp64_rays_per_s": resh[True],
                                 "err_vs_gpu_fp64_direct": nfw_err,
@@ -476,8 +610,12 @@ def main():
                    "order": ORDER, "leaf_size": LEAF, "q": lens.q, "step": "build_tree + shoot (alpha, kappa, gamma)"},
         "roofline": {"bound": "alu", "kernel": "k_walk", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
-                     "kernel_ms": walk_ms, "flop_per_launch": flop},
+                     "kernel_ms": walk_ms, "flop_per_launch": flop, "lane_use": lane_use,
+                     "search_overhead_flop_per_launch": scan_flop, **issued_valu(flop)},
+        "fwd_adjoint": fwd_adjoint,
+        "full_grid_err_vs_gpu_fp64_direct": full_err,
         "extras": {"build_ms": build_ms, "walk_only_rays_per_s": R / (walk_ms * 1e-3),
+                   "fwd_adjoint_1e6_rays_per_s": fwd_adjoint["value"],
                    "ncells": info["ncells"], "nlisted": info["nlisted"],
                    "counts_per_ray": dict(zip(["visited", "accepted", "leaf", "list_hits"], cnt.mean(0).tolist())),
                    **extras},
@@ -489,27 +627,60 @@ def main():
         oracle.build(force=False)
         nt = cpu_threads()
         gen = synth.rng(synth.BASE_SEED + 99)
+        # oracle A (FP64 brute force): a probe sizes a sample of ~12 s on all threads
         probe = gen.choice(R, 256, replace=False)
         t = time.perf_counter()
         oracle.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx_t[probe], ry_t[probe], threads=nt)
         per_ray = (time.perf_counter() - t) / probe.size
-        k = int(min(R, max(256, 15.0 / per_ray)))
+        k = int(min(R, max(256, 12.0 / per_ray)))
         idx = np.sort(gen.choice(R, k, replace=False))
         t = time.perf_counter()
         ref = oracle.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx_t[idx], ry_t[idx], threads=nt)
         cpu_el = time.perf_counter() - t
+        # ... and on one thread, over the sample's first k1 rays (~6 s)
+        k1 = int(max(16, min(k, 6.0 / (cpu_el / k * nt))))
+        t = time.perf_counter()
+        oracle.direct(lens.x, lens.y, lens.m, lens.s, lens.q, rx_t[idx[:k1]], ry_t[idx[:k1]], threads=1)
+        cpu1_el = time.perf_counter() - t
         g.shoot(tree, rx, ry, out=out, workspace=ws)
         got = np.stack([out[kk].double().cpu().numpy()[idx] for kk in ["a1", "a2", "kappa", "g1", "g2"]], axis=1)
         ea = np.linalg.norm(got[:, :2] - ref[:, :2], axis=1) / np.linalg.norm(ref[:, :2], axis=1)
         ek = np.abs(got[:, 2] - ref[:, 2]) / np.abs(ref[:, 2])
         eg = np.linalg.norm(got[:, 3:] - ref[:, 3:], axis=1) / np.linalg.norm(ref[:, 3:], axis=1)
-        line["cpu_baseline"] = {"value": k / cpu_el, "unit": "rays/s", "cores": nt, "kind": "oracle",
-                                "sample": f"{k} random rays of the 2048^2 grid, FP64 brute force over all "
-                                          f"{lens.n} particles ({cpu_el:.1f} s)"}
+        # oracle B (FP64 reference tree, the CPU analogue of the paper's threaded tree
+        # solver) at the same theta, order and leaf size: build, then a sample of ~4 s
+        t = time.perf_counter()
+        T = oracle.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, THETA, LEAF, ORDER)
+        treeB_build = time.perf_counter() - t
+        t = time.perf_counter()
+        T.shoot(rx_t[idx], ry_t[idx], threads=nt)
+        per_rayB = (time.perf_counter() - t) / idx.size
+        kB = int(min(R, max(idx.size, 4.0 / per_rayB)))
+        idxB = np.sort(gen.choice(R, kB, replace=False))
+        t = time.perf_counter()
+        T.shoot(rx_t[idxB], ry_t[idxB], threads=nt)
+        treeB_el = time.perf_counter() - t
+        kB1 = int(max(64, min(kB, 4.0 / (treeB_el / kB * nt))))
+        t = time.perf_counter()
+        T.shoot(rx_t[idxB[:kB1]], ry_t[idxB[:kB1]], threads=1)
+        treeB1_el = time.perf_counter() - t
+        del T
+        line["cpu_baseline"] = {
+            "value": k / cpu_el, "unit": "rays/s", "cores": nt, "kind": "oracle",
+            "sample": f"{k} random rays of the 2048^2 grid, FP64 brute force (oracle A) over all {lens.n} "
+                      f"particles ({cpu_el:.1f} s on {nt} threads; {k1} of them on 1 thread, {cpu1_el:.1f} s)",
+            "value_1_thread": k1 / cpu1_el, "cpu_model": cpu_model(),
+            "tree": {"kind": "oracle", "value": kB / treeB_el, "value_1_thread": kB1 / treeB1_el, "cores": nt,
+                     "build_s": treeB_build,
+                     "sample": f"FP64 reference tree (oracle B), theta {THETA}, order {ORDER}, leaf {LEAF}: "
+                               f"{kB} random rays of the grid on {nt} threads ({treeB_el:.1f} s), {kB1} on 1 thread "
+                               f"({treeB1_el:.1f} s); the single-threaded build of the 1e6-particle tree "
+                               f"({treeB_build:.1f} s) is not in the rate"}}
         line["parity_vs_fp64_sample"] = {"rays": k, "alpha_max": float(ea.max()), "kappa_max": float(ek.max()),
                                          "gamma_max": float(eg.max())}
-        log(f"cpu oracle: {k / cpu_el:.1f} rays/s on {nt} threads; sample max rel err "
-            f"alpha {ea.max():.2e} kappa {ek.max():.2e} gamma {eg.max():.2e}")
+        log(f"cpu oracle A: {k / cpu_el:.1f} rays/s on {nt} threads, {k1 / cpu1_el:.1f} on 1; oracle B tree: "
+            f"{kB / treeB_el:.1f} rays/s on {nt} threads, {kB1 / treeB1_el:.1f} on 1 (build {treeB_build:.1f} s); "
+            f"sample max rel err alpha {ea.max():.2e} kappa {ek.max():.2e} gamma {eg.max():.2e}")
     print(json.dumps(line), flush=True)
 
 

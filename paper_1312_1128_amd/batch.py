@@ -271,14 +271,23 @@ def validation_rays(x, y, s, rx, ry, sample: int = 16384, dense: int = 4096, see
     return torch.unique(torch.cat([pick, near]))
 
 
+def _rel_errors(err, mag):
+    """Per-ray error over the reference magnitude; rays whose reference is under
+    1e-3 of the median magnitude are measured against the median instead (the
+    error definition of the accuracy bar: a near-zero reference has no
+    meaningful relative error)."""
+    med = mag.median()
+    return err / torch.where(mag >= 1e-3 * med, mag, med)
+
+
 def _errors(o, ref):
     ra = torch.stack([ref["a1"], ref["a2"]], 1)
     rg = torch.stack([ref["g1"], ref["g2"]], 1)
     rk = ref["kappa"]
-    ea = ((torch.stack([o["a1"], o["a2"]], 1).double() - ra).norm(dim=1) / ra.norm(dim=1)).max().item()
-    eg = ((torch.stack([o["g1"], o["g2"]], 1).double() - rg).norm(dim=1) / rg.norm(dim=1)).max().item()
+    ea = _rel_errors((torch.stack([o["a1"], o["a2"]], 1).double() - ra).norm(dim=1), ra.norm(dim=1)).max().item()
+    eg = _rel_errors((torch.stack([o["g1"], o["g2"]], 1).double() - rg).norm(dim=1), rg.norm(dim=1)).max().item()
     nz = rk != 0
-    ek = ((o["kappa"].double() - rk).abs()[nz] / rk.abs()[nz]).max().item() if bool(nz.any()) else 0.0
+    ek = _rel_errors((o["kappa"].double() - rk).abs()[nz], rk.abs()[nz]).max().item() if bool(nz.any()) else 0.0
     # kappa must vanish exactly where no particle holds the ray
     if bool((~nz).any()) and bool((o["kappa"][~nz] != 0).any()):
         ek = float("inf")
@@ -295,7 +304,9 @@ def autotune(x, y, m, s, rx, ry, q: float = 3.0, tol: float = 1e-4, thetas=(0.2,
     point; every ray when sample + dense covers them).  For each (leaf size,
     theta) only the smallest passing order is timed (a larger order costs more
     and is no more needed).  The walk group is one wavefront (64 rays) by
-    construction.  Returns (best, table); best is None when nothing passes,
+    construction.  Errors are per ray relative to the reference magnitude,
+    except on rays whose reference is under 1e-3 of the median magnitude, which
+    are measured against the median.  Returns (best, table); best is None when nothing passes,
     table has a row per evaluated (theta, order, leaf size) with its errors,
     whether it passed, and its time (NaN unless timed)."""
     from . import Tree, shoot, shoot_direct, workspace_bytes
