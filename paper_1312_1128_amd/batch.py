@@ -296,14 +296,15 @@ def _errors(o, ref):
 
 def autotune(x, y, m, s, rx, ry, q: float = 3.0, tol: float = 1e-4, thetas=(0.2, 0.3, 0.4, 0.5),
              orders=(4, 6, 8, 10, 12), leaves=(8, 16, 24), sample: int = 16384, dense: int = 4096, reps: int = 3,
-             seed: int = 0, nfw: bool = False):
+             seed: int = 0, nfw: bool = False, every_order: bool = False):
     """Pick (theta, order, leaf size) for one lens: the fastest build + walk of
     all rays rx, ry whose max fractional errors of alpha, kappa and gamma stay
     within `tol` against the library's FP64 direct sum on the validation rays
     (validation_rays: `sample` random rays plus the `dense` nearest the densest
     point; every ray when sample + dense covers them).  For each (leaf size,
     theta) only the smallest passing order is timed (a larger order costs more
-    and is no more needed).  The walk group is one wavefront (64 rays) by
+    and is no more needed), unless every_order is set: then every order is
+    checked and timed (a batch needs each lens's best setting at one order).  The walk group is one wavefront (64 rays) by
     construction.  Errors are per ray relative to the reference magnitude,
     except on rays whose reference is under 1e-3 of the median magnitude, which
     are measured against the median.  Returns (best, table); best is None when nothing passes,
@@ -342,7 +343,7 @@ def autotune(x, y, m, s, rx, ry, q: float = 3.0, tol: float = 1e-4, thetas=(0.2,
                                     err_alpha=ea, err_kappa=ek, err_gamma=eg, rays_checked=int(idx.numel()))
                 table.append(dict(theta=th, order=p, leaf_size=L, err_alpha=ea, err_kappa=ek, err_gamma=eg, ok=ok,
                                   ms=ms))
-                if ok:
+                if ok and not every_order:
                     break  # larger orders at this (leaf size, theta) only cost more
     return best, table
 
@@ -352,19 +353,43 @@ def autotune_batch(lenses, q: float = 3.0, tol: float = 1e-4, thetas=(0.2, 0.3, 
     """Tune a batch of lenses for one persistent launch: every tree of a batch
     has the same order, while theta and the leaf size may differ per lens.
     lenses: list of (x, y, m, s, rx, ry) CUDA float64 tensors.  Each lens is
-    tuned by `autotune` over the orders; the common order is the one with the
-    smallest summed time of the lenses' fastest passing (theta, leaf size) at
-    that order.  Returns (order, [per-lens dict(theta, leaf_size, ms, err...)])
-    or (None, []) when no order passes on every lens."""
+    tuned by `autotune` over the orders (accepted on its validation rays);
+    then, for every order that passes on all lenses, the trees are built at
+    each lens's fastest passing (theta, leaf size) for that order and the
+    batched launch is timed; the order of the fastest launch wins.  Returns
+    (order, [per-lens dict(theta, leaf_size, ms, err...)], batched ms) or
+    (None, [], nan) when no order passes on every lens."""
+    from . import Tree
+
     per_order = {p: [] for p in orders}
     for li, (x, y, m, s, rx, ry) in enumerate(lenses):
         _, table = autotune(x, y, m, s, rx, ry, q=q, tol=tol, thetas=thetas, orders=orders, leaves=leaves,
-                            sample=sample, dense=dense, reps=reps, seed=seed + li)
+                            sample=sample, dense=dense, reps=reps, seed=seed + li, every_order=True)
         for p in orders:
             rows = [t for t in table if t["ok"] and t["order"] == p]
             per_order[p].append(min(rows, key=lambda t: t["ms"]) if rows else None)
-    feasible = {p: sum(r["ms"] for r in rows) for p, rows in per_order.items() if all(r is not None for r in rows)}
+    feasible = [p for p, rows in per_order.items() if all(r is not None for r in rows)]
     if not feasible:
-        return None, []
-    p = min(feasible, key=feasible.get)
-    return p, per_order[p]
+        return None, [], float("nan")
+    rays = [(rx, ry) for (_, _, _, _, rx, ry) in lenses]
+    dev = rays[0][0].device
+    outs = [{k: torch.empty(r[0].numel(), dtype=torch.float32, device=dev) for k in ["a1", "a2", "kappa", "g1", "g2"]}
+            for r in rays]
+    ws = torch.empty(batched_workspace_bytes([r[0].numel() for r in rays]), dtype=torch.uint8, device=dev)
+    best = (None, float("inf"))
+    for p in feasible:
+        trees = [Tree().build(x, y, m, s, theta=r["theta"], q=q, leaf_size=r["leaf_size"], order=p)
+                 for (x, y, m, s, _, _), r in zip(lenses, per_order[p])]
+        shoot_batched(trees, rays, outs=outs, workspace=ws)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            shoot_batched(trees, rays, outs=outs, workspace=ws)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ms = 1e3 * sorted(ts)[len(ts) // 2]
+        if ms < best[1]:
+            best = (p, ms)
+        del trees
+    return best[0], per_order[best[0]], best[1]

@@ -69,7 +69,7 @@ def test_batched_64_lenses_full_size(ora):
     say(f"[gpu] full-size batch: {sum(l.n for l, _, _ in lenses)} particles, "
         f"{sum(rx.size for _, rx, _ in lenses)} rays")
     dl = [(d(l.x), d(l.y), d(l.m), d(l.s), d(rx), d(ry)) for l, rx, ry in lenses]
-    order, picks = g.autotune_batch(dl, q=lenses[0][0].q)
+    order, picks, _ = g.autotune_batch(dl, q=lenses[0][0].q)
     assert order is not None
     say(f"  tuned order {order}; (theta, leaf) per lens: {[(p['theta'], p['leaf_size']) for p in picks]}")
     trees = [g.Tree().build(x, y, m, s, theta=p["theta"], q=l.q, leaf_size=p["leaf_size"], order=order)
