@@ -534,7 +534,7 @@ __device__ inline void store_moments(int c, int u, const double* Qr, const doubl
 // for every leaf at once (they depend on no other box): kLeafLanes lanes per
 // box, lane u summing the leaf's particles u, u + kLeafLanes, ...; the lanes'
 // partial sums meet by butterfly exchanges.
-constexpr int kLeafLanes = 16;
+constexpr int kLeafLanes = 4;
 
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_moments_leaves(int ncells, BoxArrays b, const double* __restrict__ xs,
