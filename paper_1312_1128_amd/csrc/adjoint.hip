@@ -426,39 +426,37 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
         const bool acc = act && d2 > h.rcut2;
         const bool opn = act && !acc;
         if (__any(acc)) {
-            // per-lane box adjoint terms (zero on lanes that did not accept)
+            // per-lane box adjoint terms; every lane evaluates them, the lanes that
+            // did not accept with zero cotangents and w = (1, 0), so that their
+            // words are exactly 0 (no branch, no clearing of the words)
             float a[NA];
-#pragma unroll
-            for (int k = 0; k < NA; ++k) a[k] = 0.0f;
+            const float f1 = acc ? (float)w1 : 1.0f, f2 = acc ? (float)w2 : 0.0f;
+            const float e1 = acc ? g1 : 0.0f, e2 = acc ? g2 : 0.0f;
             if constexpr (!KG) {
                 // alpha cotangents only: the words are g_hat v t^k for k = 0 .. P + 1; the
                 // centre-of-mass adjoint sum_k (k + 1) Q_k Abar_{k+1} is formed from them
                 // in the push-down
-                if (acc) {
-                    const float rcm = T.mom[(size_t)cur * mom_stride(P) + 1];
-                    const float f1 = (float)w1, f2 = (float)w2;
-                    const float inv = __builtin_amdgcn_rcpf(f1 * f1 + f2 * f2);
-                    const float v1 = f1 * inv, v2 = -f2 * inv;
-                    const float t1 = rcm * v1, t2 = rcm * v2;
-                    float p1 = fmaf(g1, v1, -g2 * v2), p2 = fmaf(g1, v2, g2 * v1);
+                const float rcm = T.mom[(size_t)cur * mom_stride(P) + 1];
+                const float inv = __builtin_amdgcn_rcpf(f1 * f1 + f2 * f2);
+                const float v1 = f1 * inv, v2 = -f2 * inv;
+                const float t1 = rcm * v1, t2 = rcm * v2;
+                float p1 = fmaf(e1, v1, -e2 * v2), p2 = fmaf(e1, v2, e2 * v1);
 #pragma unroll
-                    for (int k = 0; k <= P + 1; ++k) {
-                        a[2 * k] = p1;
-                        a[2 * k + 1] = p2;
-                        const float n1 = fmaf(p1, t1, -p2 * t2), n2 = fmaf(p1, t2, p2 * t1);
-                        p1 = n1;
-                        p2 = n2;
-                    }
+                for (int k = 0; k <= P + 1; ++k) {
+                    a[2 * k] = p1;
+                    a[2 * k + 1] = p2;
+                    const float n1 = fmaf(p1, t1, -p2 * t2), n2 = fmaf(p1, t2, p2 * t1);
+                    p1 = n1;
+                    p2 = n2;
                 }
-            } else if (acc) {
+            } else {
                 const float* mo = T.mom + (size_t)cur * mom_stride(P);
                 const float M = mo[0], rcm = mo[1];
-                const float f1 = (float)w1, f2 = (float)w2;
                 const float inv = __builtin_amdgcn_rcpf(f1 * f1 + f2 * f2);
                 const float v1 = f1 * inv, v2 = -f2 * inv;
                 const float t1 = rcm * v1, t2 = rcm * v2;
                 // g_hat v t^k
-                float p1 = fmaf(g1, v1, -g2 * v2), p2 = fmaf(g1, v2, g2 * v1);
+                float p1 = fmaf(e1, v1, -e2 * v2), p2 = fmaf(e1, v2, e2 * v1);
 #pragma unroll
                 for (int k = 0; k <= P; ++k) {
                     a[2 * k] = p1;
@@ -492,11 +490,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 const float S1 = fmaf(t1, c1, fmaf(-t2, c2, b1)), S2 = fmaf(t1, c2, fmaf(t2, c1, b2));
                 const float w21 = fmaf(v1, v1, -v2 * v2), w22 = 2.0f * v1 * v2;
                 const float V1 = fmaf(w21, S1, -w22 * S2), V2 = fmaf(w21, S2, w22 * S1);
-                a[NA - 2] = g1 * V1 - g2 * V2;
-                a[NA - 1] = g1 * V2 + g2 * V1;
+                a[NA - 2] = e1 * V1 - e2 * V2;
+                a[NA - 1] = e1 * V2 + e2 * V1;
                 {
                     // gamma: Abar_k r_cm^k -= (k+1) gg v^2 t^k, Bbar -= gg M v^3 T(t)
-                    const float h1 = cg.h1, h2 = cg.h2;
+                    const float h1 = acc ? cg.h1 : 0.0f, h2 = acc ? cg.h2 : 0.0f;
                     float q1 = fmaf(h1, w21, -h2 * w22), q2 = fmaf(h1, w22, h2 * w21); // gg v^2
 #pragma unroll
                     for (int k = 0; k <= P; ++k) {
