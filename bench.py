@@ -578,7 +578,34 @@ def main():
                                    ref_g.norm(dim=1))
         nfw_err["gamma_rays_above_1e-4_bar_definition"] = int((gbar > 1e-4).sum())
         nfw_err["passes_1e-4_bar_definition"] = max(ebar) <= 1e-4
-        del fullh, ref_a, ref_g, e_a, e_g, e_k, gnorm, gbar
+        # the same field at theta 0.2, order 12 (leaf 16): its time and errors
+        TH2, P2 = 0.2, 12
+
+        def steph2():
+            treeh.build(xh, yh, mh, sh, theta=TH2, q=ch, leaf_size=LEAF, order=P2, nfw=True)
+            g.shoot(treeh, hxd, hyd, out=out, workspace=ws)
+
+        for _ in range(2):
+            steph2()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            steph2()
+        torch.cuda.synchronize()
+        nfw2_ms = 1e3 * (time.perf_counter() - t) / 5
+        ebar2 = g.batch._errors(out, fullh)
+        gbar2 = g.batch._rel_errors((torch.stack([out["g1"], out["g2"]], 1).double() - ref_g).norm(dim=1),
+                                    ref_g.norm(dim=1))
+        inside2 = fullh["kappa"] > 0
+        nfw_tight = {"theta": TH2, "order": P2, "leaf_size": LEAF, "step_ms": nfw2_ms, "rays_per_s": R / (nfw2_ms * 1e-3),
+                     "max_err_bar_definition": max(ebar2), "err_alpha_kappa_gamma_bar_definition": list(ebar2),
+                     "gamma_rays_above_1e-4_bar_definition": int((gbar2 > 1e-4).sum()),
+                     "kappa_zero_outside_exact": bool((out["kappa"][~inside2] == 0).all()),
+                     "passes_1e-4_bar_definition": max(ebar2) <= 1e-4}
+        log(f"NFW halo field at theta {TH2}, order {P2}: build + shoot {nfw2_ms:.2f} ms "
+            f"({R / (nfw2_ms * 1e-3):.4e} rays/s); max error under the bar's definition {max(ebar2):.2e}, "
+            f"{nfw_tight['gamma_rays_above_1e-4_bar_definition']} rays with gamma above 1e-4")
+        del fullh, ref_a, ref_g, e_a, e_g, e_k, gnorm, gbar, gbar2, inside2
         log(f"NFW halo field under the bar's definition: max error {max(ebar):.2e}, "
             f"{nfw_err['gamma_rays_above_1e-4_bar_definition']} rays with gamma above 1e-4")
         extras = {"direct_fp32_rays_per_s": res[False], "direct_fp64_rays_per_s": res[True],
@@ -599,13 +626,14 @@ def main():
                   "batched_64_lenses": batched4,
                   "nfw_halos": {"workload": "1e4 truncated NFW halos (unit disk, sizes U(0, 0.3), dN/dm ~ m^-2 "
                                             "on [1e-3, 1], c = 3), 2048^2 grid over [-1, 1]^2",
-                                "note": "this field fails the 1e-4 bar on the shear of the rays where |gamma| is "
-                                        "under about a percent of the median (the FP32 halo terms leave ~1e-7 of "
-                                        "the summed term magnitudes; theta 0.2-0.3 with order 8-12 all fail); "
-                                        "see err_vs_gpu_fp64_direct",
+                                "note": "this field fails the 1e-4 bar on the shear of a few rays where |gamma| is "
+                                        "about 1e-3 to 2e-2 of the median (many halos' shears cancel there). At "
+                                        "theta 0.3, order 8 the FP64 oracle tree misses there too (truncation); at "
+                                        "theta 0.2, order 12 it passes, and the FP32 terms of the walk leave a few "
+                                        "rays at about 1.6e-4; see err_vs_gpu_fp64_direct and tighter_setting",
                                 "step_ms": nfw_ms, "rays_per_s": R / (nfw_ms * 1e-3), "walk_ms": nfw_walk_ms,
                                 "direct_fp32_rays_per_s": resh[False], "direct_fp64_rays_per_s": resh[True],
-                                "err_vs_gpu_fp64_direct": nfw_err,
+                                "err_vs_gpu_fp64_direct": nfw_err, "tighter_setting": nfw_tight,
                                 "counts_per_ray": dict(zip(["visited", "accepted", "leaf", "list_hits"],
                                                            cnth.mean(0).tolist()))}}
 

@@ -106,7 +106,7 @@ __device__ inline bool particle_grad(const PRec& pr, double X, double Y, int mod
         // d kappa/dR = -2 (kappa + u dkappa/du)/R, d(kappa - A)/dR = -2 u dkappa/du / R
         const double x2 = r2 * ((double)pr.h * (double)pr.h);
         float gx2, f, dfde;
-        nfw_shape<float, 12>((float)x2, (float)(x2 - 1.0), 0.25f, &gx2, &f, &dfde);
+        nfw_shape32((float)x2, (float)(x2 - 1.0), &gx2, &f, &dfde);
         const float hh2 = (invC * pr.h) * pr.h;
         const float Au = hh2 * gx2;
         const float Ku = r2 > 0.0 ? 0.5f * hh2 * f : 0.0f;

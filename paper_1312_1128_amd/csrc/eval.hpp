@@ -155,7 +155,7 @@ __device__ inline void gauss_terms(float u, float e, float ir2, float mC, float 
 //  - x < 1 beyond: atanh(y) = log1p(2 y (1 + y) / x^2) / 2 (as 1 - y = x^2 / (1 + y)),
 //    f = (F - 1) / y^2, and g / x^2 = [ln(2 / x) / (1 + y) + log1p(-a) / x^2] / y
 //    with a = x^2 / (2 (1 + y)), which keeps ln(x / 2) and F from cancelling.
-// NSER series terms suit eps: 12 at 0.25 for FP32, 17 at 0.1 for FP64.
+// NSER series terms suit eps: 17 at 0.1 for FP64 (the FP32 walk uses nfw_shape32).
 // ---------------------------------------------------------------------------
 __host__ __device__ inline float nfw_log1p(float v) { return log1pf(v); }
 __host__ __device__ inline double nfw_log1p(double v) { return log1p(v); }
@@ -220,6 +220,45 @@ __host__ __device__ inline void nfw_shape(T x2, T e, T eps, T* gx2, T* f, T* dfd
     }
 }
 
+// g(x) / x^2 as a power series in z = -e = 1 - x^2: sum_j T_j z^j with
+// T_j = sum_{k > j} 1 / (2k (2k + 1)) = (1 - ln 2) - sum_{k <= j} 1 / (2k (2k + 1)).
+// It follows from g = ln(x / 2) + F with ln x = log1p(e) / 2 and
+// F = sum_k z^k / (2k + 1), divided by x^2 = 1 - z; T_0 = g(1).  No logarithm
+// and no cancellation: for x < 1 every term is positive.
+__host__ __device__ constexpr double nfw_gx2_coef(int j)
+{
+    double t = 1.0 - 0.693147180559945309417;
+    for (int k = 1; k <= j; ++k) t -= 1.0 / ((2.0 * k) * (2.0 * k + 1.0));
+    return t;
+}
+
+template <class T, int N>
+__host__ __device__ inline T gx2_series(T z)
+{
+    T s = (T)nfw_gx2_coef(N - 1);
+#pragma unroll
+    for (int j = N - 2; j >= 0; --j) s = s * z + (T)nfw_gx2_coef(j);
+    return s;
+}
+
+// The walk's FP32 shapes.  Within |e| < 0.6 (0.63 < x < 1.26) g / x^2, f and
+// df/de come from their power series in e (30, 32 and 36 terms: the first term
+// left out is below 1e-8 of the sum); beyond, the closed forms of nfw_shape.
+// Near x = 1 the closed forms lose digits to cancellation (1 - F, F - 1 and
+// 3F - 2 - 1/x^2 are small differences of O(1) terms): the series keep the
+// shapes within about 5e-7 of their FP64 values where the closed forms alone
+// left 2e-6 next to |e| = 0.25.
+__device__ inline void nfw_shape32(float x2, float e, float* gx2, float* f, float* dfde = nullptr)
+{
+    if (e > -0.6f && e < 0.6f) {
+        *gx2 = gx2_series<float, 30>(-e);
+        *f = odd_series<float, 32, 3>(-e);
+        if (dfde) *dfde = -dseries<float, 36>(-e);
+    } else {
+        nfw_shape<float, 1>(x2, e, 0.0f, gx2, f, dfde); // no series range left
+    }
+}
+
 // g(c) on the host (FP64), for the mass normalisation of a halo of concentration c
 inline double nfw_g_at(double c)
 {
@@ -267,7 +306,7 @@ __device__ inline void profile_terms(const PRec& pr, double r2, float r2f, float
     if constexpr (KIND == kKindNfw) {
         const double x2 = r2 * ((double)pr.h * (double)pr.h);
         float gx2, f;
-        nfw_shape<float, 12>((float)x2, (float)(x2 - 1.0), 0.25f, &gx2, &f);
+        nfw_shape32((float)x2, (float)(x2 - 1.0), &gx2, &f);
         const float mh2 = (pr.mC * pr.h) * pr.h;
         *A = mh2 * gx2;
         *K = r2 > 0.0 ? 0.5f * mh2 * f : 0.0f; // a ray at the centre gets nothing
