@@ -706,49 +706,56 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int ncells, int p, double t
                                                     CellExt* __restrict__ ext, float* __restrict__ mom)
 {
 #pragma clang fp contract(off)
-    const int c = blockIdx.x * kBlock + threadIdx.x;
-    if (c >= ncells) return;
-    double bx0, bx1, by0, by1;
-    box_bounds(b, c, sync, &bx0, &bx1, &by0, &by1);
-    const double cx = ccx[c], cy = ccy[c];
-    const double X[4] = {bx0, bx1, bx0, bx1}, Y[4] = {by0, by0, by1, by1};
-    double dmax2 = 0.0;
-    for (int k = 0; k < 4; ++k) {
-        const double e1 = X[k] - cx, e2 = Y[k] - cy;
-        const double d2 = e1 * e1 + e2 * e2;
-        if (d2 > dmax2) dmax2 = d2;
-    }
-    CellHdr h;
-    h.cx = cx;
-    h.cy = cy;
-    h.rcut2 = theta > 0.0 ? dmax2 / (theta * theta) : INFINITY;
-    h.next = b.next[c];
-    h.info = (b.leaf[c] ? kInfoLeaf : 0u) | (b.lend[c] > b.lbeg[c] ? kInfoList : 0u);
-    hdr[c] = h;
-    CellExt e;
-    e.pbeg = b.beg[c];
-    e.pend = b.end[c];
-    e.lbeg = b.lbeg[c];
-    e.lend = b.lend[c];
-    ext[c] = e;
+    __shared__ double s_irc[kBlock]; // 1 / r_cm of the block's boxes
+    const int c0 = blockIdx.x * kBlock, c = c0 + threadIdx.x;
     const int st = mom_stride(p);
-    float* mo = mom + (size_t)c * st;
-    const double M = cM[c];
-    const double rcm = sqrt(dmax2);
-    mo[0] = (float)M;
-    mo[1] = (float)rcm;
-    // M Qn_k = Q_k / r_cm^k (Qn_k = Q_k / (M r_cm^k)): the walk's series then
-    // carries the box mass in its coefficients
-    const double* q = cQ + (size_t)c * (p + 1) * 2;
-    double scale = 1.0;
-    const double irc = 1.0 / rcm;
-    scale *= irc; // k = 1
-    for (int k = 2; k <= p; ++k) {
-        scale *= irc;
+    if (c < ncells) {
+        double bx0, bx1, by0, by1;
+        box_bounds(b, c, sync, &bx0, &bx1, &by0, &by1);
+        const double cx = ccx[c], cy = ccy[c];
+        const double X[4] = {bx0, bx1, bx0, bx1}, Y[4] = {by0, by0, by1, by1};
+        double dmax2 = 0.0;
+        for (int k = 0; k < 4; ++k) {
+            const double e1 = X[k] - cx, e2 = Y[k] - cy;
+            const double d2 = e1 * e1 + e2 * e2;
+            if (d2 > dmax2) dmax2 = d2;
+        }
+        CellHdr h;
+        h.cx = cx;
+        h.cy = cy;
+        h.rcut2 = theta > 0.0 ? dmax2 / (theta * theta) : INFINITY;
+        h.next = b.next[c];
+        h.info = (b.leaf[c] ? kInfoLeaf : 0u) | (b.lend[c] > b.lbeg[c] ? kInfoList : 0u);
+        hdr[c] = h;
+        CellExt e;
+        e.pbeg = b.beg[c];
+        e.pend = b.end[c];
+        e.lbeg = b.lbeg[c];
+        e.lend = b.lend[c];
+        ext[c] = e;
+        float* mo = mom + (size_t)c * st;
+        const double rcm = sqrt(dmax2);
+        mo[0] = (float)cM[c];
+        mo[1] = (float)rcm;
+        for (int k = 2 + 2 * (p > 1 ? p - 1 : 0); k < st; ++k) mo[k] = 0.0f;
+        s_irc[threadIdx.x] = 1.0 / rcm;
+    }
+    __syncthreads();
+    // M Qn_k = Q_k / r_cm^k for k = 2..p (Qn_k = Q_k / (M r_cm^k)): the walk's
+    // series then carries the box mass in its coefficients.  One (box, k) item
+    // per thread, so that the block reads its boxes' FP64 moments and writes
+    // their FP32 records in consecutive words.
+    const int per = p - 1, nb = ncells - c0 < kBlock ? ncells - c0 : kBlock;
+    for (int i = threadIdx.x; i < nb * per; i += kBlock) {
+        const int bi = i / per, k = 2 + i % per;
+        const double irc = s_irc[bi];
+        double scale = irc; // irc^k by the same k - 1 products for every k
+        for (int j = 2; j <= k; ++j) scale *= irc;
+        const double* q = cQ + (size_t)(c0 + bi) * (p + 1) * 2;
+        float* mo = mom + (size_t)(c0 + bi) * st;
         mo[2 + 2 * (k - 2)] = (float)(q[2 * k] * scale);
         mo[3 + 2 * (k - 2)] = (float)(q[2 * k + 1] * scale);
     }
-    for (int k = 2 + 2 * (p > 1 ? p - 1 : 0); k < st; ++k) mo[k] = 0.0f;
 }
 
 } // namespace
