@@ -271,12 +271,22 @@ __global__ __launch_bounds__(kBlock) void k_topo_count(const uint64_t* __restric
         cnt[i] = c;
     }
     __syncthreads();
-    if (threadIdx.x <= kMaxLevel && hist[threadIdx.x]) atomicAdd(&sync->levcnt[threadIdx.x], hist[threadIdx.x]);
+    if (threadIdx.x <= kMaxLevel && hist[threadIdx.x])
+        atomicAdd(&sync->levrep[blockIdx.x % kLevReps][threadIdx.x], hist[threadIdx.x]);
 }
 
+// The box total, and the boxes per level summed over their copies (thread l:
+// level l).
 __global__ void k_sync_counts(const int32_t* __restrict__ cs, int n, BuildSync* __restrict__ sync)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) sync->ncells = cs[n];
+    const int l = threadIdx.x;
+    if (l == 0) sync->ncells = cs[n];
+    if (l <= kMaxLevel) {
+        int sum = 0;
+#pragma unroll
+        for (int r = 0; r < kLevReps; ++r) sum += sync->levrep[r][l];
+        sync->levcnt[l] = sum;
+    }
 }
 
 // One thread per box: the particle whose chain holds box idx is the i with
@@ -922,7 +932,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     hipLaunchKernelGGL(k_gather, dim3(gb), dim3(kBlock), 0, st, perm, packed, (int64_t)n, xs, ys, ms, ss);
     hipLaunchKernelGGL(k_topo_count, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart, sync);
     exclusive_scan_i32(cnt, cnt, n, scr, st);
-    hipLaunchKernelGGL(k_sync_counts, dim3(1), dim3(1), 0, st, cnt, n, sync);
+    hipLaunchKernelGGL(k_sync_counts, dim3(1), dim3(kWave), 0, st, cnt, n, sync);
     GLM_HIP(hipGetLastError());
 
     BuildSync hs;

@@ -5,6 +5,9 @@
 
 namespace glm {
 
+constexpr int kLevReps = 16;
+static_assert(kMaxLevel + 1 <= 64, "a level-count copy holds 64 levels");
+
 // Small device struct written by the build kernels; copied to the host once.
 struct BuildSync {
     double x0, y0, side, scale; // root square and 32-bit quantisation scale
@@ -16,6 +19,10 @@ struct BuildSync {
     int32_t internal;           // consistency flags of the build (0 = ok)
     int32_t levcnt[kMaxLevel + 2];  // boxes per level
     int32_t levfill[kMaxLevel + 2]; // fill counters of the per-level box index
+    // boxes per level counted in kLevReps copies (block b adds into copy
+    // b % kLevReps, each in its own 256-byte line), so that the topology
+    // blocks' atomics do not all queue on one line; summed into levcnt
+    alignas(256) int32_t levrep[kLevReps][64];
 };
 
 // Host copy of the per-level layout of the box index.
