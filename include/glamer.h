@@ -317,9 +317,12 @@ GLM_API glm_status glm_shoot_direct_nfw(const double* x, const double* y, const 
  * GLM_NFW_HALOS, ds receives dL/dR (the halo size, concentration fixed).
  *   workspace: at least glm_adjoint_workspace_bytes(t, nrays) bytes: the ray
  *   staging of glm_shoot, then FP64 scratch for the box adjoints (2 (order +
- *   1) + 2 words per box) and the per-particle direct-term sums (4 words per
- *   particle).  The tree itself is only read, so adjoints on one tree may run
- *   concurrently on separate streams with separate workspaces.
+ *   1) + 2 words per box, in several copies that the wavefronts add into in
+ *   turn and that are summed before the push-down, so that the atomics on the
+ *   boxes near the root spread over more memory lines) and the per-particle
+ *   direct-term sums (4 words per particle).  The tree itself is only read,
+ *   so adjoints on one tree may run concurrently on separate streams with
+ *   separate workspaces.
  */
 GLM_API glm_status glm_adjoint_workspace_bytes(const glm_tree* t, int64_t nrays, size_t* bytes);
 GLM_API glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* ry,

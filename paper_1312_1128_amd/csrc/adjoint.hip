@@ -40,6 +40,13 @@ namespace glm {
 
 namespace {
 
+// The wavefronts add their box adjoints into kAdjCopies copies (wavefront w
+// into copy w % kAdjCopies), summed into copy 0 before the push-down: the boxes
+// near the root are accepted by nearly every ray group, and with one copy their
+// FP64 atomics all queued on the same few lines.
+constexpr int kAdjCopies = 8;
+
+
 // Cotangents of one ray: alpha (g1, g2), kappa (k), gamma (h1, h2).
 struct Cot {
     float g1, g2, k, h1, h2;
@@ -369,6 +376,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
     int kr;
     int64_t grp;
     if (!walk_task(blockIdx.x, w, groups, K, &kr, &grp)) return;
+    // this wavefront's copy of the box adjoints (see kAdjCopies)
+    double* abox = abar + (size_t)((blockIdx.x * (kBlock / kWave) + w) % kAdjCopies) * T.ncells * NA;
     const int64_t r = grp * kWave + lane;
     const bool valid = r < nrays;
     const double X = valid ? rxs[r] : 0.0, Y = valid ? rys[r] : 0.0;
@@ -523,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
             }
             // lane k adds total k: one atomic instruction over NA adjacent words
             const float mine = word_totals<NA>(a, red, lane);
-            if (lane < NA) unsafeAtomicAdd(abar + (size_t)cur * NA + lane, (double)mine);
+            if (lane < NA) unsafeAtomicAdd(abox + (size_t)cur * NA + lane, (double)mine);
         }
         if (h.info & kInfoLeaf) {
             if (__any(opn)) {
@@ -651,11 +660,23 @@ __global__ void k_fill_zero(double* p, int64_t n)
     if (i < n) p[i] = 0.0;
 }
 
-// FP64 scratch words: box adjoints (NA per box), then 4 direct-term gradients per particle.
+// copy 0 of the box adjoints += copies 1 .. kAdjCopies - 1 (n words each)
+__global__ void k_sum_copies(double* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double s = p[i];
+#pragma unroll
+    for (int r = 1; r < kAdjCopies; ++r) s += p[(size_t)r * n + i];
+    p[i] = s;
+}
+
+// FP64 scratch words: kAdjCopies copies of the box adjoints (NA per box),
+// then 4 direct-term gradients per particle.
 size_t adjoint_scratch_words(const TreeStorage& ts)
 {
     const int NA = 2 * (ts.params.order + 1) + 2;
-    return (size_t)ts.ncells * NA + 4 * (size_t)ts.n;
+    return (size_t)kAdjCopies * ts.ncells * NA + 4 * (size_t)ts.n;
 }
 
 template <int P>
@@ -665,7 +686,8 @@ glm_status launch_adjoint(const TreeStorage& ts, const StagedRays& sr, int64_t n
 {
     constexpr int NA = 2 * (P + 1) + 2;
     const size_t words = adjoint_scratch_words(ts);
-    double* pg = abar + (size_t)ts.ncells * NA;
+    const int64_t nbox = (int64_t)ts.ncells * NA;
+    double* pg = abar + (size_t)kAdjCopies * nbox;
     hipLaunchKernelGGL(k_fill_zero, dim3(ceil_div((int64_t)words, kBlock)), dim3(kBlock), 0, st, abar, (int64_t)words);
     const int64_t blocks = walk_grid_blocks((nrays + kWave - 1) / kWave, K);
     const bool kg = ci.gk || ci.gg1 || ci.gg2;
@@ -680,6 +702,7 @@ glm_status launch_adjoint(const TreeStorage& ts, const StagedRays& sr, int64_t n
         else GLM_ADJ(false, kKindGauss);
     }
 #undef GLM_ADJ
+    hipLaunchKernelGGL(k_sum_copies, dim3(ceil_div(nbox, (int64_t)kBlock)), dim3(kBlock), 0, st, abar, nbox);
     if (kg)
         hipLaunchKernelGGL((k_pushdown<P, true>), dim3(ceil_div(ts.n, kBlock)), dim3(kBlock), 0, st, ts.dev, ts.ms, abar,
                            pg, dm, dx, dy, ds);
