@@ -320,7 +320,7 @@ GLM_API glm_status glm_shoot_direct_nfw(const double* x, const double* y, const 
  *   1) + 2 words per box, in several copies that the wavefronts add into in
  *   turn and that are summed before the push-down, so that the atomics on the
  *   boxes near the root spread over more memory lines) and the per-particle
- *   direct-term sums (4 words per particle).  The tree itself is only read,
+ *   direct-term sums (4 words per particle, likewise in copies).  The tree itself is only read,
  *   so adjoints on one tree may run concurrently on separate streams with
  *   separate workspaces.
  */

@@ -45,6 +45,9 @@ namespace {
 // near the root are accepted by nearly every ray group, and with one copy their
 // FP64 atomics all queued on the same few lines.
 constexpr int kAdjCopies = 8;
+// Likewise the per-particle direct-term sums, in kPgCopies copies that the
+// push-down adds up.
+constexpr int kPgCopies = 4;
 
 
 // Cotangents of one ray: alpha (g1, g2), kappa (k), gamma (h1, h2).
@@ -376,8 +379,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
     int kr;
     int64_t grp;
     if (!walk_task(blockIdx.x, w, groups, K, &kr, &grp)) return;
-    // this wavefront's copy of the box adjoints (see kAdjCopies)
-    double* abox = abar + (size_t)((blockIdx.x * (kBlock / kWave) + w) % kAdjCopies) * T.ncells * NA;
+    // this wavefront's copies of the box adjoints and of the particle sums (see kAdjCopies)
+    const int wid = (int)(blockIdx.x * (kBlock / kWave) + w);
+    double* abox = abar + (size_t)(wid % kAdjCopies) * T.ncells * NA;
+    pg += (size_t)(wid % kPgCopies) * 4 * T.n;
     const int64_t r = grp * kWave + lane;
     const bool valid = r < nrays;
     const double X = valid ? rxs[r] : 0.0, Y = valid ? rys[r] : 0.0;
@@ -647,7 +652,11 @@ __global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __
         c = ch;
     }
     // plus the direct terms the walk gathered for this particle
-    const double* q = pg + 4 * (size_t)k;
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < kPgCopies; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[j] += pg[(size_t)r * 4 * T.n + 4 * (size_t)k + j];
     if (dm) dm[i] += gm + q[0];
     if (dx) dx[i] += gzr + q[1];
     if (dy) dy[i] += q[2] - gzi;
@@ -676,7 +685,7 @@ __global__ void k_sum_copies(double* p, int64_t n)
 size_t adjoint_scratch_words(const TreeStorage& ts)
 {
     const int NA = 2 * (ts.params.order + 1) + 2;
-    return (size_t)kAdjCopies * ts.ncells * NA + 4 * (size_t)ts.n;
+    return (size_t)kAdjCopies * ts.ncells * NA + 4 * (size_t)kPgCopies * ts.n;
 }
 
 template <int P>
