@@ -58,6 +58,7 @@ typedef enum {
 #define GLM_ALPHA_ONLY 1u   /* skip kappa and gamma (Sec. 3.2: the solver's option) */
 #define GLM_FP32_ALPHA 2u   /* alpha terms summed in plain FP32, not FP64 (debug) */
 #define GLM_RAYS_ORDERED 4u /* rays already in a spatially coherent order: skip the ray sort */
+#define GLM_RAYS_STAGED 16u /* the workspace holds these rays as glm_stage_rays left them: skip the ray sort */
 /* build: the particles are truncated NFW halos (Sec. 3.2: analytic halos as
  * particles), not Gaussians.  A halo of mass m, size s = R (its truncation
  * radius, the support) and concentration c = q has the projected NFW surface
@@ -237,13 +238,28 @@ GLM_API glm_status glm_shoot_workspace_bytes(int64_t nrays, size_t* bytes);
  *   workspace: device buffer of at least glm_shoot_workspace_bytes(nrays)
  *   (ray sort, and for small ray counts the partial sums of several
  *   wavefronts per ray group, each walking one range of the box array).
- *   flags: GLM_ALPHA_ONLY, GLM_FP32_ALPHA, GLM_RAYS_ORDERED (or-ed with the
- *   tree's).
+ *   flags: GLM_ALPHA_ONLY, GLM_FP32_ALPHA, GLM_RAYS_ORDERED or GLM_RAYS_STAGED
+ *   (not both; see glm_stage_rays), or-ed with the tree's.
  * nrays may be 0 (nothing is launched).
  */
 GLM_API glm_status glm_shoot(const glm_tree* t, const double* rx, const double* ry, int64_t nrays,
                      float* a1, float* a2, float* kappa, float* g1, float* g2, int32_t* counts,
                      uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * The ray staging of glm_shoot (Sec. 3.3: rays are independent; here they are
+ * sorted along a Morton curve of their bounding square into spatially compact
+ * 64-ray groups, and copied in that order) on its own, so that it can run on
+ * another stream than the tree build, which it does not depend on.  It writes
+ * the staged rays into `workspace` (at least glm_shoot_workspace_bytes(nrays)
+ * bytes, device); a following glm_shoot of the same rx, ry, nrays with flag
+ * GLM_RAYS_STAGED and the same workspace skips its own staging and gives the
+ * same results, bit for bit.  The caller orders that glm_shoot after this call
+ * (an event between the streams), and keeps rx, ry and the workspace unchanged
+ * in between.  rx, ry: device FP64, length nrays; nrays may be 0.
+ */
+GLM_API glm_status glm_stage_rays(const double* rx, const double* ry, int64_t nrays, void* workspace,
+                          size_t workspace_bytes, void* stream);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph
@@ -257,6 +273,8 @@ GLM_API glm_status glm_shoot(const glm_tree* t, const double* rx, const double* 
  * must be ordered by the caller.
  *   nrays: 0 .. GLM_NOALLOC_MAX_RAYS, else GLM_EINVAL with nothing launched;
  *   stream: must belong to the current device (GLM_EINVAL otherwise);
+ *   flags: as glm_shoot except GLM_RAYS_STAGED (GLM_EINVAL: the static array
+ *   holds no rays the caller staged);
  *   other arguments as glm_shoot.
  */
 #define GLM_NOALLOC_MAX_RAYS 1048576
@@ -320,9 +338,12 @@ GLM_API glm_status glm_shoot_direct_nfw(const double* x, const double* y, const 
  *   1) + 2 words per box, in several copies that the wavefronts add into in
  *   turn and that are summed before the push-down, so that the atomics on the
  *   boxes near the root spread over more memory lines) and the per-particle
- *   direct-term sums (4 words per particle, likewise in copies).  The tree itself is only read,
- *   so adjoints on one tree may run concurrently on separate streams with
- *   separate workspaces.
+ *   direct-term sums (4 words per particle, likewise in copies).  The tree
+ *   itself is only read, so adjoints on one tree may run concurrently on
+ *   separate streams with separate workspaces.
+ *   flags: GLM_RAYS_ORDERED, or GLM_RAYS_STAGED when glm_stage_rays staged
+ *   these rays into the start of this workspace (a glm_shoot with the same
+ *   workspace and flag may use them too), or 0.
  */
 GLM_API glm_status glm_adjoint_workspace_bytes(const glm_tree* t, int64_t nrays, size_t* bytes);
 GLM_API glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* ry,

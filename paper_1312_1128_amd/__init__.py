@@ -14,14 +14,14 @@ import ctypes
 import torch
 
 from . import _capi
-from ._capi import (GLM_ALPHA_ONLY, GLM_NFW_HALOS, GLM_FP32_ALPHA, GLM_RAYS_ORDERED, GlamerError,  # noqa: F401
+from ._capi import (GLM_ALPHA_ONLY, GLM_NFW_HALOS, GLM_FP32_ALPHA, GLM_RAYS_ORDERED, GLM_RAYS_STAGED, GlamerError,  # noqa: F401
                     GlmParams, GlmTreeInfo)
 
 __all__ = ["Tree", "shoot", "shoot_direct", "shoot_adjoint", "ShootFn", "GlamerError", "GLM_ALPHA_ONLY",
            "GLM_NFW_HALOS", "GLM_FP32_ALPHA", "GLM_RAYS_ORDERED", "workspace_bytes", "shoot_batched", "refine_round",
            "refine_schedule", "RefinementRun", "autotune", "autotune_batch", "smoothing_lengths", "interp_init",
            "refine_interp_round", "shoot_indexed", "shoot_potential", "knn", "knn_workspace_bytes",
-           "tree_workspace_bytes", "adjoint_workspace_bytes", "shoot_noalloc"]
+           "tree_workspace_bytes", "adjoint_workspace_bytes", "shoot_noalloc", "stage_rays"]
 
 
 def _ptr(t):
@@ -148,17 +148,31 @@ class Tree:
         return out
 
 
+def stage_rays(rx, ry, workspace, stream=None):
+    """glm_stage_rays: the ray staging of shoot() into `workspace` (at least
+    workspace_bytes(R) bytes), on `stream` (a torch.cuda.Stream; default the
+    current one), so that it can overlap the tree build; then
+    shoot(..., staged=True, workspace=workspace) on the build's stream, after
+    an event recorded here, walks the staged rays."""
+    rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
+    s = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    _capi.check(_capi.load().glm_stage_rays(_ptr(rx), _ptr(ry), rx.shape[0], _ptr(workspace), workspace.numel(), s))
+
+
 def shoot(tree: Tree, rx, ry, counts: bool = False, alpha_only: bool = False, fp32_alpha: bool = False,
-          ordered: bool = False, out=None, workspace=None):
+          ordered: bool = False, out=None, workspace=None, staged: bool = False):
     """Forward walk: returns a dict of float32 tensors a1, a2 (and kappa, g1, g2
     unless alpha_only), plus counts [R, 8] int32 if requested: per ray boxes
     visited, accepted, leaf particles, list hits; per wavefront list entries
-    tested, boxes accepted, leaf particles and list candidates evaluated."""
+    tested, boxes accepted, leaf particles and list candidates evaluated.
+    staged: the workspace holds these rays as stage_rays() left them."""
     rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
     R = rx.shape[0]
     dev = rx.device
+    if staged and workspace is None:
+        raise ValueError("staged=True needs the workspace stage_rays() wrote")
     flags = (GLM_ALPHA_ONLY if alpha_only else 0) | (GLM_FP32_ALPHA if fp32_alpha else 0) | \
-            (GLM_RAYS_ORDERED if ordered else 0)
+            (GLM_RAYS_ORDERED if ordered else 0) | (GLM_RAYS_STAGED if staged else 0)
     if out is None:
         names = ["a1", "a2"] if alpha_only else ["a1", "a2", "kappa", "g1", "g2"]
         out = {k: torch.empty(R, dtype=torch.float32, device=dev) for k in names}
@@ -264,10 +278,13 @@ def shoot_direct(x, y, m, s, q, rx, ry, fp64: bool = False, alpha_only: bool = F
 
 
 def shoot_adjoint(tree: Tree, rx, ry, ga1, ga2, dm=None, dx=None, dy=None, ds=None, ordered: bool = False,
-                  workspace=None, gk=None, gg1=None, gg2=None):
+                  workspace=None, gk=None, gg1=None, gg2=None, staged: bool = False):
     """Adjoint walk: accumulates dL/d(m, x, y, s) (float64, original particle
     order) for cotangents ga = dL/dalpha and optionally gk = dL/dkappa,
-    gg = dL/dgamma (float32; any may be None).  Returns (dm, dx, dy, ds)."""
+    gg = dL/dgamma (float32; any may be None).  Returns (dm, dx, dy, ds).
+    staged: stage_rays() staged these rays into the start of `workspace`."""
+    if staged and workspace is None:
+        raise ValueError("staged=True needs the workspace stage_rays() wrote")
     rx, ry = _f64(rx, "rx"), _f64(ry, "ry")
     R = rx.shape[0]
     dev = rx.device
@@ -281,7 +298,7 @@ def shoot_adjoint(tree: Tree, rx, ry, ga1, ga2, dm=None, dx=None, dy=None, ds=No
     if workspace is None:
         workspace = torch.empty(max(adjoint_workspace_bytes(tree, R), 1), dtype=torch.uint8, device=dev)
     ws_bytes = workspace.numel()
-    flags = GLM_RAYS_ORDERED if ordered else 0
+    flags = (GLM_RAYS_ORDERED if ordered else 0) | (GLM_RAYS_STAGED if staged else 0)
     lib = _capi.load()
     _capi.check(lib.glm_shoot_adjoint(tree.handle, _ptr(rx), _ptr(ry), R, _ptr(ga1), _ptr(ga2), _ptr(gk), _ptr(gg1),
                                       _ptr(gg2), _ptr(dm), _ptr(dx), _ptr(dy), _ptr(ds), flags, _ptr(workspace),

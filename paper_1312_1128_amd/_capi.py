@@ -18,6 +18,7 @@ GLM_ALPHA_ONLY = 1
 GLM_FP32_ALPHA = 2
 GLM_RAYS_ORDERED = 4
 GLM_NFW_HALOS = 8
+GLM_RAYS_STAGED = 16
 GLM_INTERP_DEFLECTIONS = 1
 
 # every symbol include/glamer.h declares
@@ -29,7 +30,7 @@ EXPORTED = [
     "glm_interp_round_workspace_bytes", "glm_interp_init", "glm_refine_interp_round",
     "glm_shoot_indexed_workspace_bytes", "glm_shoot_indexed", "glm_shoot_potential", "glm_shoot_direct_nfw",
     "glm_knn_workspace_bytes", "glm_knn", "glm_interp_estimate", "glm_tree_workspace_bytes",
-    "glm_tree_required_bytes", "glm_adjoint_workspace_bytes", "glm_shoot_noalloc",
+    "glm_tree_required_bytes", "glm_adjoint_workspace_bytes", "glm_shoot_noalloc", "glm_stage_rays",
 ]
 
 GLM_NOALLOC_MAX_RAYS = 1048576
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH):
     lib.glm_shoot_workspace_bytes.argtypes = [i64, P(ctypes.c_size_t)]
     lib.glm_shoot_workspace_bytes.restype = st
     lib.glm_shoot.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp]
+    lib.glm_stage_rays.argtypes = [vp, vp, i64, vp, ctypes.c_size_t, vp]
+    lib.glm_stage_rays.restype = st
     lib.glm_shoot.restype = st
     lib.glm_shoot_noalloc.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, u32, vp]
     lib.glm_shoot_noalloc.restype = st

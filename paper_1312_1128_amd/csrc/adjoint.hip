@@ -736,7 +736,9 @@ glm_status adjoint_device(const TreeStorage& ts, const double* rx, const double*
     if (nrays == 0) return GLM_OK;
     StagedRays sr{rx, ry, nullptr};
     const RayLayout L = ray_layout(nrays);
-    if (!(flags & GLM_RAYS_ORDERED)) {
+    if (flags & GLM_RAYS_STAGED) {
+        sr = staged_rays_view(nrays, ws, L); // glm_stage_rays left them at the workspace's start
+    } else if (!(flags & GLM_RAYS_ORDERED)) {
         glm_status rc = stage_rays(rx, ry, nrays, ws, L, &sr, st);
         if (rc != GLM_OK) return rc;
     }

@@ -184,7 +184,10 @@ glm_status glm_shoot(const glm_tree* t, const double* rx, const double* ry, int6
     if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays must be in 0 .. 2^31 - 256");
     if (nrays == 0) return GLM_OK;
     if (!rx || !ry || !a1 || !a2) return fail(GLM_EINVAL, "rx, ry, a1, a2 must be device pointers");
-    if (flags & ~(GLM_ALPHA_ONLY | GLM_FP32_ALPHA | GLM_RAYS_ORDERED)) return fail(GLM_EINVAL, "unknown flag bits");
+    if (flags & ~(GLM_ALPHA_ONLY | GLM_FP32_ALPHA | GLM_RAYS_ORDERED | GLM_RAYS_STAGED))
+        return fail(GLM_EINVAL, "unknown flag bits");
+    if ((flags & GLM_RAYS_ORDERED) && (flags & GLM_RAYS_STAGED))
+        return fail(GLM_EINVAL, "GLM_RAYS_ORDERED and GLM_RAYS_STAGED exclude each other");
     flags |= t->ts.params.flags;
     if (!(flags & GLM_ALPHA_ONLY) && (!kappa || !g1 || !g2))
         return fail(GLM_EINVAL, "kappa, g1, g2 are required unless GLM_ALPHA_ONLY");
@@ -195,6 +198,19 @@ glm_status glm_shoot(const glm_tree* t, const double* rx, const double* ry, int6
     }
     return shoot_device(t->ts, rx, ry, nrays, a1, a2, kappa, g1, g2, counts, flags, workspace,
                         static_cast<hipStream_t>(stream));
+}
+
+glm_status glm_stage_rays(const double* rx, const double* ry, int64_t nrays, void* workspace, size_t workspace_bytes,
+                          void* stream)
+{
+    if (nrays < 0 || nrays > 0x7fffff00) return fail(GLM_EINVAL, "nrays must be in 0 .. 2^31 - 256");
+    if (nrays == 0) return GLM_OK;
+    if (!rx || !ry) return fail(GLM_EINVAL, "rx, ry must be device pointers");
+    const RayLayout L = ray_layout(nrays);
+    if (!workspace || workspace_bytes < L.bytes)
+        return fail(GLM_ENOMEM, "workspace smaller than glm_shoot_workspace_bytes(nrays) = " + std::to_string(L.bytes));
+    StagedRays sr{};
+    return stage_rays(rx, ry, nrays, workspace, L, &sr, static_cast<hipStream_t>(stream));
 }
 
 glm_status glm_shoot_potential(const glm_tree* t, const double* rx, const double* ry, int64_t nrays, float* a1,
@@ -277,7 +293,10 @@ glm_status glm_shoot_adjoint(const glm_tree* t, const double* rx, const double* 
     if (nrays == 0) return GLM_OK;
     if (!rx || !ry) return fail(GLM_EINVAL, "rx, ry must be device pointers");
     if (!ga1 && !ga2 && !gk && !gg1 && !gg2) return fail(GLM_EINVAL, "every cotangent is NULL");
-    if (flags & ~(GLM_FP32_ALPHA | GLM_RAYS_ORDERED | GLM_ALPHA_ONLY)) return fail(GLM_EINVAL, "unknown flag bits");
+    if (flags & ~(GLM_FP32_ALPHA | GLM_RAYS_ORDERED | GLM_ALPHA_ONLY | GLM_RAYS_STAGED))
+        return fail(GLM_EINVAL, "unknown flag bits");
+    if ((flags & GLM_RAYS_ORDERED) && (flags & GLM_RAYS_STAGED))
+        return fail(GLM_EINVAL, "GLM_RAYS_ORDERED and GLM_RAYS_STAGED exclude each other");
     {
         const size_t need = adjoint_workspace_bytes(t->ts, nrays);
         if (!workspace || workspace_bytes < need)

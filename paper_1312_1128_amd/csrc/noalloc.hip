@@ -52,6 +52,7 @@ extern "C" glm_status glm_shoot_noalloc(const glm_tree* t, const double* rx, con
         return fail(GLM_EINVAL, "glm_shoot_noalloc takes at most GLM_NOALLOC_MAX_RAYS = " +
                                     std::to_string((long long)GLM_NOALLOC_MAX_RAYS) + " rays, got " +
                                     std::to_string((long long)nrays));
+    if (flags & GLM_RAYS_STAGED) return fail(GLM_EINVAL, "GLM_RAYS_STAGED needs a caller workspace (glm_stage_rays)");
     const size_t need = ray_layout(nrays).bytes;
     if (need > kScratchBytes) return fail(GLM_EINVAL, "ray workspace exceeds the static scratch array");
     const hipStream_t st = static_cast<hipStream_t>(stream);

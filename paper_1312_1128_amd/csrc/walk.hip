@@ -456,6 +456,16 @@ RayLayout ray_layout(int64_t nrays)
     return L;
 }
 
+// Bits per axis of the ray sort key.  The key only forms the 64-ray groups
+// (per-ray results do not depend on them): about four cells per ray suffice,
+// 8 to 16 bits per axis.
+static int ray_key_bits(int64_t nrays)
+{
+    int bits = 8;
+    while (bits < 16 && (1ll << (2 * bits)) < 4 * nrays) ++bits;
+    return bits;
+}
+
 glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* ws, const RayLayout& L,
                       StagedRays* out, hipStream_t st)
 {
@@ -472,19 +482,23 @@ glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* w
     const int g = ceil_div(nrays, kBlock);
     hipLaunchKernelGGL(k_ray_bbox, dim3(nbb), dim3(kBlock), 0, st, rx, ry, nrays, part);
     hipLaunchKernelGGL(k_ray_root, dim3(1), dim3(kBlock), 0, st, part, nbb, part + 4 * nbb);
-    // the key only forms the 64-ray groups (per-ray results do not depend on
-    // them): about four cells per ray suffice, 8 to 16 bits per axis
-    int bits = 8;
-    while (bits < 16 && (1ll << (2 * bits)) < 4 * nrays) ++bits;
+    const int bits = ray_key_bits(nrays);
     hipLaunchKernelGGL(k_ray_keys, dim3(g), dim3(kBlock), 0, st, rx, ry, nrays, part + 4 * nbb, bits, k0, v0);
     const int w = radix_sort_u32(k0, v0, k1, v1, nrays, (2 * bits + 7) / 8, hist, st);
     const uint32_t* perm = w ? v1 : v0;
     hipLaunchKernelGGL(k_ray_gather, dim3(g), dim3(kBlock), 0, st, perm, rx, ry, nrays, xs, ys);
     GLM_HIP(hipGetLastError());
-    out->xs = xs;
-    out->ys = ys;
-    out->perm = perm;
+    *out = staged_rays_view(nrays, ws, L);
     return GLM_OK;
+}
+
+StagedRays staged_rays_view(int64_t nrays, void* ws, const RayLayout& L)
+{
+    char* W = static_cast<char*>(ws);
+    // the sort ends in (k1, v1) after an odd number of passes (radix_sort_u32)
+    const int passes = (2 * ray_key_bits(nrays) + 7) / 8;
+    const uint32_t* perm = reinterpret_cast<const uint32_t*>(W + ((passes & 1) ? L.v1 : L.v0));
+    return StagedRays{reinterpret_cast<const double*>(W + L.xs), reinterpret_cast<const double*>(W + L.ys), perm};
 }
 
 // ------------------------------------------------------------ batched walk
@@ -722,7 +736,9 @@ glm_status shoot_device(const TreeStorage& ts, const double* rx, const double* r
     if (nrays == 0) return GLM_OK;
     StagedRays sr{rx, ry, nullptr};
     const RayLayout L = ray_layout(nrays);
-    if (!(flags & GLM_RAYS_ORDERED)) {
+    if (flags & GLM_RAYS_STAGED) {
+        sr = staged_rays_view(nrays, ws, L); // glm_stage_rays left them in the workspace
+    } else if (!(flags & GLM_RAYS_ORDERED)) {
         glm_status rc = stage_rays(rx, ry, nrays, ws, L, &sr, st);
         if (rc != GLM_OK) return rc;
     }

@@ -126,6 +126,8 @@ struct StagedRays {
 // each 64-ray group is spatially compact.
 glm_status stage_rays(const double* rx, const double* ry, int64_t nrays, void* ws, const RayLayout& L,
                       StagedRays* out, hipStream_t st);
+// The staged rays that stage_rays left in the workspace (no launch).
+StagedRays staged_rays_view(int64_t nrays, void* ws, const RayLayout& L);
 
 // Index of the deepest box holding the rays' bounding box, written to the
 // workspace (computes the box unless stage_rays did).
