@@ -645,10 +645,15 @@ __global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __
             gzi += szi;
         }
         if (h.info & kInfoLeaf) break;
-        // descend into the child whose Morton range holds position k
-        int ch = c + 1;
-        while (ch < h.next && !(k >= T.cbeg[ch] && k < T.cend[ch])) ch = T.hdr[ch].next > ch ? T.hdr[ch].next : ch + 1;
-        if (ch >= h.next) break;
+        // descend into the child whose Morton range holds position k (the four
+        // children's ranges load together)
+        const int4 kc = *reinterpret_cast<const int4*>(T.kids + 4 * (size_t)c);
+        const int cu[4] = {kc.x, kc.y, kc.z, kc.w};
+        int ch = -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (cu[u] >= 0 && k >= T.cbeg[cu[u]] && k < T.cend[cu[u]]) ch = cu[u];
+        if (ch < 0) break;
         c = ch;
     }
     // plus the direct terms the walk gathered for this particle

@@ -1073,6 +1073,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     ts.dev.cbeg = b.beg;
     ts.dev.cend = b.end;
     ts.dev.perm = reinterpret_cast<int32_t*>(perm);
+    ts.dev.kids = kids;
     ts.dev.lreach = lreach;
     ts.dev.ncells = nc;
     ts.dev.n = n;

@@ -76,6 +76,7 @@ struct TreeDev {
     const int32_t* cbeg;    // box particle range (Morton order)
     const int32_t* cend;
     const int32_t* perm;    // Morton position -> original index
+    const int32_t* kids;    // internal box c: its children at 4c .. 4c + 3 in preorder, -1 past the last
     const double* lreach;   // per box with a list: x0, x1, y0, y1 of the union of its list particles' supports
     int32_t ncells;
     int32_t n;
