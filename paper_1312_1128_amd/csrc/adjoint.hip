@@ -305,12 +305,14 @@ __device__ inline void particles_grad(const PRec* __restrict__ rec, uint64_t sel
             A[2] += Gt[2];
             A[3] += Gt[3];
         }
-        for (int gg = 1; gg < G; ++gg) {
-            const int src = c + gg * C;
+        // the G ray groups' sums meet in group 0 pairwise, in ceil(log2 G) rounds
+        for (int st = 1; st < G; st <<= 1) {
+            const bool take = (g & (2 * st - 1)) == 0 && g + st < G;
+            const int src = take ? lane + st * C : lane;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
                 const double v = __shfl(A[w], src, kWave);
-                if (g == 0) A[w] += v;
+                if (take) A[w] += v;
             }
         }
         if (g == 0) {
@@ -324,34 +326,113 @@ __device__ inline void particles_grad(const PRec* __restrict__ rec, uint64_t sel
     wave_lds_sync(); // the slice is written again by the next user
 }
 
-// Totals over the wavefront of NA per-lane words, returned in lane k for word
-// k < NA.  The lanes store their words in the wavefront's LDS slice (NA * 64
-// floats); lane (k, g) = (l % NA, l / NA) then sums word k over the g-th of
-// G = 64 / NA slices of lanes, and the G partial sums meet by lane shuffles.
-// This replaces NA six-step wavefront sums.
-template <int NA>
-__device__ inline float word_totals(const float* a, float* red, int lane)
+// The words of one lane handed to the lane that DPP control CTRL names, within
+// its 16-lane row.
+template <int CTRL>
+__device__ inline float row_peer(float v)
 {
-    constexpr int G = kWave / NA;            // lane slices (>= 2 for NA <= 32)
-    constexpr int SL = (kWave + G - 1) / G;  // lanes per slice
-    static_assert(G >= 2, "at most 32 words");
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// One halving step inside the rows: the M words of each lane become ceil(M / 2).
+// Partner lanes (as DPP control CTRL pairs them) keep opposite words of each
+// pair (hi: the second) and add the partner's copy; an odd last word is summed
+// over both partners, who then hold the same total.
+template <int M, int CTRL>
+__device__ inline void row_halve(float* v, bool hi)
+{
+    constexpr int NP = M / 2;
 #pragma unroll
-    for (int k = 0; k < NA; ++k) red[lane * NA + k] = a[k];
-    wave_lds_sync();
-    const int k = lane % NA, g = lane / NA;
-    float sum = 0.0f;
-    if (g < G) {
-#pragma unroll
-        for (int i = 0; i < SL; ++i) {
-            const int j = g * SL + i;
-            if (j < kWave) sum += red[j * NA + k];
-        }
+    for (int p = 0; p < NP; ++p) {
+        const float keep = hi ? v[2 * p + 1] : v[2 * p];
+        const float send = hi ? v[2 * p] : v[2 * p + 1];
+        v[p] = keep + row_peer<CTRL>(send);
     }
-    wave_lds_sync(); // the slice is written again for the next box
-    float tot = sum; // every shuffle reads the slices' own sums, not updated ones
+    if constexpr ((M & 1) != 0) v[NP] = v[M - 1] + row_peer<CTRL>(v[M - 1]);
+}
+
+// The halving steps inside a row pair lane j with j ^ 8 (row_ror:8), with
+// 7 - j inside its 8-lane half (row_half_mirror), then with j ^ 2 and j ^ 1
+// (quad_perm); lane bit 3, 2, 1, 0 in turn picks the word kept.
+constexpr int kRowStep[4] = {0x128, 0x141, 0x04E, 0x0B1};
+
+// Totals over the wavefront of NA per-lane words (NA even), by recursive
+// halving across the lanes, in registers.  The 32-lane halves swap the half of
+// the words that the other one keeps (v_permlane32_swap: lane i < 32 exchanges
+// its second operand with the first operand of lane i + 32) and add, so that
+// half h holds words h H .. h H + H - 1 (H = NA / 2), each summed over two
+// lanes; the two 16-lane rows of each half do the same with v_permlane16_swap,
+// so that row R = 2 h + r holds words h H + r Q .. h H + r Q + Q - 1
+// (Q = ceil(H / 2), a zero word filling an odd H) summed over four lanes; four
+// halving steps inside the rows complete the sums over each row's 16 lanes.
+// A lane's total is that of the word word_slot names.  Every lane of the
+// wavefront takes part.
+template <int NA>
+__device__ inline float word_totals(const float* a)
+{
+    static_assert(NA % 2 == 0 && NA <= 64, "an even number of words");
+    constexpr int H = NA / 2;
+    constexpr int Q = (H + 1) / 2;
+    constexpr int M2 = (Q + 1) / 2, M3 = (M2 + 1) / 2, M4 = (M3 + 1) / 2;
+    static_assert((M4 + 1) / 2 == 1, "one word per lane after four steps");
+    float b[H];
 #pragma unroll
-    for (int gg = 1; gg < G; ++gg) tot += __shfl(sum, k + gg * NA, kWave);
-    return tot;
+    for (int k = 0; k < H; ++k) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a[k]), __float_as_uint(a[H + k]), false,
+                                                        false);
+        b[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    float c[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const float hi = k + Q < H ? b[k + Q] : 0.0f;
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[k]), __float_as_uint(hi), false, false);
+        c[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const int j = (int)__lane_id() & 15;
+    row_halve<Q, kRowStep[0]>(c, (j >> 3) & 1);
+    row_halve<M2, kRowStep[1]>(c, (j >> 2) & 1);
+    row_halve<M3, kRowStep[2]>(c, (j >> 1) & 1);
+    row_halve<M4, kRowStep[3]>(c, j & 1);
+    return c[0];
+}
+
+// The word whose total word_totals leaves in this lane: the same halving
+// steps applied to word indices.  -1 where the lane holds no word, or a copy of
+// a total that another lane holds too (only one lane adds it).
+template <int NA>
+__device__ inline int word_slot(int lane)
+{
+    constexpr int H = NA / 2;
+    constexpr int Q = (H + 1) / 2;
+    const int j = lane & 15, R = lane >> 4;
+    int wd[Q];
+    bool own[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        wd[k] = k;
+        own[k] = true;
+    }
+    int m = Q;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        const bool hi = ((j >> (3 - st)) & 1) != 0;
+        const int np = m / 2;
+#pragma unroll
+        for (int p = 0; p < Q / 2; ++p) {
+            if (p < np) {
+                wd[p] = hi ? wd[2 * p + 1] : wd[2 * p];
+                own[p] = hi ? own[2 * p + 1] : own[2 * p];
+            }
+        }
+        if (m & 1) {
+            wd[np] = wd[m - 1];
+            own[np] = own[m - 1] && !hi;
+        }
+        m = np + (m & 1);
+    }
+    const int i = (R & 1) * Q + wd[0];
+    return own[0] && i < H ? (R >> 1) * H + i : -1;
 }
 
 // Cotangent arrays of the rays (input order); any may be NULL (zero).
@@ -368,14 +449,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
 {
     // (Re, Im) of Abar_0 .. Abar_{P+1}, or with KG of Abar_0 .. Abar_P and Bbar
     constexpr int NA = 2 * (P + 1) + 2;
-    // per wavefront: the box words of its 64 lanes, or the packed ray table of a particle pass
-    constexpr int kSlice = kWave * NA > kRayTableFloats ? kWave * NA : kRayTableFloats;
-    __shared__ __align__(16) float red_all[(kBlock / kWave) * kSlice];
+    // per wavefront: the packed ray table of a particle pass
+    __shared__ __align__(16) float red_all[(kBlock / kWave) * kRayTableFloats];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t groups = (nrays + kWave - 1) / kWave;
     // wave-uniform work item (kept in SGPRs): box range kr, ray group grp
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    float* red = red_all + (size_t)w * kSlice;
+    float* red = red_all + (size_t)w * kRayTableFloats;
     int kr;
     int64_t grp;
     if (!walk_task(blockIdx.x, w, groups, K, &kr, &grp)) return;
@@ -401,6 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
     const double gx0 = wave_min(valid ? X : INFINITY), gx1 = wave_max(valid ? X : -INFINITY);
     const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
     const float invC = T.invC;
+    const int wslot = word_slot<NA>(lane); // the box word this lane adds (see word_totals)
 
     // this wavefront's range of the preorder box array (see ancestor_skip)
     const int nc = T.ncells;
@@ -408,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
     if (K > 1) {
         const int B = __builtin_amdgcn_readfirstlane(*split_box);
         if (B >= 0) {
-            split_range(kr, K, B, T.hdr[B].next, nc, &c0, &c1);
+            split_range(kr, K, B, uniform_ld(T.hdr, B).next, nc, &c0, &c1);
         } else { // no split: the first range takes every box
             c1 = kr == 0 ? nc : 0;
         }
@@ -418,10 +499,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
     int cur = c0;
     while (cur < c1) {
         cur = __builtin_amdgcn_readfirstlane(cur);
-        const CellHdr h = T.hdr[cur];
+        const CellHdr h = uniform_ld(T.hdr, cur);
         const bool act = cur >= skip;
         if ((h.info & kInfoList) && list_reaches(T, cur, gx0, gx1, gy0, gy1)) {
-            const CellExt e = T.ext[cur];
+            const CellExt e = uniform_ld(T.ext, cur);
             for (int base = e.lbeg; base < e.lend; base += kWave) {
                 const int j = base + lane;
                 bool cand = false;
@@ -450,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                 // alpha cotangents only: the words are g_hat v t^k for k = 0 .. P + 1; the
                 // centre-of-mass adjoint sum_k (k + 1) Q_k Abar_{k+1} is formed from them
                 // in the push-down
-                const float rcm = T.mom[(size_t)cur * mom_stride(P) + 1];
+                const float rcm = uniform_ld(T.mom, (int64_t)cur * mom_stride(P) + 1);
                 const float inv = __builtin_amdgcn_rcpf(f1 * f1 + f2 * f2);
                 const float v1 = f1 * inv, v2 = -f2 * inv;
                 const float t1 = rcm * v1, t2 = rcm * v2;
@@ -535,13 +616,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
                     a[NA - 1] -= h1 * U2 + h2 * U1;
                 }
             }
-            // lane k adds total k: one atomic instruction over NA adjacent words
-            const float mine = word_totals<NA>(a, red, lane);
-            if (lane < NA) unsafeAtomicAdd(abox + (size_t)cur * NA + lane, (double)mine);
+            // one atomic instruction over the NA adjacent words
+            const float mine = word_totals<NA>(a);
+            if (wslot >= 0) unsafeAtomicAdd(abox + (size_t)cur * NA + wslot, (double)mine);
         }
         if (h.info & kInfoLeaf) {
             if (__any(opn)) {
-                const CellExt e = T.ext[cur];
+                const CellExt e = uniform_ld(T.ext, cur);
                 const uint64_t rays = __ballot(opn);
                 for (int j = e.pbeg; j < e.pend; j += kWave) { // a leaf at the depth cap may exceed 64
                     const int np = e.pend - j < kWave ? e.pend - j : kWave;

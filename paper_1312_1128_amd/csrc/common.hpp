@@ -89,6 +89,25 @@ struct TreeDev {
     double psiK;            // potential constant: Ein(q^2/2) (Gaussians) or H(c) (NFW halos)
 };
 
+// Element i of tree data that no kernel writes while the reading kernel runs,
+// at a wavefront-uniform index: read through the constant address space, so
+// that it becomes a scalar load whatever else the kernel stores (LDS stores
+// at computed addresses otherwise make the compiler fall back to vector loads).
+// (Read as 32-bit words: a class type has no copy from that address space.)
+template <class E>
+__device__ __forceinline__ E uniform_ld(const E* p, int64_t i)
+{
+    static_assert(sizeof(E) % 4 == 0, "whole 32-bit words");
+    using ConstW = const __attribute__((address_space(4))) uint32_t;
+    ConstW* q = (ConstW*)(p + i); // an address-space conversion, which only a C-style cast spells
+    struct Words {
+        uint32_t w[sizeof(E) / 4];
+    } v;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(E) / 4); ++k) v.w[k] = q[k];
+    return __builtin_bit_cast(E, v);
+}
+
 // ---------------------------------------------------------------------------
 // host-side error plumbing
 // ---------------------------------------------------------------------------

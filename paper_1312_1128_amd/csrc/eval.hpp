@@ -522,8 +522,9 @@ __device__ inline void eval_box(const float* __restrict__ mo, double w1, double 
 __device__ inline bool list_reaches(const TreeDev& T, int c, double gx0, double gx1, double gy0, double gy1)
 {
     // the four bounds load together and the tests combine without branches
-    const double* lr = T.lreach + 4 * (size_t)c;
-    const double r0 = lr[0], r1 = lr[1], r2 = lr[2], r3 = lr[3];
+    const int64_t i = 4 * (int64_t)c;
+    const double r0 = uniform_ld(T.lreach, i), r1 = uniform_ld(T.lreach, i + 1);
+    const double r2 = uniform_ld(T.lreach, i + 2), r3 = uniform_ld(T.lreach, i + 3);
     return (gx1 >= r0) & (gx0 <= r1) & (gy1 >= r2) & (gy0 <= r3);
 }
 
