@@ -241,6 +241,28 @@ def test_adjoint_kappa_gamma_matches_oracle_tree(ora, case):
         compare(name, a, b, 1e-4, 2e-6)
 
 
+@pytest.mark.parametrize("order", range(13))
+def test_adjoint_every_order_matches_oracle_tree(ora, order):
+    """Every multipole order the boundary accepts, with alpha cotangents and with
+    kappa and gamma ones: an accepted box's 2p + 4 adjoint words are summed over
+    the wavefront's lanes in registers, in a lane layout that depends on the
+    number of words (odd and even halves, every count from 4 to 28)."""
+    lens = mixed_lens(1500, 331)
+    theta, leaf = 0.6, 8
+    say(f"[gpu] adjoint at order {order}: n={lens.n} theta={theta}")
+    rx, ry = synth.uniform_points(1500, 333)
+    g0 = synth.rng(335 + order)
+    ga, gk, gg = f32(g0.normal(size=(rx.size, 2))), f32(g0.normal(size=rx.size)), f32(g0.normal(size=(rx.size, 2)))
+    tree = build(lens, theta, leaf, order)
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, theta, leaf, order)
+    for name, a, b in zip(["dL/dm", "dL/dx", "dL/dy", "dL/ds"], gpu_grad(tree, rx, ry, ga), T.grad(rx, ry, ga)):
+        compare(name, a, b, 1e-4, 2e-6)
+    got = gpu_grad_kg(tree, rx, ry, ga, gk, gg)
+    ref = T.grad(rx, ry, ga, gk=gk, gg=gg)
+    for name, a, b in zip(["kg dL/dm", "kg dL/dx", "kg dL/dy", "kg dL/ds"], got, ref):
+        compare(name, a, b, 1e-4, 2e-6)
+
+
 def test_adjoint_kappa_gamma_theta_zero_vs_bruteforce(ora):
     lens = mixed_lens(2500, 321)
     rx, ry = synth.uniform_points(1500, 323)
