@@ -127,9 +127,11 @@ GLM_API glm_status glm_tree_workspace_bytes(int64_t n, const glm_params* params,
 /*
  * Build the tree of n particles (Sec. 3.2): the root square covers the
  * particles' bounding box (side = max extent * (1 + 2^-40)); particles are
- * ordered by 64-bit Morton keys of 32-bit quantised coordinates; boxes are the
- * Morton-prefix ranges, a box with <= leaf_size particles (or at depth 32) is a
- * leaf; the moments Q_k = sum m (z - z_cm)^k, k <= order, are built in FP64;
+ * ordered by 64-bit Morton keys of 32-bit quantised coordinates, compared on
+ * their top 32 bits when the tree has no box below level 16 and on all 64
+ * otherwise (equal keys in input order; both orders give the same boxes);
+ * boxes are the Morton-prefix ranges, a box with <= leaf_size particles (or at
+ * depth 32) is a leaf; the moments Q_k = sum m (z - z_cm)^k, k <= order, are built in FP64;
  * r_cut^2 = (farthest-corner distance from the centre of mass / theta)^2; a
  * smoothed particle is listed in the highest box where q s > side / 2, if that
  * box is not below its leaf.
@@ -172,7 +174,7 @@ GLM_API glm_status glm_tree_get_info(const glm_tree* t, glm_tree_info* out);
  *     leaf (0/1), lbeg, lend (range in the list arrays);
  *     M, cx, cy, rcut2 (FP64); Q: 2*(order+1) doubles per box, (Re, Im) of
  *     Q_0..Q_order about the centre of mass (Q_1 as computed, ~0);
- *   per particle (n, Morton order): perm (original index of the k-th
+ *   per particle (n, the build's order): perm (original index of the k-th
  *     particle), key (its 64-bit Morton key, x bits even, y bits odd);
  *   per list entry (nlisted): list_idx (original particle index).
  * Synchronises the device.

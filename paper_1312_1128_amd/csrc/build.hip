@@ -226,9 +226,44 @@ __global__ __launch_bounds__(kBlock) void k_gather(const uint32_t* __restrict__ 
 //    [i - L, i) and ends in (i, i + L].
 // A window of L positions on either side of i decides both; the block keeps
 // ls over its window in LDS.
+// After the sort on the keys' top digits: the runs of keys equal in those
+// digits ordered by the whole key, from (Ki, Vi) into (Ko, Vo), with the
+// values also into perm.  Thread i finds its run (a scan of at most kTieRun
+// keys each way) and its rank in it by (key, position), so equal keys keep
+// their order.  Runs longer than kTieRun keep their order: they hold more than
+// L particles, which the topology count flags.
+__global__ __launch_bounds__(kBlock) void k_order_ties(const uint64_t* __restrict__ Ki, const uint32_t* __restrict__ Vi,
+                                                       uint64_t* __restrict__ Ko, uint32_t* __restrict__ Vo,
+                                                       uint32_t* __restrict__ perm, int n)
+{
+    constexpr int sh = 64 - 2 * kTopLevel;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t key = Ki[i];
+    const uint64_t top = key >> sh;
+    int b = i, e = i + 1;
+    while (b > 0 && i - b < kTieRun && (Ki[b - 1] >> sh) == top) --b;
+    while (e < n && e - i <= kTieRun && (Ki[e] >> sh) == top) ++e;
+    int pos = i;
+    // every thread of a run of at most kTieRun keys sees all of it; a longer
+    // run is seen as longer by each of its threads, so all of them keep their place
+    const bool long_run = e - b > kTieRun || (b > 0 && (Ki[b - 1] >> sh) == top) || (e < n && (Ki[e] >> sh) == top);
+    if (e - b > 1 && !long_run) {
+        pos = b;
+        for (int j = b; j < e; ++j) {
+            const uint64_t kj = Ki[j];
+            pos += (kj < key || (kj == key && j < i)) ? 1 : 0;
+        }
+    }
+    const uint32_t v = Vi[i];
+    Ko[pos] = key;
+    Vo[pos] = v;
+    perm[pos] = v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_topo_count(const uint64_t* __restrict__ K, int n, int L,
                                                       int32_t* __restrict__ cnt, int8_t* __restrict__ lstart,
-                                                      BuildSync* __restrict__ sync)
+                                                      BuildSync* __restrict__ sync, int check)
 {
     __shared__ int32_t hist[kMaxLevel + 1];
     __shared__ int8_t lsw[kBlock + 2 * kMaxLeafSize + 1]; // ls(j) for j in [base - L, base + kBlock + L]
@@ -270,7 +305,12 @@ __global__ __launch_bounds__(kBlock) void k_topo_count(const uint64_t* __restric
         }
         cnt[i] = c;
     }
-    __syncthreads();
+    // check: is there a box below level kTopLevel, i.e. L + 1 consecutive
+    // keys sharing their top 2 kTopLevel bits?  (After the sort on the top
+    // digits only, the counts above hold unless there is.)
+    const bool full = check && i + L < n &&
+                      (K[i] >> (64 - 2 * kTopLevel)) == (K[i + L] >> (64 - 2 * kTopLevel));
+    if (__syncthreads_or(full) && threadIdx.x == 0) atomicOr(&sync->deep, 1);
     if (threadIdx.x <= kMaxLevel && hist[threadIdx.x])
         atomicAdd(&sync->levrep[blockIdx.x % kLevReps][threadIdx.x], hist[threadIdx.x]);
 }
@@ -925,20 +965,51 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
     static_assert(sizeof(PRec) >= sizeof(Particle4), "packed inputs must fit the record array");
     Particle4* packed = reinterpret_cast<Particle4*>(prt);
     hipLaunchKernelGGL(k_morton, dim3(gb), dim3(kBlock), 0, st, x, y, m, s, (int64_t)n, sync, k0, v0, packed);
-    const int where = radix_sort_u64(k0, v0, k1, v1, n, 8, hist, st);
+    // the keys' top digits, then the runs equal in them (see kTopDigits); all
+    // 64 bits where a box below level kTopLevel exists.  Either way the
+    // particles end in the full-key order.
+    const bool full_first = ts.deep;
+    int where = full_first ? radix_sort_u64(k0, v0, k1, v1, n, 8, hist, st)
+                           : radix_sort_u64_digits(k0, v0, k1, v1, n, 8 - kTopDigits, kTopDigits, hist, st);
     uint64_t* K = where ? k1 : k0;
     uint32_t* pv = where ? v1 : v0;
-    GLM_HIP(hipMemcpyAsync(perm, pv, 4ull * n, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_gather, dim3(gb), dim3(kBlock), 0, st, perm, packed, (int64_t)n, xs, ys, ms, ss);
-    hipLaunchKernelGGL(k_topo_count, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart, sync);
-    exclusive_scan_i32(cnt, cnt, n, scr, st);
-    hipLaunchKernelGGL(k_sync_counts, dim3(1), dim3(kWave), 0, st, cnt, n, sync);
-    GLM_HIP(hipGetLastError());
-
+    if (!full_first) { // the runs equal in the top digits, into the spare buffers (and perm)
+        hipLaunchKernelGGL(k_order_ties, dim3(gb), dim3(kBlock), 0, st, K, pv, where ? k0 : k1, where ? v0 : v1,
+                           perm, n);
+        where = !where;
+        K = where ? k1 : k0;
+        pv = where ? v1 : v0;
+    }
     BuildSync hs;
-    GLM_HIP(hipMemcpyAsync(&hs, sync, sizeof(BuildSync), hipMemcpyDeviceToHost, st));
-    GLM_HIP(hipStreamSynchronize(st));
+    auto count_boxes = [&](bool copy_perm) -> glm_status {
+        if (copy_perm) GLM_HIP(hipMemcpyAsync(perm, pv, 4ull * n, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_gather, dim3(gb), dim3(kBlock), 0, st, perm, packed, (int64_t)n, xs, ys, ms, ss);
+        hipLaunchKernelGGL(k_topo_count, dim3(gb), dim3(kBlock), 0, st, K, n, L, cnt, lstart, sync, 1);
+        exclusive_scan_i32(cnt, cnt, n, scr, st);
+        hipLaunchKernelGGL(k_sync_counts, dim3(1), dim3(kWave), 0, st, cnt, n, sync);
+        GLM_HIP(hipGetLastError());
+        GLM_HIP(hipMemcpyAsync(&hs, sync, sizeof(BuildSync), hipMemcpyDeviceToHost, st));
+        GLM_HIP(hipStreamSynchronize(st));
+        return GLM_OK;
+    };
+    glm_status cst = count_boxes(full_first);
+    if (cst != GLM_OK) return cst;
     if (hs.bad) return fail(GLM_EDATA, "build_tree: NaN/Inf value or negative mass/smoothing length");
+    ts.deep = hs.deep != 0;
+    if (hs.deep && !full_first) {
+        // a box at level kTopLevel holds more than L particles: order on every
+        // digit (a stable sort of the top-digit order gives the full-key order)
+        // and count the boxes again
+        const int w2 = radix_sort_u64(K, pv, where ? k0 : k1, where ? v0 : v1, n, 8, hist, st);
+        if (w2) {
+            K = where ? k0 : k1;
+            pv = where ? v0 : v1;
+            where = !where;
+        }
+        GLM_HIP(hipMemsetAsync(sync->levrep, 0, sizeof(sync->levrep), st));
+        cst = count_boxes(true);
+        if (cst != GLM_OK) return cst;
+    }
     const int nc = hs.ncells;
 
     // ---- per-box part of the workspace, after the per-particle part

@@ -6,6 +6,21 @@
 namespace glm {
 
 constexpr int kLevReps = 16;
+
+// The particle sort first orders the Morton keys on their top kTopDigits
+// 8-bit digits only (the boxes down to level 4 kTopDigits), then orders each
+// run of keys equal in those digits by the rest (runs of up to kTieRun keys):
+// the full-key order, unless a box at level kTopLevel holds more than L
+// particles.  The topology count flags that case
+// (BuildSync::deep), and the build then sorts on all 64 bits; a tree that was
+// deep at its last build starts with the full sort.
+constexpr int kTopDigits = 4;
+constexpr int kTieRun = 64;
+constexpr int kTopLevel = 4 * kTopDigits;
+
+// radix_sort_u64 on the digits first .. first + passes - 1 only (sort.hip).
+int radix_sort_u64_digits(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t n, int first, int passes,
+                          uint32_t* hist, hipStream_t s);
 static_assert(kMaxLevel + 1 <= 64, "a level-count copy holds 64 levels");
 
 // Small device struct written by the build kernels; copied to the host once.
@@ -17,6 +32,7 @@ struct BuildSync {
     int32_t max_level;
     int32_t nlisted;
     int32_t internal;           // consistency flags of the build (0 = ok)
+    int32_t deep;               // a box at level kTopLevel holds more than L particles
     int32_t levcnt[kMaxLevel + 2];  // boxes per level
     int32_t levfill[kMaxLevel + 2]; // fill counters of the per-level box index
     // boxes per level counted in kLevReps copies (block b adds into copy
@@ -64,6 +80,7 @@ struct TreeStorage {
     BoxArrays b{};
     int32_t* perm = nullptr;   // Morton position -> original index
     uint64_t* key = nullptr;   // sorted Morton keys
+    bool deep = false;         // the last build had a box below level kTopLevel
     double *ccx = nullptr, *ccy = nullptr;
     double* ms = nullptr;      // FP64 masses in Morton order
     TreeDev dev{};

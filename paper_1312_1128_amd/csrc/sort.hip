@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K* kin, const ui
 }
 
 template <class K>
-int radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n, int passes, uint32_t* hist,
+int radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n, int first, int passes, uint32_t* hist,
                     hipStream_t s)
 {
     if (n <= 1 || passes <= 0) return 0;
@@ -258,7 +258,7 @@ int radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n, int pas
     K* ko = k1;
     uint32_t* vo = v1;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
+        const int shift = 8 * (first + p);
         hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(kBlock), 0, s, ki, n, shift, hist, nb);
         hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kBlock), 0, s, hist, nb, pre, dtot);
         hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, n, shift, hist,
@@ -291,13 +291,19 @@ size_t radix_hist_words(int64_t n)
 int radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t n, int passes,
                    uint32_t* hist, hipStream_t s)
 {
-    return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n, passes, hist, s);
+    return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n, 0, passes, hist, s);
+}
+
+int radix_sort_u64_digits(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t n, int first, int passes,
+                          uint32_t* hist, hipStream_t s)
+{
+    return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n, first, passes, hist, s);
 }
 
 int radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int passes,
                    uint32_t* hist, hipStream_t s)
 {
-    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, passes, hist, s);
+    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, 0, passes, hist, s);
 }
 
 } // namespace glm

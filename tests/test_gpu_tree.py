@@ -26,10 +26,14 @@ CASES = {
 }
 
 
-def compare_topology(ora, lens, theta, leaf, order):
+def compare_topology(ora, lens, theta, leaf, order, tree=None):
     T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, theta, leaf, order)
     ex = T.export()
-    tree = build(lens, theta, leaf, order)
+    if tree is None:
+        tree = build(lens, theta, leaf, order)
+    else:  # rebuild the given handle
+        tree.build(dev(lens.x), dev(lens.y), dev(lens.m), dev(lens.s), theta=theta, q=lens.q, leaf_size=leaf,
+                   order=order)
     g = tree.export()
     assert g["check_flags"] == 0
     nc = T.ncells
@@ -54,10 +58,17 @@ def compare_topology(ora, lens, theta, leaf, order):
     side = S / 2.0 ** ex["level"]
     assert np.all(np.abs(g["cx"] - ex["cx"]) <= 1e-12 * np.maximum(side, 1e-300) + 1e-15)
     assert np.all(np.abs(g["cy"] - ex["cy"]) <= 1e-12 * np.maximum(side, 1e-300) + 1e-15)
-    np.testing.assert_allclose(g["rcut2"], ex["rcut2"], rtol=1e-10)
+    # r_cut = r_cm / theta moves with the centre of mass: by at most what the
+    # tolerance above allows for it (the bound that decides at boxes ~1e-7 across)
+    dr = np.sqrt(2.0) * (1e-12 * np.maximum(side, 1e-300) + 1e-15) / theta
+    assert np.all(np.abs(g["rcut2"] - ex["rcut2"]) <= 1e-10 * ex["rcut2"] + 2 * np.sqrt(ex["rcut2"]) * dr + dr * dr)
+    # Q_k about the centre of mass: a shift dz of the centre moves it by
+    # k dz Q_{k-1}, |Q_{k-1}| <= M (sqrt(2) side)^(k-1); dz as allowed above
+    dz = np.sqrt(2.0) * (1e-12 * np.maximum(side, 1e-300) + 1e-15)
     for k in range(order + 1):
         scale = ex["M"] * (np.sqrt(2) * side) ** k
-        assert np.all(np.abs(g["Q"][:, k] - ex["Q"][:, k]) <= 1e-10 * scale + 1e-300), k
+        shift = k * ex["M"] * dz * (np.sqrt(2) * side) ** max(k - 1, 0)
+        assert np.all(np.abs(g["Q"][:, k] - ex["Q"][:, k]) <= 1e-10 * scale + shift + 1e-300), k
     return T, tree
 
 
@@ -82,6 +93,42 @@ def test_tree_and_walk_match_oracle_tree(ora, case):
         stats("kappa vs oracle tree", ek[ok])
         assert np.all(ek[ok] < 5e-6)
     assert_matches_oracle_tree(got, ref)
+
+
+def test_particle_order_on_every_sort_path(ora):
+    """The particles end in the full Morton-key order (equal keys in input
+    order) whichever way the build sorted them: on the keys' top 32 bits with
+    the runs equal in them ordered afterwards (no box below level 16), on all
+    64 bits after finding such a box, and on all 64 bits first when the handle's
+    last build had one; each time with the oracle tree's topology."""
+    g0 = synth.rng(341)
+    base = mixed_lens(4000, 343)
+    S = 1.0  # the lenses span about one unit
+
+    def with_clusters(sizes, spread):
+        lens = synth.Lens(base.x.copy(), base.y.copy(), base.m.copy(), base.s.copy(), q=base.q)
+        at = 0
+        for k in sizes:  # k particles within spread * S of particle `at`
+            lens.x[at + 1:at + k] = lens.x[at] + spread * S * g0.uniform(-1, 1, k - 1)
+            lens.y[at + 1:at + k] = lens.y[at] + spread * S * g0.uniform(-1, 1, k - 1)
+            at += k
+        return lens
+
+    shallow = with_clusters([2, 3, 5, 2, 4, 3, 6, 2] * 3, 1e-7)  # runs equal in the top bits, none above L
+    deep = with_clusters([40, 3, 2], 1e-7)                        # a box below level 16
+    deep.x[100:120], deep.y[100:120] = deep.x[100], deep.y[100]   # and 20 coincident ones (the depth cap)
+    tree = None
+    for name, lens in [("shallow", shallow), ("deep", deep), ("deep again", deep), ("shallow after deep", shallow),
+                       ("shallow again", shallow)]:
+        say(f"[gpu] sort path: {name}")
+        T, tree = compare_topology(ora, lens, 0.5, 8, 3, tree=tree)
+        ex = tree.export()
+        key, perm = ex["key"], ex["perm"]
+        assert np.all(key[1:] >= key[:-1]), name
+        eq = key[1:] == key[:-1]
+        assert np.all(perm[1:][eq] > perm[:-1][eq]), name
+        np.testing.assert_array_equal(np.sort(perm), np.arange(lens.n))
+    assert int(eq.sum()) == 0  # the shallow lens has no equal keys, only keys equal in their top bits
 
 
 def test_massless_boxes_match_oracle_tree(ora):
