@@ -688,6 +688,8 @@ __global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __
                 }
             }
             // sm = sum_k Abar_k dQ_k/dm + Bbar d/M ; sz = sum_k Abar_k dQ_k/dz + Bbar m/M
+            // (one reciprocal of M per box: an FP64 division is a long instruction sequence)
+            const double iM = M > 0.0 ? 1.0 / M : 0.0, miM = mi * iM;
             double smr = 0.0, smi = 0.0, szr = 0.0, szi = 0.0;
             double dkr = 1.0, dki = 0.0, dkm1r = 0.0, dkm1i = 0.0; // d^k, d^(k-1)
             double irk = 1.0;                                      // r_cm^-k
@@ -699,10 +701,10 @@ __global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __
                 if (M > 0.0 && kk > 0) {
                     const double qr = Q[2 * (kk - 1)], qi = Q[2 * (kk - 1) + 1];
                     // k Q_{k-1} d / M and k Q_{k-1} m / M
-                    tmr -= kk * (qr * dr - qi * di) / M;
-                    tmi -= kk * (qr * di + qi * dr) / M;
-                    tzr -= kk * qr * mi / M;
-                    tzi -= kk * qi * mi / M;
+                    tmr -= kk * (qr * dr - qi * di) * iM;
+                    tmi -= kk * (qr * di + qi * dr) * iM;
+                    tzr -= kk * qr * miM;
+                    tzi -= kk * qi * miM;
                 }
                 smr += Ar * tmr - Ai * tmi;
                 smi += Ar * tmi + Ai * tmr;
@@ -716,10 +718,10 @@ __global__ __launch_bounds__(kBlock) void k_pushdown(TreeDev T, const double* __
                 irk *= irc;
             }
             if (M > 0.0) {
-                smr += (Br * dr - Bi * di) / M;
-                smi += (Br * di + Bi * dr) / M;
-                szr += Br * mi / M;
-                szi += Bi * mi / M;
+                smr += (Br * dr - Bi * di) * iM;
+                smi += (Br * di + Bi * dr) * iM;
+                szr += Br * miM;
+                szi += Bi * miM;
             }
             gm += smr;
             gzr += szr;
