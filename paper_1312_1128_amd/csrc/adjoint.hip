@@ -495,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_walk(TreeDev T, const double
         }
     }
     int skip = valid ? 0 : 0x7fffffff;
-    if (c0 > 0) skip = ancestor_skip(T, X, Y, c0, skip);
+    if (c0 > 0 && c0 < c1) skip = ancestor_skip(T, X, Y, c0, skip); // (an empty range walks nothing)
     int cur = c0;
     while (cur < c1) {
         cur = __builtin_amdgcn_readfirstlane(cur);

@@ -531,18 +531,21 @@ __device__ inline bool list_reaches(const TreeDev& T, int c, double gx0, double 
 // The walk of a preorder range [c0, c1) of boxes: every ancestor of a box in
 // the range is either in the range or an ancestor of c0.  A lane that accepts
 // an ancestor of c0 skips that ancestor's whole subtree; returns the preorder
-// index at which the lane becomes active (its current skip if none).
+// index at which the lane becomes active (its current skip if none).  c0 must
+// be a box (c0 < ncells): an empty range at the end of the array has no
+// ancestors to replay, and its walk is not made.
 __device__ inline int ancestor_skip(const TreeDev& T, double X, double Y, int c0, int skip)
 {
+    const int nc = T.ncells;
     int a = 0;
-    while (a < c0) {
+    while (a < c0 && a < nc) {
         a = __builtin_amdgcn_readfirstlane(a);
         const CellHdr ha = T.hdr[a];
         double w1, w2;
         const double d2 = sqdist(X, Y, ha.cx, ha.cy, &w1, &w2);
         if (skip == 0 && d2 > ha.rcut2) skip = ha.next;
         int ch = a + 1; // the child of a whose subtree holds c0
-        for (int guard = 0; guard < 4; ++guard) {
+        for (int guard = 0; guard < 4 && ch < nc; ++guard) {
             const int nx = T.hdr[ch].next;
             if (c0 < nx) break;
             ch = nx;

@@ -45,7 +45,7 @@ __device__ inline void walk_group(const TreeDev& T, double X, double Y, bool val
     const double gy0 = wave_min(valid ? Y : INFINITY), gy1 = wave_max(valid ? Y : -INFINITY);
     int n_vis = 0, n_acc = 0, n_dir = 0, n_hit = 0, n_scan = 0, w_acc = 0, w_dir = 0, w_cand = 0;
     int skip = valid ? 0 : 0x7fffffff;
-    if (c0 > 0) skip = ancestor_skip(T, X, Y, c0, skip);
+    if (c0 > 0 && c0 < c1) skip = ancestor_skip(T, X, Y, c0, skip); // (an empty range walks nothing)
     int cur = c0;
     while (cur < c1) {
         cur = __builtin_amdgcn_readfirstlane(cur);

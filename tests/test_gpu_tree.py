@@ -300,6 +300,46 @@ def test_split_walk_matches_single_range(ora):
     np.testing.assert_allclose(got_big[:, :2], got[:, :2], rtol=2e-6, atol=1e-7 * np.abs(got[:, :2]).max())
 
 
+def test_split_walk_with_an_empty_last_range(ora):
+    """Rays over the whole lens: the box that holds them all is the root, so the
+    split walk's last range (the boxes after that box's subtree) is empty.  Its
+    wavefronts replay no ancestors: the replay for a range starting at the end
+    of the box array used to step past the root's last child (two children
+    here, a collinear lens) and read a header beyond the array.  Forward and
+    adjoint against the oracle tree."""
+    import paper_1312_1128_amd as g
+    import torch
+
+    gen = synth.rng(119)
+    n = 2000
+    t = gen.uniform(0.05, 0.5, n) * np.where(gen.random(n) < 0.5, -1.0, 1.0)
+    x, y = t, 0.3 * t * (1.0 + 1e-2 * gen.normal(size=n))  # two opposite quadrants of the root, none near its centre
+    s = gen.uniform(0.002, 0.1, n)
+    s[gen.random(n) < 0.2] = 0.0
+    lens = synth.Lens(x, y, gen.uniform(0.1, 1.0, n) / n, s, q=3.0)
+    rx, ry = gen.uniform(-0.6, 0.6, 300), gen.uniform(-0.6, 0.6, 300)
+    say("[gpu] split walk with an empty last range (collinear lens, 300 rays)")
+    tree = build(lens, 0.4, 4, 5)
+    T = ora.Tree(lens.x, lens.y, lens.m, lens.s, lens.q, 0.4, 4, 5)
+    ex = T.export()
+    kids, ch = 0, 1
+    while ch < T.ncells:
+        kids += 1
+        ch = int(ex["next"][ch])
+    assert kids <= 2 and T.ncells >= 256  # the case above: a split walk over a root with two children
+    got, cnt = shoot(tree, rx, ry, counts=True)
+    ref, rc = T.shoot(rx, ry, counts=True)
+    np.testing.assert_array_equal(cnt, rc[:, [0, 1, 2, 4]])
+    assert_matches_oracle_tree(got, ref)
+    ga = synth.rng(121).normal(size=(rx.size, 2)).astype(np.float32).astype(np.float64)
+    tt = torch.from_numpy(np.ascontiguousarray(ga, dtype=np.float32)).cuda()
+    grads = g.shoot_adjoint(tree, dev(rx), dev(ry), tt[:, 0].contiguous(), tt[:, 1].contiguous())
+    torch.cuda.synchronize()
+    for name, a, b in zip("mxys", grads, T.grad(rx, ry, ga)):
+        a = a.cpu().numpy()
+        assert np.all(np.abs(a - b) <= 1e-4 * np.abs(b) + 2e-6 * np.abs(b).max()), name
+
+
 def test_bad_inputs_are_rejected():
     import paper_1312_1128_amd as g
 
