@@ -5,7 +5,14 @@ theta, leaf size, order and cutoff drawn at random; rays uniform over and
 around the particles plus rays exactly on particles.  Per ray the interaction
 counts must be identical and alpha, kappa, gamma and the potential equal to
 FP32 rounding; the adjoint (random cotangents, rays off the particles) must
-match the oracle's frozen-tree gradient."""
+match the oracle's frozen-tree gradient.
+
+GLM_RANDOM_SEEDS=a:b runs seeds a .. b-1 instead of the default 0 .. 47.  Of
+seeds 0 .. 1447 one misses: seed 203 (NFW halos up to 0.3 across, collinear,
+leaf size 1), where one particle's adjoint component is 2.6 times outside the
+bound, the FP32 halo terms summed over the rays with cancellation."""
+import os
+
 import numpy as np
 import pytest
 
@@ -14,7 +21,7 @@ from gpu_helpers import assert_matches_oracle_tree, build, dev, say, shoot
 
 pytestmark = pytest.mark.gpu
 
-NCASES = 48
+SEEDS = range(*(int(v) for v in os.environ.get("GLM_RANDOM_SEEDS", "0:48").split(":")))
 
 
 def make_case(seed):
@@ -55,7 +62,7 @@ def make_case(seed):
     return lens, nfw, theta, leaf, order, rx, ry
 
 
-@pytest.mark.parametrize("seed", range(NCASES))
+@pytest.mark.parametrize("seed", SEEDS)
 def test_random_configuration_matches_oracle_tree(ora, seed):
     from paper_1312_1128_amd import GLM_NFW_HALOS
 
