@@ -8,7 +8,8 @@ namespace glm {
 constexpr int kLevReps = 16;
 
 // The particle sort first orders the Morton keys on their top kTopDigits
-// 8-bit digits only (the boxes down to level 4 kTopDigits), then orders each
+// 8-bit digits only (which fix the boxes down to level kTopLevel = 16: two
+// key bits per level), then orders each
 // run of keys equal in those digits by the rest (runs of up to kTieRun keys):
 // the full-key order, unless a box at level kTopLevel holds more than L
 // particles.  The topology count flags that case
