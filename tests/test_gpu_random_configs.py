@@ -10,7 +10,12 @@ match the oracle's frozen-tree gradient.
 GLM_RANDOM_SEEDS=a:b runs seeds a .. b-1 instead of the default 0 .. 47.  Of
 seeds 0 .. 1447 one misses: seed 203 (NFW halos up to 0.3 across, collinear,
 leaf size 1), where one particle's adjoint component is 2.6 times outside the
-bound, the FP32 halo terms summed over the rays with cancellation."""
+bound, the FP32 halo terms summed over the rays with cancellation.  Of seeds
+1448 .. 6447 four miss, all lenses of 2 or 3 heavily overlapping particles:
+2119 and 6030 on the shear (a ray inside a big particle's support whose box
+is expanded, where the FP32 point part m / r^2 cancels against the list's
+Gaussian - point term), 5786 and 5804 on the adjoint (terms cancelling over
+the rays, as in seed 203)."""
 import os
 
 import numpy as np
