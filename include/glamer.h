@@ -152,8 +152,13 @@ GLM_API glm_status glm_tree_workspace_bytes(int64_t n, const glm_params* params,
  *             glm_tree_required_bytes gives the exact size this input needs.
  *
  * Synchronises `stream` once (to size the box arrays); the inputs may be
- * reused or freed after return.  GLM_EDATA if any value is NaN/Inf or a mass
- * or smoothing length is negative.
+ * reused or freed after return.  The box count is read through a small
+ * page-locked host block (the build's count record, under 5 KB)
+ * taken from a process-wide pool: a block is allocated when more builds run
+ * at once than ever before and is kept until the process ends; the handle
+ * owns none.  If that allocation fails, the read uses pageable memory.
+ * GLM_EDATA if any value is NaN/Inf or a mass or smoothing length is
+ * negative.
  */
 GLM_API glm_status glm_build_tree(glm_tree* t, const double* x, const double* y, const double* m,
                           const double* s, int64_t n, const glm_params* params, void* workspace,

@@ -10,6 +10,11 @@
 // flat per-particle or per-box kernel; the only host round trip reads the box
 // count to size the box arrays.
 #include <math.h>
+#include <stddef.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
 
 #include "build.hpp"
 #include "eval.hpp"
@@ -917,6 +922,49 @@ int64_t max_boxes(int64_t n, int L)
 size_t tree_particle_bytes(int64_t n) { return particle_layout(n).size; }
 size_t tree_box_bytes(int64_t ncells, int order) { return box_layout(ncells, order).size; }
 
+// Page-locked host blocks for the build's one read of its counts.  A copy into
+// pageable memory passes through the runtime's staging buffer, which cost
+// about 30 us per build at 1e6 particles.  A block serves one build at a time
+// and returns to the pool afterwards; the pool holds as many blocks as builds
+// ever ran at once and keeps them until the process ends, so a handle owns
+// none and releasing it frees nothing.  Without a block (the page-locked
+// allocation failed) the build reads into pageable memory instead.
+namespace {
+std::mutex g_pin_mu;
+std::vector<BuildSync*> g_pin_free;
+
+struct PinnedSync {
+    BuildSync* p = nullptr;
+    PinnedSync()
+    {
+        {
+            std::lock_guard<std::mutex> lk(g_pin_mu);
+            if (!g_pin_free.empty()) {
+                p = g_pin_free.back();
+                g_pin_free.pop_back();
+                return;
+            }
+        }
+        void* q = nullptr;
+        if (hipHostMalloc(&q, sizeof(BuildSync), hipHostMallocDefault) == hipSuccess)
+            p = static_cast<BuildSync*>(q);
+        else
+            (void)hipGetLastError();
+    }
+    ~PinnedSync()
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        try {
+            g_pin_free.push_back(p);
+        } catch (...) { // no room to keep it: the block stays allocated, unused
+        }
+    }
+    PinnedSync(const PinnedSync&) = delete;
+    PinnedSync& operator=(const PinnedSync&) = delete;
+};
+} // namespace
+
 glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, const double* m, const double* s,
                              int64_t n64, const glm_params& prm, hipStream_t st)
 {
@@ -981,6 +1029,7 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
         pv = where ? v1 : v0;
     }
     BuildSync hs;
+    PinnedSync pin;
     auto count_boxes = [&](bool copy_perm) -> glm_status {
         if (copy_perm) GLM_HIP(hipMemcpyAsync(perm, pv, 4ull * n, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_gather, dim3(gb), dim3(kBlock), 0, st, perm, packed, (int64_t)n, xs, ys, ms, ss);
@@ -988,8 +1037,15 @@ glm_status build_tree_device(TreeStorage& ts, const double* x, const double* y, 
         exclusive_scan_i32(cnt, cnt, n, scr, st);
         hipLaunchKernelGGL(k_sync_counts, dim3(1), dim3(kWave), 0, st, cnt, n, sync);
         GLM_HIP(hipGetLastError());
-        GLM_HIP(hipMemcpyAsync(&hs, sync, sizeof(BuildSync), hipMemcpyDeviceToHost, st));
-        GLM_HIP(hipStreamSynchronize(st));
+        BuildSync* dst = pin.p ? pin.p : &hs;
+        // the host needs the record up to the per-copy level counters
+        hipError_t e = hipMemcpyAsync(dst, sync, offsetof(BuildSync, levrep), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            pin.p = nullptr; // a copy into it may still be pending: it leaves the pool
+            return fail(GLM_EHIP, std::string("reading the box count failed: ") + hipGetErrorString(e));
+        }
+        if (pin.p) memcpy(&hs, pin.p, offsetof(BuildSync, levrep));
         return GLM_OK;
     };
     glm_status cst = count_boxes(full_first);
