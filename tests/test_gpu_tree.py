@@ -453,3 +453,55 @@ def test_wavefront_counts_and_list_search(ora):
         f"{lane_use[1]:.2f} list {lane_use[2]:.2f}")
     assert c[:, 4].mean() < 0.5 * rc[:, 3].mean()
     assert all(0.3 < u <= 1.0 for u in lane_use)
+
+
+def test_builds_on_several_host_threads():
+    """Four handles built from four host threads at once, each thread on its
+    own stream, five builds each (the builds share the pool of page-locked
+    blocks through which they read their box counts), equal the same builds run
+    one after another, bit for bit.  One lens has a clump of coincident
+    particles, so its builds take the full-key sort."""
+    import threading
+
+    import paper_1312_1128_amd as g
+    import torch
+
+    say("[gpu] builds on several host threads")
+    lenses = [synth.nfw_halo(20000 + 5000 * k, 70 + k) for k in range(3)]
+    deep = synth.nfw_halo(20000, 74)
+    deep.x[:40], deep.y[:40] = deep.x[0], deep.y[0]  # 40 > L + 1 equal keys: a box below level 16
+    lenses.append(deep)
+    inputs = [(dev(c.x), dev(c.y), dev(c.m), dev(c.s), c.q) for c in lenses]
+    torch.cuda.synchronize()
+    keys = ("ncells", "max_level", "beg", "end", "next", "leaf", "lbeg", "lend", "M", "cx", "cy", "rcut2", "Q",
+            "perm", "key", "list_idx")
+
+    def build_one(t, i):
+        x, y, m, s, q = inputs[i]
+        return t.build(x, y, m, s, theta=0.3, q=q, leaf_size=8, order=6)
+
+    ref = [build_one(g.Tree(), i).export() for i in range(4)]
+    assert ref[3]["max_level"] > 16 and max(r["max_level"] for r in ref[:3]) <= 16
+    out, errs = [None] * 4, []
+
+    def worker(i):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                t = g.Tree()
+                for _ in range(5):
+                    build_one(t, i)
+                st.synchronize()
+                out[i] = t.export()
+        except Exception as e:  # reported after the join
+            errs.append(f"lens {i}: {e!r}")
+
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errs, errs
+    for i in range(4):
+        for k in keys:
+            np.testing.assert_array_equal(out[i][k], ref[i][k], err_msg=f"lens {i}: {k}")
